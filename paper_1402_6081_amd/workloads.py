@@ -1,0 +1,205 @@
+"""Seeded synthetic inputs: block layouts and source fields.
+
+This module holds input generation only (numpy PCG64 streams); it contains none of
+the solver's arithmetic and is shared by the tests, the benchmark and the CPU checks.
+
+Conventions used throughout the package:
+  * a layout is an int32 array [N_B, 3] of block coordinates (bx, by, bz);
+  * a field on a layout is an array [N_B, n, n, n] indexed [block, z, y, x] (x fastest);
+    the grid point of entry (b, z, y, x) is (bx*n + x, by*n + y, bz*n + z).
+
+Workload families (shapes after the paper's experiments, Sec. 4, and the vortex-ring
+application of Sec. 5): cubes, spheres and thin spherical shells of blocks,
+face-connected random layouts grown by an Eden process, Gaussian-bump sources, a thin
+vortex-ring-shaped source, and random manufactured solutions (Sec. 4.1).
+"""
+import numpy as np
+
+__all__ = [
+    "cube_layout", "sphere_layout", "shell_layout", "eden_layout", "points_of",
+    "gaussian_source", "zero_mean_gaussians", "vortex_ring_source", "random_manufactured",
+    "boundary_mask", "config_small", "config_medium", "config_large",
+]
+
+
+def cube_layout(nb):
+    """All blocks of an nb^3 cube, lexicographic (x fastest)."""
+    z, y, x = np.meshgrid(np.arange(nb), np.arange(nb), np.arange(nb), indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(np.int32)
+
+
+def sphere_layout(nb):
+    """Blocks of an nb^3 box whose centres lie inside the inscribed sphere."""
+    c = cube_layout(nb).astype(np.float64) + 0.5
+    r = np.linalg.norm(c - nb / 2.0, axis=1)
+    return cube_layout(nb)[r <= nb / 2.0]
+
+
+def shell_layout(nb, thickness=0.1):
+    """Blocks whose centres lie in a spherical shell of the given thickness (fraction
+    of the diameter), as in the paper's shell geometry (Sec. 4.2)."""
+    c = cube_layout(nb).astype(np.float64) + 0.5
+    r = np.linalg.norm(c - nb / 2.0, axis=1)
+    R = nb / 2.0
+    keep = (r <= R) & (r >= R - thickness * nb - 0.5)
+    return cube_layout(nb)[keep]
+
+
+def eden_layout(nblocks, rng, max_extent=None):
+    """Face-connected random set of `nblocks` blocks grown from the origin by an Eden
+    process (each step activates a uniformly chosen face neighbour of the set)."""
+    cur = {(0, 0, 0)}
+    frontier = []
+
+    def push(b):
+        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            nb = (b[0] + d[0], b[1] + d[1], b[2] + d[2])
+            if nb in cur:
+                continue
+            if max_extent is not None and max(abs(v) for v in nb) >= max_extent:
+                continue
+            frontier.append(nb)
+
+    push((0, 0, 0))
+    while len(cur) < nblocks and frontier:
+        i = int(rng.integers(len(frontier)))
+        b = frontier[i]
+        frontier[i] = frontier[-1]
+        frontier.pop()
+        if b in cur:
+            continue
+        cur.add(b)
+        push(b)
+    arr = np.array(sorted(cur, key=lambda t: (t[2], t[1], t[0])), dtype=np.int64)
+    arr -= arr.min(axis=0)
+    return arr.astype(np.int32)
+
+
+def points_of(blocks, n):
+    """Grid coordinates [N_B, n, n, n, 3] (x, y, z) of every point of every block."""
+    b = np.asarray(blocks, dtype=np.int64)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    local = np.stack([x, y, z], axis=-1)
+    return b[:, None, None, None, :] * n + local[None]
+
+
+def gaussian_source(blocks, n, centres, sigmas, amps):
+    """sum_g amps[g] exp(-|x - c_g|^2 / (2 sigma_g^2)) sampled on the layout's points."""
+    P = points_of(blocks, n).astype(np.float64)
+    f = np.zeros(P.shape[:-1])
+    for c, s, a in zip(np.atleast_2d(centres), np.atleast_1d(sigmas), np.atleast_1d(amps)):
+        d2 = np.sum((P - np.asarray(c)[None, None, None, None, :]) ** 2, axis=-1)
+        f += a * np.exp(-d2 / (2.0 * s * s))
+    return f
+
+
+def zero_mean_gaussians(blocks, n, rng, count, sigma_lo=2.0, sigma_hi=6.0):
+    """`count` Gaussians with centres uniform over the layout's bounding box, sigma
+    ~ U[sigma_lo, sigma_hi], amplitudes N(0,1), then scaled so the net source is 0:
+    the least-squares multiple of each bump's own discrete mass is removed, i.e.
+    amps <- amps - m (m . amps) / (m . m) with m_g the sampled mass of bump g."""
+    b = np.asarray(blocks)
+    lo = b.min(axis=0) * n
+    hi = (b.max(axis=0) + 1) * n
+    centres = lo + rng.random((count, 3)) * (hi - lo)
+    sigmas = rng.uniform(sigma_lo, sigma_hi, count)
+    amps = rng.standard_normal(count)
+    P = points_of(blocks, n).astype(np.float64)
+    bumps = []
+    for c, s in zip(centres, sigmas):
+        d2 = np.sum((P - c[None, None, None, None, :]) ** 2, axis=-1)
+        bumps.append(np.exp(-d2 / (2.0 * s * s)))
+    mass = np.array([bb.sum() for bb in bumps])
+    amps = amps - mass * (mass @ amps) / (mass @ mass)
+    f = np.zeros(P.shape[:-1])
+    for a, bb in zip(amps, bumps):
+        f += a * bb
+    return f, dict(centres=centres, sigmas=sigmas, amps=amps)
+
+
+def _random_rotation(rng):
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def vortex_ring_source(blocks, n, rng, radius=80.0, core=4.0, component=0):
+    """Thin vortex-ring-shaped source: one Cartesian component of the vorticity of a
+    ring of the given radius with a Gaussian core, centred in the layout's bounding
+    box, normal tilted by a seeded random rotation.  The component of the unit
+    tangent gives a field with (near) zero net source."""
+    b = np.asarray(blocks)
+    centre = (b.min(axis=0) * n + (b.max(axis=0) + 1) * n) / 2.0
+    Rm = _random_rotation(rng)
+    P = points_of(blocks, n).astype(np.float64) - centre
+    Q = P @ Rm  # coordinates in the ring frame (ring in the local x-y plane)
+    rho = np.sqrt(Q[..., 0] ** 2 + Q[..., 1] ** 2)
+    d2 = (rho - radius) ** 2 + Q[..., 2] ** 2
+    amp = np.exp(-d2 / (2.0 * core * core))
+    safe = np.where(rho > 0, rho, 1.0)
+    tang_local = np.stack([-Q[..., 1] / safe, Q[..., 0] / safe, np.zeros_like(rho)], axis=-1)
+    tang = tang_local @ Rm.T
+    return amp * tang[..., component]
+
+
+def boundary_mask(blocks, n):
+    """True at active points with at least one of the 6 lattice neighbours outside
+    the active grid (the paper's boundary points, Sec. 4.1)."""
+    b = np.asarray(blocks, dtype=np.int64)
+    lo = b.min(axis=0)
+    ext = b.max(axis=0) - lo + 1
+    occ = np.zeros((ext[2] * n + 2, ext[1] * n + 2, ext[0] * n + 2), dtype=bool)
+    for (bx, by, bz) in (b - lo).tolist():
+        occ[1 + bz * n:1 + (bz + 1) * n, 1 + by * n:1 + (by + 1) * n, 1 + bx * n:1 + (bx + 1) * n] = True
+    inner = (occ[2:, 1:-1, 1:-1] & occ[:-2, 1:-1, 1:-1] & occ[1:-1, 2:, 1:-1] & occ[1:-1, :-2, 1:-1]
+             & occ[1:-1, 1:-1, 2:] & occ[1:-1, 1:-1, :-2])
+    mask = np.zeros((b.shape[0], n, n, n), dtype=bool)
+    for i, (bx, by, bz) in enumerate((b - lo).tolist()):
+        mask[i] = ~inner[bz * n:(bz + 1) * n, by * n:(by + 1) * n, bx * n:(bx + 1) * n]
+    return mask
+
+
+def random_manufactured(blocks, n, rng):
+    """u_rand ~ U[-1, 1] on the active grid, 0 on its boundary points (Sec. 4.1)."""
+    u = rng.uniform(-1.0, 1.0, (len(blocks), n, n, n))
+    u[boundary_mask(blocks, n)] = 0.0
+    return u
+
+
+# ----------------------------------------------------------------------------- named workloads
+
+def config_small(seed=0):
+    """32^3 cube as 4^3 blocks of 8^3, p = 6, 2 levels, FP64; 4 Gaussians (sigma = 3,
+    centres uniform over the cube, amplitudes U[-1, 1])."""
+    rng = np.random.default_rng(seed)
+    blocks = cube_layout(4)
+    n = 8
+    centres = rng.random((4, 3)) * 32.0
+    amps = rng.uniform(-1.0, 1.0, 4)
+    f = gaussian_source(blocks, n, centres, np.full(4, 3.0), amps)
+    return dict(blocks=blocks, n=n, p=6, levels=2, f=f, name="cube32_n8_p6_L2")
+
+
+def config_medium(seed=1):
+    """128^3 cube as 8^3 blocks of 16^3, p = 8, 4 levels; 32 Gaussians with sigma in
+    U[2, 6], amplitudes N(0, 1) scaled to zero net source."""
+    rng = np.random.default_rng(seed)
+    blocks = cube_layout(8)
+    n = 16
+    f, _ = zero_mean_gaussians(blocks, n, rng, 32)
+    return dict(blocks=blocks, n=n, p=8, levels=4, f=f, name="cube128_n16_p8_L4")
+
+
+def config_large(seed=2):
+    """256^3 cube as 16^3 blocks of 16^3, p = 8, full depth; thin vortex-ring source
+    (R = 80, core sigma = 4, seeded tilt)."""
+    rng = np.random.default_rng(seed)
+    blocks = cube_layout(16)
+    n = 16
+    f = vortex_ring_source(blocks, n, rng)
+    return dict(blocks=blocks, n=n, p=8, levels=0, f=f, name="cube256_n16_p8_vortexring")
