@@ -1,0 +1,147 @@
+/*
+ * lgf.h — C ABI of the MI355X (gfx950) lattice Green's function solver.
+ *
+ * Problem (Sec. 2.1, Eq. dpoisson / dpoissonsoln): on the unbounded lattice Z^3 with
+ * the 7-point Laplacian [L u](n) = sum_{+-e_i} u(n +- e_i) - 6 u(n) and unit spacing,
+ * compute u = G * f, i.e. u(n) = sum_m G(n - m) f(m), where G is the lattice Green's
+ * function (Eq. lgf1) and f is supported on a union of equal cubic blocks of n^3
+ * points (Sec. 2.3).  u is evaluated on the same blocks (B_e = B_s, Sec. 3.1).
+ * The sum is evaluated with the Fast Lattice Green's Function method of Sec. 3.1:
+ * block-wise zero-padded FFT convolutions with the exact G between neighbouring
+ * blocks (level 0) and, on an octree of interpolation intervals, Lagrange
+ * anterpolation (Reg) up the tree, FFT convolutions with the far kernel between the
+ * intervals of each interaction list, and interpolation (Interp) back down.
+ * For spacing h the caller scales f by h^2.
+ *
+ * Layouts.  A layout is an array block_ijk[nblocks][3] of int32 block coordinates
+ * (bx, by, bz), any origin, no duplicates.  Fields f and u are DEVICE arrays
+ * [nblocks][n][n][n] indexed [block][z][y][x] with x fastest, in layout order; entry
+ * (b, z, y, x) is the lattice point (bx*n + x, by*n + y, bz*n + z).  Element type is
+ * double for LGF_F64 plans and float for LGF_F32 plans.
+ *
+ * Ownership and streams.  The plan owns its lists, device workspace and a reference
+ * to the process-wide cache of kernel spectra (shared by all plans with equal
+ * (n, p, level geometry, precision)).  f and u stay owned by the caller and must
+ * stay alive until the work enqueued on `hip_stream` has completed.  All device work
+ * of lgf_solve is asynchronous on `hip_stream` (a hipStream_t; NULL = default
+ * stream); no host<->device copy happens inside a solve.  lgf_plan itself performs
+ * synchronous device work (kernel spectra, list upload) on `hip_stream`.
+ * A plan holds one workspace: solves on one plan must not overlap in time (enqueue
+ * them on one stream).  Different plans may run concurrently on different streams.
+ *
+ * Errors.  Every entry point returns an lgf_status; nothing is printed and no C++
+ * exception crosses the ABI.  lgf_last_error() returns a thread-local message for the
+ * most recent failure on the calling thread.
+ */
+#ifndef LGF_H_
+#define LGF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lgf_plan_s* lgf_plan_t;
+
+typedef enum {
+    LGF_OK = 0,
+    LGF_ERR_ARG = 1,     /* NULL pointer, unsupported n, p outside [2, 10], bad count   */
+    LGF_ERR_LAYOUT = 2,  /* empty layout, duplicate blocks, coordinate span > 2^20      */
+    LGF_ERR_OOM = 3,     /* device allocation failed                                     */
+    LGF_ERR_BUDGET = 4,  /* the plan would exceed the configured device-memory budget    */
+    LGF_ERR_DEVICE = 5,  /* a HIP runtime call or kernel launch failed                   */
+    LGF_ERR_BUSY = 6     /* reserved for the request server                              */
+} lgf_status;
+
+typedef enum { LGF_F64 = 0, LGF_F32 = 1 } lgf_precision;
+
+/* Plan summary filled by lgf_plan_query. */
+typedef struct {
+    int64_t nblocks;          /* active blocks N_B^0                                   */
+    int64_t npoints;          /* nblocks * n^3                                         */
+    int32_t n, p;             /* block edge and interpolation nodes per interval edge  */
+    int32_t levels;           /* tree levels L actually built (leaves at level 1)      */
+    int32_t top_level;        /* highest level with a non-empty interaction list (0 = none) */
+    int64_t near_pairs;       /* entries of all level-0 near-neighbour lists           */
+    int64_t far_pairs[16];    /* entries of the interaction lists, index = level       */
+    int64_t intervals[16];    /* intervals per level, index = level                    */
+    int64_t workspace_bytes;  /* device bytes owned by the plan                        */
+    int64_t spectra_bytes;    /* device bytes of the (shared) kernel spectra it uses   */
+    int32_t precision;        /* lgf_precision                                         */
+} lgf_plan_info;
+
+/*
+ * Build a plan (Sec. 3.1 tree and lists; Step 0 pre-computation, Eq. precomp).
+ *   block_ijk : HOST array [nblocks][3] of block coordinates (read during the call only)
+ *   nblocks   : >= 1
+ *   n         : points per block edge; 4, 8 or 16 (padded FFT length 2n)
+ *   p         : interpolation nodes per interval edge at every level >= 1, 2..10
+ *               (n_max = p, Sec. 2.5 Lebesgue rule); p = n+1 reproduces the paper's
+ *               experimental scheme (nodes on the lattice)
+ *   levels    : tree levels L (leaves at 1); <= 0 selects the full depth
+ *               1 + ceil(log2(extent)).  When L is below full depth the top level's
+ *               list holds every non-adjacent interval.
+ *   prec      : LGF_F64, or LGF_F32 (FP32 transforms and products, FP64 kernel tables
+ *               and spectrum generation, FP64 final add of far and near fields)
+ *   hip_stream: stream for the set-up work (hipStream_t or NULL)
+ *   out       : receives the plan on success
+ * Errors: LGF_ERR_ARG, LGF_ERR_LAYOUT, LGF_ERR_OOM, LGF_ERR_BUDGET, LGF_ERR_DEVICE.
+ */
+lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p,
+                           int32_t levels, lgf_precision prec, void* hip_stream, lgf_plan_t* out);
+
+/*
+ * u = G * f on the plan's layout (Steps 1-3 of Sec. 3.1).  f, u: DEVICE pointers as
+ * described above (may not alias).  u is overwritten entirely.  Asynchronous on
+ * hip_stream.  Errors: LGF_ERR_ARG (NULL), LGF_ERR_DEVICE (launch failure).
+ */
+lgf_status lgf_solve(lgf_plan_t plan, const void* f, void* u, void* hip_stream);
+
+/*
+ * Several independent solves enqueued back to back on one stream; plans[i] is used
+ * with f[i], u[i].  Plans must be distinct (each owns one workspace).
+ */
+lgf_status lgf_solve_many(const lgf_plan_t* plans, const void* const* f, void* const* u,
+                          int32_t count, void* hip_stream);
+
+/* Fill *info (HOST struct).  Errors: LGF_ERR_ARG. */
+lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info);
+
+/* Release the plan's device memory (synchronises with nothing: the caller must make
+ * sure no enqueued solve still uses it).  NULL is accepted. */
+lgf_status lgf_plan_destroy(lgf_plan_t plan);
+
+/* Device-memory budget in bytes for all plan workspaces + spectra of this process
+ * (0 = unlimited, the default).  Plans that would exceed it fail with LGF_ERR_BUDGET. */
+lgf_status lgf_set_memory_budget(int64_t bytes);
+
+/* Bytes currently held by live plans and the spectra cache. */
+int64_t lgf_memory_in_use(void);
+
+/* Drop cached kernel spectra not referenced by a live plan. */
+lgf_status lgf_spectra_cache_trim(void);
+
+/* Thread-local message for the last failure on this thread ("" if none). */
+const char* lgf_last_error(void);
+
+/*
+ * Lattice Green's function values computed by the library's own FP64 device table
+ * (Appendix A, Eq. lgf3 Bessel integral), exposed for validation:
+ *   out[(a*R + b)*R + c] = G(a, b, c) for 0 <= a, b, c < R.  out is a HOST array of
+ *   R^3 doubles.  Synchronous.  Errors: LGF_ERR_ARG (R < 1 or R > 128), LGF_ERR_DEVICE.
+ */
+lgf_status lgf_green_table(int32_t R, double* out);
+
+/*
+ * The library's far-field kernel A^q (Sec. 2.1, Eq. lgf2, q = 8 terms) at npts HOST
+ * points pts[npts][3] (x, y, z), written to HOST out[npts].  Synchronous; evaluated
+ * on the device in FP64.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
+ */
+lgf_status lgf_far_kernel(const double* pts, int64_t npts, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGF_H_ */

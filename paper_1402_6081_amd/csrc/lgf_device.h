@@ -1,0 +1,249 @@
+// Device-side building blocks of the LGF solve: complex type, compile-time roots of
+// unity and register-resident pencil transforms (zero-padded forward, truncated inverse).
+//
+// The fast block convolution of Sec. 2.2 (Pad -> FFT -> Prod -> IFFT -> Trunc) is done
+// per block/interval as three 1D passes over a [z][ky][kx] staging tile in LDS; each
+// thread owns whole pencils in registers, so a pass is a register transform plus one
+// LDS read and one LDS (or HBM) write per element.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lgfdev {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+    T x, y;
+};
+
+// ---------------------------------------------------------------- compile-time roots
+// cos / sin of 2*pi*k/M, reduced exactly to [0, pi/4] by integer octant arithmetic and
+// then summed as Taylor series (|error| < 1e-17 on that range).
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+constexpr double taylor_sin(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int i = 1; i < 16; ++i) {
+        term *= -x2 / ((2.0 * i) * (2.0 * i + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int i = 1; i < 16; ++i) {
+        term *= -x2 / ((2.0 * i - 1.0) * (2.0 * i));
+        sum += term;
+    }
+    return sum;
+}
+
+struct Root {
+    double c, s;
+};
+
+// e^{+2 pi i k / M}
+constexpr Root unit_root(int k, int M) {
+    k = ((k % M) + M) % M;
+    // angle = (pi/2) * (4k / M) = quarter turns q plus fraction r/M of a quarter turn
+    int q = (4 * k) / M;
+    int r = 4 * k - q * M;  // 0 <= r < M
+    double c = 1.0, s = 0.0;
+    if (2 * r <= M) {
+        double phi = (kTwoPi / 4.0) * r / M;
+        c = taylor_cos(phi);
+        s = taylor_sin(phi);
+    } else {
+        double phi = (kTwoPi / 4.0) * (M - r) / M;
+        c = taylor_sin(phi);
+        s = taylor_cos(phi);
+    }
+    // rotate by q quarter turns
+    for (int i = 0; i < q; ++i) {
+        double nc = -s, ns = c;
+        c = nc;
+        s = ns;
+    }
+    return Root{c, s};
+}
+
+template <int M>
+struct RootTable {
+    double c[M];
+    double s[M];
+    constexpr RootTable() : c(), s() {
+        for (int k = 0; k < M; ++k) {
+            Root r = unit_root(k, M);
+            c[k] = r.c;
+            s[k] = r.s;
+        }
+    }
+};
+
+constexpr bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+constexpr int bitrev(int i, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+
+// a * w with w = (wr, wi); exact shortcuts for w in {1, -1, i, -i} once constants fold
+template <typename T>
+__device__ __forceinline__ void cmul_const(T ar, T ai, double wr, double wi, T& orr, T& oi) {
+    if (wr == 1.0 && wi == 0.0) {
+        orr = ar; oi = ai;
+    } else if (wr == -1.0 && wi == 0.0) {
+        orr = -ar; oi = -ai;
+    } else if (wr == 0.0 && wi == 1.0) {
+        orr = -ai; oi = ar;
+    } else if (wr == 0.0 && wi == -1.0) {
+        orr = ai; oi = -ar;
+    } else {
+        const T r = (T)wr, i = (T)wi;
+        orr = ar * r - ai * i;
+        oi = ar * i + ai * r;
+    }
+}
+
+// In-place radix-2 DIT FFT of length N (power of two) in registers.
+// SIGN = -1: X[k] = sum x[j] e^{-2 pi i jk/N};  SIGN = +1: unnormalised inverse.
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void fft_reg(T (&re)[N], T (&im)[N]) {
+    constexpr int bits = ilog2(N);
+    constexpr RootTable<N> R{};
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int j = bitrev(i, bits);
+        if (j > i) {
+            T t = re[i]; re[i] = re[j]; re[j] = t;
+            t = im[i]; im[i] = im[j]; im[j] = t;
+        }
+    }
+#pragma unroll
+    for (int half = 1; half < N; half <<= 1) {
+#pragma unroll
+        for (int start = 0; start < N; start += 2 * half) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const int idx = j * (N / (2 * half));
+                const double wr = R.c[idx];
+                const double wi = SIGN * R.s[idx];
+                const int a = start + j, b = a + half;
+                T tr, ti;
+                cmul_const<T>(re[b], im[b], wr, wi, tr, ti);
+                re[b] = re[a] - tr;
+                im[b] = im[a] - ti;
+                re[a] = re[a] + tr;
+                im[a] = im[a] + ti;
+            }
+        }
+    }
+}
+
+// Forward transform of m inputs zero-padded to M outputs:
+//   X[k] = sum_{j<m} x[j] e^{-2 pi i jk/M},  k < M.
+// Power-of-two M with m = M/2: X[2k] = FFT_m(x)[k], X[2k+1] = FFT_m(x_j w^j)[k].
+// Otherwise a direct DFT with compile-time roots.
+template <typename T, int m, int M>
+__device__ __forceinline__ void pencil_fwd(const T (&xr)[m], const T (&xi)[m], T (&Xr)[M], T (&Xi)[M]) {
+    if constexpr (is_pow2(M) && 2 * m == M && m >= 2) {
+        constexpr RootTable<M> R{};
+        T er[m], ei[m], orr[m], oi[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            er[j] = xr[j];
+            ei[j] = xi[j];
+            cmul_const<T>(xr[j], xi[j], R.c[j], -R.s[j], orr[j], oi[j]);
+        }
+        fft_reg<T, m, -1>(er, ei);
+        fft_reg<T, m, -1>(orr, oi);
+#pragma unroll
+        for (int k = 0; k < m; ++k) {
+            Xr[2 * k] = er[k];
+            Xi[2 * k] = ei[k];
+            Xr[2 * k + 1] = orr[k];
+            Xi[2 * k + 1] = oi[k];
+        }
+    } else {
+        constexpr RootTable<M> R{};
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            T sr = xr[0], si = xi[0];
+#pragma unroll
+            for (int j = 1; j < m; ++j) {
+                const int idx = (j * k) % M;
+                T tr, ti;
+                cmul_const<T>(xr[j], xi[j], R.c[idx], -R.s[idx], tr, ti);
+                sr += tr;
+                si += ti;
+            }
+            Xr[k] = sr;
+            Xi[k] = si;
+        }
+    }
+}
+
+// Truncated inverse: x[j] = sum_{k<M} X[k] e^{+2 pi i jk/M}, j < m (unnormalised).
+template <typename T, int m, int M>
+__device__ __forceinline__ void pencil_inv(const T (&Xr)[M], const T (&Xi)[M], T (&xr)[m], T (&xi)[m]) {
+    if constexpr (is_pow2(M) && 2 * m == M && m >= 2) {
+        constexpr RootTable<M> R{};
+        T er[m], ei[m], orr[m], oi[m];
+#pragma unroll
+        for (int k = 0; k < m; ++k) {
+            er[k] = Xr[2 * k];
+            ei[k] = Xi[2 * k];
+            orr[k] = Xr[2 * k + 1];
+            oi[k] = Xi[2 * k + 1];
+        }
+        fft_reg<T, m, +1>(er, ei);
+        fft_reg<T, m, +1>(orr, oi);
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            T tr, ti;
+            cmul_const<T>(orr[j], oi[j], R.c[j], R.s[j], tr, ti);
+            xr[j] = er[j] + tr;
+            xi[j] = ei[j] + ti;
+        }
+    } else {
+        constexpr RootTable<M> R{};
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            T sr = Xr[0], si = Xi[0];
+#pragma unroll
+            for (int k = 1; k < M; ++k) {
+                const int idx = (j * k) % M;
+                T tr, ti;
+                cmul_const<T>(Xr[k], Xi[k], R.c[idx], R.s[idx], tr, ti);
+                sr += tr;
+                si += ti;
+            }
+            xr[j] = sr;
+            xi[j] = si;
+        }
+    }
+}
+
+// Real part only of the truncated inverse of a Hermitian spectrum given by its first
+// H = M/2 + 1 coefficients (C2R): x[j] = sum_{k<M} Z[k] e^{+2 pi i jk/M}, Z[M-k] = conj Z[k].
+template <typename T, int m, int M>
+__device__ __forceinline__ void pencil_c2r(const T (&Yr)[M / 2 + 1], const T (&Yi)[M / 2 + 1], T (&x)[m]) {
+    T Zr[M], Zi[M];
+#pragma unroll
+    for (int k = 0; k <= M / 2; ++k) {
+        Zr[k] = Yr[k];
+        Zi[k] = Yi[k];
+    }
+#pragma unroll
+    for (int k = M / 2 + 1; k < M; ++k) {
+        Zr[k] = Yr[M - k];
+        Zi[k] = -Yi[M - k];
+    }
+    T xr[m], xi[m];
+    pencil_inv<T, m, M>(Zr, Zi, xr, xi);
+#pragma unroll
+    for (int j = 0; j < m; ++j) x[j] = xr[j];
+}
+
+}  // namespace lgfdev

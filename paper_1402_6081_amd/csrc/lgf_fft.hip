@@ -1,0 +1,204 @@
+// Zero-padded forward FFT (Pad + FFT, Eq. alg_upfft) and truncated inverse FFT
+// (FFT^-1 + Trunc, Eq. alg_dwfft) of one block or interval per workgroup.
+//
+// Data: an m^3 real tile [z][y][x] <-> its padded M^3 real-to-complex spectrum
+// [kz][ky][kx], M = 2m, kx in [0, M/2].  One workgroup per tile; the tile lives in a
+// [z < m][ky < M][kx <= M/2] LDS array (the largest intermediate of either direction),
+// the real input/output is staged in the not-yet-used upper ky half of each z plane
+// so that HBM reads and writes are fully coalesced.  Passes: x (real rows), y (complex
+// columns of the z < m planes), z (complex columns, straight to/from HBM).
+#include "lgf_device.h"
+#include "lgf_internal.h"
+
+namespace lgfdev {
+
+template <typename T, int m, int M, int NT>
+__global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T>* __restrict__ out) {
+    constexpr int H = M / 2 + 1;
+    constexpr int PLANE = M * H;
+    static_assert(M == 2 * m, "padded length is twice the tile edge");
+    __shared__ cplx<T> buf[m * PLANE];
+    const int tid = threadIdx.x;
+    const size_t b = blockIdx.x;
+    const T* src = in + b * (m * m * m);
+
+    // stage the real tile: plane z -> upper ky half of LDS plane z
+    for (int i = tid; i < m * m * m; i += NT) {
+        const int z = i / (m * m), r = i - z * (m * m);
+        reinterpret_cast<T*>(buf + z * PLANE + m * H)[r] = src[i];
+    }
+    __syncthreads();
+    // x pass: real rows (z, y) -> kx in [0, M/2]
+    for (int row = tid; row < m * m; row += NT) {
+        const int z = row / m, y = row - z * m;
+        const T* s = reinterpret_cast<const T*>(buf + z * PLANE + m * H) + y * m;
+        T xr[m], xi[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            xr[j] = s[j];
+            xi[j] = T(0);
+        }
+        T Xr[M], Xi[M];
+        pencil_fwd<T, m, M>(xr, xi, Xr, Xi);
+        cplx<T>* d = buf + z * PLANE + y * H;
+#pragma unroll
+        for (int k = 0; k < H; ++k) d[k] = cplx<T>{Xr[k], Xi[k]};
+    }
+    __syncthreads();
+    // y pass: columns (z, kx), y < m -> ky < M
+    for (int col = tid; col < m * H; col += NT) {
+        const int z = col / H, kx = col - z * H;
+        cplx<T>* base = buf + z * PLANE + kx;
+        T xr[m], xi[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            const cplx<T> v = base[j * H];
+            xr[j] = v.x;
+            xi[j] = v.y;
+        }
+        T Xr[M], Xi[M];
+        pencil_fwd<T, m, M>(xr, xi, Xr, Xi);
+#pragma unroll
+        for (int k = 0; k < M; ++k) base[k * H] = cplx<T>{Xr[k], Xi[k]};
+    }
+    __syncthreads();
+    // z pass: columns (ky, kx), z < m -> kz < M, written to HBM
+    cplx<T>* dst = out + b * (M * PLANE);
+    for (int col = tid; col < PLANE; col += NT) {
+        T xr[m], xi[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            const cplx<T> v = buf[j * PLANE + col];
+            xr[j] = v.x;
+            xi[j] = v.y;
+        }
+        T Xr[M], Xi[M];
+        pencil_fwd<T, m, M>(xr, xi, Xr, Xi);
+#pragma unroll
+        for (int k = 0; k < M; ++k) dst[k * PLANE + col] = cplx<T>{Xr[k], Xi[k]};
+    }
+}
+
+template <typename T, int m, int M, int NT>
+__global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<T>* __restrict__ in, T* __restrict__ out) {
+    constexpr int H = M / 2 + 1;
+    constexpr int PLANE = M * H;
+    static_assert(M == 2 * m, "padded length is twice the tile edge");
+    __shared__ cplx<T> buf[m * PLANE];
+    const int tid = threadIdx.x;
+    const size_t b = blockIdx.x;
+    const cplx<T>* src = in + b * (M * PLANE);
+
+    // z pass: HBM columns (ky, kx), kz < M -> z < m
+    for (int col = tid; col < PLANE; col += NT) {
+        T Xr[M], Xi[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const cplx<T> v = src[k * PLANE + col];
+            Xr[k] = v.x;
+            Xi[k] = v.y;
+        }
+        T xr[m], xi[m];
+        pencil_inv<T, m, M>(Xr, Xi, xr, xi);
+#pragma unroll
+        for (int j = 0; j < m; ++j) buf[j * PLANE + col] = cplx<T>{xr[j], xi[j]};
+    }
+    __syncthreads();
+    // y pass: columns (z, kx), ky < M -> y < m
+    for (int col = tid; col < m * H; col += NT) {
+        const int z = col / H, kx = col - z * H;
+        cplx<T>* base = buf + z * PLANE + kx;
+        T Xr[M], Xi[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const cplx<T> v = base[k * H];
+            Xr[k] = v.x;
+            Xi[k] = v.y;
+        }
+        T xr[m], xi[m];
+        pencil_inv<T, m, M>(Xr, Xi, xr, xi);
+#pragma unroll
+        for (int j = 0; j < m; ++j) base[j * H] = cplx<T>{xr[j], xi[j]};
+    }
+    __syncthreads();
+    // x pass: Hermitian rows (z, y) -> real x < m, staged in the upper ky half
+    for (int row = tid; row < m * m; row += NT) {
+        const int z = row / m, y = row - z * m;
+        const cplx<T>* s = buf + z * PLANE + y * H;
+        T Yr[H], Yi[H];
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const cplx<T> v = s[k];
+            Yr[k] = v.x;
+            Yi[k] = v.y;
+        }
+        T x[m];
+        pencil_c2r<T, m, M>(Yr, Yi, x);
+        T* d = reinterpret_cast<T*>(buf + z * PLANE + m * H) + y * m;
+#pragma unroll
+        for (int j = 0; j < m; ++j) d[j] = x[j];
+    }
+    __syncthreads();
+    T* dst = out + b * (m * m * m);
+    for (int i = tid; i < m * m * m; i += NT) {
+        const int z = i / (m * m), r = i - z * (m * m);
+        dst[i] = reinterpret_cast<const T*>(buf + z * PLANE + m * H)[r];
+    }
+}
+
+template <typename T, int m>
+static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s) {
+    constexpr int NT = m >= 12 ? 256 : 128;
+    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out);
+    return hipGetLastError();
+}
+
+template <typename T, int m>
+static hipError_t launch_inv_m(const cplx<T>* in, T* out, int64_t nbatch, hipStream_t s) {
+    constexpr int NT = m >= 12 ? 256 : 128;
+    hipLaunchKernelGGL((k_ifft_trunc<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s) {
+    if (nbatch <= 0) return hipSuccess;
+    switch (m) {
+        case 2: return launch_fwd_m<T, 2>(in, out, nbatch, s);
+        case 3: return launch_fwd_m<T, 3>(in, out, nbatch, s);
+        case 4: return launch_fwd_m<T, 4>(in, out, nbatch, s);
+        case 5: return launch_fwd_m<T, 5>(in, out, nbatch, s);
+        case 6: return launch_fwd_m<T, 6>(in, out, nbatch, s);
+        case 7: return launch_fwd_m<T, 7>(in, out, nbatch, s);
+        case 8: return launch_fwd_m<T, 8>(in, out, nbatch, s);
+        case 9: return launch_fwd_m<T, 9>(in, out, nbatch, s);
+        case 10: return launch_fwd_m<T, 10>(in, out, nbatch, s);
+        case 16: return launch_fwd_m<T, 16>(in, out, nbatch, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_ifft_trunc(int m, const cplx<T>* in, T* out, int64_t nbatch, hipStream_t s) {
+    if (nbatch <= 0) return hipSuccess;
+    switch (m) {
+        case 2: return launch_inv_m<T, 2>(in, out, nbatch, s);
+        case 3: return launch_inv_m<T, 3>(in, out, nbatch, s);
+        case 4: return launch_inv_m<T, 4>(in, out, nbatch, s);
+        case 5: return launch_inv_m<T, 5>(in, out, nbatch, s);
+        case 6: return launch_inv_m<T, 6>(in, out, nbatch, s);
+        case 7: return launch_inv_m<T, 7>(in, out, nbatch, s);
+        case 8: return launch_inv_m<T, 8>(in, out, nbatch, s);
+        case 9: return launch_inv_m<T, 9>(in, out, nbatch, s);
+        case 10: return launch_inv_m<T, 10>(in, out, nbatch, s);
+        case 16: return launch_inv_m<T, 16>(in, out, nbatch, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t);
+template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t);
+template hipError_t launch_ifft_trunc<double>(int, const cplx<double>*, double*, int64_t, hipStream_t);
+template hipError_t launch_ifft_trunc<float>(int, const cplx<float>*, float*, int64_t, hipStream_t);
+
+}  // namespace lgfdev

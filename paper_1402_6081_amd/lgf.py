@@ -1,0 +1,181 @@
+"""Python binding of the C ABI in include/lgf.h (argument marshalling only).
+
+Every step of a solve runs in the HIP kernels of libpaper_lgf.so; this module only
+passes torch device pointers and streams through ctypes.  There is no CPU fallback:
+if the library is not built, or no GPU is visible, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # imported before the library so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpaper_lgf.so")
+
+F64, F32 = 0, 1
+_STATUS = {0: "LGF_OK", 1: "LGF_ERR_ARG", 2: "LGF_ERR_LAYOUT", 3: "LGF_ERR_OOM", 4: "LGF_ERR_BUDGET",
+           5: "LGF_ERR_DEVICE", 6: "LGF_ERR_BUSY"}
+
+
+class LGFError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("nblocks", ctypes.c_int64), ("npoints", ctypes.c_int64),
+        ("n", ctypes.c_int32), ("p", ctypes.c_int32),
+        ("levels", ctypes.c_int32), ("top_level", ctypes.c_int32),
+        ("near_pairs", ctypes.c_int64), ("far_pairs", ctypes.c_int64 * 16),
+        ("intervals", ctypes.c_int64 * 16), ("workspace_bytes", ctypes.c_int64),
+        ("spectra_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
+    ]
+
+
+EXPORTS = ["lgf_plan_create", "lgf_solve", "lgf_solve_many", "lgf_plan_query", "lgf_plan_destroy",
+           "lgf_set_memory_budget", "lgf_memory_in_use", "lgf_spectra_cache_trim", "lgf_last_error",
+           "lgf_green_table", "lgf_far_kernel"]
+
+_lib = None
+
+
+def library():
+    """Load libpaper_lgf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpaper_lgf.so is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.lgf_plan_create.argtypes = [vp, i64, i32, i32, i32, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.lgf_solve.argtypes = [vp, vp, vp, vp]
+        L.lgf_solve_many.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+        L.lgf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.lgf_plan_destroy.argtypes = [vp]
+        L.lgf_set_memory_budget.argtypes = [i64]
+        L.lgf_memory_in_use.restype = i64
+        L.lgf_last_error.restype = ctypes.c_char_p
+        L.lgf_green_table.argtypes = [i32, vp]
+        L.lgf_far_kernel.argtypes = [vp, i64, vp]
+        for name in ["lgf_plan_create", "lgf_solve", "lgf_solve_many", "lgf_plan_query", "lgf_plan_destroy",
+                     "lgf_set_memory_budget", "lgf_spectra_cache_trim", "lgf_green_table", "lgf_far_kernel"]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise LGFError(status, library().lgf_last_error().decode())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the LGF solver runs only on the device")
+
+
+class Plan:
+    """lgf_plan_create / lgf_solve / lgf_plan_query / lgf_plan_destroy."""
+
+    def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None):
+        _require_gpu()
+        b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+        self.blocks = b
+        self.n, self.p = int(n), int(p)
+        self.precision = precision
+        prec = {"f64": F64, "f32": F32}[precision]
+        self.dtype = torch.float64 if prec == F64 else torch.float32
+        h = ctypes.c_void_p()
+        _check(library().lgf_plan_create(b.ctypes.data, b.shape[0], self.n, self.p, int(levels), prec,
+                                         _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def shape(self):
+        return (self.blocks.shape[0], self.n, self.n, self.n)
+
+    def solve(self, f, u=None, stream=None):
+        """u = G * f on the plan's layout; f is a contiguous device tensor [N_B, n, n, n]."""
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        if not (f.is_cuda and f.is_contiguous() and f.dtype == self.dtype and tuple(f.shape) == self.shape()):
+            raise ValueError("f must be a contiguous %s device tensor of shape %s" % (self.dtype, self.shape()))
+        if u is None:
+            u = torch.empty_like(f)
+        elif not (u.is_cuda and u.is_contiguous() and u.dtype == self.dtype and tuple(u.shape) == self.shape()):
+            raise ValueError("u must match f")
+        _check(library().lgf_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                   _stream_handle(stream)))
+        return u
+
+    def info(self):
+        inf = PlanInfo()
+        _check(library().lgf_plan_query(self._h, ctypes.byref(inf)))
+        d = {k: getattr(inf, k) for k, _ in PlanInfo._fields_}
+        d["far_pairs"] = list(inf.far_pairs)
+        d["intervals"] = list(inf.intervals)
+        return d
+
+    def close(self):
+        if self._h is not None:
+            library().lgf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_many(plans, fs, us, stream=None):
+    n = len(plans)
+    hp = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    hf = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    hu = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+    _check(library().lgf_solve_many(hp, hf, hu, n, _stream_handle(stream)))
+    return us
+
+
+def green_table(R):
+    """G[a, b, c] for 0 <= a, b, c < R from the library's FP64 device table."""
+    _require_gpu()
+    out = np.zeros((R, R, R), dtype=np.float64)
+    _check(library().lgf_green_table(int(R), out.ctypes.data))
+    return out
+
+
+def far_kernel(points):
+    """The library's A^q far kernel at real points [..., 3]."""
+    _require_gpu()
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
+    shape = pts.shape[:-1]
+    pts = pts.reshape(-1, 3)
+    out = np.zeros(pts.shape[0], dtype=np.float64)
+    _check(library().lgf_far_kernel(pts.ctypes.data, pts.shape[0], out.ctypes.data))
+    return out.reshape(shape)
+
+
+def set_memory_budget(nbytes):
+    _check(library().lgf_set_memory_budget(int(nbytes)))
+
+
+def memory_in_use():
+    return int(library().lgf_memory_in_use())
+
+
+def trim_spectra_cache():
+    _check(library().lgf_spectra_cache_trim())

@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every entry point declared in include/lgf.h
+(no compute: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lgf.h")
+LIB = os.path.join(ROOT, "paper_1402_6081_amd", "libpaper_lgf.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lgf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("lgf_plan_create", "lgf_solve", "lgf_plan_destroy", "lgf_plan_query"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    import torch  # noqa: F401  (shares the HIP runtime with the library)
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_names_match_header():
+    from paper_1402_6081_amd import lgf as L
+    assert sorted(L.EXPORTS) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_argument_errors_without_gpu_work():
+    # argument validation happens before any device call
+    import torch  # noqa: F401
+    from paper_1402_6081_amd import lgf as L
+    lib = L.library()
+    h = ctypes.c_void_p()
+    blocks = (ctypes.c_int32 * 3)(0, 0, 0)
+    assert lib.lgf_plan_create(blocks, 1, 5, 4, 0, 0, None, ctypes.byref(h)) == 1   # n unsupported
+    assert lib.lgf_plan_create(blocks, 1, 8, 11, 0, 0, None, ctypes.byref(h)) == 1  # p > 10
+    assert lib.lgf_plan_create(blocks, 1, 8, 1, 0, 0, None, ctypes.byref(h)) == 1   # p < 2
+    assert lib.lgf_plan_create(blocks, 0, 8, 6, 0, 0, None, ctypes.byref(h)) == 2   # empty layout
+    assert lib.lgf_plan_create(None, 1, 8, 6, 0, 0, None, ctypes.byref(h)) == 1     # NULL
+    assert b"p must" in lib.lgf_last_error() or b"NULL" in lib.lgf_last_error()
+    assert lib.lgf_solve(None, None, None, None) == 1
+    assert lib.lgf_plan_query(None, None) == 1
+    assert lib.lgf_set_memory_budget(-1) == 1
+    assert lib.lgf_plan_destroy(None) == 0
