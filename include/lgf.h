@@ -122,6 +122,32 @@ int64_t lgf_memory_in_use(void);
 /* Drop cached kernel spectra not referenced by a live plan. */
 lgf_status lgf_spectra_cache_trim(void);
 
+/*
+ * Per-step device timing of a plan's solves (measurement support).
+ * lgf_profile_enable(plan, max_solves): the next max_solves calls of lgf_solve on this
+ * plan record a HIP event on their stream before the first and after every step
+ * (fwd FFT, Reg, Prod, inverse FFT, Interp, final add of each level).  Recording
+ * adds no synchronisation.  lgf_profile_collect waits for the recorded events and
+ * fills *out with, per step in launch order: its name, the summed device time over
+ * the nsolves recorded solves (one launch per step per solve), and the step's
+ * algorithmic bytes and flops per launch (compulsory HBM traffic: every input read once, every output
+ * written once; flops by the paper's operation counts, Table 1).  Per-solve times
+ * are written to solve_ms[0..min(recorded, max_out)-1] when solve_ms is non-NULL.
+ * Collecting disables recording.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
+ */
+#define LGF_MAX_STEPS 64
+typedef struct {
+    int32_t nsteps;                 /* steps per solve                              */
+    int32_t nsolves;                /* solves recorded                              */
+    char name[LGF_MAX_STEPS][32];   /* step names, e.g. "prod_l0", "fft_fwd_l1"     */
+    double total_ms[LGF_MAX_STEPS]; /* device time summed over the recorded solves  */
+    double bytes[LGF_MAX_STEPS];    /* algorithmic bytes per launch                 */
+    double flops[LGF_MAX_STEPS];    /* algorithmic flops per launch                 */
+} lgf_step_profile;
+
+lgf_status lgf_profile_enable(lgf_plan_t plan, int32_t max_solves);
+lgf_status lgf_profile_collect(lgf_plan_t plan, lgf_step_profile* out, double* solve_ms, int32_t max_out);
+
 /* Thread-local message for the last failure on this thread ("" if none). */
 const char* lgf_last_error(void);
 

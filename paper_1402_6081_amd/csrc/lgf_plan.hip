@@ -12,6 +12,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -94,9 +95,19 @@ struct lgf_plan_s {
     std::vector<DevBuf> allocs;
     int64_t ws_bytes = 0;
     int device = 0;
+    // step profiling (events recorded on the solve stream)
+    struct StepInfo {
+        std::string name;
+        double bytes, flops;
+    };
+    std::vector<StepInfo> steps;  // filled by the first profiled solve
+    std::vector<hipEvent_t> events;
+    int prof_max = 0, prof_solves = 0, prof_cursor = 0;
+    bool prof_on = false;
 
     ~lgf_plan_s() {
         for (auto& b : allocs) hipFree(b.ptr);
+        for (auto& e : events) hipEventDestroy(e);
         budget_release(ws_bytes);
     }
 };
@@ -133,46 +144,100 @@ hipError_t checked(hipError_t e, const char* what, hipStream_t s) {
     return e;
 }
 
+// Profiling: record an event after a step (and describe the step on the first solve).
+struct Marker {
+    lgf_plan_s* pl;
+    hipStream_t s;
+    bool on;
+    int step = 0;
+    Marker(lgf_plan_s* p, hipStream_t st) : pl(p), s(st) {
+        on = pl->prof_on && pl->prof_solves < pl->prof_max;
+        if (on) {
+            if (pl->prof_solves == 0) pl->steps.clear();
+            hipEventRecord(pl->events[pl->prof_cursor++], s);
+        }
+    }
+    void operator()(const std::string& name, double bytes, double flops) {
+        if (!on) return;
+        if (pl->prof_solves == 0) pl->steps.push_back({name, bytes, flops});
+        hipEventRecord(pl->events[pl->prof_cursor++], s);
+        ++step;
+    }
+    void finish() {
+        if (on) ++pl->prof_solves;
+    }
+};
+
+inline double fft_flops(int M) {  // Table 1: 2 (8 N_b) log2(8 N_b) for a padded M^3 transform
+    const double N = (double)M * M * M;
+    return 2.0 * N * std::log2(N);
+}
+
 template <typename T>
 hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     using C = cplx<T>;
     const int n = pl->n, p = pl->p;
     hipError_t e;
+    Marker mark(pl, s);
+    const double es = sizeof(T), cs = 2.0 * sizeof(T);
+    const double n3 = (double)n * n * n, p3 = (double)p * p * p;
+    const double S0 = pl->spectra0->S, S1 = (double)(2 * p) * (2 * p) * (p + 1);
+    const double nb = (double)pl->nb;
+    auto lvN = [&](int l) { return (double)pl->lv[l].nint; };
 #define LGF_CHECK(x)                                      \
     do {                                                  \
         if ((e = checked((x), #x, s)) != hipSuccess) return e; \
     } while (0)
     LGF_CHECK(launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nb, s));
+    mark("fft_fwd_l0", nb * (n3 * es + S0 * cs), nb * fft_flops(2 * n));
     if (pl->Ltop >= 1) {
         LGF_CHECK(launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nb, n, p, s));
-        for (int l = 1; l < pl->Ltop; ++l)
+        mark("reg_l0_l1", nb * (n3 + p3) * es, nb * 2.0 * (p * n3 + p * p * n * n + p3 * n));
+        for (int l = 1; l < pl->Ltop; ++l) {
             LGF_CHECK(launch_reg_up<T>((const T*)pl->lv[l].d_ftil, pl->lv[l + 1].d_child8, pl->d_C01,
                                        (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s));
+            mark("reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1), (lvN(l) + lvN(l + 1)) * p3 * es,
+                 lvN(l) * 2.0 * 3.0 * p3 * p);
+        }
         for (int l = 1; l <= pl->Ltop; ++l)
-            if (!pl->lv[l].il_src.empty())
+            if (!pl->lv[l].il_src.empty()) {
                 LGF_CHECK(launch_pad_fft<T>(p, (const T*)pl->lv[l].d_ftil, (C*)pl->lv[l].d_fhat, pl->lv[l].nint, s));
+                mark("fft_fwd_l" + std::to_string(l), lvN(l) * (p3 * es + S1 * cs), lvN(l) * fft_flops(2 * p));
+            }
     }
     LGF_CHECK(launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_nbr0, (C*)pl->d_uhat0,
                                   pl->nb, pl->spectra0->S, s));
+    mark("prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
     for (int l = 1; l <= pl->Ltop; ++l) {
         LevelPlan& L = pl->lv[l];
         if (L.il_src.empty()) continue;
         LGF_CHECK(launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, L.d_ptr, L.d_src, L.d_off,
                                      (C*)L.d_uhat, L.nint, L.spectra->S, s));
+        mark("prod_l" + std::to_string(l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.il_src.size() * S1 * 8.0);
     }
     for (int l = pl->Ltop; l >= 1; --l) {
         LevelPlan& L = pl->lv[l];
         if (L.il_src.empty()) {
             LGF_CHECK(zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(T), s));
+            mark("zero_l" + std::to_string(l), lvN(l) * p3 * es, 0.0);
         } else {
             LGF_CHECK(launch_ifft_trunc<T>(p, (const C*)L.d_uhat, (T*)L.d_util, L.nint, s));
+            mark("fft_inv_l" + std::to_string(l), lvN(l) * (S1 * cs + p3 * es), lvN(l) * fft_flops(2 * p));
         }
-        if (l < pl->Ltop)
+        if (l < pl->Ltop) {
             LGF_CHECK(launch_interp_down<T>((const T*)pl->lv[l + 1].d_util, L.d_parent, L.d_cpos, pl->d_C01,
                                             (T*)L.d_util, L.nint, p, s));
+            mark("interp_l" + std::to_string(l + 1) + "_l" + std::to_string(l), (lvN(l + 1) + 2.0 * lvN(l)) * p3 * es,
+                 lvN(l) * 2.0 * 3.0 * p3 * p);
+        }
     }
     LGF_CHECK(launch_ifft_trunc<T>(n, (const C*)pl->d_uhat0, u, pl->nb, s));
-    if (pl->Ltop >= 1) LGF_CHECK(launch_final<T>(u, (const T*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s));
+    mark("fft_inv_l0", nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
+    if (pl->Ltop >= 1) {
+        LGF_CHECK(launch_final<T>(u, (const T*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s));
+        mark("final_l1_l0", nb * (2.0 * n3 + p3) * es, nb * 2.0 * (p3 * n + p * p * n * n + p * n3));
+    }
+    mark.finish();
 #undef LGF_CHECK
     return hipSuccess;
 }
@@ -502,6 +567,55 @@ lgf_status lgf_spectra_cache_trim(void) {
 }
 
 const char* lgf_last_error(void) { return t_err.c_str(); }
+
+lgf_status lgf_profile_enable(lgf_plan_t plan, int32_t max_solves) {
+    if (!plan || max_solves < 1) return fail(LGF_ERR_ARG, "lgf_profile_enable: bad arguments");
+    const size_t need = (size_t)max_solves * (LGF_MAX_STEPS + 1);
+    while (plan->events.size() < need) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return fail(LGF_ERR_DEVICE, "hipEventCreate failed");
+        plan->events.push_back(ev);
+    }
+    plan->prof_max = max_solves;
+    plan->prof_solves = 0;
+    plan->prof_cursor = 0;
+    plan->prof_on = true;
+    return LGF_OK;
+}
+
+lgf_status lgf_profile_collect(lgf_plan_t plan, lgf_step_profile* out, double* solve_ms, int32_t max_out) {
+    if (!plan || !out) return fail(LGF_ERR_ARG, "lgf_profile_collect: bad arguments");
+    std::memset(out, 0, sizeof(*out));
+    plan->prof_on = false;
+    const int ns = (int)plan->steps.size();
+    if (ns > LGF_MAX_STEPS) return fail(LGF_ERR_ARG, "too many steps");
+    out->nsteps = ns;
+    out->nsolves = plan->prof_solves;
+    if (plan->prof_cursor > 0 && hipEventSynchronize(plan->events[plan->prof_cursor - 1]) != hipSuccess)
+        return fail(LGF_ERR_DEVICE, "hipEventSynchronize failed");
+    for (int j = 0; j < ns; ++j) {
+        std::snprintf(out->name[j], sizeof(out->name[j]), "%s", plan->steps[j].name.c_str());
+        out->bytes[j] = plan->steps[j].bytes;
+        out->flops[j] = plan->steps[j].flops;
+    }
+    for (int i = 0; i < plan->prof_solves; ++i) {
+        hipEvent_t* ev = &plan->events[(size_t)i * (ns + 1)];
+        for (int j = 0; j < ns; ++j) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[j], ev[j + 1]) != hipSuccess)
+                return fail(LGF_ERR_DEVICE, "hipEventElapsedTime failed");
+            out->total_ms[j] += ms;
+        }
+        if (solve_ms && i < max_out) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ev[0], ev[ns]);
+            solve_ms[i] = ms;
+        }
+    }
+    plan->prof_solves = 0;
+    plan->prof_cursor = 0;
+    return LGF_OK;
+}
 
 lgf_status lgf_green_table(int32_t R, double* out) {
     if (R < 1 || R > 128 || !out) return fail(LGF_ERR_ARG, "lgf_green_table: R must be in [1, 128]");

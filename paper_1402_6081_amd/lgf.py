@@ -36,9 +36,17 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class StepProfile(ctypes.Structure):
+    _fields_ = [
+        ("nsteps", ctypes.c_int32), ("nsolves", ctypes.c_int32),
+        ("name", (ctypes.c_char * 32) * 64), ("total_ms", ctypes.c_double * 64),
+        ("bytes", ctypes.c_double * 64), ("flops", ctypes.c_double * 64),
+    ]
+
+
 EXPORTS = ["lgf_plan_create", "lgf_solve", "lgf_solve_many", "lgf_plan_query", "lgf_plan_destroy",
            "lgf_set_memory_budget", "lgf_memory_in_use", "lgf_spectra_cache_trim", "lgf_last_error",
-           "lgf_green_table", "lgf_far_kernel"]
+           "lgf_green_table", "lgf_far_kernel", "lgf_profile_enable", "lgf_profile_collect"]
 
 _lib = None
 
@@ -61,8 +69,11 @@ def library():
         L.lgf_last_error.restype = ctypes.c_char_p
         L.lgf_green_table.argtypes = [i32, vp]
         L.lgf_far_kernel.argtypes = [vp, i64, vp]
+        L.lgf_profile_enable.argtypes = [vp, i32]
+        L.lgf_profile_collect.argtypes = [vp, ctypes.POINTER(StepProfile), vp, i32]
         for name in ["lgf_plan_create", "lgf_solve", "lgf_solve_many", "lgf_plan_query", "lgf_plan_destroy",
-                     "lgf_set_memory_budget", "lgf_spectra_cache_trim", "lgf_green_table", "lgf_far_kernel"]:
+                     "lgf_set_memory_budget", "lgf_spectra_cache_trim", "lgf_green_table", "lgf_far_kernel",
+                     "lgf_profile_enable", "lgf_profile_collect"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -128,6 +139,20 @@ class Plan:
         d["far_pairs"] = list(inf.far_pairs)
         d["intervals"] = list(inf.intervals)
         return d
+
+    def profile_enable(self, max_solves):
+        _check(library().lgf_profile_enable(self._h, int(max_solves)))
+
+    def profile_collect(self, max_solves=4096):
+        """Per-step device times of the solves recorded since profile_enable."""
+        prof = StepProfile()
+        per_solve = np.zeros(max_solves, dtype=np.float64)
+        _check(library().lgf_profile_collect(self._h, ctypes.byref(prof), per_solve.ctypes.data, max_solves))
+        steps = []
+        for j in range(prof.nsteps):
+            steps.append(dict(name=bytes(prof.name[j]).split(b"\0")[0].decode(), total_ms=prof.total_ms[j],
+                              bytes=prof.bytes[j], flops=prof.flops[j]))
+        return dict(nsolves=prof.nsolves, steps=steps, solve_ms=per_solve[:min(prof.nsolves, max_solves)])
 
     def close(self):
         if self._h is not None:
