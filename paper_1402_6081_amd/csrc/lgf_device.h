@@ -16,6 +16,66 @@ struct alignas(2 * sizeof(T)) cplx {
     T x, y;
 };
 
+// ---------------------------------------------------------------- spectrum layout
+// Every spectrum array (sources, fields, kernels) is stored frequency-chunk major:
+// coefficient w of item i lives at ((w / 64) * nitems + i) * 64 + w % 64.  The Prod kernels
+// work one frequency chunk at a time across all items, so the data they touch together is
+// contiguous (no aliasing of many items onto the same memory channels), and a wave's 64
+// lanes of one item read or write one 64-coefficient run.  S is padded to a multiple of 64.
+constexpr int kSpecChunk = 64;
+__host__ __device__ constexpr int spec_padded(int S) { return (S + kSpecChunk - 1) / kSpecChunk * kSpecChunk; }
+__host__ __device__ __forceinline__ int64_t spec_at(int64_t item, int w, int64_t nitems) {
+    return ((int64_t)(w >> 6) * nitems + item) * kSpecChunk + (w & 63);
+}
+
+// ---------------------------------------------------------------- float-float numbers
+// An unevaluated sum hi + lo of two floats (|lo| <= ulp(hi)/2), with error-free
+// transformations (Knuth TwoSum, FMA-based TwoProduct).  Used by the FP32 path to carry
+// the far-field level contributions with compensation through the inverse transforms and
+// the interpolation down the tree, where the Lebesgue constant of equispaced
+// interpolation would otherwise amplify FP32 rounding of the node values.
+struct alignas(8) ff32 {
+    float hi, lo;
+    ff32() = default;
+    __host__ __device__ constexpr ff32(float h, float l) : hi(h), lo(l) {}
+    __host__ __device__ ff32(int v) : hi((float)v), lo(0.f) {}
+    __host__ __device__ ff32(float v) : hi(v), lo(0.f) {}
+    __host__ __device__ ff32(double d) : hi((float)d), lo((float)(d - (double)(float)d)) {}
+};
+
+__device__ __forceinline__ ff32 ff_two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    const float e = (a - (s - bb)) + (b - bb);
+    return ff32(s, e);
+}
+__device__ __forceinline__ ff32 ff_fast_two_sum(float a, float b) {
+    const float s = a + b;
+    return ff32(s, b - (s - a));
+}
+__device__ __forceinline__ ff32 operator+(ff32 a, ff32 b) {
+    ff32 s = ff_two_sum(a.hi, b.hi);
+    s.lo += a.lo + b.lo;
+    return ff_fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ ff32 operator-(ff32 a) { return ff32(-a.hi, -a.lo); }
+__device__ __forceinline__ ff32 operator-(ff32 a, ff32 b) { return a + (-b); }
+__device__ __forceinline__ ff32 operator*(ff32 a, ff32 b) {
+    const float p = a.hi * b.hi;
+    float e = __builtin_fmaf(a.hi, b.hi, -p);
+    e = __builtin_fmaf(a.hi, b.lo, e);
+    e = __builtin_fmaf(a.lo, b.hi, e);
+    return ff_fast_two_sum(p, e);
+}
+__device__ __forceinline__ ff32& operator+=(ff32& a, ff32 b) {
+    a = a + b;
+    return a;
+}
+
+__device__ __forceinline__ double to_double(double v) { return v; }
+__device__ __forceinline__ double to_double(float v) { return (double)v; }
+__device__ __forceinline__ double to_double(ff32 v) { return (double)v.hi + (double)v.lo; }
+
 // ---------------------------------------------------------------- compile-time roots
 // cos / sin of 2*pi*k/M, reduced exactly to [0, pi/4] by integer octant arithmetic and
 // then summed as Taylor series (|error| < 1e-17 on that range).

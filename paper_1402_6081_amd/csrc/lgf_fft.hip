@@ -2,18 +2,21 @@
 // (FFT^-1 + Trunc, Eq. alg_dwfft) of one block or interval per workgroup.
 //
 // Data: an m^3 real tile [z][y][x] <-> its padded M^3 real-to-complex spectrum
-// [kz][ky][kx], M = 2m, kx in [0, M/2].  One workgroup per tile; the tile lives in a
+// [kz][ky][kx], M = 2m, kx in [0, M/2], stored chunk-major (spec_at) across the batch.  One workgroup per tile; the tile lives in a
 // [z < m][ky < M][kx <= M/2] LDS array (the largest intermediate of either direction),
 // the real input/output is staged in the not-yet-used upper ky half of each z plane
 // so that HBM reads and writes are fully coalesced.  Passes: x (real rows), y (complex
 // columns of the z < m planes), z (complex columns, straight to/from HBM).
+#include <type_traits>
+
 #include "lgf_device.h"
 #include "lgf_internal.h"
 
 namespace lgfdev {
 
 template <typename T, int m, int M, int NT>
-__global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T>* __restrict__ out) {
+__global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T>* __restrict__ out,
+                                                int64_t nbatch) {
     constexpr int H = M / 2 + 1;
     constexpr int PLANE = M * H;
     static_assert(M == 2 * m, "padded length is twice the tile edge");
@@ -62,8 +65,7 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T
         for (int k = 0; k < M; ++k) base[k * H] = cplx<T>{Xr[k], Xi[k]};
     }
     __syncthreads();
-    // z pass: columns (ky, kx), z < m -> kz < M, written to HBM
-    cplx<T>* dst = out + b * (M * PLANE);
+    // z pass: columns (ky, kx), z < m -> kz < M, written to HBM (chunk-major spectrum)
     for (int col = tid; col < PLANE; col += NT) {
         T xr[m], xi[m];
 #pragma unroll
@@ -75,88 +77,92 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T
         T Xr[M], Xi[M];
         pencil_fwd<T, m, M>(xr, xi, Xr, Xi);
 #pragma unroll
-        for (int k = 0; k < M; ++k) dst[k * PLANE + col] = cplx<T>{Xr[k], Xi[k]};
+        for (int k = 0; k < M; ++k) out[spec_at(b, k * PLANE + col, nbatch + 1)] = cplx<T>{Xr[k], Xi[k]};
     }
 }
 
-template <typename T, int m, int M, int NT>
-__global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<T>* __restrict__ in, T* __restrict__ out) {
+// Inverse: spectrum elements of type Tin, arithmetic in A, real output of type Tout.
+// (FP64 path: all double.  FP32 path: float at level 0; at levels >= 1 float spectra are
+// inverted in float-float arithmetic and written as float-float node values.)
+template <typename Tin, typename A, typename Tout, int m, int M, int NT>
+__global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__ in, Tout* __restrict__ out,
+                                                   int64_t nbatch) {
     constexpr int H = M / 2 + 1;
     constexpr int PLANE = M * H;
     static_assert(M == 2 * m, "padded length is twice the tile edge");
-    __shared__ cplx<T> buf[m * PLANE];
+    __shared__ cplx<A> buf[m * PLANE];
     const int tid = threadIdx.x;
     const size_t b = blockIdx.x;
-    const cplx<T>* src = in + b * (M * PLANE);
 
     // z pass: HBM columns (ky, kx), kz < M -> z < m
     for (int col = tid; col < PLANE; col += NT) {
-        T Xr[M], Xi[M];
+        A Xr[M], Xi[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            const cplx<T> v = src[k * PLANE + col];
-            Xr[k] = v.x;
-            Xi[k] = v.y;
+            const cplx<Tin> v = in[spec_at(b, k * PLANE + col, nbatch)];
+            Xr[k] = A(v.x);
+            Xi[k] = A(v.y);
         }
-        T xr[m], xi[m];
-        pencil_inv<T, m, M>(Xr, Xi, xr, xi);
+        A xr[m], xi[m];
+        pencil_inv<A, m, M>(Xr, Xi, xr, xi);
 #pragma unroll
-        for (int j = 0; j < m; ++j) buf[j * PLANE + col] = cplx<T>{xr[j], xi[j]};
+        for (int j = 0; j < m; ++j) buf[j * PLANE + col] = cplx<A>{xr[j], xi[j]};
     }
     __syncthreads();
     // y pass: columns (z, kx), ky < M -> y < m
     for (int col = tid; col < m * H; col += NT) {
         const int z = col / H, kx = col - z * H;
-        cplx<T>* base = buf + z * PLANE + kx;
-        T Xr[M], Xi[M];
+        cplx<A>* base = buf + z * PLANE + kx;
+        A Xr[M], Xi[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            const cplx<T> v = base[k * H];
+            const cplx<A> v = base[k * H];
             Xr[k] = v.x;
             Xi[k] = v.y;
         }
-        T xr[m], xi[m];
-        pencil_inv<T, m, M>(Xr, Xi, xr, xi);
+        A xr[m], xi[m];
+        pencil_inv<A, m, M>(Xr, Xi, xr, xi);
 #pragma unroll
-        for (int j = 0; j < m; ++j) base[j * H] = cplx<T>{xr[j], xi[j]};
+        for (int j = 0; j < m; ++j) base[j * H] = cplx<A>{xr[j], xi[j]};
     }
     __syncthreads();
     // x pass: Hermitian rows (z, y) -> real x < m, staged in the upper ky half
     for (int row = tid; row < m * m; row += NT) {
         const int z = row / m, y = row - z * m;
-        const cplx<T>* s = buf + z * PLANE + y * H;
-        T Yr[H], Yi[H];
+        const cplx<A>* s = buf + z * PLANE + y * H;
+        A Yr[H], Yi[H];
 #pragma unroll
         for (int k = 0; k < H; ++k) {
-            const cplx<T> v = s[k];
+            const cplx<A> v = s[k];
             Yr[k] = v.x;
             Yi[k] = v.y;
         }
-        T x[m];
-        pencil_c2r<T, m, M>(Yr, Yi, x);
-        T* d = reinterpret_cast<T*>(buf + z * PLANE + m * H) + y * m;
+        A x[m];
+        pencil_c2r<A, m, M>(Yr, Yi, x);
+        A* d = reinterpret_cast<A*>(buf + z * PLANE + m * H) + y * m;
 #pragma unroll
         for (int j = 0; j < m; ++j) d[j] = x[j];
     }
     __syncthreads();
-    T* dst = out + b * (m * m * m);
+    Tout* dst = out + b * (m * m * m);
     for (int i = tid; i < m * m * m; i += NT) {
         const int z = i / (m * m), r = i - z * (m * m);
-        dst[i] = reinterpret_cast<const T*>(buf + z * PLANE + m * H)[r];
+        dst[i] = (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[r];
     }
 }
 
 template <typename T, int m>
 static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s) {
     constexpr int NT = m >= 12 ? 256 : 128;
-    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out);
+    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out, nbatch);
     return hipGetLastError();
 }
 
-template <typename T, int m>
-static hipError_t launch_inv_m(const cplx<T>* in, T* out, int64_t nbatch, hipStream_t s) {
+template <typename Tin, typename A, typename Tout, int m>
+static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s) {
     constexpr int NT = m >= 12 ? 256 : 128;
-    hipLaunchKernelGGL((k_ifft_trunc<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out);
+    hipLaunchKernelGGL((k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out,
+                       nbatch);
     return hipGetLastError();
 }
 
@@ -178,27 +184,31 @@ hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipS
     }
 }
 
-template <typename T>
-hipError_t launch_ifft_trunc(int m, const cplx<T>* in, T* out, int64_t nbatch, hipStream_t s) {
+template <typename Tin, typename A, typename Tout>
+hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s) {
     if (nbatch <= 0) return hipSuccess;
     switch (m) {
-        case 2: return launch_inv_m<T, 2>(in, out, nbatch, s);
-        case 3: return launch_inv_m<T, 3>(in, out, nbatch, s);
-        case 4: return launch_inv_m<T, 4>(in, out, nbatch, s);
-        case 5: return launch_inv_m<T, 5>(in, out, nbatch, s);
-        case 6: return launch_inv_m<T, 6>(in, out, nbatch, s);
-        case 7: return launch_inv_m<T, 7>(in, out, nbatch, s);
-        case 8: return launch_inv_m<T, 8>(in, out, nbatch, s);
-        case 9: return launch_inv_m<T, 9>(in, out, nbatch, s);
-        case 10: return launch_inv_m<T, 10>(in, out, nbatch, s);
-        case 16: return launch_inv_m<T, 16>(in, out, nbatch, s);
+        case 2: return launch_inv_m<Tin, A, Tout, 2>(in, out, nbatch, s);
+        case 3: return launch_inv_m<Tin, A, Tout, 3>(in, out, nbatch, s);
+        case 4: return launch_inv_m<Tin, A, Tout, 4>(in, out, nbatch, s);
+        case 5: return launch_inv_m<Tin, A, Tout, 5>(in, out, nbatch, s);
+        case 6: return launch_inv_m<Tin, A, Tout, 6>(in, out, nbatch, s);
+        case 7: return launch_inv_m<Tin, A, Tout, 7>(in, out, nbatch, s);
+        case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, s);
+        case 9: return launch_inv_m<Tin, A, Tout, 9>(in, out, nbatch, s);
+        case 10: return launch_inv_m<Tin, A, Tout, 10>(in, out, nbatch, s);
+        case 16:
+            if constexpr (!std::is_same<A, ff32>::value) return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
 template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t);
 template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t);
-template hipError_t launch_ifft_trunc<double>(int, const cplx<double>*, double*, int64_t, hipStream_t);
-template hipError_t launch_ifft_trunc<float>(int, const cplx<float>*, float*, int64_t, hipStream_t);
+template hipError_t launch_ifft_trunc<double, double, double>(int, const cplx<double>*, double*, int64_t,
+                                                               hipStream_t);
+template hipError_t launch_ifft_trunc<float, float, float>(int, const cplx<float>*, float*, int64_t, hipStream_t);
+template hipError_t launch_ifft_trunc<float, ff32, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t);
 
 }  // namespace lgfdev

@@ -20,17 +20,34 @@ constexpr int kFarTerms = 8;
 constexpr int kMaxLevels = 16;
 
 // ------------------------------------------------------------------ launchers (device code)
+// out: chunk-major spectra with nbatch + 1 items (the last, a zero sentinel, is not written)
 template <typename T>
 hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s);
-template <typename T>
-hipError_t launch_ifft_trunc(int m, const cplx<T>* in, T* out, int64_t nbatch, hipStream_t s);
+template <typename Tin, typename A, typename Tout>
+hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s);
 
+// Far-field node values of the down pass: double on the FP64 path, float-float on the
+// FP32 path (8 bytes either way).
+template <typename T> struct FarAcc;
+template <> struct FarAcc<double> { using type = double; };
+template <> struct FarAcc<float> { using type = ff32; };
+
+// Source spectra (fhat) arrays hold nitems + 1 items per frequency chunk; the last is a zero
+// sentinel that inactive neighbours point to.  Field spectra (uhat) hold nitems items.
+// Level 0 over groups of 2x2x2 target blocks (tgt8) with their 4^3 source neighbourhood (src64).
 template <typename T>
-hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* nbr, cplx<T>* uhat,
-                            int64_t ntarget, int S, hipStream_t s);
+hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
+                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, hipStream_t s);
+// Levels >= 1 below the top: over parents (child8 and the 216 candidate sources src216 of
+// each parent), offsets radius 3.
+template <typename T>
+hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
+                               const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
+                               hipStream_t s);
+// Any level from CSR lists (used for the top level of a truncated tree).
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
-                           const int32_t* off, cplx<T>* uhat, int64_t ntarget, int S, hipStream_t s);
+                           const int32_t* off, cplx<T>* uhat, int64_t ntarget, int noff, int S, hipStream_t s);
 
 // Reg block -> level-1 interval: out[b] = (A x A x A) f[b], A is p x n (row-major)
 template <typename T>
@@ -39,13 +56,13 @@ hipError_t launch_reg_block(const T* f, const double* A, T* out, int64_t nb, int
 template <typename T>
 hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, T* out, int64_t nparent, int p,
                          hipStream_t s);
-// Interp parent -> children, accumulate: io[c] += (C^T x C^T x C^T) par[parent(c)]
-template <typename T>
-hipError_t launch_interp_down(const T* par, const int32_t* parent, const int32_t* cpos, const double* C01,
-                              T* io, int64_t nchild, int p, hipStream_t s);
+// Interp parent -> its children, accumulate: io[child8[J][c]] += (C_c^T x C_c^T x C_c^T) par[J]
+template <typename U>
+hipError_t launch_interp_down(const U* par, const int32_t* child8, const double* C01, U* io, int64_t nparent,
+                              int p, hipStream_t s);
 // Final: u[b] = vnear[b] + (A^T x A^T x A^T) ut[b], accumulated in FP64 (u may alias vnear)
-template <typename T>
-hipError_t launch_final(const T* vnear, const T* ut, const double* A, T* u, int64_t nb, int n, int p,
+template <typename T, typename U>
+hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, int n, int p,
                         hipStream_t s);
 
 // ------------------------------------------------------------------ kernel spectra
@@ -59,7 +76,7 @@ struct SpectraKey {
 struct SpectraEntry {
     SpectraKey key;
     int M = 0, S = 0, noff = 0;
-    void* dev = nullptr;  // [noff][S] complex of the plan precision, scaled by 1/M^3
+    void* dev = nullptr;  // noff x S complex of the plan precision, chunk-major (spec_at), scaled by 1/M^3
     int64_t bytes = 0;
     ~SpectraEntry();
 };

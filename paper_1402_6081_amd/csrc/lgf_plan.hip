@@ -71,11 +71,14 @@ struct LevelPlan {
     std::vector<int32_t> parent;    // [nint] -> level l+1 (empty at the top)
     std::vector<int32_t> cpos;      // [nint] child position bits x | y<<1 | z<<2
     std::vector<int32_t> child8;    // [nint][8] children at level l-1 (levels >= 2)
+    std::vector<int32_t> nbr27;     // [nint][27] same-level neighbours (levels >= 2)
+    std::vector<int32_t> src216;    // [nint][216] children of the 27 neighbours (sentinel if absent)
     std::vector<int32_t> il_ptr, il_src, il_off;
     int radius = 3;
     std::shared_ptr<SpectraEntry> spectra;
     // device
-    int32_t *d_parent = nullptr, *d_cpos = nullptr, *d_child8 = nullptr;
+    int32_t *d_parent = nullptr, *d_cpos = nullptr, *d_child8 = nullptr, *d_src216 = nullptr;
+    bool sibling = false;  // level list served by the sibling-blocked kernel
     int32_t *d_ptr = nullptr, *d_src = nullptr, *d_off = nullptr;
     void *d_ftil = nullptr, *d_fhat = nullptr, *d_uhat = nullptr, *d_util = nullptr;
 };
@@ -87,6 +90,9 @@ struct lgf_plan_s {
     std::vector<int32_t> blocks;
     std::vector<int32_t> nbr0;  // [nb][27]
     int64_t near_pairs = 0;
+    std::vector<int32_t> g0_tgt8, g0_src64;  // level-0 target groups (2x2x2) and their 4^3 sources
+    int64_t ngroups0 = 0;
+    int32_t *d_g0_tgt8 = nullptr, *d_g0_src64 = nullptr;
     std::vector<LevelPlan> lv;  // index 0 unused, 1..L
     std::shared_ptr<SpectraEntry> spectra0;
     int32_t* d_nbr0 = nullptr;
@@ -176,6 +182,7 @@ inline double fft_flops(int M) {  // Table 1: 2 (8 N_b) log2(8 N_b) for a padded
 template <typename T>
 hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     using C = cplx<T>;
+    using U = typename FarAcc<T>::type;
     const int n = pl->n, p = pl->p;
     hipError_t e;
     Marker mark(pl, s);
@@ -205,36 +212,42 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
                 mark("fft_fwd_l" + std::to_string(l), lvN(l) * (p3 * es + S1 * cs), lvN(l) * fft_flops(2 * p));
             }
     }
-    LGF_CHECK(launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_nbr0, (C*)pl->d_uhat0,
-                                  pl->nb, pl->spectra0->S, s));
+    LGF_CHECK(launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8, pl->d_g0_src64,
+                                  (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S, s));
     mark("prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
     for (int l = 1; l <= pl->Ltop; ++l) {
         LevelPlan& L = pl->lv[l];
         if (L.il_src.empty()) continue;
-        LGF_CHECK(launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, L.d_ptr, L.d_src, L.d_off,
-                                     (C*)L.d_uhat, L.nint, L.spectra->S, s));
+        if (L.sibling) {
+            const LevelPlan& Pp = pl->lv[l + 1];
+            LGF_CHECK(launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216,
+                                             (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S, s));
+        } else {
+            LGF_CHECK(launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, L.d_ptr, L.d_src, L.d_off,
+                                         (C*)L.d_uhat, L.nint, L.spectra->noff, L.spectra->S, s));
+        }
         mark("prod_l" + std::to_string(l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.il_src.size() * S1 * 8.0);
     }
     for (int l = pl->Ltop; l >= 1; --l) {
         LevelPlan& L = pl->lv[l];
         if (L.il_src.empty()) {
-            LGF_CHECK(zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(T), s));
+            LGF_CHECK(zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(U), s));
             mark("zero_l" + std::to_string(l), lvN(l) * p3 * es, 0.0);
         } else {
-            LGF_CHECK(launch_ifft_trunc<T>(p, (const C*)L.d_uhat, (T*)L.d_util, L.nint, s));
+            LGF_CHECK((launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, s)));
             mark("fft_inv_l" + std::to_string(l), lvN(l) * (S1 * cs + p3 * es), lvN(l) * fft_flops(2 * p));
         }
         if (l < pl->Ltop) {
-            LGF_CHECK(launch_interp_down<T>((const T*)pl->lv[l + 1].d_util, L.d_parent, L.d_cpos, pl->d_C01,
-                                            (T*)L.d_util, L.nint, p, s));
+            LGF_CHECK(launch_interp_down<U>((const U*)pl->lv[l + 1].d_util, pl->lv[l + 1].d_child8, pl->d_C01,
+                                            (U*)L.d_util, pl->lv[l + 1].nint, p, s));
             mark("interp_l" + std::to_string(l + 1) + "_l" + std::to_string(l), (lvN(l + 1) + 2.0 * lvN(l)) * p3 * es,
                  lvN(l) * 2.0 * 3.0 * p3 * p);
         }
     }
-    LGF_CHECK(launch_ifft_trunc<T>(n, (const C*)pl->d_uhat0, u, pl->nb, s));
+    LGF_CHECK((launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s)));
     mark("fft_inv_l0", nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
     if (pl->Ltop >= 1) {
-        LGF_CHECK(launch_final<T>(u, (const T*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s));
+        LGF_CHECK((launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s)));
         mark("final_l1_l0", nb * (2.0 * n3 + p3) * es, nb * 2.0 * (p3 * n + p * p * n * n + p * n3));
     }
     mark.finish();
@@ -289,6 +302,33 @@ lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
             }
         }
     }
+    // ---- level-0 target groups: blocks 2J + c, sources 2J + (-1..2)^3
+    {
+        std::unordered_map<uint64_t, int32_t> gidx;
+        for (int64_t b = 0; b < nblocks; ++b) {
+            const int32_t* P = &pl->blocks[3 * b];
+            const uint64_t key = pack(P[0] >> 1, P[1] >> 1, P[2] >> 1);
+            auto it = gidx.find(key);
+            int32_t g;
+            if (it == gidx.end()) {
+                g = (int32_t)pl->ngroups0++;
+                gidx.emplace(key, g);
+                pl->g0_tgt8.resize(8 * pl->ngroups0, -1);
+                pl->g0_src64.resize(64 * pl->ngroups0, (int32_t)nblocks);  // zero sentinel item
+                for (int sidx = 0; sidx < 64; ++sidx) {
+                    const int64_t qx = 2 * (int64_t)(P[0] >> 1) + (sidx & 3) - 1;
+                    const int64_t qy = 2 * (int64_t)(P[1] >> 1) + ((sidx >> 2) & 3) - 1;
+                    const int64_t qz = 2 * (int64_t)(P[2] >> 1) + (sidx >> 4) - 1;
+                    if (qx < 0 || qy < 0 || qz < 0) continue;
+                    auto jt = idx0.find(pack(qx, qy, qz));
+                    if (jt != idx0.end()) pl->g0_src64[64 * g + sidx] = jt->second;
+                }
+            } else {
+                g = it->second;
+            }
+            pl->g0_tgt8[8 * g + ((P[0] & 1) | ((P[1] & 1) << 1) | ((P[2] & 1) << 2))] = (int32_t)b;
+        }
+    }
     // ---- levels: coordinates, parents, children
     pl->lv.assign(pl->L + 1, LevelPlan());
     std::vector<std::unordered_map<uint64_t, int32_t>> idx(pl->L + 2);
@@ -319,6 +359,29 @@ lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
         }
         P.child8.assign(8 * P.nint, -1);
         for (int64_t i = 0; i < C.nint; ++i) P.child8[8 * C.parent[i] + C.cpos[i]] = (int32_t)i;
+    }
+    for (int l = 2; l <= pl->L; ++l) {
+        LevelPlan& Lv = pl->lv[l];
+        Lv.nbr27.assign(27 * Lv.nint, -1);
+        for (int64_t i = 0; i < Lv.nint; ++i)
+            for (int e = 0; e < 27; ++e) {
+                const int64_t jx = Lv.coords[3 * i] + e % 3 - 1, jy = Lv.coords[3 * i + 1] + (e / 3) % 3 - 1,
+                              jz = Lv.coords[3 * i + 2] + e / 9 - 1;
+                if (jx < 0 || jy < 0 || jz < 0) continue;
+                auto it = idx[l].find(pack(jx, jy, jz));
+                if (it != idx[l].end()) Lv.nbr27[27 * i + e] = it->second;
+            }
+        const int32_t sentinel = (int32_t)pl->lv[l - 1].nint;
+        Lv.src216.assign(216 * Lv.nint, sentinel);
+        for (int64_t i = 0; i < Lv.nint; ++i)
+            for (int e = 0; e < 27; ++e) {
+                const int32_t Jn = Lv.nbr27[27 * i + e];
+                if (Jn < 0) continue;
+                for (int cs = 0; cs < 8; ++cs) {
+                    const int32_t q = Lv.child8[8 * Jn + cs];
+                    if (q >= 0) Lv.src216[216 * i + 8 * e + cs] = q;
+                }
+            }
     }
     // ---- interaction lists
     for (int l = 1; l <= pl->L; ++l) {
@@ -372,6 +435,7 @@ lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
         for (size_t e = 0; e < src.size(); ++e)
             Lv.il_off[e] = (dvec[e][0] + R) + W * ((dvec[e][1] + R) + W * (dvec[e][2] + R));
         if (!src.empty()) pl->Ltop = l;
+        Lv.sibling = (l < pl->L) && !src.empty();
     }
     if (pl->Ltop >= 1 && (int64_t)(2 * pl->lv[pl->Ltop].radius + 1) * (2 * pl->lv[pl->Ltop].radius + 1) *
                                  (2 * pl->lv[pl->Ltop].radius + 1) > 300000)
@@ -400,34 +464,45 @@ lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
 
     // ---- device memory
     const size_t esz = prec == LGF_F64 ? sizeof(double) : sizeof(float);
-    const int64_t S0 = pl->spectra0->S;
+    const int64_t S0 = spec_padded(pl->spectra0->S);
     const int M1 = 2 * p;
-    const int64_t S1 = (int64_t)M1 * M1 * (M1 / 2 + 1);
+    const int64_t S1 = spec_padded(M1 * M1 * (M1 / 2 + 1));
     const int64_t p3 = (int64_t)p * p * p;
-    int64_t need = 27 * nblocks * 4 + (p * n + 2 * p * p) * 8 + 2 * nblocks * S0 * 2 * esz;
+    const int64_t usz = 8;  // far-field down-pass values: double or float-float
+    const int topc = std::min(pl->Ltop + 1, pl->L);  // highest level whose child8 / nbr27 is used
+    int64_t need = 27 * nblocks * 4 + pl->ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (2 * nblocks + 1) * S0 * 2 * esz;
     for (int l = 1; l <= pl->Ltop; ++l) {
         const LevelPlan& Lv = pl->lv[l];
-        need += Lv.nint * (2 * p3 * esz + 2 * 4 + 8 * 4) + (Lv.nint + 1) * 4 + Lv.il_src.size() * 8;
-        if (!Lv.il_src.empty()) need += 2 * Lv.nint * S1 * 2 * esz;
+        need += Lv.nint * (p3 * (esz + usz) + 2 * 4) + (Lv.nint + 1) * 4 + Lv.il_src.size() * 8;
+        if (!Lv.il_src.empty()) need += (2 * Lv.nint + 1) * S1 * 2 * esz;
     }
+    for (int l = 2; l <= topc && pl->Ltop >= 1; ++l) need += pl->lv[l].nint * 224 * 4;
     if (!budget_reserve(need)) return fail(LGF_ERR_BUDGET, "plan workspace exceeds the device-memory budget");
     pl->ws_bytes = need;
-    bool ok = dev_alloc(pl, &pl->d_nbr0, 27 * nblocks * 4) && dev_alloc(pl, &pl->d_A, p * n * 8) &&
-              dev_alloc(pl, &pl->d_C01, 2 * p * p * 8) && dev_alloc(pl, &pl->d_fhat0, nblocks * S0 * 2 * esz) &&
+    bool ok = dev_alloc(pl, &pl->d_nbr0, 27 * nblocks * 4) && dev_alloc(pl, &pl->d_g0_tgt8, pl->ngroups0 * 8 * 4) &&
+              dev_alloc(pl, &pl->d_g0_src64, pl->ngroups0 * 64 * 4) && dev_alloc(pl, &pl->d_A, p * n * 8) &&
+              dev_alloc(pl, &pl->d_C01, 2 * p * p * 8) && dev_alloc(pl, &pl->d_fhat0, (nblocks + 1) * S0 * 2 * esz) &&
               dev_alloc(pl, &pl->d_uhat0, nblocks * S0 * 2 * esz);
     for (int l = 1; ok && l <= pl->Ltop; ++l) {
         LevelPlan& Lv = pl->lv[l];
-        ok = dev_alloc(pl, &Lv.d_ftil, Lv.nint * p3 * esz) && dev_alloc(pl, &Lv.d_util, Lv.nint * p3 * esz);
+        ok = dev_alloc(pl, &Lv.d_ftil, Lv.nint * p3 * esz) && dev_alloc(pl, &Lv.d_util, Lv.nint * p3 * usz);
         if (ok && l < pl->Ltop)
             ok = dev_alloc(pl, &Lv.d_parent, Lv.nint * 4) && dev_alloc(pl, &Lv.d_cpos, Lv.nint * 4);
-        if (ok && l >= 2) ok = dev_alloc(pl, &Lv.d_child8, Lv.nint * 32);
         if (ok && !Lv.il_src.empty())
             ok = dev_alloc(pl, &Lv.d_ptr, (Lv.nint + 1) * 4) && dev_alloc(pl, &Lv.d_src, Lv.il_src.size() * 4) &&
                  dev_alloc(pl, &Lv.d_off, Lv.il_src.size() * 4) &&
-                 dev_alloc(pl, &Lv.d_fhat, Lv.nint * S1 * 2 * esz) && dev_alloc(pl, &Lv.d_uhat, Lv.nint * S1 * 2 * esz);
+                 dev_alloc(pl, &Lv.d_fhat, (Lv.nint + 1) * S1 * 2 * esz) &&
+                 dev_alloc(pl, &Lv.d_uhat, Lv.nint * S1 * 2 * esz);
     }
+    for (int l = 2; ok && l <= topc && pl->Ltop >= 1; ++l)
+        ok = dev_alloc(pl, &pl->lv[l].d_child8, pl->lv[l].nint * 32) &&
+             dev_alloc(pl, &pl->lv[l].d_src216, pl->lv[l].nint * 216 * 4);
     if (!ok) return fail(LGF_ERR_OOM, "device allocation failed for the plan workspace");
     hipError_t e = hipMemcpyAsync(pl->d_nbr0, pl->nbr0.data(), 27 * nblocks * 4, hipMemcpyHostToDevice, s);
+    e = e == hipSuccess ? hipMemcpyAsync(pl->d_g0_tgt8, pl->g0_tgt8.data(), pl->g0_tgt8.size() * 4,
+                                         hipMemcpyHostToDevice, s) : e;
+    e = e == hipSuccess ? hipMemcpyAsync(pl->d_g0_src64, pl->g0_src64.data(), pl->g0_src64.size() * 4,
+                                         hipMemcpyHostToDevice, s) : e;
     e = e == hipSuccess ? hipMemcpyAsync(pl->d_A, A.data(), A.size() * 8, hipMemcpyHostToDevice, s) : e;
     e = e == hipSuccess ? hipMemcpyAsync(pl->d_C01, C01.data(), C01.size() * 8, hipMemcpyHostToDevice, s) : e;
     for (int l = 1; e == hipSuccess && l <= pl->Ltop; ++l) {
@@ -435,8 +510,7 @@ lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
         if (Lv.d_parent) e = hipMemcpyAsync(Lv.d_parent, Lv.parent.data(), Lv.nint * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess && Lv.d_cpos)
             e = hipMemcpyAsync(Lv.d_cpos, Lv.cpos.data(), Lv.nint * 4, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && Lv.d_child8)
-            e = hipMemcpyAsync(Lv.d_child8, Lv.child8.data(), Lv.nint * 32, hipMemcpyHostToDevice, s);
+
         if (e == hipSuccess && Lv.d_ptr) {
             e = hipMemcpyAsync(Lv.d_ptr, Lv.il_ptr.data(), (Lv.nint + 1) * 4, hipMemcpyHostToDevice, s);
             if (e == hipSuccess)
@@ -445,6 +519,15 @@ lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
                 e = hipMemcpyAsync(Lv.d_off, Lv.il_off.data(), Lv.il_off.size() * 4, hipMemcpyHostToDevice, s);
         }
     }
+    for (int l = 2; e == hipSuccess && l <= topc && pl->Ltop >= 1; ++l) {
+        LevelPlan& Lv = pl->lv[l];
+        e = hipMemcpyAsync(Lv.d_child8, Lv.child8.data(), Lv.nint * 32, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(Lv.d_src216, Lv.src216.data(), Lv.nint * 216 * 4, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = zero_fill(pl->d_fhat0, (nblocks + 1) * S0 * 2 * esz, s);
+    for (int l = 1; e == hipSuccess && l <= pl->Ltop; ++l)
+        if (pl->lv[l].d_fhat) e = zero_fill(pl->lv[l].d_fhat, (pl->lv[l].nint + 1) * S1 * 2 * esz, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(LGF_ERR_DEVICE, std::string("plan upload failed: ") + hipGetErrorString(e));
     return LGF_OK;

@@ -1,43 +1,180 @@
 // Level interactions (Step 2 of Sec. 3.1, Eq. alg_mult):
-//   uhat^P = sum_{Q in InflList(P)} Prod(fhat^Q, khat^{P-Q})
-// computed independently for every DFT coefficient.  One thread owns one coefficient
-// of one target; the list of P is uniform across the workgroup, so list entries are
-// scalar loads and the fhat / khat streams are contiguous across lanes.
+//   uhat^P = sum_{Q in InflList(P)} Prod(fhat^Q, khat^{P-Q}),
+// independently for every DFT coefficient.
+//
+// Source spectra arrays hold one extra, all-zero item (index = item count) that stands in
+// for inactive neighbours, so the inner loops load without branches or selects.
+// Both blocked kernels exploit the lattice structure of the lists: the 8 targets that
+// share a parent J see the same candidate sources (level 0: the 4^3 blocks 2J-1..2J+2;
+// levels >= 1: the 6^3 children of the 27 neighbours of J) at offsets D = P - Q that
+// depend only on the two child positions.  Each source spectrum is therefore read once per
+// group instead of once per (target, source) pair, and the kernel spectra of a frequency
+// chunk sit in an LDS tile shared by the workgroup (27 offsets at level 0, the 343 offsets
+// of [-3, 3]^3 at levels >= 1).
+// A plain CSR kernel covers the top level of a truncated tree, whose list is "every
+// non-adjacent interval" and has no such structure.
 #include "lgf_internal.h"
 
 namespace lgfdev {
 
-constexpr int kProdThreads = 256;
-
-// Level 0: the near-neighbour list is dense: nbr[P][27] holds the index of block
-// P - D (or -1), D = (d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1).
-template <typename T>
-__global__ void __launch_bounds__(kProdThreads)
-    k_prod_near(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
-                const int32_t* __restrict__ nbr, cplx<T>* __restrict__ uhat, int S) {
-    const int w = blockIdx.y * kProdThreads + threadIdx.x;
-    const int64_t P = blockIdx.x;
-    if (w >= S) return;
-    const int32_t* nb = nbr + P * 27;
-    T ar = T(0), ai = T(0);
-#pragma unroll 3
-    for (int d = 0; d < 27; ++d) {
-        const int q = nb[d];
-        if (q < 0) continue;
-        const cplx<T> f = fhat[(int64_t)q * S + w];
-        const cplx<T> k = khat[(int64_t)d * S + w];
-        ar += f.x * k.x - f.y * k.y;
-        ai += f.x * k.y + f.y * k.x;
-    }
-    uhat[P * S + w] = cplx<T>{ar, ai};
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Both
+// blocked kernels map a 1D grid so that XCD x processes whole frequency chunks
+// {c : c % 8 == x}, walking every group of such a chunk back to back: all reuse of a source
+// spectrum within a chunk then stays in one L2.  Returns false for padding workgroups.
+constexpr int kXcds = 8;
+__device__ __forceinline__ bool xcd_tile(int nchunks, int ngroupblocks, int& chunk, int& gblock) {
+    const int L = blockIdx.x;
+    const int xcd = L % kXcds, k = L / kXcds;
+    chunk = (k / ngroupblocks) * kXcds + xcd;
+    gblock = k % ngroupblocks;
+    return chunk < nchunks;
+}
+__host__ __forceinline__ unsigned xcd_grid(int nchunks, int ngroupblocks) {
+    const int padded = (nchunks + kXcds - 1) / kXcds * kXcds;
+    return (unsigned)padded * (unsigned)ngroupblocks;
 }
 
-// Levels >= 1: CSR interaction lists (ptr, src, off) with off indexing the level's spectra.
+// complex multiply-accumulate as four FMAs
+template <typename T>
+__device__ __forceinline__ void cmac(T& ar, T& ai, const cplx<T>& f, const cplx<T>& k) {
+    ar = fma(f.x, k.x, ar);
+    ar = fma(-f.y, k.y, ar);
+    ai = fma(f.x, k.y, ai);
+    ai = fma(f.y, k.x, ai);
+}
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------ level 0
+// Groups g: tgt8[g][c] = block 2J + c (c = cx | cy<<1 | cz<<2) or -1;
+// src64[g][s] = block 2J + (sx-1, sy-1, sz-1), s = sx + 4 sy + 16 sz, or the zero sentinel
+// item (index nb) when that block is not active.  fhat holds nb + 1 items (the last is 0).
+// One wave = 64 consecutive frequencies of one group; the 4 waves of a workgroup share the
+// frequency chunk and its kernel tile in LDS.  The tile has rows for dz in [-2, 2] (the
+// rows with |dz| = 2 are zero) so the source-slab loop needs no branches.
+constexpr int kNearWaves = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kNearWaves)
+    k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
+                        const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
+                        cplx<T>* __restrict__ uhat, int S, int ngroups, int nb) {
+    __shared__ cplx<T> tile[45 * 64];  // row (dx+1) + 3 (dy+1) + 9 (dz+2)
+    const int lane = threadIdx.x & 63;
+    int chunk, gb;
+    if (!xcd_tile(S / 64, (ngroups + kNearWaves - 1) / kNearWaves, chunk, gb)) return;
+    const int w0 = chunk * 64;
+    const int w = w0 + lane;  // frequency (S is a multiple of 64)
+    for (int i = threadIdx.x; i < 45 * 64; i += 64 * kNearWaves) {
+        const int r = i >> 6, dz = r / 9 - 2;
+        tile[i] = (dz < -1 || dz > 1) ? cplx<T>{T(0), T(0)} : khat[spec_at(r - 9, w0 + (i & 63), 27)];
+    }
+    __syncthreads();
+    const int g = wave_uniform(gb * kNearWaves + (threadIdx.x >> 6));
+    if (g >= ngroups) return;
+    T ar[8], ai[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        ar[c] = T(0);
+        ai[c] = T(0);
+    }
+    const int32_t* sg = src64 + (int64_t)g * 64;
+    const cplx<T>* fl = fhat + (int64_t)chunk * (nb + 1) * 64 + lane;  // this lane's frequency
+#pragma unroll 1
+    for (int sz = 0; sz < 4; ++sz) {  // source z slab; x and y unrolled
+        cplx<T> f[16];
+#pragma unroll
+        for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = fl[(int64_t)sg[sz * 16 + sxy] * 64];
+        // dz = cz - (sz - 1) in [-2, 2]; row base for cz = 0 and cz = 1
+        const cplx<T>* t0 = tile + (9 * (3 - sz)) * 64 + lane;
+        const cplx<T>* t1 = tile + (9 * (4 - sz)) * 64 + lane;
+#pragma unroll
+        for (int sxy = 0; sxy < 16; ++sxy) {
+            const int sx = (sxy & 3) - 1, sy = (sxy >> 2) - 1;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int dx = (c & 1) - sx, dy = ((c >> 1) & 1) - sy;
+                if (dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;  // compile-time
+                const cplx<T> k = ((c >> 2) ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
+                cmac(ar[c], ai[c], f[sxy], k);
+            }
+        }
+    }
+    const int32_t* tg = tgt8 + (int64_t)g * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int t = tg[c];
+        if (t >= 0) uhat[spec_at(t, w, nb)] = cplx<T>{ar[c], ai[c]};
+    }
+}
+
+// ------------------------------------------------------------------ levels >= 1, sibling blocked
+// Parents J (level l+1): src216[J][e * 8 + cs] = level-l interval 2(J + e') + cs with
+// e' = (ex-1, ey-1, ez-1), e = ex + 3 ey + 9 ez, or the zero sentinel item (index nitems);
+// child8[J][c] = target 2J + c (or -1).  khat: 343 offsets, id (Dx+3) + 7 (Dy+3) + 49 (Dz+3).
+// Lane = (child c, frequency j of a chunk of 8); one wave per parent, the waves of a
+// workgroup share the [343][8] kernel tile in LDS.  The 8 child lanes of a frequency read
+// the same source coefficient, so each source spectrum is fetched once per parent.
+constexpr int kFarWC = 8;
+constexpr int kFarRow = kFarWC + 1;  // padded tile row (breaks LDS bank aliasing between rows)
+constexpr int kFarWaves = 8;
+
+// Tile layout: row ((3 - Dx) + 7 (3 - Dy) + 49 (3 - Dz)), column j holds khat^D at frequency
+// w0 + j, and 0 for the 27 offsets with |D|_inf <= 1 (not interaction-list offsets).  With
+// D = c - cs - 2e the row is base(c, e) + (csx + 7 csy + 49 csz): a compile-time offset for
+// the unrolled source child cs, and near pairs add exact zeros.
+template <typename T>
+__global__ void __launch_bounds__(64 * kFarWaves)
+    k_prod_far_sib(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
+                   const int32_t* __restrict__ child8, const int32_t* __restrict__ src216,
+                   cplx<T>* __restrict__ uhat, int S, int nparents, int nitems) {
+    __shared__ cplx<T> tile[343 * kFarRow];
+    const int nchunks = (S + kFarWC - 1) / kFarWC;
+    int chunk, pb;
+    if (!xcd_tile(nchunks, (nparents + kFarWaves - 1) / kFarWaves, chunk, pb)) return;
+    const int w0 = chunk * kFarWC;
+    for (int i = threadIdx.x; i < 343 * kFarWC; i += 64 * kFarWaves) {
+        const int r = i / kFarWC, j = i - r * kFarWC;
+        const int Dx = 3 - r % 7, Dy = 3 - (r / 7) % 7, Dz = 3 - r / 49;
+        const int o = (Dx + 3) + 7 * (Dy + 3) + 49 * (Dz + 3);
+        const bool near = Dx >= -1 && Dx <= 1 && Dy >= -1 && Dy <= 1 && Dz >= -1 && Dz <= 1;
+        tile[r * kFarRow + j] = (w0 + j < S && !near) ? khat[spec_at(o, w0 + j, 343)] : cplx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int c = lane >> 3, j = lane & 7;
+    const int w = w0 + j;
+    const bool live = w < S;
+    const int J = wave_uniform(pb * kFarWaves + (threadIdx.x >> 6));
+    if (J >= nparents) return;
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+    // this lane's frequency column of the source spectra (padding lanes read column w0)
+    const cplx<T>* fl = fhat + (int64_t)((live ? w : w0) >> 6) * (nitems + 1) * 64 + ((live ? w : w0) & 63);
+    const int32_t* sj = src216 + (int64_t)J * 216;
+    T ar = T(0), ai = T(0);
+#pragma unroll 1
+    for (int e = 0; e < 27; ++e) {
+        const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+        const cplx<T>* kb = tile + ((3 - cx + 2 * ex) + 7 * (3 - cy + 2 * ey) + 49 * (3 - cz + 2 * ez)) * kFarRow + j;
+        cplx<T> f[8];
+#pragma unroll
+        for (int cs = 0; cs < 8; ++cs) f[cs] = fl[(int64_t)sj[e * 8 + cs] * 64];
+#pragma unroll
+        for (int cs = 0; cs < 8; ++cs)
+            cmac(ar, ai, f[cs], kb[((cs & 1) + 7 * ((cs >> 1) & 1) + 49 * (cs >> 2)) * kFarRow]);
+    }
+    const int t = child8[(int64_t)J * 8 + c];
+    if (t >= 0 && live) uhat[spec_at(t, w, nitems)] = cplx<T>{ar, ai};
+}
+
+// ------------------------------------------------------------------ generic CSR (top level)
+constexpr int kProdThreads = 256;
+
 template <typename T>
 __global__ void __launch_bounds__(kProdThreads)
     k_prod_far(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
-               const int32_t* __restrict__ off, cplx<T>* __restrict__ uhat, int S) {
+               const int32_t* __restrict__ off, cplx<T>* __restrict__ uhat, int S, int nitems, int noff) {
     const int w = blockIdx.y * kProdThreads + threadIdx.x;
     const int64_t P = blockIdx.x;
     if (w >= S) return;
@@ -46,41 +183,54 @@ __global__ void __launch_bounds__(kProdThreads)
     for (int e = e0; e < e1; ++e) {
         const int q = src[e];
         const int o = off[e];
-        const cplx<T> f = fhat[(int64_t)q * S + w];
-        const cplx<T> k = khat[(int64_t)o * S + w];
-        ar += f.x * k.x - f.y * k.y;
-        ai += f.x * k.y + f.y * k.x;
+        const cplx<T> f = fhat[spec_at(q, w, nitems + 1)];
+        const cplx<T> k = khat[spec_at(o, w, noff)];
+        cmac(ar, ai, f, k);
     }
-    uhat[P * S + w] = cplx<T>{ar, ai};
+    uhat[spec_at(P, w, nitems)] = cplx<T>{ar, ai};
 }
 
 template <typename T>
-hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* nbr, cplx<T>* uhat,
-                            int64_t ntarget, int S, hipStream_t s) {
-    if (ntarget <= 0) return hipSuccess;
-    dim3 grid((unsigned)ntarget, (unsigned)((S + kProdThreads - 1) / kProdThreads));
-    hipLaunchKernelGGL(k_prod_near<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, nbr, uhat, S);
+hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
+                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, hipStream_t s) {
+    if (ngroups <= 0) return hipSuccess;
+    if (S % 64) return hipErrorInvalidValue;
+    const unsigned grid = xcd_grid(S / 64, (int)((ngroups + kNearWaves - 1) / kNearWaves));
+    hipLaunchKernelGGL(k_prod_near_grouped<T>, dim3(grid), dim3(64 * kNearWaves), 0, s, fhat, khat, tgt8, src64, uhat,
+                       S, (int)ngroups, (int)nitems);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
+                               const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
+                               hipStream_t s) {
+    if (nparents <= 0) return hipSuccess;
+    const unsigned grid = xcd_grid((S + kFarWC - 1) / kFarWC, (int)((nparents + kFarWaves - 1) / kFarWaves));
+    hipLaunchKernelGGL(k_prod_far_sib<T>, dim3(grid), dim3(64 * kFarWaves), 0, s, fhat, khat, child8, src216, uhat, S,
+                       (int)nparents, (int)nitems);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
-                           const int32_t* off, cplx<T>* uhat, int64_t ntarget, int S, hipStream_t s) {
+                           const int32_t* off, cplx<T>* uhat, int64_t ntarget, int noff, int S, hipStream_t s) {
     if (ntarget <= 0) return hipSuccess;
     dim3 grid((unsigned)ntarget, (unsigned)((S + kProdThreads - 1) / kProdThreads));
-    hipLaunchKernelGGL(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, uhat, S);
+    hipLaunchKernelGGL(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, uhat, S, (int)ntarget,
+                       noff);
     return hipGetLastError();
 }
 
-template hipError_t launch_prod_near<double>(const cplx<double>*, const cplx<double>*, const int32_t*,
-                                             cplx<double>*, int64_t, int, hipStream_t);
-template hipError_t launch_prod_near<float>(const cplx<float>*, const cplx<float>*, const int32_t*,
-                                            cplx<float>*, int64_t, int, hipStream_t);
-template hipError_t launch_prod_far<double>(const cplx<double>*, const cplx<double>*, const int32_t*,
-                                            const int32_t*, const int32_t*, cplx<double>*, int64_t, int,
-                                            hipStream_t);
-template hipError_t launch_prod_far<float>(const cplx<float>*, const cplx<float>*, const int32_t*,
-                                           const int32_t*, const int32_t*, cplx<float>*, int64_t, int,
-                                           hipStream_t);
+#define LGF_INST(T)                                                                                              \
+    template hipError_t launch_prod_near<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,      \
+                                            cplx<T>*, int64_t, int64_t, int, hipStream_t);                       \
+    template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
+                                               cplx<T>*, int64_t, int64_t, int, hipStream_t);                    \
+    template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \
+                                           const int32_t*, cplx<T>*, int64_t, int, int, hipStream_t);
+LGF_INST(double)
+LGF_INST(float)
+#undef LGF_INST
 
 }  // namespace lgfdev

@@ -392,12 +392,14 @@ __global__ void k_dft_r2c_x(const double* __restrict__ in, cplx<double>* __restr
     out[id] = cplx<double>{sr, si};
 }
 
+// scale, cast and scatter [noff][S] into the chunk-major layout
 template <typename T>
-__global__ void k_scale_cast(const cplx<double>* __restrict__ in, cplx<T>* __restrict__ out, int64_t count,
+__global__ void k_scale_cast(const cplx<double>* __restrict__ in, cplx<T>* __restrict__ out, int noff, int S,
                              double scale) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    out[i] = cplx<T>{(T)(in[i].x * scale), (T)(in[i].y * scale)};
+    if (i >= (int64_t)noff * S) return;
+    const int o = (int)(i / S), w = (int)(i % S);
+    out[spec_at(o, w, noff)] = cplx<T>{(T)(in[i].x * scale), (T)(in[i].y * scale)};
 }
 
 // ============================================================== host glue
@@ -546,7 +548,7 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
     entry->S = S;
     entry->noff = noff;
     const size_t esz = key.prec == 0 ? sizeof(cplx<double>) : sizeof(cplx<float>);
-    entry->bytes = (int64_t)noff * S * esz;
+    entry->bytes = (int64_t)noff * spec_padded(S) * esz;
     if (!budget_reserve(entry->bytes)) {
         err = "kernel spectra exceed the device-memory budget";
         return nullptr;
@@ -588,10 +590,10 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
     const double scale = 1.0 / (double)M3;
     if (key.prec == 0)
         hipLaunchKernelGGL(k_scale_cast<double>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t1,
-                           (cplx<double>*)entry->dev, tot, scale);
+                           (cplx<double>*)entry->dev, noff, S, scale);
     else
         hipLaunchKernelGGL(k_scale_cast<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t1,
-                           (cplx<float>*)entry->dev, tot, scale);
+                           (cplx<float>*)entry->dev, noff, S, scale);
     hipError_t e = hipStreamSynchronize(s);
     hipFree(kb);
     hipFree(t1);

@@ -2,10 +2,11 @@
 element, on seeded inputs.
 
 Tolerances (relative L-infinity, max|u - u_ref| / max|u_ref|):
-  * FP64 solve vs oracle B (same FLGF operator, different rounding order): 1e-12.
-    Both sides evaluate the same linear operator in FP64; the bound allows for
-    the Lebesgue amplification of rounding differences through Reg/Interp
-    (Lambda_p^3 per side, Sec. 2.5) on top of O(eps log M) FFT rounding.
+  * FP64 solve vs oracle B (same FLGF operator, different rounding order):
+    max(1e-12, 2 Lambda_p^3 eps_64).  Both sides evaluate the same linear operator in
+    FP64; rounding differences of node values are amplified by up to the Lebesgue
+    constant Lambda_p^3 of p equispaced nodes in 3D (Sec. 2.5, Eq. leb: the paper's
+    own bound Lambda^3 eps = 1.25e-12 at n_max = 10).
   * FP64 solve vs oracle A (exact direct sum): eps_trunc + 1e-12, eps_trunc being
     the oracle-B-vs-oracle-A difference on the same input.
   * Device LGF table vs the oracle's Bessel table: 1e-14 relative.
@@ -39,6 +40,16 @@ def L():
 
 def rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def lebesgue(p):
+    """Lebesgue constant of p equispaced nodes on [0, p-1] (dense sampling)."""
+    t = np.linspace(0, p - 1, 20001)
+    return float(np.max(np.sum(np.abs(flgf.lagrange(p, t)), axis=0)))
+
+
+def fp64_tol(p):
+    return max(1e-12, 2.0 * lebesgue(p) ** 3 * 2.22e-16)
 
 
 def gpu_solve(L, blocks, f, n, p, levels, precision="f64"):
@@ -94,8 +105,8 @@ def test_solve_fp64_matches_oracle(L, case):
     ref = flgf.solve(blocks, f, n, p, levels)
     got = gpu_solve(L, blocks, f, n, p, levels)
     e = rel(got, ref)
-    _say("   rel Linf vs oracle B = %.3e" % e)
-    assert e < 1e-12
+    _say("   rel Linf vs oracle B = %.3e (tol %.1e)" % (e, fp64_tol(p)))
+    assert e < fp64_tol(p)
 
 
 def test_small_config_against_exact(L):
@@ -110,3 +121,58 @@ def test_small_config_against_exact(L):
     _say("   vs B %.3e  vs A %.3e  eps_trunc %.3e" % (eb, ea, eps_trunc))
     assert eb < 1e-12
     assert ea < eps_trunc + 1e-12
+
+
+def test_medium_config_full_size(L):
+    # the 128^3 workload at full size, every point against oracle B
+    c = W.config_medium()
+    _say("case: 128^3 cube, n=16 p=8 4 levels, 32 zero-net Gaussians, FP64 vs oracle B (all points)")
+    ref = flgf.solve(c["blocks"], c["f"], c["n"], c["p"], c["levels"])
+    got = gpu_solve(L, c["blocks"], c["f"], c["n"], c["p"], c["levels"])
+    e = rel(got, ref)
+    _say("   rel Linf vs oracle B = %.3e" % e)
+    assert e < 1e-12
+
+
+FP32_CASES = [
+    ("cube4_n8_p6_L2", lambda r: W.cube_layout(4), 8, 6, 2),
+    ("eden60_n16_p8_full", lambda r: W.eden_layout(60, r), 16, 8, 0),
+    ("eden40_n8_p9_lattice", lambda r: W.eden_layout(40, r), 8, 9, 0),
+]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=[c[0] for c in FP32_CASES])
+def test_fp32_path_within_1e6_of_fp64(L, case):
+    # FP32 transforms and products, float-float down pass, FP64 tables and final add:
+    # max|u32 - u64| / max|u64| <= 1e-6 on smooth (Gaussian) sources
+    label, mk, n, p, levels = case
+    rng = np.random.default_rng(zlib.crc32(label.encode()))
+    blocks = mk(rng)
+    f, _ = W.zero_mean_gaussians(blocks, n, rng, max(4, len(blocks) // 8))
+    _say("case: FP32", label, "blocks", len(blocks))
+    u64 = gpu_solve(L, blocks, f, n, p, levels, "f64")
+    u32 = gpu_solve(L, blocks, f, n, p, levels, "f32")
+    e = rel(u32, u64)
+    _say("   FP32 vs FP64 rel Linf = %.3e" % e)
+    assert e < 1e-6
+
+
+def test_medium_config_fp32(L):
+    c = W.config_medium()
+    _say("case: 128^3 workload FP32 vs FP64")
+    u64 = gpu_solve(L, c["blocks"], c["f"], c["n"], c["p"], c["levels"], "f64")
+    u32 = gpu_solve(L, c["blocks"], c["f"], c["n"], c["p"], c["levels"], "f32")
+    e = rel(u32, u64)
+    _say("   FP32 vs FP64 rel Linf = %.3e" % e)
+    assert e < 1e-6
+
+
+def test_deterministic(L):
+    # no atomics and a fixed summation order: two solves are bitwise equal
+    rng = np.random.default_rng(9)
+    blocks = W.eden_layout(50, rng)
+    f = rng.standard_normal((len(blocks), 16, 16, 16))
+    for prec in ("f64", "f32"):
+        a = gpu_solve(L, blocks, f, 16, 8, 0, prec)
+        b = gpu_solve(L, blocks, f, 16, 8, 0, prec)
+        assert np.array_equal(a, b), prec
