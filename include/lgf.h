@@ -28,6 +28,10 @@
  * synchronous device work (kernel spectra, list upload) on `hip_stream`.
  * A plan holds one workspace: solves on one plan must not overlap in time (enqueue
  * them on one stream).  Different plans may run concurrently on different streams.
+ * For plans of at most 256 blocks the far-field chain (levels >= 1) of a solve runs on a
+ * second stream owned by the plan, forked from and joined back into hip_stream with
+ * events, so it overlaps the near-field transforms; from the caller's view the solve is
+ * ordinary stream work on hip_stream either way.
  *
  * Errors.  Every entry point returns an lgf_status; nothing is printed and no C++
  * exception crosses the ABI.  lgf_last_error() returns a thread-local message for the
@@ -105,6 +109,68 @@ lgf_status lgf_solve(lgf_plan_t plan, const void* f, void* u, void* hip_stream);
 lgf_status lgf_solve_many(const lgf_plan_t* plans, const void* const* f, void* const* u,
                           int32_t count, void* hip_stream);
 
+/*
+ * Batched solves (many independent problems, one launch sequence).  The problems of a
+ * batch share n, p, levels and precision; their layouts may differ.  The plan is the
+ * union of the per-layout trees: every list stays inside its own layout (the union is
+ * exact, not an approximation: each problem's u depends on its own f only, Sec. 3.1
+ * applied per layout), while each kernel of Steps 1-3 runs once over all layouts.
+ *   layouts[i] : HOST array [nblocks[i]][3] of block coordinates of problem i (each
+ *                layout has its own origin; coordinates of different layouts may overlap)
+ *   count      : number of problems, >= 1
+ * The plan's f and u are the problems' fields concatenated in batch order: problem i owns
+ * blocks [offsets[i], offsets[i+1]) as returned by lgf_plan_solve_offsets.  All other
+ * arguments and errors as for lgf_plan_create; the plan is used with lgf_solve.
+ */
+lgf_status lgf_plan_create_batch(const int32_t* const* layouts, const int64_t* nblocks, int32_t count,
+                                 int32_t n, int32_t p, int32_t levels, lgf_precision prec,
+                                 void* hip_stream, lgf_plan_t* out);
+
+/*
+ * Block offsets of the problems of a plan: *count receives the number of problems (1 for
+ * a plan from lgf_plan_create) and offsets[0..min(count+1, max_entries)-1] (HOST, may be
+ * NULL) the first block of each problem followed by the total block count.
+ * Errors: LGF_ERR_ARG.
+ */
+lgf_status lgf_plan_solve_offsets(lgf_plan_t plan, int64_t* offsets, int32_t max_entries, int32_t* count);
+
+/*
+ * HIP graph of one solve.  lgf_graph_create captures the launch sequence of
+ * lgf_solve(plan, f, u, .) into an executable graph (f and u are baked in: the graph
+ * always reads f and writes u at these DEVICE addresses).  The caller's hip_stream is
+ * synchronised first; capture uses a private stream and enqueues no device work.
+ * lgf_graph_launch enqueues the whole solve as one graph launch on hip_stream, with the
+ * same result as lgf_solve; the plan's single-workspace rule applies (no overlap with
+ * other solves or graph launches of the same plan).  The graph must be destroyed
+ * before its plan.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
+ */
+typedef struct lgf_graph_s* lgf_graph_t;
+lgf_status lgf_graph_create(lgf_plan_t plan, const void* f, void* u, void* hip_stream, lgf_graph_t* out);
+lgf_status lgf_graph_launch(lgf_graph_t graph, void* hip_stream);
+lgf_status lgf_graph_destroy(lgf_graph_t graph);
+
+/*
+ * Autotuner of the plan's kernel variants: threads per workgroup of the level-0
+ * transforms (128 / 256 / 512) and waves per workgroup of the level-0 and level >= 1
+ * Prod kernels.  Runs (1 + reps) solves per candidate on (f, u) (DEVICE buffers of the
+ * plan's shape; u is overwritten) in a coordinate search, keeps the fastest median
+ * device time, and remembers the choice for later plans of the same (n, p, precision,
+ * power-of-two block-count bucket) in this process; if the environment variable
+ * LGF_TUNE_FILE names a file the choice is appended there and read by later processes.
+ * Synchronous.  Variants differ in scheduling only: every variant gives the same u bit
+ * for bit.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
+ */
+lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_stream, int32_t reps);
+
+/* The plan's current variant choice (0 threads = the default per block size). */
+lgf_status lgf_plan_get_tuning(lgf_plan_t plan, int32_t* fft0_threads, int32_t* near_waves,
+                               int32_t* far_waves);
+
+/* Pin the plan's variants by hand: fft0_threads in {0, 128, 256, 512}, near_waves in
+ * {2, 4, 8}, far_waves in {4, 8, 16}.  Errors: LGF_ERR_ARG (other values). */
+lgf_status lgf_plan_set_tuning(lgf_plan_t plan, int32_t fft0_threads, int32_t near_waves,
+                               int32_t far_waves);
+
 /* Fill *info (HOST struct).  Errors: LGF_ERR_ARG. */
 lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info);
 
@@ -125,9 +191,10 @@ lgf_status lgf_spectra_cache_trim(void);
 /*
  * Per-step device timing of a plan's solves (measurement support).
  * lgf_profile_enable(plan, max_solves): the next max_solves calls of lgf_solve on this
- * plan record a HIP event on their stream before the first and after every step
- * (fwd FFT, Reg, Prod, inverse FFT, Interp, final add of each level).  Recording
- * adds no synchronisation.  lgf_profile_collect waits for the recorded events and
+ * plan record HIP events around the whole solve and before and after every step (fwd
+ * FFT, Reg, Prod, inverse FFT, Interp, final add of each level), each on the stream the
+ * step runs on (for small plans the far-field steps run on the plan's internal second stream,
+ * concurrently with the near field).  Recording adds no synchronisation.  lgf_profile_collect waits for the recorded events and
  * fills *out with, per step in launch order: its name, the summed device time over
  * the nsolves recorded solves (one launch per step per solve), and the step's
  * algorithmic bytes and flops per launch (compulsory HBM traffic: every input read once, every output

@@ -6,6 +6,7 @@
 // thread owns whole pencils in registers, so a pass is a register transform plus one
 // LDS read and one LDS (or HBM) write per element.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -159,6 +160,12 @@ __device__ __forceinline__ void cmul_const(T ar, T ai, double wr, double wi, T& 
         orr = -ai; oi = ar;
     } else if (wr == 0.0 && wi == -1.0) {
         orr = ai; oi = -ar;
+    } else if constexpr (std::is_floating_point<T>::value) {
+        // fused explicitly, so the rounding does not depend on how the compiler unrolls or
+        // schedules a kernel variant (every variant of a transform gives the same bits)
+        const T r = (T)wr, i = (T)wi;
+        orr = fma(ar, r, -(ai * i));
+        oi = fma(ar, i, ai * r);
     } else {
         const T r = (T)wr, i = (T)wi;
         orr = ar * r - ai * i;

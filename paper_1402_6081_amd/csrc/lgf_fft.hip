@@ -151,23 +151,46 @@ __global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__
     }
 }
 
-template <typename T, int m>
-static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s) {
-    constexpr int NT = m >= 12 ? 256 : 128;
+// nt: threads per workgroup (0 = default: 256 for m >= 12, else 128); the autotuner picks
+// among {128, 256, 512} for the level-0 tiles (m = 8, 16).  512 threads are not offered for
+// the FP64 16^3 tile, whose 32-point pencils then no longer fit the register file.
+template <typename T, int m, int NT>
+static hipError_t fwd_mnt(const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s) {
     hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out, nbatch);
     return hipGetLastError();
 }
 
-template <typename Tin, typename A, typename Tout, int m>
-static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s) {
-    constexpr int NT = m >= 12 ? 256 : 128;
+template <typename T, int m>
+static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt = 0) {
+    if constexpr (m == 8 || m == 16) {
+        if constexpr (!(m == 16 && sizeof(T) == 8))
+            if (nt == 512) return fwd_mnt<T, m, 512>(in, out, nbatch, s);
+        if (nt == 128 && m >= 12) return fwd_mnt<T, m, 128>(in, out, nbatch, s);
+        if (nt == 256 && m < 12) return fwd_mnt<T, m, 256>(in, out, nbatch, s);
+    }
+    return fwd_mnt<T, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, s);
+}
+
+template <typename Tin, typename A, typename Tout, int m, int NT>
+static hipError_t inv_mnt(const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s) {
     hipLaunchKernelGGL((k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out,
                        nbatch);
     return hipGetLastError();
 }
 
+template <typename Tin, typename A, typename Tout, int m>
+static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0) {
+    if constexpr ((m == 8 || m == 16) && !std::is_same<A, ff32>::value) {
+        if constexpr (!(m == 16 && sizeof(A) == 8))
+            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(in, out, nbatch, s);
+        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(in, out, nbatch, s);
+        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(in, out, nbatch, s);
+    }
+    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, s);
+}
+
 template <typename T>
-hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s) {
+hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt) {
     if (nbatch <= 0) return hipSuccess;
     switch (m) {
         case 2: return launch_fwd_m<T, 2>(in, out, nbatch, s);
@@ -176,16 +199,16 @@ hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipS
         case 5: return launch_fwd_m<T, 5>(in, out, nbatch, s);
         case 6: return launch_fwd_m<T, 6>(in, out, nbatch, s);
         case 7: return launch_fwd_m<T, 7>(in, out, nbatch, s);
-        case 8: return launch_fwd_m<T, 8>(in, out, nbatch, s);
+        case 8: return launch_fwd_m<T, 8>(in, out, nbatch, s, nt);
         case 9: return launch_fwd_m<T, 9>(in, out, nbatch, s);
         case 10: return launch_fwd_m<T, 10>(in, out, nbatch, s);
-        case 16: return launch_fwd_m<T, 16>(in, out, nbatch, s);
+        case 16: return launch_fwd_m<T, 16>(in, out, nbatch, s, nt);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename Tin, typename A, typename Tout>
-hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s) {
+hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt) {
     if (nbatch <= 0) return hipSuccess;
     switch (m) {
         case 2: return launch_inv_m<Tin, A, Tout, 2>(in, out, nbatch, s);
@@ -194,21 +217,22 @@ hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbat
         case 5: return launch_inv_m<Tin, A, Tout, 5>(in, out, nbatch, s);
         case 6: return launch_inv_m<Tin, A, Tout, 6>(in, out, nbatch, s);
         case 7: return launch_inv_m<Tin, A, Tout, 7>(in, out, nbatch, s);
-        case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, s);
+        case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, s, nt);
         case 9: return launch_inv_m<Tin, A, Tout, 9>(in, out, nbatch, s);
         case 10: return launch_inv_m<Tin, A, Tout, 10>(in, out, nbatch, s);
         case 16:
-            if constexpr (!std::is_same<A, ff32>::value) return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, s);
+            if constexpr (!std::is_same<A, ff32>::value) return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, s, nt);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t);
-template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t);
+template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t, int);
+template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t, int);
 template hipError_t launch_ifft_trunc<double, double, double>(int, const cplx<double>*, double*, int64_t,
-                                                               hipStream_t);
-template hipError_t launch_ifft_trunc<float, float, float>(int, const cplx<float>*, float*, int64_t, hipStream_t);
-template hipError_t launch_ifft_trunc<float, ff32, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t);
+                                                               hipStream_t, int);
+template hipError_t launch_ifft_trunc<float, float, float>(int, const cplx<float>*, float*, int64_t, hipStream_t,
+                                                             int);
+template hipError_t launch_ifft_trunc<float, ff32, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t, int);
 
 }  // namespace lgfdev

@@ -21,10 +21,11 @@ constexpr int kMaxLevels = 16;
 
 // ------------------------------------------------------------------ launchers (device code)
 // out: chunk-major spectra with nbatch + 1 items (the last, a zero sentinel, is not written)
+// nt: threads per workgroup variant (0 = default; tunable for level-0 tiles)
 template <typename T>
-hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s);
+hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt = 0);
 template <typename Tin, typename A, typename Tout>
-hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s);
+hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0);
 
 // Far-field node values of the down pass: double on the FP64 path, float-float on the
 // FP32 path (8 bytes either way).
@@ -37,17 +38,25 @@ template <> struct FarAcc<float> { using type = ff32; };
 // Level 0 over groups of 2x2x2 target blocks (tgt8) with their 4^3 source neighbourhood (src64).
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, hipStream_t s);
+                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, hipStream_t s);
 // Levels >= 1 below the top: over parents (child8 and the 216 candidate sources src216 of
 // each parent), offsets radius 3.
 template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
-                               hipStream_t s);
-// Any level from CSR lists (used for the top level of a truncated tree).
+                               int waves, hipStream_t s);
+// Targets tgt[0..ntgt) from CSR lists (the top level of a truncated tree).
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
-                           const int32_t* off, cplx<T>* uhat, int64_t ntarget, int noff, int S, hipStream_t s);
+                           const int32_t* off, const int32_t* tgt, cplx<T>* uhat, int64_t ntgt, int64_t nitems,
+                           int noff, int S, hipStream_t s);
+
+// Kernel variants picked per plan (by the autotuner, or defaults).
+struct TuneConfig {
+    int fft0_threads = 0;  // 0 = default per tile size, else 128 / 256 / 512
+    int near_waves = 4;    // waves per workgroup of the level-0 Prod kernel: 2, 4, 8
+    int far_waves = 8;     // waves per workgroup of the level >= 1 Prod kernel: 4, 8, 16
+};
 
 // Reg block -> level-1 interval: out[b] = (A x A x A) f[b], A is p x n (row-major)
 template <typename T>

@@ -1,6 +1,7 @@
 // Host side of the solver: layout validation, the octree of intervals and its lists
 // (Sec. 3.1: RegSupp, IntrpSupp, InflList), 1D Lagrange matrices (Sec. 2.5), device
-// workspace, the launch sequence of one solve (Steps 1-3) and the C ABI of lgf.h.
+// workspace, the launch sequence of one solve (Steps 1-3), batches of independent layouts
+// as one union plan, hipGraph capture, the kernel-variant autotuner and the C ABI of lgf.h.
 //
 // Tree conventions: block coordinates are shifted so the bounding-box minimum is 0;
 // the level-1 interval of block B has index B and the parent of interval I is
@@ -9,13 +10,16 @@
 // Lists: level 0 near neighbours |Q-P|_inf <= 1; level l < L: children of the parent's
 // neighbours with |Q-P|_inf >= 2; top level L: every interval with |Q-P|_inf >= 2.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
-#include <cstdlib>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -23,6 +27,8 @@
 #include "lgf_internal.h"
 
 using namespace lgfdev;
+
+constexpr int64_t kOverlapMaxBlocks = 256;
 
 namespace {
 
@@ -58,6 +64,247 @@ hipError_t zero_fill(void* p, int64_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// LGF_SYNC_CHECK=1 in the environment: synchronise after every launch and report the
+// first failing step by name (debugging aid; off by default, never inside a capture).
+bool sync_check_enabled() {
+    static const bool on = [] {
+        const char* v = std::getenv("LGF_SYNC_CHECK");
+        return v && v[0] == '1';
+    }();
+    return on;
+}
+
+thread_local bool t_capturing = false;
+
+hipError_t checked(hipError_t e, const char* what, hipStream_t s) {
+    if (e == hipSuccess && sync_check_enabled() && !t_capturing) {
+        e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    if (e != hipSuccess) t_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e;
+}
+
+// ------------------------------------------------------------------ host description of a plan
+struct HostLevel {
+    int64_t nint = 0;
+    std::vector<int32_t> coords;  // [nint][3] (single layouts only; empty in unions)
+    std::vector<int32_t> child8;  // [nint][8] children at level l-1 (levels >= 2)
+    std::vector<int32_t> src216;  // [nint][216] children of the 27 neighbours, sentinel = N_{l-1}
+    int64_t sib_pairs = 0;        // interaction-list entries of targets served through parents
+    // top level of a truncated tree: explicit lists over a target subset
+    std::vector<int32_t> csr_tgt, csr_ptr{0}, csr_src;
+    std::vector<std::array<int32_t, 3>> csr_D;
+    bool zero_uhat = false;  // some targets are served by neither list kind (unions)
+    int64_t pairs() const { return sib_pairs + (int64_t)csr_src.size(); }
+};
+
+struct HostPlan {
+    int n = 0, p = 0, L = 0, Ltop = 0;
+    int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
+    std::vector<int32_t> g0_tgt8, g0_src64;  // sentinel = nb
+    std::vector<HostLevel> lv;               // index 0 unused, 1..L
+    std::vector<int64_t> solve_offsets{0};   // block offsets of the layouts of a batch
+};
+
+lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int levels, HostPlan& H) {
+    H.n = n;
+    H.p = p;
+    H.nb = nblocks;
+    H.solve_offsets = {0, nblocks};
+    int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+    for (int64_t b = 0; b < nblocks; ++b)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min<int64_t>(lo[d], ijk[3 * b + d]);
+            hi[d] = std::max<int64_t>(hi[d], ijk[3 * b + d]);
+        }
+    int64_t ext = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (hi[d] - lo[d] >= (1 << 20)) return fail(LGF_ERR_LAYOUT, "layout spans more than 2^20 blocks");
+        ext = std::max<int64_t>(ext, hi[d] - lo[d] + 1);
+    }
+    std::vector<int32_t> blocks(3 * nblocks);
+    std::unordered_map<uint64_t, int32_t> idx0;
+    idx0.reserve(nblocks * 2);
+    for (int64_t b = 0; b < nblocks; ++b) {
+        for (int d = 0; d < 3; ++d) blocks[3 * b + d] = (int32_t)(ijk[3 * b + d] - lo[d]);
+        const uint64_t key = pack(blocks[3 * b], blocks[3 * b + 1], blocks[3 * b + 2]);
+        if (!idx0.emplace(key, (int32_t)b).second) return fail(LGF_ERR_LAYOUT, "duplicate block in layout");
+    }
+    int full = 1;
+    while ((int64_t(1) << (full - 1)) < ext) ++full;
+    H.L = levels <= 0 ? full : std::min(levels, full);
+    if (H.L >= kMaxLevels) return fail(LGF_ERR_LAYOUT, "tree deeper than supported");
+
+    // ---- level 0: near pairs and 2x2x2 target groups with their 4^3 sources
+    std::unordered_map<uint64_t, int32_t> gidx;
+    for (int64_t b = 0; b < nblocks; ++b) {
+        const int32_t* P = &blocks[3 * b];
+        for (int d = 0; d < 27; ++d) {
+            const int64_t qx = P[0] - (d % 3 - 1), qy = P[1] - ((d / 3) % 3 - 1), qz = P[2] - (d / 9 - 1);
+            if (qx >= 0 && qy >= 0 && qz >= 0 && idx0.count(pack(qx, qy, qz))) ++H.near_pairs;
+        }
+        const uint64_t key = pack(P[0] >> 1, P[1] >> 1, P[2] >> 1);
+        auto it = gidx.find(key);
+        int32_t g;
+        if (it == gidx.end()) {
+            g = (int32_t)H.ngroups0++;
+            gidx.emplace(key, g);
+            H.g0_tgt8.resize(8 * H.ngroups0, -1);
+            H.g0_src64.resize(64 * H.ngroups0, (int32_t)nblocks);
+            for (int sidx = 0; sidx < 64; ++sidx) {
+                const int64_t qx = 2 * (int64_t)(P[0] >> 1) + (sidx & 3) - 1;
+                const int64_t qy = 2 * (int64_t)(P[1] >> 1) + ((sidx >> 2) & 3) - 1;
+                const int64_t qz = 2 * (int64_t)(P[2] >> 1) + (sidx >> 4) - 1;
+                if (qx < 0 || qy < 0 || qz < 0) continue;
+                auto jt = idx0.find(pack(qx, qy, qz));
+                if (jt != idx0.end()) H.g0_src64[64 * g + sidx] = jt->second;
+            }
+        } else {
+            g = it->second;
+        }
+        H.g0_tgt8[8 * g + ((P[0] & 1) | ((P[1] & 1) << 1) | ((P[2] & 1) << 2))] = (int32_t)b;
+    }
+
+    // ---- levels: coordinates, parents, children
+    H.lv.assign(H.L + 1, HostLevel());
+    std::vector<std::unordered_map<uint64_t, int32_t>> idx(H.L + 2);
+    H.lv[1].nint = nblocks;
+    H.lv[1].coords = blocks;
+    idx[1] = idx0;
+    for (int l = 1; l < H.L; ++l) {
+        HostLevel& C = H.lv[l];
+        HostLevel& P = H.lv[l + 1];
+        std::vector<int32_t> parent(C.nint), cpos(C.nint);
+        for (int64_t i = 0; i < C.nint; ++i) {
+            const int32_t x = C.coords[3 * i], y = C.coords[3 * i + 1], z = C.coords[3 * i + 2];
+            const uint64_t key = pack(x >> 1, y >> 1, z >> 1);
+            auto it = idx[l + 1].find(key);
+            int32_t j;
+            if (it == idx[l + 1].end()) {
+                j = (int32_t)P.nint++;
+                idx[l + 1].emplace(key, j);
+                P.coords.push_back(x >> 1);
+                P.coords.push_back(y >> 1);
+                P.coords.push_back(z >> 1);
+            } else {
+                j = it->second;
+            }
+            parent[i] = j;
+            cpos[i] = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+        }
+        P.child8.assign(8 * P.nint, -1);
+        for (int64_t i = 0; i < C.nint; ++i) P.child8[8 * parent[i] + cpos[i]] = (int32_t)i;
+    }
+    // ---- levels >= 2: the 216 candidate sources of each parent (children of its neighbours);
+    //      the interaction-list size of every child follows from them
+    for (int l = 2; l <= H.L; ++l) {
+        HostLevel& Lv = H.lv[l];
+        const HostLevel& Ch = H.lv[l - 1];
+        const int32_t sentinel = (int32_t)Ch.nint;
+        Lv.src216.assign(216 * Lv.nint, sentinel);
+        int64_t pairs = 0;
+        for (int64_t i = 0; i < Lv.nint; ++i) {
+            for (int e = 0; e < 27; ++e) {
+                const int64_t jx = Lv.coords[3 * i] + e % 3 - 1, jy = Lv.coords[3 * i + 1] + (e / 3) % 3 - 1,
+                              jz = Lv.coords[3 * i + 2] + e / 9 - 1;
+                if (jx < 0 || jy < 0 || jz < 0) continue;
+                auto it = idx[l].find(pack(jx, jy, jz));
+                if (it == idx[l].end()) continue;
+                for (int cs = 0; cs < 8; ++cs) {
+                    const int32_t q = Lv.child8[8 * it->second + cs];
+                    if (q >= 0) Lv.src216[216 * i + 8 * e + cs] = q;
+                }
+            }
+            for (int c = 0; c < 8; ++c) {
+                const int32_t t = Lv.child8[8 * i + c];
+                if (t < 0) continue;
+                for (int s = 0; s < 216; ++s) {
+                    const int32_t q = Lv.src216[216 * i + s];
+                    if (q == sentinel) continue;
+                    const int32_t* P = &Ch.coords[3 * t];
+                    const int32_t* Q = &Ch.coords[3 * q];
+                    const int dinf =
+                        std::max(std::abs(P[0] - Q[0]), std::max(std::abs(P[1] - Q[1]), std::abs(P[2] - Q[2])));
+                    if (dinf >= 2) ++pairs;
+                }
+            }
+        }
+        H.lv[l - 1].sib_pairs = pairs;
+    }
+    // ---- top level: every non-adjacent interval (non-empty only below the full depth)
+    {
+        HostLevel& T = H.lv[H.L];
+        for (int64_t i = 0; i < T.nint; ++i) {
+            const int32_t* P = &T.coords[3 * i];
+            T.csr_tgt.push_back((int32_t)i);
+            for (int64_t q = 0; q < T.nint; ++q) {
+                const int32_t* Q = &T.coords[3 * q];
+                std::array<int32_t, 3> D{P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
+                if (std::max(std::abs(D[0]), std::max(std::abs(D[1]), std::abs(D[2]))) < 2) continue;
+                T.csr_src.push_back((int32_t)q);
+                T.csr_D.push_back(D);
+            }
+            T.csr_ptr.push_back((int32_t)T.csr_src.size());
+        }
+        if (T.csr_src.empty()) {
+            T.csr_tgt.clear();
+            T.csr_ptr = {0};
+        }
+    }
+    for (int l = 1; l <= H.L; ++l)
+        if (H.lv[l].pairs() > 0) H.Ltop = l;
+    return LGF_OK;
+}
+
+// Union of independent layouts: every index is offset by the items of the earlier
+// layouts; sentinels map to the union's sentinel; lists never cross layouts.
+HostPlan concat(const std::vector<HostPlan>& parts) {
+    HostPlan U;
+    U.n = parts[0].n;
+    U.p = parts[0].p;
+    for (const auto& P : parts) {
+        U.L = std::max(U.L, P.L);
+        U.Ltop = std::max(U.Ltop, P.Ltop);
+    }
+    U.lv.assign(U.L + 1, HostLevel());
+    for (const auto& P : parts) {
+        U.nb += P.nb;
+        U.ngroups0 += P.ngroups0;
+        U.near_pairs += P.near_pairs;
+        for (int l = 1; l <= P.L; ++l) U.lv[l].nint += P.lv[l].nint;
+    }
+    U.solve_offsets = {0};
+    std::vector<int64_t> off(U.L + 1, 0);  // running item offset per level (level 1 = blocks)
+    for (const auto& P : parts) {
+        const int64_t ob = off[1];
+        for (int32_t t : P.g0_tgt8) U.g0_tgt8.push_back(t < 0 ? -1 : (int32_t)(t + ob));
+        for (int32_t q : P.g0_src64) U.g0_src64.push_back(q == (int32_t)P.nb ? (int32_t)U.nb : (int32_t)(q + ob));
+        for (int l = 1; l <= P.L; ++l) {
+            const HostLevel& A = P.lv[l];
+            HostLevel& B = U.lv[l];
+            B.sib_pairs += A.sib_pairs;
+            if (l >= 2) {
+                const int64_t oc = off[l - 1];
+                const int32_t sent_in = (int32_t)P.lv[l - 1].nint, sent_out = (int32_t)U.lv[l - 1].nint;
+                for (int32_t c : A.child8) B.child8.push_back(c < 0 ? -1 : (int32_t)(c + oc));
+                for (int32_t q : A.src216) B.src216.push_back(q == sent_in ? sent_out : (int32_t)(q + oc));
+            }
+            const int64_t ol = off[l];
+            for (int32_t t : A.csr_tgt) B.csr_tgt.push_back((int32_t)(t + ol));
+            for (size_t k = 1; k < A.csr_ptr.size(); ++k)
+                B.csr_ptr.push_back((int32_t)(B.csr_src.size() + A.csr_ptr[k]));
+            for (int32_t q : A.csr_src) B.csr_src.push_back((int32_t)(q + ol));
+            for (const auto& D : A.csr_D) B.csr_D.push_back(D);
+            // a layout's top level with an empty list gets no Prod: clear its targets' fields
+            if (l == P.L && A.csr_src.empty()) B.zero_uhat = true;
+        }
+        for (int l = 1; l <= P.L; ++l) off[l] += P.lv[l].nint;
+        U.solve_offsets.push_back(off[1]);
+    }
+    return U;
+}
+
 struct DevBuf {
     void* ptr = nullptr;
     int64_t bytes = 0;
@@ -65,56 +312,62 @@ struct DevBuf {
 
 }  // namespace
 
+// ------------------------------------------------------------------ the plan
 struct LevelPlan {
     int64_t nint = 0;
-    std::vector<int32_t> coords;    // [nint][3]
-    std::vector<int32_t> parent;    // [nint] -> level l+1 (empty at the top)
-    std::vector<int32_t> cpos;      // [nint] child position bits x | y<<1 | z<<2
-    std::vector<int32_t> child8;    // [nint][8] children at level l-1 (levels >= 2)
-    std::vector<int32_t> nbr27;     // [nint][27] same-level neighbours (levels >= 2)
-    std::vector<int32_t> src216;    // [nint][216] children of the 27 neighbours (sentinel if absent)
-    std::vector<int32_t> il_ptr, il_src, il_off;
-    int radius = 3;
-    std::shared_ptr<SpectraEntry> spectra;
-    // device
-    int32_t *d_parent = nullptr, *d_cpos = nullptr, *d_child8 = nullptr, *d_src216 = nullptr;
-    bool sibling = false;  // level list served by the sibling-blocked kernel
-    int32_t *d_ptr = nullptr, *d_src = nullptr, *d_off = nullptr;
+    int64_t sib_pairs = 0, csr_entries = 0, ncsr = 0;
+    bool zero_uhat = false;
+    std::shared_ptr<SpectraEntry> spectra, spectra_csr;  // radius 3 / radius of the CSR offsets
+    int32_t *d_child8 = nullptr, *d_src216 = nullptr;
+    int32_t *d_csr_tgt = nullptr, *d_csr_ptr = nullptr, *d_csr_src = nullptr, *d_csr_off = nullptr;
     void *d_ftil = nullptr, *d_fhat = nullptr, *d_uhat = nullptr, *d_util = nullptr;
+    int64_t pairs() const { return sib_pairs + csr_entries; }
 };
 
 struct lgf_plan_s {
     int n = 0, p = 0, L = 0, Ltop = 0;
     lgf_precision prec = LGF_F64;
-    int64_t nb = 0;
-    std::vector<int32_t> blocks;
-    std::vector<int32_t> nbr0;  // [nb][27]
-    int64_t near_pairs = 0;
-    std::vector<int32_t> g0_tgt8, g0_src64;  // level-0 target groups (2x2x2) and their 4^3 sources
-    int64_t ngroups0 = 0;
-    int32_t *d_g0_tgt8 = nullptr, *d_g0_src64 = nullptr;
+    int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
+    std::vector<int64_t> solve_offsets;
     std::vector<LevelPlan> lv;  // index 0 unused, 1..L
     std::shared_ptr<SpectraEntry> spectra0;
-    int32_t* d_nbr0 = nullptr;
+    int32_t *d_g0_tgt8 = nullptr, *d_g0_src64 = nullptr;
     double *d_A = nullptr, *d_C01 = nullptr;
     void *d_fhat0 = nullptr, *d_uhat0 = nullptr;
     std::vector<DevBuf> allocs;
     int64_t ws_bytes = 0;
     int device = 0;
-    // step profiling (events recorded on the solve stream)
+    TuneConfig tune;
+    // step profiling (events recorded on the stream each step runs on)
     struct StepInfo {
         std::string name;
         double bytes, flops;
     };
-    std::vector<StepInfo> steps;  // filled by the first profiled solve
+    std::vector<StepInfo> steps;
     std::vector<hipEvent_t> events;
     int prof_max = 0, prof_solves = 0, prof_cursor = 0;
     bool prof_on = false;
+    // far-field chain on a second (default-priority) stream for small plans
+    hipStream_t far_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool overlap = false;
 
     ~lgf_plan_s() {
         for (auto& b : allocs) hipFree(b.ptr);
         for (auto& e : events) hipEventDestroy(e);
+        if (ev_fork) hipEventDestroy(ev_fork);
+        if (ev_join) hipEventDestroy(ev_join);
+        if (far_stream) hipStreamDestroy(far_stream);
         budget_release(ws_bytes);
+    }
+};
+
+struct lgf_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~lgf_graph_s() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
     }
 };
 
@@ -131,46 +384,44 @@ bool dev_alloc(lgf_plan_s* pl, P** out, int64_t bytes) {
     return true;
 }
 
-// LGF_SYNC_CHECK=1 in the environment: synchronise after every launch and report the
-// first failing step by name (debugging aid; off by default).
-bool sync_check_enabled() {
-    static const bool on = [] {
-        const char* v = std::getenv("LGF_SYNC_CHECK");
-        return v && v[0] == '1';
-    }();
-    return on;
+template <typename V>
+hipError_t upload(void* dst, const std::vector<V>& v, hipStream_t s) {
+    if (v.empty() || !dst) return hipSuccess;
+    return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s);
 }
 
-hipError_t checked(hipError_t e, const char* what, hipStream_t s) {
-    if (e == hipSuccess && sync_check_enabled()) {
-        e = hipStreamSynchronize(s);
-        if (e == hipSuccess) e = hipGetLastError();
-    }
-    if (e != hipSuccess) t_err = std::string(what) + ": " + hipGetErrorString(e);
-    return e;
-}
-
-// Profiling: record an event after a step (and describe the step on the first solve).
+// Profiling: a solve records [solve start, solve end] and, per step, [start, end] events on
+// the stream the step runs on (the step list is described on the first recorded solve).
 struct Marker {
     lgf_plan_s* pl;
-    hipStream_t s;
     bool on;
+    size_t base = 0;
     int step = 0;
-    Marker(lgf_plan_s* p, hipStream_t st) : pl(p), s(st) {
-        on = pl->prof_on && pl->prof_solves < pl->prof_max;
+    explicit Marker(lgf_plan_s* p) : pl(p) {
+        on = pl->prof_on && pl->prof_solves < pl->prof_max && !t_capturing;
         if (on) {
             if (pl->prof_solves == 0) pl->steps.clear();
-            hipEventRecord(pl->events[pl->prof_cursor++], s);
+            base = (size_t)pl->prof_cursor;
         }
     }
-    void operator()(const std::string& name, double bytes, double flops) {
+    hipEvent_t ev(size_t k) { return pl->events[base + k]; }
+    void solve_begin(hipStream_t s) {
+        if (on) hipEventRecord(ev(0), s);
+    }
+    void begin(hipStream_t s) {
+        if (on) hipEventRecord(ev(2 + 2 * step), s);
+    }
+    void end(hipStream_t s, const std::string& name, double bytes, double flops) {
         if (!on) return;
         if (pl->prof_solves == 0) pl->steps.push_back({name, bytes, flops});
-        hipEventRecord(pl->events[pl->prof_cursor++], s);
+        hipEventRecord(ev(3 + 2 * step), s);
         ++step;
     }
-    void finish() {
-        if (on) ++pl->prof_solves;
+    void solve_end(hipStream_t s) {
+        if (!on) return;
+        hipEventRecord(ev(1), s);
+        pl->prof_cursor += 2 + 2 * step;
+        ++pl->prof_solves;
     }
 };
 
@@ -184,276 +435,162 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     using C = cplx<T>;
     using U = typename FarAcc<T>::type;
     const int n = pl->n, p = pl->p;
+    const TuneConfig& tc = pl->tune;
     hipError_t e;
-    Marker mark(pl, s);
-    const double es = sizeof(T), cs = 2.0 * sizeof(T);
+    Marker mark(pl);
+    const double es = sizeof(T), cs = 2.0 * sizeof(T), us = sizeof(U);
     const double n3 = (double)n * n * n, p3 = (double)p * p * p;
     const double S0 = pl->spectra0->S, S1 = (double)(2 * p) * (2 * p) * (p + 1);
+    const int64_t S1p = spec_padded(2 * p * 2 * p * (p + 1));
     const double nb = (double)pl->nb;
     auto lvN = [&](int l) { return (double)pl->lv[l].nint; };
-#define LGF_CHECK(x)                                      \
-    do {                                                  \
-        if ((e = checked((x), #x, s)) != hipSuccess) return e; \
+    auto lname = [](const char* a, int l) { return std::string(a) + std::to_string(l); };
+#define LGF_STEP(st, x, name, bytes, flops)                              \
+    do {                                                                 \
+        mark.begin(st);                                                  \
+        if ((e = checked((x), #x, st)) != hipSuccess) return e;          \
+        mark.end(st, name, bytes, flops);                                \
     } while (0)
-    LGF_CHECK(launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nb, s));
-    mark("fft_fwd_l0", nb * (n3 * es + S0 * cs), nb * fft_flops(2 * n));
-    if (pl->Ltop >= 1) {
-        LGF_CHECK(launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nb, n, p, s));
-        mark("reg_l0_l1", nb * (n3 + p3) * es, nb * 2.0 * (p * n3 + p * p * n * n + p3 * n));
-        for (int l = 1; l < pl->Ltop; ++l) {
-            LGF_CHECK(launch_reg_up<T>((const T*)pl->lv[l].d_ftil, pl->lv[l + 1].d_child8, pl->d_C01,
-                                       (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s));
-            mark("reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1), (lvN(l) + lvN(l + 1)) * p3 * es,
-                 lvN(l) * 2.0 * 3.0 * p3 * p);
+    mark.solve_begin(s);
+    const bool far = pl->Ltop >= 1;
+    hipStream_t s2 = pl->overlap ? pl->far_stream : s;
+    if (far) {
+        // ---- far field (levels >= 1), on the second stream for small plans: Reg up, FFT,
+        //      M2L, IFFT, Interp down
+        if (pl->overlap) {
+            if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s2, pl->ev_fork, 0)) != hipSuccess) return e;
         }
-        for (int l = 1; l <= pl->Ltop; ++l)
-            if (!pl->lv[l].il_src.empty()) {
-                LGF_CHECK(launch_pad_fft<T>(p, (const T*)pl->lv[l].d_ftil, (C*)pl->lv[l].d_fhat, pl->lv[l].nint, s));
-                mark("fft_fwd_l" + std::to_string(l), lvN(l) * (p3 * es + S1 * cs), lvN(l) * fft_flops(2 * p));
+        LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nb, n, p, s2)), "reg_l0_l1",
+                 nb * (n3 + p3) * es, nb * 2.0 * (p * n3 + p * p * n * n + p3 * n));
+        for (int l = 1; l < pl->Ltop; ++l)
+            LGF_STEP(s2,
+                     (launch_reg_up<T>((const T*)pl->lv[l].d_ftil, pl->lv[l + 1].d_child8, pl->d_C01,
+                                       (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s2)),
+                     "reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1), (lvN(l) + lvN(l + 1)) * p3 * es,
+                     lvN(l) * 2.0 * 3.0 * p3 * p);
+        for (int l = 1; l <= pl->Ltop; ++l) {
+            LevelPlan& L = pl->lv[l];
+            if (L.pairs() == 0) continue;
+            LGF_STEP(s2, (launch_pad_fft<T>(p, (const T*)L.d_ftil, (C*)L.d_fhat, L.nint, s2)), lname("fft_fwd_l", l),
+                     lvN(l) * (p3 * es + S1 * cs), lvN(l) * fft_flops(2 * p));
+            if (L.zero_uhat)
+                LGF_STEP(s2, zero_fill(L.d_uhat, L.nint * S1p * 2 * (int64_t)sizeof(T), s2), lname("zero_uhat_l", l),
+                         lvN(l) * S1 * cs, 0.0);
+            if (L.sib_pairs > 0) {
+                const LevelPlan& Pp = pl->lv[l + 1];
+                LGF_STEP(s2,
+                         (launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8,
+                                                 Pp.d_src216, (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S,
+                                                 tc.far_waves, s2)),
+                         lname("prod_l", l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.sib_pairs * S1 * 8.0);
             }
-    }
-    LGF_CHECK(launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8, pl->d_g0_src64,
-                                  (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S, s));
-    mark("prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
-    for (int l = 1; l <= pl->Ltop; ++l) {
-        LevelPlan& L = pl->lv[l];
-        if (L.il_src.empty()) continue;
-        if (L.sibling) {
-            const LevelPlan& Pp = pl->lv[l + 1];
-            LGF_CHECK(launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216,
-                                             (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S, s));
-        } else {
-            LGF_CHECK(launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, L.d_ptr, L.d_src, L.d_off,
-                                         (C*)L.d_uhat, L.nint, L.spectra->noff, L.spectra->S, s));
+            if (L.csr_entries > 0)
+                LGF_STEP(s2,
+                         (launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra_csr->dev, L.d_csr_ptr,
+                                             L.d_csr_src, L.d_csr_off, L.d_csr_tgt, (C*)L.d_uhat, L.ncsr, L.nint,
+                                             L.spectra_csr->noff, L.spectra_csr->S, s2)),
+                         lname("prod_top_l", l), (2.0 * lvN(l) + L.spectra_csr->noff) * S1 * cs,
+                         (double)L.csr_entries * S1 * 8.0);
         }
-        mark("prod_l" + std::to_string(l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.il_src.size() * S1 * 8.0);
-    }
-    for (int l = pl->Ltop; l >= 1; --l) {
-        LevelPlan& L = pl->lv[l];
-        if (L.il_src.empty()) {
-            LGF_CHECK(zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(U), s));
-            mark("zero_l" + std::to_string(l), lvN(l) * p3 * es, 0.0);
-        } else {
-            LGF_CHECK((launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, s)));
-            mark("fft_inv_l" + std::to_string(l), lvN(l) * (S1 * cs + p3 * es), lvN(l) * fft_flops(2 * p));
+        for (int l = pl->Ltop; l >= 1; --l) {
+            LevelPlan& L = pl->lv[l];
+            if (L.pairs() == 0) {
+                LGF_STEP(s2, zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(U), s2), lname("zero_l", l),
+                         lvN(l) * p3 * us, 0.0);
+            } else {
+                LGF_STEP(s2, (launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, s2)),
+                         lname("fft_inv_l", l), lvN(l) * (S1 * cs + p3 * us), lvN(l) * fft_flops(2 * p));
+            }
+            if (l < pl->Ltop)
+                LGF_STEP(s2,
+                         (launch_interp_down<U>((const U*)pl->lv[l + 1].d_util, pl->lv[l + 1].d_child8, pl->d_C01,
+                                                (U*)L.d_util, pl->lv[l + 1].nint, p, s2)),
+                         "interp_l" + std::to_string(l + 1) + "_l" + std::to_string(l),
+                         (lvN(l + 1) + 2.0 * lvN(l)) * p3 * us, lvN(l) * 2.0 * 3.0 * p3 * p);
         }
-        if (l < pl->Ltop) {
-            LGF_CHECK(launch_interp_down<U>((const U*)pl->lv[l + 1].d_util, pl->lv[l + 1].d_child8, pl->d_C01,
-                                            (U*)L.d_util, pl->lv[l + 1].nint, p, s));
-            mark("interp_l" + std::to_string(l + 1) + "_l" + std::to_string(l), (lvN(l + 1) + 2.0 * lvN(l)) * p3 * es,
-                 lvN(l) * 2.0 * 3.0 * p3 * p);
-        }
+        if (pl->overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
     }
-    LGF_CHECK((launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s)));
-    mark("fft_inv_l0", nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
-    if (pl->Ltop >= 1) {
-        LGF_CHECK((launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s)));
-        mark("final_l1_l0", nb * (2.0 * n3 + p3) * es, nb * 2.0 * (p3 * n + p * p * n * n + p * n3));
+    // ---- near field (level 0) on the caller's stream
+    LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nb, s, tc.fft0_threads), "fft_fwd_l0",
+             nb * (n3 * es + S0 * cs), nb * fft_flops(2 * n));
+    LGF_STEP(s,
+             launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8, pl->d_g0_src64,
+                                 (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S, tc.near_waves, s),
+             "prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
+    LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s, tc.fft0_threads)), "fft_inv_l0",
+             nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
+    if (far) {
+        if (pl->overlap && (e = hipStreamWaitEvent(s, pl->ev_join, 0)) != hipSuccess) return e;
+        LGF_STEP(s, (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s)), "final_l1_l0",
+                 nb * (2.0 * n3 * es + p3 * us), nb * 2.0 * (p3 * n + p * p * n * n + p * n3));
     }
-    mark.finish();
-#undef LGF_CHECK
+    mark.solve_end(s);
+#undef LGF_STEP
     return hipSuccess;
 }
 
-lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int levels, lgf_precision prec,
-                      hipStream_t s, lgf_plan_s* pl) {
+hipError_t solve_dispatch(lgf_plan_s* pl, const void* f, void* u, hipStream_t s) {
+    return pl->prec == LGF_F64 ? run_solve<double>(pl, (const double*)f, (double*)u, s)
+                               : run_solve<float>(pl, (const float*)f, (float*)u, s);
+}
+
+lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan_s* pl) {
+    const int n = H.n, p = H.p;
     pl->n = n;
     pl->p = p;
     pl->prec = prec;
-    pl->nb = nblocks;
+    pl->nb = H.nb;
+    pl->L = H.L;
+    pl->Ltop = H.Ltop;
+    pl->near_pairs = H.near_pairs;
+    pl->ngroups0 = H.ngroups0;
+    pl->solve_offsets = H.solve_offsets;
     hipGetDevice(&pl->device);
-    // ---- layout: shift to the bounding-box minimum, reject duplicates and huge spans
-    int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
-    for (int64_t b = 0; b < nblocks; ++b)
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = std::min<int64_t>(lo[d], ijk[3 * b + d]);
-            hi[d] = std::max<int64_t>(hi[d], ijk[3 * b + d]);
-        }
-    int64_t ext = 1;
-    for (int d = 0; d < 3; ++d) {
-        if (hi[d] - lo[d] >= (1 << 20)) return fail(LGF_ERR_LAYOUT, "layout spans more than 2^20 blocks");
-        ext = std::max<int64_t>(ext, hi[d] - lo[d] + 1);
+    if (hipStreamCreateWithFlags(&pl->far_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)
+        return fail(LGF_ERR_DEVICE, "stream/event creation failed");
+    // Large plans saturate the GPU with either chain alone; measured on MI355X the
+    // concurrent chains then only contend, so overlap is used for small plans only.
+    pl->overlap = H.nb <= kOverlapMaxBlocks;
+    pl->lv.assign(H.L + 1, LevelPlan());
+    for (int l = 1; l <= H.L; ++l) {
+        pl->lv[l].nint = H.lv[l].nint;
+        pl->lv[l].sib_pairs = H.lv[l].sib_pairs;
+        pl->lv[l].csr_entries = (int64_t)H.lv[l].csr_src.size();
+        pl->lv[l].ncsr = (int64_t)H.lv[l].csr_tgt.size();
+        pl->lv[l].zero_uhat = H.lv[l].zero_uhat;
     }
-    pl->blocks.resize(3 * nblocks);
-    std::unordered_map<uint64_t, int32_t> idx0;
-    idx0.reserve(nblocks * 2);
-    for (int64_t b = 0; b < nblocks; ++b) {
-        for (int d = 0; d < 3; ++d) pl->blocks[3 * b + d] = (int32_t)(ijk[3 * b + d] - lo[d]);
-        const uint64_t key = pack(pl->blocks[3 * b], pl->blocks[3 * b + 1], pl->blocks[3 * b + 2]);
-        if (!idx0.emplace(key, (int32_t)b).second) return fail(LGF_ERR_LAYOUT, "duplicate block in layout");
-    }
-    int full = 1;
-    while ((int64_t(1) << (full - 1)) < ext) ++full;
-    pl->L = levels <= 0 ? full : std::min(levels, full);
-    if (pl->L >= kMaxLevels) return fail(LGF_ERR_LAYOUT, "tree deeper than supported");
-
-    // ---- level 0 near-neighbour table
-    pl->nbr0.assign(27 * nblocks, -1);
-    for (int64_t b = 0; b < nblocks; ++b) {
-        const int32_t* P = &pl->blocks[3 * b];
-        for (int d = 0; d < 27; ++d) {
-            const int Dx = d % 3 - 1, Dy = (d / 3) % 3 - 1, Dz = d / 9 - 1;
-            const int64_t qx = P[0] - Dx, qy = P[1] - Dy, qz = P[2] - Dz;  // Q = P - D
-            if (qx < 0 || qy < 0 || qz < 0) continue;
-            auto it = idx0.find(pack(qx, qy, qz));
-            if (it != idx0.end()) {
-                pl->nbr0[27 * b + d] = it->second;
-                ++pl->near_pairs;
-            }
-        }
-    }
-    // ---- level-0 target groups: blocks 2J + c, sources 2J + (-1..2)^3
-    {
-        std::unordered_map<uint64_t, int32_t> gidx;
-        for (int64_t b = 0; b < nblocks; ++b) {
-            const int32_t* P = &pl->blocks[3 * b];
-            const uint64_t key = pack(P[0] >> 1, P[1] >> 1, P[2] >> 1);
-            auto it = gidx.find(key);
-            int32_t g;
-            if (it == gidx.end()) {
-                g = (int32_t)pl->ngroups0++;
-                gidx.emplace(key, g);
-                pl->g0_tgt8.resize(8 * pl->ngroups0, -1);
-                pl->g0_src64.resize(64 * pl->ngroups0, (int32_t)nblocks);  // zero sentinel item
-                for (int sidx = 0; sidx < 64; ++sidx) {
-                    const int64_t qx = 2 * (int64_t)(P[0] >> 1) + (sidx & 3) - 1;
-                    const int64_t qy = 2 * (int64_t)(P[1] >> 1) + ((sidx >> 2) & 3) - 1;
-                    const int64_t qz = 2 * (int64_t)(P[2] >> 1) + (sidx >> 4) - 1;
-                    if (qx < 0 || qy < 0 || qz < 0) continue;
-                    auto jt = idx0.find(pack(qx, qy, qz));
-                    if (jt != idx0.end()) pl->g0_src64[64 * g + sidx] = jt->second;
-                }
-            } else {
-                g = it->second;
-            }
-            pl->g0_tgt8[8 * g + ((P[0] & 1) | ((P[1] & 1) << 1) | ((P[2] & 1) << 2))] = (int32_t)b;
-        }
-    }
-    // ---- levels: coordinates, parents, children
-    pl->lv.assign(pl->L + 1, LevelPlan());
-    std::vector<std::unordered_map<uint64_t, int32_t>> idx(pl->L + 2);
-    pl->lv[1].nint = nblocks;
-    pl->lv[1].coords = pl->blocks;
-    idx[1] = idx0;
-    for (int l = 1; l < pl->L; ++l) {
-        LevelPlan& C = pl->lv[l];
-        LevelPlan& P = pl->lv[l + 1];
-        C.parent.resize(C.nint);
-        C.cpos.resize(C.nint);
-        for (int64_t i = 0; i < C.nint; ++i) {
-            const int32_t x = C.coords[3 * i], y = C.coords[3 * i + 1], z = C.coords[3 * i + 2];
-            const uint64_t key = pack(x >> 1, y >> 1, z >> 1);
-            auto it = idx[l + 1].find(key);
-            int32_t j;
-            if (it == idx[l + 1].end()) {
-                j = (int32_t)P.nint++;
-                idx[l + 1].emplace(key, j);
-                P.coords.push_back(x >> 1);
-                P.coords.push_back(y >> 1);
-                P.coords.push_back(z >> 1);
-            } else {
-                j = it->second;
-            }
-            C.parent[i] = j;
-            C.cpos[i] = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-        }
-        P.child8.assign(8 * P.nint, -1);
-        for (int64_t i = 0; i < C.nint; ++i) P.child8[8 * C.parent[i] + C.cpos[i]] = (int32_t)i;
-    }
-    for (int l = 2; l <= pl->L; ++l) {
-        LevelPlan& Lv = pl->lv[l];
-        Lv.nbr27.assign(27 * Lv.nint, -1);
-        for (int64_t i = 0; i < Lv.nint; ++i)
-            for (int e = 0; e < 27; ++e) {
-                const int64_t jx = Lv.coords[3 * i] + e % 3 - 1, jy = Lv.coords[3 * i + 1] + (e / 3) % 3 - 1,
-                              jz = Lv.coords[3 * i + 2] + e / 9 - 1;
-                if (jx < 0 || jy < 0 || jz < 0) continue;
-                auto it = idx[l].find(pack(jx, jy, jz));
-                if (it != idx[l].end()) Lv.nbr27[27 * i + e] = it->second;
-            }
-        const int32_t sentinel = (int32_t)pl->lv[l - 1].nint;
-        Lv.src216.assign(216 * Lv.nint, sentinel);
-        for (int64_t i = 0; i < Lv.nint; ++i)
-            for (int e = 0; e < 27; ++e) {
-                const int32_t Jn = Lv.nbr27[27 * i + e];
-                if (Jn < 0) continue;
-                for (int cs = 0; cs < 8; ++cs) {
-                    const int32_t q = Lv.child8[8 * Jn + cs];
-                    if (q >= 0) Lv.src216[216 * i + 8 * e + cs] = q;
-                }
-            }
-    }
-    // ---- interaction lists
-    for (int l = 1; l <= pl->L; ++l) {
-        LevelPlan& Lv = pl->lv[l];
-        Lv.il_ptr.assign(Lv.nint + 1, 0);
-        int maxd = 0;
-        std::vector<std::pair<int32_t, int32_t>> tmp;  // (src, D packed later)
-        std::vector<int32_t> src, offs;
-        std::vector<std::array<int32_t, 3>> dvec;
-        for (int64_t i = 0; i < Lv.nint; ++i) {
-            const int32_t* P = &Lv.coords[3 * i];
-            std::vector<std::pair<int64_t, std::array<int32_t, 3>>> cand;  // (q, D)
-            if (l < pl->L) {
-                const int32_t* Pp = &pl->lv[l + 1].coords[3 * Lv.parent[i]];
-                for (int dz = -1; dz <= 1; ++dz)
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            const int64_t jx = Pp[0] + dx, jy = Pp[1] + dy, jz = Pp[2] + dz;
-                            if (jx < 0 || jy < 0 || jz < 0) continue;
-                            auto it = idx[l + 1].find(pack(jx, jy, jz));
-                            if (it == idx[l + 1].end()) continue;
-                            for (int c = 0; c < 8; ++c) {
-                                const int32_t q = pl->lv[l + 1].child8[8 * it->second + c];
-                                if (q < 0) continue;
-                                const int32_t* Q = &Lv.coords[3 * q];
-                                std::array<int32_t, 3> D{P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
-                                const int dinf = std::max(std::abs(D[0]), std::max(std::abs(D[1]), std::abs(D[2])));
-                                if (dinf >= 2) cand.push_back({q, D});
-                            }
-                        }
-            } else {
-                for (int64_t q = 0; q < Lv.nint; ++q) {
-                    const int32_t* Q = &Lv.coords[3 * q];
-                    std::array<int32_t, 3> D{P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
-                    const int dinf = std::max(std::abs(D[0]), std::max(std::abs(D[1]), std::abs(D[2])));
-                    if (dinf >= 2) cand.push_back({q, D});
-                }
-            }
-            std::sort(cand.begin(), cand.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
-            for (const auto& cd : cand) {
-                src.push_back((int32_t)cd.first);
-                dvec.push_back(cd.second);
-                maxd = std::max(maxd, std::max(std::abs(cd.second[0]), std::max(std::abs(cd.second[1]), std::abs(cd.second[2]))));
-            }
-            Lv.il_ptr[i + 1] = (int32_t)src.size();
-        }
-        Lv.radius = std::max(3, maxd);
-        const int R = Lv.radius, W = 2 * R + 1;
-        Lv.il_src = src;
-        Lv.il_off.resize(src.size());
-        for (size_t e = 0; e < src.size(); ++e)
-            Lv.il_off[e] = (dvec[e][0] + R) + W * ((dvec[e][1] + R) + W * (dvec[e][2] + R));
-        if (!src.empty()) pl->Ltop = l;
-        Lv.sibling = (l < pl->L) && !src.empty();
-    }
-    if (pl->Ltop >= 1 && (int64_t)(2 * pl->lv[pl->Ltop].radius + 1) * (2 * pl->lv[pl->Ltop].radius + 1) *
-                                 (2 * pl->lv[pl->Ltop].radius + 1) > 300000)
-        return fail(LGF_ERR_LAYOUT, "top-level interaction offsets too large: use more levels");
-
-    // ---- kernel spectra (shared cache)
+    // ---- kernel spectra (shared cache): radius 1 at level 0, 3 for the sibling kernel,
+    //      the CSR offsets' own radius for a truncated top level
     std::string err;
     const int ip = prec == LGF_F64 ? 0 : 1;
+    auto err_status = [&](const std::string& m) {
+        return fail(m.find("budget") != std::string::npos ? LGF_ERR_BUDGET : LGF_ERR_DEVICE, m);
+    };
     pl->spectra0 = get_spectra(SpectraKey{n, p, 0, 1, ip}, s, err);
-    if (!pl->spectra0) return fail(err.find("budget") != std::string::npos ? LGF_ERR_BUDGET : LGF_ERR_DEVICE, err);
+    if (!pl->spectra0) return err_status(err);
+    std::vector<std::vector<int32_t>> csr_off(H.L + 1);
     for (int l = 1; l <= pl->Ltop; ++l) {
-        if (pl->lv[l].il_src.empty()) continue;
-        pl->lv[l].spectra = get_spectra(SpectraKey{n, p, l, pl->lv[l].radius, ip}, s, err);
-        if (!pl->lv[l].spectra)
-            return fail(err.find("budget") != std::string::npos ? LGF_ERR_BUDGET : LGF_ERR_DEVICE, err);
+        LevelPlan& L = pl->lv[l];
+        if (L.sib_pairs > 0) {
+            L.spectra = get_spectra(SpectraKey{n, p, l, 3, ip}, s, err);
+            if (!L.spectra) return err_status(err);
+        }
+        if (L.csr_entries > 0) {
+            int R = 3;
+            for (const auto& D : H.lv[l].csr_D)
+                R = std::max(R, std::max(std::abs(D[0]), std::max(std::abs(D[1]), std::abs(D[2]))));
+            const int W = 2 * R + 1;
+            if ((int64_t)W * W * W > 300000)
+                return fail(LGF_ERR_LAYOUT, "top-level offsets too large: use more levels");
+            for (const auto& D : H.lv[l].csr_D) csr_off[l].push_back((D[0] + R) + W * ((D[1] + R) + W * (D[2] + R)));
+            L.spectra_csr = get_spectra(SpectraKey{n, p, l, R, ip}, s, err);
+            if (!L.spectra_csr) return err_status(err);
+        }
     }
-
-    // ---- matrices (FP64)
+    // ---- 1D Lagrange matrices (FP64)
     std::vector<double> A(p * n), C01(2 * p * p);
     for (int k = 0; k < p; ++k)
         for (int j = 0; j < n; ++j) A[k * n + j] = (double)lagrange(p, k, (long double)j * (p - 1) / n);
@@ -461,76 +598,152 @@ lgf_status build_plan(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
         for (int mm = 0; mm < p; ++mm)
             for (int k = 0; k < p; ++k)
                 C01[c * p * p + mm * p + k] = (double)lagrange(p, mm, (long double)(c * (p - 1) + k) / 2.0L);
-
     // ---- device memory
-    const size_t esz = prec == LGF_F64 ? sizeof(double) : sizeof(float);
-    const int64_t S0 = spec_padded(pl->spectra0->S);
-    const int M1 = 2 * p;
-    const int64_t S1 = spec_padded(M1 * M1 * (M1 / 2 + 1));
-    const int64_t p3 = (int64_t)p * p * p;
+    const int64_t esz = prec == LGF_F64 ? sizeof(double) : sizeof(float);
     const int64_t usz = 8;  // far-field down-pass values: double or float-float
-    const int topc = std::min(pl->Ltop + 1, pl->L);  // highest level whose child8 / nbr27 is used
-    int64_t need = 27 * nblocks * 4 + pl->ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (2 * nblocks + 1) * S0 * 2 * esz;
+    const int64_t S0 = spec_padded(pl->spectra0->S);
+    const int64_t S1 = spec_padded(2 * p * 2 * p * (p + 1));
+    const int64_t p3 = (int64_t)p * p * p;
+    const int64_t nb = H.nb;
+    const int topc = std::min(pl->Ltop + 1, H.L);  // highest level whose child8 / src216 is used
+    int64_t need = H.ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (2 * nb + 1) * S0 * 2 * esz;
     for (int l = 1; l <= pl->Ltop; ++l) {
-        const LevelPlan& Lv = pl->lv[l];
-        need += Lv.nint * (p3 * (esz + usz) + 2 * 4) + (Lv.nint + 1) * 4 + Lv.il_src.size() * 8;
-        if (!Lv.il_src.empty()) need += (2 * Lv.nint + 1) * S1 * 2 * esz;
+        const HostLevel& h = H.lv[l];
+        need += h.nint * p3 * (esz + usz);
+        if (h.pairs() > 0) need += (2 * h.nint + 1) * S1 * 2 * esz;
+        need += (int64_t)(h.csr_tgt.size() + h.csr_ptr.size() + 2 * h.csr_src.size()) * 4;
     }
-    for (int l = 2; l <= topc && pl->Ltop >= 1; ++l) need += pl->lv[l].nint * 224 * 4;
+    for (int l = 2; l <= topc && pl->Ltop >= 1; ++l) need += H.lv[l].nint * 224 * 4;
     if (!budget_reserve(need)) return fail(LGF_ERR_BUDGET, "plan workspace exceeds the device-memory budget");
     pl->ws_bytes = need;
-    bool ok = dev_alloc(pl, &pl->d_nbr0, 27 * nblocks * 4) && dev_alloc(pl, &pl->d_g0_tgt8, pl->ngroups0 * 8 * 4) &&
-              dev_alloc(pl, &pl->d_g0_src64, pl->ngroups0 * 64 * 4) && dev_alloc(pl, &pl->d_A, p * n * 8) &&
-              dev_alloc(pl, &pl->d_C01, 2 * p * p * 8) && dev_alloc(pl, &pl->d_fhat0, (nblocks + 1) * S0 * 2 * esz) &&
-              dev_alloc(pl, &pl->d_uhat0, nblocks * S0 * 2 * esz);
+    bool ok = dev_alloc(pl, &pl->d_g0_tgt8, H.ngroups0 * 8 * 4) &&
+              dev_alloc(pl, &pl->d_g0_src64, H.ngroups0 * 64 * 4) && dev_alloc(pl, &pl->d_A, p * n * 8) &&
+              dev_alloc(pl, &pl->d_C01, 2 * p * p * 8) && dev_alloc(pl, &pl->d_fhat0, (nb + 1) * S0 * 2 * esz) &&
+              dev_alloc(pl, &pl->d_uhat0, nb * S0 * 2 * esz);
     for (int l = 1; ok && l <= pl->Ltop; ++l) {
         LevelPlan& Lv = pl->lv[l];
+        const HostLevel& h = H.lv[l];
         ok = dev_alloc(pl, &Lv.d_ftil, Lv.nint * p3 * esz) && dev_alloc(pl, &Lv.d_util, Lv.nint * p3 * usz);
-        if (ok && l < pl->Ltop)
-            ok = dev_alloc(pl, &Lv.d_parent, Lv.nint * 4) && dev_alloc(pl, &Lv.d_cpos, Lv.nint * 4);
-        if (ok && !Lv.il_src.empty())
-            ok = dev_alloc(pl, &Lv.d_ptr, (Lv.nint + 1) * 4) && dev_alloc(pl, &Lv.d_src, Lv.il_src.size() * 4) &&
-                 dev_alloc(pl, &Lv.d_off, Lv.il_src.size() * 4) &&
-                 dev_alloc(pl, &Lv.d_fhat, (Lv.nint + 1) * S1 * 2 * esz) &&
+        if (ok && h.pairs() > 0)
+            ok = dev_alloc(pl, &Lv.d_fhat, (Lv.nint + 1) * S1 * 2 * esz) &&
                  dev_alloc(pl, &Lv.d_uhat, Lv.nint * S1 * 2 * esz);
+        if (ok && !h.csr_src.empty())
+            ok = dev_alloc(pl, &Lv.d_csr_tgt, h.csr_tgt.size() * 4) &&
+                 dev_alloc(pl, &Lv.d_csr_ptr, h.csr_ptr.size() * 4) &&
+                 dev_alloc(pl, &Lv.d_csr_src, h.csr_src.size() * 4) &&
+                 dev_alloc(pl, &Lv.d_csr_off, h.csr_src.size() * 4);
     }
     for (int l = 2; ok && l <= topc && pl->Ltop >= 1; ++l)
-        ok = dev_alloc(pl, &pl->lv[l].d_child8, pl->lv[l].nint * 32) &&
-             dev_alloc(pl, &pl->lv[l].d_src216, pl->lv[l].nint * 216 * 4);
+        ok = dev_alloc(pl, &pl->lv[l].d_child8, H.lv[l].nint * 32) &&
+             dev_alloc(pl, &pl->lv[l].d_src216, H.lv[l].nint * 216 * 4);
     if (!ok) return fail(LGF_ERR_OOM, "device allocation failed for the plan workspace");
-    hipError_t e = hipMemcpyAsync(pl->d_nbr0, pl->nbr0.data(), 27 * nblocks * 4, hipMemcpyHostToDevice, s);
-    e = e == hipSuccess ? hipMemcpyAsync(pl->d_g0_tgt8, pl->g0_tgt8.data(), pl->g0_tgt8.size() * 4,
-                                         hipMemcpyHostToDevice, s) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(pl->d_g0_src64, pl->g0_src64.data(), pl->g0_src64.size() * 4,
-                                         hipMemcpyHostToDevice, s) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(pl->d_A, A.data(), A.size() * 8, hipMemcpyHostToDevice, s) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(pl->d_C01, C01.data(), C01.size() * 8, hipMemcpyHostToDevice, s) : e;
+    hipError_t e = upload(pl->d_g0_tgt8, H.g0_tgt8, s);
+    if (e == hipSuccess) e = upload(pl->d_g0_src64, H.g0_src64, s);
+    if (e == hipSuccess) e = upload(pl->d_A, A, s);
+    if (e == hipSuccess) e = upload(pl->d_C01, C01, s);
     for (int l = 1; e == hipSuccess && l <= pl->Ltop; ++l) {
         LevelPlan& Lv = pl->lv[l];
-        if (Lv.d_parent) e = hipMemcpyAsync(Lv.d_parent, Lv.parent.data(), Lv.nint * 4, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && Lv.d_cpos)
-            e = hipMemcpyAsync(Lv.d_cpos, Lv.cpos.data(), Lv.nint * 4, hipMemcpyHostToDevice, s);
-
-        if (e == hipSuccess && Lv.d_ptr) {
-            e = hipMemcpyAsync(Lv.d_ptr, Lv.il_ptr.data(), (Lv.nint + 1) * 4, hipMemcpyHostToDevice, s);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(Lv.d_src, Lv.il_src.data(), Lv.il_src.size() * 4, hipMemcpyHostToDevice, s);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(Lv.d_off, Lv.il_off.data(), Lv.il_off.size() * 4, hipMemcpyHostToDevice, s);
+        if (Lv.d_csr_tgt) {
+            e = upload(Lv.d_csr_tgt, H.lv[l].csr_tgt, s);
+            if (e == hipSuccess) e = upload(Lv.d_csr_ptr, H.lv[l].csr_ptr, s);
+            if (e == hipSuccess) e = upload(Lv.d_csr_src, H.lv[l].csr_src, s);
+            if (e == hipSuccess) e = upload(Lv.d_csr_off, csr_off[l], s);
         }
     }
     for (int l = 2; e == hipSuccess && l <= topc && pl->Ltop >= 1; ++l) {
-        LevelPlan& Lv = pl->lv[l];
-        e = hipMemcpyAsync(Lv.d_child8, Lv.child8.data(), Lv.nint * 32, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(Lv.d_src216, Lv.src216.data(), Lv.nint * 216 * 4, hipMemcpyHostToDevice, s);
+        e = upload(pl->lv[l].d_child8, H.lv[l].child8, s);
+        if (e == hipSuccess) e = upload(pl->lv[l].d_src216, H.lv[l].src216, s);
     }
-    if (e == hipSuccess) e = zero_fill(pl->d_fhat0, (nblocks + 1) * S0 * 2 * esz, s);
+    // the source-spectra arrays start zeroed: their last item is the zero sentinel
+    if (e == hipSuccess) e = zero_fill(pl->d_fhat0, (nb + 1) * S0 * 2 * esz, s);
     for (int l = 1; e == hipSuccess && l <= pl->Ltop; ++l)
         if (pl->lv[l].d_fhat) e = zero_fill(pl->lv[l].d_fhat, (pl->lv[l].nint + 1) * S1 * 2 * esz, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(LGF_ERR_DEVICE, std::string("plan upload failed: ") + hipGetErrorString(e));
     return LGF_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+// Candidate kernel variants are timed on the plan itself (median of a few solves); the
+// winner is remembered per (n, p, precision, block-count bucket) for the process and, if
+// LGF_TUNE_FILE names a file, appended there and read back by later processes.
+struct TuneKey {
+    int n, p, prec, bucket;
+    bool operator<(const TuneKey& o) const {
+        return std::make_tuple(n, p, prec, bucket) < std::make_tuple(o.n, o.p, o.prec, o.bucket);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneConfig> g_tune;
+bool g_tune_loaded = false;
+
+int bucket_of(int64_t nb) {
+    int b = 0;
+    while ((int64_t(1) << b) < nb) ++b;
+    return b;
+}
+
+bool valid_tune(const TuneConfig& c) {
+    const bool f = c.fft0_threads == 0 || c.fft0_threads == 128 || c.fft0_threads == 256 || c.fft0_threads == 512;
+    const bool nw = c.near_waves == 2 || c.near_waves == 4 || c.near_waves == 8;
+    const bool fw = c.far_waves == 4 || c.far_waves == 8 || c.far_waves == 16;
+    return f && nw && fw;
+}
+
+void tune_load_file() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("LGF_TUNE_FILE");
+    if (!path) return;
+    FILE* fh = std::fopen(path, "r");
+    if (!fh) return;
+    TuneKey k;
+    TuneConfig c;
+    while (std::fscanf(fh, "%d %d %d %d %d %d %d", &k.n, &k.p, &k.prec, &k.bucket, &c.fft0_threads, &c.near_waves,
+                       &c.far_waves) == 7)
+        if (valid_tune(c)) g_tune[k] = c;
+    std::fclose(fh);
+}
+
+void tune_store(const TuneKey& k, const TuneConfig& c) {
+    g_tune[k] = c;
+    const char* path = std::getenv("LGF_TUNE_FILE");
+    if (!path) return;
+    FILE* fh = std::fopen(path, "a");
+    if (!fh) return;
+    std::fprintf(fh, "%d %d %d %d %d %d %d\n", k.n, k.p, k.prec, k.bucket, c.fft0_threads, c.near_waves, c.far_waves);
+    std::fclose(fh);
+}
+
+// median device time (ms) of `reps` solves with the plan's current configuration
+float time_solves(lgf_plan_s* pl, const void* f, void* u, hipStream_t s, int reps) {
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    std::vector<float> t;
+    for (int r = 0; r < reps + 1; ++r) {
+        hipEventRecord(a, s);
+        if (solve_dispatch(pl, f, u, s) != hipSuccess) {
+            t.assign(1, 1e30f);
+            break;
+        }
+        hipEventRecord(b, s);
+        hipEventSynchronize(b);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, a, b);
+        if (r > 0) t.push_back(ms);  // the first solve warms caches and code objects
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+void apply_cached_tune(lgf_plan_s* pl) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_file();
+    auto it = g_tune.find(TuneKey{pl->n, pl->p, (int)pl->prec, bucket_of(pl->nb)});
+    if (it != g_tune.end()) pl->tune = it->second;
 }
 
 }  // namespace
@@ -554,6 +767,25 @@ void budget_set(int64_t bytes) { g_budget.store(bytes); }
 // ============================================================== C ABI
 extern "C" {
 
+static lgf_status check_args(int32_t n, int32_t p, lgf_precision prec) {
+    if (n != 4 && n != 8 && n != 16) return fail(LGF_ERR_ARG, "n must be 4, 8 or 16");
+    if (p < 2 || p > 10) return fail(LGF_ERR_ARG, "p must lie in [2, 10]");
+    if (prec != LGF_F64 && prec != LGF_F32) return fail(LGF_ERR_ARG, "unknown precision");
+    return LGF_OK;
+}
+
+static lgf_status make_plan(HostPlan& H, lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
+    lgf_plan_s* pl = new lgf_plan_s();
+    lgf_status st = setup_device(H, prec, (hipStream_t)hip_stream, pl);
+    if (st != LGF_OK) {
+        delete pl;
+        return st;
+    }
+    apply_cached_tune(pl);
+    *out = pl;
+    return LGF_OK;
+}
+
 lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
                            lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
     t_err.clear();
@@ -562,34 +794,61 @@ lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n,
     if (!block_ijk) return fail(LGF_ERR_ARG, "block_ijk is NULL");
     if (nblocks < 1) return fail(LGF_ERR_LAYOUT, "empty layout");
     if (nblocks > (int64_t)1 << 30) return fail(LGF_ERR_ARG, "too many blocks");
-    if (n != 4 && n != 8 && n != 16) return fail(LGF_ERR_ARG, "n must be 4, 8 or 16");
-    if (p < 2 || p > 10) return fail(LGF_ERR_ARG, "p must lie in [2, 10]");
-    if (prec != LGF_F64 && prec != LGF_F32) return fail(LGF_ERR_ARG, "unknown precision");
-    lgf_plan_s* pl = nullptr;
+    lgf_status st = check_args(n, p, prec);
+    if (st != LGF_OK) return st;
     try {
-        pl = new lgf_plan_s();
-        lgf_status st = build_plan(block_ijk, nblocks, n, p, levels, prec, (hipStream_t)hip_stream, pl);
-        if (st != LGF_OK) {
-            delete pl;
-            return st;
-        }
+        HostPlan H;
+        st = build_host(block_ijk, nblocks, n, p, levels, H);
+        if (st != LGF_OK) return st;
+        return make_plan(H, prec, hip_stream, out);
     } catch (const std::bad_alloc&) {
-        delete pl;
         return fail(LGF_ERR_OOM, "host allocation failed");
     } catch (...) {
-        delete pl;
         return fail(LGF_ERR_DEVICE, "unexpected failure while building the plan");
     }
-    *out = pl;
+}
+
+lgf_status lgf_plan_create_batch(const int32_t* const* layouts, const int64_t* nblocks, int32_t count, int32_t n,
+                                 int32_t p, int32_t levels, lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
+    t_err.clear();
+    if (!out) return fail(LGF_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !layouts || !nblocks) return fail(LGF_ERR_ARG, "bad batch arguments");
+    lgf_status st = check_args(n, p, prec);
+    if (st != LGF_OK) return st;
+    try {
+        std::vector<HostPlan> parts(count);
+        int64_t total = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            if (!layouts[i]) return fail(LGF_ERR_ARG, "NULL layout in batch");
+            if (nblocks[i] < 1) return fail(LGF_ERR_LAYOUT, "empty layout in batch");
+            total += nblocks[i];
+            if (total > (int64_t)1 << 30) return fail(LGF_ERR_ARG, "too many blocks");
+            st = build_host(layouts[i], nblocks[i], n, p, levels, parts[i]);
+            if (st != LGF_OK) return st;
+        }
+        HostPlan U = concat(parts);
+        return make_plan(U, prec, hip_stream, out);
+    } catch (const std::bad_alloc&) {
+        return fail(LGF_ERR_OOM, "host allocation failed");
+    } catch (...) {
+        return fail(LGF_ERR_DEVICE, "unexpected failure while building the batch plan");
+    }
+}
+
+lgf_status lgf_plan_solve_offsets(lgf_plan_t plan, int64_t* offsets, int32_t max_entries, int32_t* count) {
+    if (!plan || !count) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_solve_offsets");
+    *count = (int32_t)plan->solve_offsets.size() - 1;
+    if (offsets)
+        for (int32_t i = 0; i < max_entries && i < (int32_t)plan->solve_offsets.size(); ++i)
+            offsets[i] = plan->solve_offsets[i];
     return LGF_OK;
 }
 
 lgf_status lgf_solve(lgf_plan_t plan, const void* f, void* u, void* hip_stream) {
     if (!plan || !f || !u) return fail(LGF_ERR_ARG, "NULL argument to lgf_solve");
     t_err.clear();
-    hipError_t e = plan->prec == LGF_F64
-                       ? run_solve<double>(plan, (const double*)f, (double*)u, (hipStream_t)hip_stream)
-                       : run_solve<float>(plan, (const float*)f, (float*)u, (hipStream_t)hip_stream);
+    hipError_t e = solve_dispatch(plan, f, u, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(LGF_ERR_DEVICE, std::string("solve failed at ") + t_err);
     return LGF_OK;
 }
@@ -607,6 +866,97 @@ lgf_status lgf_solve_many(const lgf_plan_t* plans, const void* const* f, void* c
     return LGF_OK;
 }
 
+lgf_status lgf_graph_create(lgf_plan_t plan, const void* f, void* u, void* hip_stream, lgf_graph_t* out) {
+    if (!plan || !f || !u || !out) return fail(LGF_ERR_ARG, "NULL argument to lgf_graph_create");
+    *out = nullptr;
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return fail(LGF_ERR_DEVICE, "stream creation failed");
+    // the capture must not start while the caller's stream still has work for these buffers
+    if (hip_stream) hipStreamSynchronize((hipStream_t)hip_stream);
+    lgf_graph_s* g = new lgf_graph_s();
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        t_capturing = true;
+        hipError_t es = solve_dispatch(plan, f, u, cap);
+        t_capturing = false;
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cap, &graph);
+        g->graph = graph;
+        if (es != hipSuccess) e = es;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(LGF_ERR_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return LGF_OK;
+}
+
+lgf_status lgf_graph_launch(lgf_graph_t graph, void* hip_stream) {
+    if (!graph || !graph->exec) return fail(LGF_ERR_ARG, "NULL graph");
+    hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(LGF_ERR_DEVICE, std::string("graph launch failed: ") + hipGetErrorString(e));
+    return LGF_OK;
+}
+
+lgf_status lgf_graph_destroy(lgf_graph_t graph) {
+    delete graph;
+    return LGF_OK;
+}
+
+lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_stream, int32_t reps) {
+    if (!plan || !f || !u) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_autotune");
+    if (reps < 1) reps = 3;
+    hipStream_t s = (hipStream_t)hip_stream;
+    TuneConfig best = plan->tune;
+    float best_ms = time_solves(plan, f, u, s, reps);
+    // coordinate search: each knob in turn, keeping the best value of the others
+    const int fft_opts[] = {128, 256, 512};
+    const int near_opts[] = {2, 4, 8};
+    const int far_opts[] = {4, 8, 16};
+    for (int knob = 0; knob < 3; ++knob) {
+        for (int k = 0; k < 3; ++k) {
+            TuneConfig c = best;
+            if (knob == 0) c.fft0_threads = fft_opts[k];
+            if (knob == 1) c.near_waves = near_opts[k];
+            if (knob == 2) c.far_waves = far_opts[k];
+            plan->tune = c;
+            const float ms = time_solves(plan, f, u, s, reps);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    plan->tune = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_file();
+    tune_store(TuneKey{plan->n, plan->p, (int)plan->prec, bucket_of(plan->nb)}, best);
+    return LGF_OK;
+}
+
+lgf_status lgf_plan_get_tuning(lgf_plan_t plan, int32_t* fft0_threads, int32_t* near_waves, int32_t* far_waves) {
+    if (!plan) return fail(LGF_ERR_ARG, "NULL plan");
+    if (fft0_threads) *fft0_threads = plan->tune.fft0_threads;
+    if (near_waves) *near_waves = plan->tune.near_waves;
+    if (far_waves) *far_waves = plan->tune.far_waves;
+    return LGF_OK;
+}
+
+lgf_status lgf_plan_set_tuning(lgf_plan_t plan, int32_t fft0_threads, int32_t near_waves, int32_t far_waves) {
+    if (!plan) return fail(LGF_ERR_ARG, "NULL plan");
+    TuneConfig c;
+    c.fft0_threads = fft0_threads;
+    c.near_waves = near_waves;
+    c.far_waves = far_waves;
+    if (!valid_tune(c)) return fail(LGF_ERR_ARG, "lgf_plan_set_tuning: unsupported variant");
+    plan->tune = c;
+    return LGF_OK;
+}
+
 lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info) {
     if (!plan || !info) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_query");
     std::memset(info, 0, sizeof(*info));
@@ -618,14 +968,17 @@ lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info) {
     info->top_level = plan->Ltop;
     info->near_pairs = plan->near_pairs;
     for (int l = 1; l <= plan->L && l < 16; ++l) {
-        info->far_pairs[l] = (int64_t)plan->lv[l].il_src.size();
+        info->far_pairs[l] = plan->lv[l].pairs();
         info->intervals[l] = plan->lv[l].nint;
     }
     info->intervals[0] = plan->nb;
     info->workspace_bytes = plan->ws_bytes;
     int64_t sb = plan->spectra0 ? plan->spectra0->bytes : 0;
-    for (int l = 1; l <= plan->Ltop; ++l)
+    for (int l = 1; l <= plan->Ltop; ++l) {
         if (plan->lv[l].spectra) sb += plan->lv[l].spectra->bytes;
+        if (plan->lv[l].spectra_csr && plan->lv[l].spectra_csr != plan->lv[l].spectra)
+            sb += plan->lv[l].spectra_csr->bytes;
+    }
     info->spectra_bytes = sb;
     info->precision = plan->prec;
     return LGF_OK;
@@ -653,7 +1006,7 @@ const char* lgf_last_error(void) { return t_err.c_str(); }
 
 lgf_status lgf_profile_enable(lgf_plan_t plan, int32_t max_solves) {
     if (!plan || max_solves < 1) return fail(LGF_ERR_ARG, "lgf_profile_enable: bad arguments");
-    const size_t need = (size_t)max_solves * (LGF_MAX_STEPS + 1);
+    const size_t need = (size_t)max_solves * (2 * LGF_MAX_STEPS + 2);
     while (plan->events.size() < need) {
         hipEvent_t ev;
         if (hipEventCreate(&ev) != hipSuccess) return fail(LGF_ERR_DEVICE, "hipEventCreate failed");
@@ -674,24 +1027,25 @@ lgf_status lgf_profile_collect(lgf_plan_t plan, lgf_step_profile* out, double* s
     if (ns > LGF_MAX_STEPS) return fail(LGF_ERR_ARG, "too many steps");
     out->nsteps = ns;
     out->nsolves = plan->prof_solves;
-    if (plan->prof_cursor > 0 && hipEventSynchronize(plan->events[plan->prof_cursor - 1]) != hipSuccess)
-        return fail(LGF_ERR_DEVICE, "hipEventSynchronize failed");
+    for (int i = 0; i < plan->prof_solves; ++i)
+        if (hipEventSynchronize(plan->events[(size_t)i * (2 * ns + 2) + 1]) != hipSuccess)
+            return fail(LGF_ERR_DEVICE, "hipEventSynchronize failed");
     for (int j = 0; j < ns; ++j) {
         std::snprintf(out->name[j], sizeof(out->name[j]), "%s", plan->steps[j].name.c_str());
         out->bytes[j] = plan->steps[j].bytes;
         out->flops[j] = plan->steps[j].flops;
     }
     for (int i = 0; i < plan->prof_solves; ++i) {
-        hipEvent_t* ev = &plan->events[(size_t)i * (ns + 1)];
+        hipEvent_t* ev = &plan->events[(size_t)i * (2 * ns + 2)];
         for (int j = 0; j < ns; ++j) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev[j], ev[j + 1]) != hipSuccess)
+            if (hipEventElapsedTime(&ms, ev[2 + 2 * j], ev[3 + 2 * j]) != hipSuccess)
                 return fail(LGF_ERR_DEVICE, "hipEventElapsedTime failed");
             out->total_ms[j] += ms;
         }
         if (solve_ms && i < max_out) {
             float ms = 0.f;
-            hipEventElapsedTime(&ms, ev[0], ev[ns]);
+            hipEventElapsedTime(&ms, ev[0], ev[1]);
             solve_ms[i] = ms;
         }
     }

@@ -52,9 +52,7 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 // One wave = 64 consecutive frequencies of one group; the 4 waves of a workgroup share the
 // frequency chunk and its kernel tile in LDS.  The tile has rows for dz in [-2, 2] (the
 // rows with |dz| = 2 are zero) so the source-slab loop needs no branches.
-constexpr int kNearWaves = 4;
-
-template <typename T>
+template <typename T, int kNearWaves>
 __global__ void __launch_bounds__(64 * kNearWaves)
     k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                         const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
@@ -117,13 +115,11 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 // the same source coefficient, so each source spectrum is fetched once per parent.
 constexpr int kFarWC = 8;
 constexpr int kFarRow = kFarWC + 1;  // padded tile row (breaks LDS bank aliasing between rows)
-constexpr int kFarWaves = 8;
-
 // Tile layout: row ((3 - Dx) + 7 (3 - Dy) + 49 (3 - Dz)), column j holds khat^D at frequency
 // w0 + j, and 0 for the 27 offsets with |D|_inf <= 1 (not interaction-list offsets).  With
 // D = c - cs - 2e the row is base(c, e) + (csx + 7 csy + 49 csz): a compile-time offset for
 // the unrolled source child cs, and near pairs add exact zeros.
-template <typename T>
+template <typename T, int kFarWaves>
 __global__ void __launch_bounds__(64 * kFarWaves)
     k_prod_far_sib(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                    const int32_t* __restrict__ child8, const int32_t* __restrict__ src216,
@@ -152,16 +148,36 @@ __global__ void __launch_bounds__(64 * kFarWaves)
     const cplx<T>* fl = fhat + (int64_t)((live ? w : w0) >> 6) * (nitems + 1) * 64 + ((live ? w : w0) & 63);
     const int32_t* sj = src216 + (int64_t)J * 216;
     T ar = T(0), ai = T(0);
+    // double-buffered: the 8 source loads of neighbour e+1 are in flight while e is consumed
+    cplx<T> fa[8], fb[8];
+#pragma unroll
+    for (int cs = 0; cs < 8; ++cs) fa[cs] = fl[(int64_t)sj[cs] * 64];
 #pragma unroll 1
-    for (int e = 0; e < 27; ++e) {
-        const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
-        const cplx<T>* kb = tile + ((3 - cx + 2 * ex) + 7 * (3 - cy + 2 * ey) + 49 * (3 - cz + 2 * ez)) * kFarRow + j;
-        cplx<T> f[8];
+    for (int e = 0; e < 27; e += 2) {
+        if (e + 1 < 27) {
 #pragma unroll
-        for (int cs = 0; cs < 8; ++cs) f[cs] = fl[(int64_t)sj[e * 8 + cs] * 64];
+            for (int cs = 0; cs < 8; ++cs) fb[cs] = fl[(int64_t)sj[(e + 1) * 8 + cs] * 64];
+        }
+        {
+            const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
+            const cplx<T>* kb = tile + ((3 - cx + 2 * ex) + 7 * (3 - cy + 2 * ey) + 49 * (3 - cz + 2 * ez)) * kFarRow + j;
 #pragma unroll
-        for (int cs = 0; cs < 8; ++cs)
-            cmac(ar, ai, f[cs], kb[((cs & 1) + 7 * ((cs >> 1) & 1) + 49 * (cs >> 2)) * kFarRow]);
+            for (int cs = 0; cs < 8; ++cs)
+                cmac(ar, ai, fa[cs], kb[((cs & 1) + 7 * ((cs >> 1) & 1) + 49 * (cs >> 2)) * kFarRow]);
+        }
+        if (e + 1 >= 27) break;
+        if (e + 2 < 27) {
+#pragma unroll
+            for (int cs = 0; cs < 8; ++cs) fa[cs] = fl[(int64_t)sj[(e + 2) * 8 + cs] * 64];
+        }
+        {
+            const int e1 = e + 1;
+            const int ex = e1 % 3 - 1, ey = (e1 / 3) % 3 - 1, ez = e1 / 9 - 1;
+            const cplx<T>* kb = tile + ((3 - cx + 2 * ex) + 7 * (3 - cy + 2 * ey) + 49 * (3 - cz + 2 * ez)) * kFarRow + j;
+#pragma unroll
+            for (int cs = 0; cs < 8; ++cs)
+                cmac(ar, ai, fb[cs], kb[((cs & 1) + 7 * ((cs >> 1) & 1) + 49 * (cs >> 2)) * kFarRow]);
+        }
     }
     const int t = child8[(int64_t)J * 8 + c];
     if (t >= 0 && live) uhat[spec_at(t, w, nitems)] = cplx<T>{ar, ai};
@@ -170,15 +186,18 @@ __global__ void __launch_bounds__(64 * kFarWaves)
 // ------------------------------------------------------------------ generic CSR (top level)
 constexpr int kProdThreads = 256;
 
+// Targets tgt[i] (i = blockIdx.x) with list entries [ptr[i], ptr[i+1]).
 template <typename T>
 __global__ void __launch_bounds__(kProdThreads)
     k_prod_far(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
-               const int32_t* __restrict__ off, cplx<T>* __restrict__ uhat, int S, int nitems, int noff) {
+               const int32_t* __restrict__ off, const int32_t* __restrict__ tgt, cplx<T>* __restrict__ uhat, int S,
+               int nitems, int noff) {
     const int w = blockIdx.y * kProdThreads + threadIdx.x;
-    const int64_t P = blockIdx.x;
+    const int64_t i = blockIdx.x;
     if (w >= S) return;
-    const int e0 = ptr[P], e1 = ptr[P + 1];
+    const int64_t P = tgt[i];
+    const int e0 = ptr[i], e1 = ptr[i + 1];
     T ar = T(0), ai = T(0);
     for (int e = e0; e < e1; ++e) {
         const int q = src[e];
@@ -190,45 +209,67 @@ __global__ void __launch_bounds__(kProdThreads)
     uhat[spec_at(P, w, nitems)] = cplx<T>{ar, ai};
 }
 
+template <typename T, int NW>
+static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
+                          cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, hipStream_t s) {
+    const unsigned grid = xcd_grid(S / 64, (int)((ngroups + NW - 1) / NW));
+    hipLaunchKernelGGL((k_prod_near_grouped<T, NW>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64, uhat, S,
+                       (int)ngroups, (int)nitems);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, hipStream_t s) {
+                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, hipStream_t s) {
     if (ngroups <= 0) return hipSuccess;
     if (S % 64) return hipErrorInvalidValue;
-    const unsigned grid = xcd_grid(S / 64, (int)((ngroups + kNearWaves - 1) / kNearWaves));
-    hipLaunchKernelGGL(k_prod_near_grouped<T>, dim3(grid), dim3(64 * kNearWaves), 0, s, fhat, khat, tgt8, src64, uhat,
-                       S, (int)ngroups, (int)nitems);
+    switch (waves) {
+        case 2: return near_nw<T, 2>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
+        case 8: return near_nw<T, 8>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
+        default: return near_nw<T, 4>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
+    }
+}
+
+template <typename T, int NW>
+static hipError_t far_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
+                         cplx<T>* uhat, int64_t nparents, int64_t nitems, int S, hipStream_t s) {
+    const unsigned grid = xcd_grid((S + kFarWC - 1) / kFarWC, (int)((nparents + NW - 1) / NW));
+    hipLaunchKernelGGL((k_prod_far_sib<T, NW>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, child8, src216, uhat, S,
+                       (int)nparents, (int)nitems);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
-                               hipStream_t s) {
+                               int waves, hipStream_t s) {
     if (nparents <= 0) return hipSuccess;
-    const unsigned grid = xcd_grid((S + kFarWC - 1) / kFarWC, (int)((nparents + kFarWaves - 1) / kFarWaves));
-    hipLaunchKernelGGL(k_prod_far_sib<T>, dim3(grid), dim3(64 * kFarWaves), 0, s, fhat, khat, child8, src216, uhat, S,
-                       (int)nparents, (int)nitems);
-    return hipGetLastError();
+    switch (waves) {
+        case 4: return far_nw<T, 4>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+        case 16: return far_nw<T, 16>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+        default: return far_nw<T, 8>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+    }
 }
 
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
-                           const int32_t* off, cplx<T>* uhat, int64_t ntarget, int noff, int S, hipStream_t s) {
-    if (ntarget <= 0) return hipSuccess;
-    dim3 grid((unsigned)ntarget, (unsigned)((S + kProdThreads - 1) / kProdThreads));
-    hipLaunchKernelGGL(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, uhat, S, (int)ntarget,
-                       noff);
+                           const int32_t* off, const int32_t* tgt, cplx<T>* uhat, int64_t ntgt, int64_t nitems,
+                           int noff, int S, hipStream_t s) {
+    if (ntgt <= 0) return hipSuccess;
+    dim3 grid((unsigned)ntgt, (unsigned)((S + kProdThreads - 1) / kProdThreads));
+    hipLaunchKernelGGL(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, tgt, uhat, S,
+                       (int)nitems, noff);
     return hipGetLastError();
 }
 
 #define LGF_INST(T)                                                                                              \
     template hipError_t launch_prod_near<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,      \
-                                            cplx<T>*, int64_t, int64_t, int, hipStream_t);                       \
+                                            cplx<T>*, int64_t, int64_t, int, int, hipStream_t);                  \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
-                                               cplx<T>*, int64_t, int64_t, int, hipStream_t);                    \
+                                               cplx<T>*, int64_t, int64_t, int, int, hipStream_t);               \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \
-                                           const int32_t*, cplx<T>*, int64_t, int, int, hipStream_t);
+                                           const int32_t*, const int32_t*, cplx<T>*, int64_t, int64_t, int, int, \
+                                           hipStream_t);
 LGF_INST(double)
 LGF_INST(float)
 #undef LGF_INST

@@ -44,9 +44,12 @@ class StepProfile(ctypes.Structure):
     ]
 
 
-EXPORTS = ["lgf_plan_create", "lgf_solve", "lgf_solve_many", "lgf_plan_query", "lgf_plan_destroy",
-           "lgf_set_memory_budget", "lgf_memory_in_use", "lgf_spectra_cache_trim", "lgf_last_error",
-           "lgf_green_table", "lgf_far_kernel", "lgf_profile_enable", "lgf_profile_collect"]
+EXPORTS = ["lgf_plan_create", "lgf_plan_create_batch", "lgf_plan_solve_offsets", "lgf_solve", "lgf_solve_many",
+           "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy", "lgf_plan_autotune", "lgf_plan_get_tuning",
+           "lgf_plan_set_tuning",
+           "lgf_plan_query", "lgf_plan_destroy", "lgf_set_memory_budget", "lgf_memory_in_use",
+           "lgf_spectra_cache_trim", "lgf_last_error", "lgf_green_table", "lgf_far_kernel", "lgf_profile_enable",
+           "lgf_profile_collect"]
 
 _lib = None
 
@@ -60,7 +63,16 @@ def library():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.lgf_plan_create.argtypes = [vp, i64, i32, i32, i32, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.lgf_plan_create_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32, i32, i32,
+                                            ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.lgf_plan_solve_offsets.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)]
         L.lgf_solve.argtypes = [vp, vp, vp, vp]
+        L.lgf_graph_create.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.lgf_graph_launch.argtypes = [vp, vp]
+        L.lgf_graph_destroy.argtypes = [vp]
+        L.lgf_plan_autotune.argtypes = [vp, vp, vp, vp, i32]
+        L.lgf_plan_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.lgf_plan_set_tuning.argtypes = [vp, i32, i32, i32]
         L.lgf_solve_many.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
         L.lgf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.lgf_plan_destroy.argtypes = [vp]
@@ -71,9 +83,9 @@ def library():
         L.lgf_far_kernel.argtypes = [vp, i64, vp]
         L.lgf_profile_enable.argtypes = [vp, i32]
         L.lgf_profile_collect.argtypes = [vp, ctypes.POINTER(StepProfile), vp, i32]
-        for name in ["lgf_plan_create", "lgf_solve", "lgf_solve_many", "lgf_plan_query", "lgf_plan_destroy",
-                     "lgf_set_memory_budget", "lgf_spectra_cache_trim", "lgf_green_table", "lgf_far_kernel",
-                     "lgf_profile_enable", "lgf_profile_collect"]:
+        for name in EXPORTS:
+            if name in ("lgf_memory_in_use", "lgf_last_error"):
+                continue
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -98,18 +110,40 @@ def _require_gpu():
 class Plan:
     """lgf_plan_create / lgf_solve / lgf_plan_query / lgf_plan_destroy."""
 
-    def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None):
+    def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None, _layouts=None):
         _require_gpu()
-        b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
-        self.blocks = b
         self.n, self.p = int(n), int(p)
         self.precision = precision
         prec = {"f64": F64, "f32": F32}[precision]
         self.dtype = torch.float64 if prec == F64 else torch.float32
         h = ctypes.c_void_p()
-        _check(library().lgf_plan_create(b.ctypes.data, b.shape[0], self.n, self.p, int(levels), prec,
-                                         _stream_handle(stream), ctypes.byref(h)))
+        if _layouts is None:
+            b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+            _check(library().lgf_plan_create(b.ctypes.data, b.shape[0], self.n, self.p, int(levels), prec,
+                                             _stream_handle(stream), ctypes.byref(h)))
+        else:
+            lay = [np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(-1, 3)) for x in _layouts]
+            ptrs = (ctypes.c_void_p * len(lay))(*[x.ctypes.data for x in lay])
+            nbs = (ctypes.c_int64 * len(lay))(*[x.shape[0] for x in lay])
+            _check(library().lgf_plan_create_batch(ptrs, nbs, len(lay), self.n, self.p, int(levels), prec,
+                                                   _stream_handle(stream), ctypes.byref(h)))
+            b = np.concatenate(lay, axis=0)
+        self.blocks = b
         self._h = h
+        cnt = ctypes.c_int32()
+        _check(library().lgf_plan_solve_offsets(h, None, 0, ctypes.byref(cnt)))
+        offs = (ctypes.c_int64 * (cnt.value + 1))()
+        _check(library().lgf_plan_solve_offsets(h, offs, cnt.value + 1, ctypes.byref(cnt)))
+        self.offsets = [int(x) for x in offs]
+
+    @classmethod
+    def batch(cls, layouts, n, p, levels=0, precision="f64", stream=None):
+        """One plan over independent layouts (lgf_plan_create_batch); fields concatenated in order."""
+        return cls(None, n, p, levels, precision, stream, _layouts=list(layouts))
+
+    def split(self, x):
+        """Views of a batch field [sum N_B, n, n, n] per problem."""
+        return [x[a:b] for a, b in zip(self.offsets[:-1], self.offsets[1:])]
 
     @property
     def handle(self):
@@ -131,6 +165,34 @@ class Plan:
         _check(library().lgf_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                    _stream_handle(stream)))
         return u
+
+    def _check_field(self, x, name):
+        if not (x.is_cuda and x.is_contiguous() and x.dtype == self.dtype and tuple(x.shape) == self.shape()):
+            raise ValueError("%s must be a contiguous %s device tensor of shape %s" % (name, self.dtype, self.shape()))
+
+    def graph(self, f, u, stream=None):
+        """Capture one solve reading f and writing u as a HIP graph (lgf_graph_create)."""
+        self._check_field(f, "f")
+        self._check_field(u, "u")
+        return Graph(self, f, u, stream)
+
+    def autotune(self, f, u=None, reps=3, stream=None):
+        """Pick the fastest kernel variants for this plan (lgf_plan_autotune); returns the choice."""
+        self._check_field(f, "f")
+        if u is None:
+            u = torch.empty_like(f)
+        self._check_field(u, "u")
+        _check(library().lgf_plan_autotune(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                           _stream_handle(stream), int(reps)))
+        return self.tuning()
+
+    def tuning(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(library().lgf_plan_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(fft0_threads=a.value, near_waves=b.value, far_waves=c.value)
+
+    def set_tuning(self, fft0_threads=0, near_waves=4, far_waves=8):
+        _check(library().lgf_plan_set_tuning(self._h, int(fft0_threads), int(near_waves), int(far_waves)))
 
     def info(self):
         inf = PlanInfo()
@@ -157,6 +219,36 @@ class Plan:
     def close(self):
         if self._h is not None:
             library().lgf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """An executable HIP graph of one solve (lgf_graph_create / launch / destroy).
+
+    It keeps references to its plan and buffers so they outlive the graph."""
+
+    def __init__(self, plan, f, u, stream=None):
+        self.plan, self.f, self.u = plan, f, u
+        h = ctypes.c_void_p()
+        _check(library().lgf_graph_create(plan.handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                          _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        if self._h is None:
+            raise RuntimeError("graph destroyed")
+        _check(library().lgf_graph_launch(self._h, _stream_handle(stream)))
+        return self.u
+
+    def close(self):
+        if self._h is not None:
+            library().lgf_graph_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,212 @@
+"""GPU tests of batched solves, HIP-graph replay and the kernel-variant autotuner.
+
+A batch plan is the union of independent per-layout trees, so every problem of a
+batch must come out exactly as it does from its own plan: the per-target summation
+orders of all kernels are the same in both.  The comparison is therefore bitwise,
+and one member of each batch is also checked against the oracle.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import flgf
+from paper_1402_6081_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_1402_6081_amd.lgf as L
+    L.library()
+    return L
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _layouts(seed, sizes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in sizes:
+        if s == "cube2":
+            out.append(W.cube_layout(2))
+        else:
+            out.append(W.eden_layout(int(s), rng))
+    return out
+
+
+def _fields(layouts, n, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((b.shape[0], n, n, n)) for b in layouts]
+
+
+BATCHES = [
+    # label, sizes, n, p, levels, precision
+    ("mixed_n8_p6_full_f64", [40, 1, 9, "cube2", 120, 3], 8, 6, 0, "f64"),
+    ("mixed_n8_p6_full_f32", [40, 1, 9, "cube2", 120, 3], 8, 6, 0, "f32"),
+    ("mixed_n4_p5_L2_f64", [60, 7, "cube2", 25], 4, 5, 2, "f64"),
+    ("mixed_n8_p9_L3_f64", [90, 2, 30], 8, 9, 3, "f64"),
+    ("many_n4_p3_full_f32", [3, 5, 8, 13, 21, 34, 55, 89, 1, 2], 4, 3, 0, "f32"),
+]
+
+
+@pytest.mark.parametrize("case", BATCHES, ids=[c[0] for c in BATCHES])
+def test_batch_equals_individual_solves(L, case):
+    label, sizes, n, p, levels, prec = case
+    seed = zlib.crc32(label.encode())
+    _say("case: batch", label, "seed", seed)
+    lays = _layouts(seed, sizes)
+    fs = _fields(lays, n, seed + 1)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    bp = L.Plan.batch(lays, n, p, levels, prec)
+    assert bp.offsets == list(np.concatenate([[0], np.cumsum([b.shape[0] for b in lays])]))
+    fb = torch.from_numpy(np.concatenate(fs)).to("cuda:0", dt)
+    ub = bp.solve(fb)
+    torch.cuda.synchronize()
+    parts = [x.double().cpu().numpy() for x in bp.split(ub)]
+    for i, (b, f) in enumerate(zip(lays, fs)):
+        pl = L.Plan(b, n, p, levels, prec)
+        ui = pl.solve(torch.from_numpy(f).to("cuda:0", dt))
+        torch.cuda.synchronize()
+        ui = ui.double().cpu().numpy()
+        pl.close()
+        assert np.array_equal(parts[i], ui), "problem %d (%d blocks) differs: %g" % (
+            i, b.shape[0], np.max(np.abs(parts[i] - ui)))
+    bp.close()
+    # the largest member against the oracle (FP64 batches)
+    if prec == "f64":
+        k = int(np.argmax([b.shape[0] for b in lays]))
+        ref = flgf.solve(lays[k], fs[k], n, p, levels)
+        assert rel(parts[k], ref) < 1e-11
+
+
+def test_batch_info_sums_members(L):
+    _say("case: batch plan summary")
+    lays = _layouts(7, [30, 12, 5])
+    bp = L.Plan.batch(lays, 8, 6, 0, "f64")
+    inf = bp.info()
+    near = far1 = 0
+    for b in lays:
+        pl = L.Plan(b, 8, 6, 0, "f64")
+        i = pl.info()
+        near += i["near_pairs"]
+        far1 += i["far_pairs"][1]
+        pl.close()
+    assert inf["nblocks"] == sum(b.shape[0] for b in lays)
+    assert inf["near_pairs"] == near
+    assert inf["far_pairs"][1] == far1
+    bp.close()
+
+
+GRAPH_CASES = [
+    ("eden60_n8_p6_f64", 60, 8, 6, "f64"),       # small plan: far chain on the second stream
+    ("eden400_n8_p6_f32", 400, 8, 6, "f32"),     # large plan: single stream
+    ("eden300_n4_p5_L2_f64", 300, 4, 5, "f64"),  # truncated top level (CSR Prod)
+]
+
+
+@pytest.mark.parametrize("case", GRAPH_CASES, ids=[c[0] for c in GRAPH_CASES])
+def test_graph_replays_match_eager(L, case):
+    label, nb, n, p, prec = case
+    levels = 2 if "_L2" in label else 0
+    seed = zlib.crc32(label.encode())
+    _say("case: graph", label, "seed", seed)
+    rng = np.random.default_rng(seed)
+    blocks = W.eden_layout(nb, rng)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = L.Plan(blocks, n, p, levels, prec)
+    f = torch.zeros(plan.shape(), dtype=dt, device="cuda:0")
+    u = torch.zeros_like(f)
+    g = plan.graph(f, u)
+    for r in range(4):
+        fr = torch.from_numpy(rng.standard_normal(plan.shape())).to("cuda:0", dt)
+        f.copy_(fr)
+        u.fill_(float("nan"))
+        g.launch()
+        torch.cuda.synchronize()
+        got = u.clone()
+        # eager work between replays: an unrelated reduction and an eager solve
+        junk = torch.randn(1 << 20, device="cuda:0").sum().item()
+        assert np.isfinite(junk)
+        ref = plan.solve(fr)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), "replay %d differs" % r
+    g.close()
+    plan.close()
+
+
+def test_batch_graph(L):
+    _say("case: graph of a batch plan")
+    lays = _layouts(11, [50, 4, 17])
+    fs = _fields(lays, 8, 12)
+    bp = L.Plan.batch(lays, 8, 6, 0, "f32")
+    f = torch.from_numpy(np.concatenate(fs)).to("cuda:0", torch.float32)
+    u = torch.empty_like(f)
+    g = bp.graph(f, u)
+    for _ in range(3):
+        u.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        ref = bp.solve(f)
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref)
+    g.close()
+    bp.close()
+
+
+def test_autotune_keeps_results(L):
+    _say("case: autotune eden200 n8 p8 f32")
+    rng = np.random.default_rng(5)
+    blocks = W.eden_layout(200, rng)
+    plan = L.Plan(blocks, 8, 8, 0, "f32")
+    f = torch.from_numpy(rng.standard_normal(plan.shape())).to("cuda:0", torch.float32)
+    before = plan.solve(f)
+    torch.cuda.synchronize()
+    choice = plan.autotune(f, reps=2)
+    assert choice["fft0_threads"] in (0, 128, 256, 512)
+    assert choice["near_waves"] in (2, 4, 8)
+    assert choice["far_waves"] in (4, 8, 16)
+    after = plan.solve(f)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+    # a new plan of the same shape class picks the remembered choice
+    plan2 = L.Plan(blocks, 8, 8, 0, "f32")
+    assert plan2.tuning() == choice
+    plan2.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_variant_same_bits(L, prec):
+    """All kernel variants the autotuner chooses among give identical results."""
+    rng = np.random.default_rng(9)
+    blocks = W.eden_layout(150, rng)
+    for n in (8, 16):
+        _say("case: kernel variants", prec, "n", n)
+        plan = L.Plan(blocks, n, 6, 0, prec)
+        f = torch.from_numpy(rng.standard_normal(plan.shape())).to("cuda:0", plan.dtype)
+        plan.set_tuning(0, 4, 8)
+        ref = plan.solve(f)
+        torch.cuda.synchronize()
+        for ft in (0, 128, 256, 512):
+            for nw in (2, 4, 8):
+                for fw in (4, 8, 16):
+                    plan.set_tuning(ft, nw, fw)
+                    got = plan.solve(f)
+                    torch.cuda.synchronize()
+                    assert torch.equal(ref, got), (ft, nw, fw)
+        with pytest.raises(L.LGFError):
+            plan.set_tuning(64, 4, 8)
+        plan.close()
