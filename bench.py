@@ -7,9 +7,12 @@ workload is also solved on the FP32 path (FP64 tables and final add), whose rate
 against the FP64 result and latencies are reported next to the FP64 numbers.
 
 Timing: W untimed warm-up solves, then K solves bracketed by device synchronisation; the
-inputs are resident in HBM before the timed region.  Every step of every timed solve is
-bracketed by HIP events on the solve's own stream (lgf_profile_*), which gives per-kernel
-device times (the roofline entry uses the dominant one) and per-solve latencies (p50/p99).
+inputs are resident in HBM before the timed region.  Two passes per precision:
+  * eager lgf_solve calls with every step bracketed by HIP events on the stream it runs on
+    (lgf_profile_*): per-kernel device times (the roofline entry uses the dominant one);
+  * the same solve captured once as a HIP graph (lgf_graph_create) and launched K times:
+    the reported rate (value) and per-solve latencies (p50/p99, events around each launch).
+A third pass times the batched workload: 64 independent Eden layouts in one batch plan.
 
 cpu_baseline: the oracle (step-by-step FLGF in numpy, single thread) timed on the host
 on the full workload (plan and pre-computation excluded).
@@ -44,6 +47,27 @@ def _time_solves(plan, f, u, steps, warmup):
     t1 = time.perf_counter()
     prof = plan.profile_collect(max(steps, 1))
     return t1 - t0, prof
+
+
+def _time_graph(plan, f, u, steps, warmup):
+    """Whole solves as one HIP-graph launch each; per-launch device latency from events."""
+    import torch
+    g = plan.graph(f, u)
+    for _ in range(warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        g.launch()
+        b.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    g.close()
+    return t1 - t0, lat
 
 
 def _roofline(prof, dtype_peak_tflops):
@@ -93,6 +117,62 @@ def cpu_baseline(cfg, budget_s=30.0):
                       "excluded, %.1f s" % (cfg["name"], npts, dt)}
 
 
+def _measure(plan, f, u, steps, warmup):
+    """Eager solves with per-step events (breakdown, roofline), then graph launches (rate)."""
+    dt_e, prof = _time_solves(plan, f, u, steps, warmup)
+    dt_g, lat = _time_graph(plan, f, u, steps, warmup)
+    return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat)
+
+
+def _pct(x):
+    return {"p50": round(float(np.percentile(x, 50)), 5), "p99": round(float(np.percentile(x, 99)), 5)}
+
+
+def batch_bench(L, W, steps, warmup, seed=4):
+    """64 independent Eden layouts of 8..512 blocks of 16^3, p = 8, FP32: one batch plan,
+    one graph launch per batch, against the same 64 solves issued as separate plans."""
+    import torch
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(8, 513, size=64)
+    lays = [W.eden_layout(int(s), rng) for s in sizes]
+    fs = []
+    for b in lays:
+        fb, _ = W.zero_mean_gaussians(b, 16, rng, max(1, b.shape[0] // 8))
+        fs.append(fb)
+    npts = int(sum(x.size for x in fs))
+    dev = torch.device("cuda:0")
+    fcat = torch.from_numpy(np.concatenate(fs)).to(dev, torch.float32)
+    ucat = torch.empty_like(fcat)
+    t0 = time.perf_counter()
+    bp = L.Plan.batch(lays, 16, 8, 0, "f32")
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    dt_g, lat = _time_graph(bp, fcat, ucat, steps, warmup)
+    # the same 64 problems as 64 plans enqueued back to back (no batching)
+    plans = [L.Plan(b, 16, 8, 0, "f32") for b in lays]
+    fl = [x.contiguous() for x in bp.split(fcat)]
+    ul = [torch.empty_like(x) for x in fl]
+    for _ in range(warmup):
+        L.solve_many(plans, fl, ul)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        L.solve_many(plans, fl, ul)
+    torch.cuda.synchronize()
+    dt_sep = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(bp.split(ucat), ul))
+    for pl in plans:
+        pl.close()
+    bp.close()
+    return {"workload": "64 Eden layouts, 8..512 blocks of 16^3 (seed %d), p=8, f32" % seed,
+            "points": npts, "blocks": int(sum(b.shape[0] for b in lays)),
+            "value": round(npts * steps / dt_g, 1), "unit": "grid points solved/s",
+            "ms_per_batch": round(dt_g / steps * 1e3, 5), "latency_ms": _pct(lat),
+            "separate_plans_value": round(npts * steps / dt_sep, 1),
+            "separate_plans_ms": round(dt_sep / steps * 1e3, 5),
+            "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +180,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--breakdown", default=None, help="write the per-step breakdown JSON here")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -120,51 +201,58 @@ def main():
     plan = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], "f64")
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t_plan
-    dt, prof = _time_solves(plan, f64, u64, args.steps, args.warmup)
-    value = npts * args.steps / dt
-    lat = prof["solve_ms"]
+    m = _measure(plan, f64, u64, args.steps, args.warmup)
+    print("fp64 measured", flush=True, file=sys.stderr)
     info = plan.info()
 
     result = {
         "metric": "grid points solved/s, FP32 vs FP64 path at rel err <=1e-6; p50/p99 solve latency",
-        "value": round(value, 1),
+        "value": round(npts * args.steps / m["dt_graph"], 1),
         "unit": "grid points solved/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "ms_per_step": round(m["dt_graph"] / args.steps * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "points": int(npts), "blocks": int(info["nblocks"]),
-                   "n": cfg["n"], "p": cfg["p"], "levels": cfg["levels"],
+                   "n": cfg["n"], "p": cfg["p"], "levels": cfg["levels"], "launch": "hip graph per solve",
                    "source": "32 seeded Gaussians, sigma U[2,6], zero net source"},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
-                       "p99": round(float(np.percentile(lat, 99)), 5)},
+        "latency_ms": _pct(m["lat_graph"]),
+        "eager": {"value": round(npts * args.steps / m["dt_eager"], 1),
+                  "ms_per_step": round(m["dt_eager"] / args.steps * 1e3, 5),
+                  "latency_ms": _pct(m["prof"]["solve_ms"]),
+                  "note": "lgf_solve per step, with per-step profiling events"},
         "plan_s": round(t_plan, 3),
-        "roofline": _roofline(prof, FP64_PEAK_TFLOPS),
+        "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS),
     }
-    breakdown = {"fp64": _breakdown(prof)}
+    breakdown = {"fp64": _breakdown(m["prof"])}
     u64_host = u64.cpu().numpy()
 
     if not args.no_fp32:
         f32 = f64.float()
         u32 = torch.empty_like(f32)
         plan32 = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], "f32")
-        dt32, prof32 = _time_solves(plan32, f32, u32, args.steps, args.warmup)
+        m32 = _measure(plan32, f32, u32, args.steps, args.warmup)
+        print("fp32 measured", flush=True, file=sys.stderr)
         u32_host = u32.double().cpu().numpy()
         err = float(np.max(np.abs(u32_host - u64_host)) / np.max(np.abs(u64_host)))
-        result["fp32"] = {"value": round(npts * args.steps / dt32, 1), "unit": "grid points solved/s",
-                          "ms_per_step": round(dt32 / args.steps * 1e3, 5),
+        result["fp32"] = {"value": round(npts * args.steps / m32["dt_graph"], 1), "unit": "grid points solved/s",
+                          "ms_per_step": round(m32["dt_graph"] / args.steps * 1e3, 5),
                           "rel_linf_err_vs_fp64": err,
-                          "latency_ms": {"p50": round(float(np.percentile(prof32["solve_ms"], 50)), 5),
-                                         "p99": round(float(np.percentile(prof32["solve_ms"], 99)), 5)},
-                          "roofline": _roofline(prof32, FP32_PEAK_TFLOPS)}
-        breakdown["fp32"] = _breakdown(prof32)
+                          "latency_ms": _pct(m32["lat_graph"]),
+                          "eager_ms_per_step": round(m32["dt_eager"] / args.steps * 1e3, 5),
+                          "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS)}
+        breakdown["fp32"] = _breakdown(m32["prof"])
         plan32.close()
     plan.close()
+
+    if not args.no_batch:
+        result["batch"] = batch_bench(L, W, max(5, args.steps // 5), 2)
+        print("batch measured", flush=True, file=sys.stderr)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg)

@@ -83,14 +83,31 @@ def points_of(blocks, n):
     return b[:, None, None, None, :] * n + local[None]
 
 
+def _axis_factors(blocks, n, centres, sigmas):
+    """Per-block 1D factors of exp(-|x - c|^2 / (2 sigma^2)) = ex(x) ey(y) ez(z):
+    E[d] has shape [N_B, G, n] (axis d = x, y, z)."""
+    b = np.asarray(blocks, dtype=np.int64)
+    c = np.atleast_2d(np.asarray(centres, dtype=np.float64))
+    s = np.atleast_1d(np.asarray(sigmas, dtype=np.float64))
+    out = []
+    for d in range(3):
+        coord = (b[:, d, None] * n + np.arange(n)[None, :]).astype(np.float64)  # [N_B, n]
+        out.append(np.exp(-(coord[:, None, :] - c[None, :, d, None]) ** 2 / (2.0 * s[None, :, None] ** 2)))
+    return out
+
+
+def _sum_separable(E, amps):
+    """f[b, z, y, x] = sum_g amps[g] ez[b, g, z] ey[b, g, y] ex[b, g, x]."""
+    ex, ey, ez = E
+    nb, g, n = ex.shape
+    zy = (ez * np.asarray(amps)[None, :, None])[:, :, :, None] * ey[:, :, None, :]  # [N_B, G, z, y]
+    zy = zy.reshape(nb, g, n * n).transpose(0, 2, 1)                               # [N_B, zy, G]
+    return np.matmul(zy, ex).reshape(nb, n, n, n)
+
+
 def gaussian_source(blocks, n, centres, sigmas, amps):
     """sum_g amps[g] exp(-|x - c_g|^2 / (2 sigma_g^2)) sampled on the layout's points."""
-    P = points_of(blocks, n).astype(np.float64)
-    f = np.zeros(P.shape[:-1])
-    for c, s, a in zip(np.atleast_2d(centres), np.atleast_1d(sigmas), np.atleast_1d(amps)):
-        d2 = np.sum((P - np.asarray(c)[None, None, None, None, :]) ** 2, axis=-1)
-        f += a * np.exp(-d2 / (2.0 * s * s))
-    return f
+    return _sum_separable(_axis_factors(blocks, n, centres, sigmas), amps)
 
 
 def zero_mean_gaussians(blocks, n, rng, count, sigma_lo=2.0, sigma_hi=6.0):
@@ -104,17 +121,10 @@ def zero_mean_gaussians(blocks, n, rng, count, sigma_lo=2.0, sigma_hi=6.0):
     centres = lo + rng.random((count, 3)) * (hi - lo)
     sigmas = rng.uniform(sigma_lo, sigma_hi, count)
     amps = rng.standard_normal(count)
-    P = points_of(blocks, n).astype(np.float64)
-    bumps = []
-    for c, s in zip(centres, sigmas):
-        d2 = np.sum((P - c[None, None, None, None, :]) ** 2, axis=-1)
-        bumps.append(np.exp(-d2 / (2.0 * s * s)))
-    mass = np.array([bb.sum() for bb in bumps])
+    E = _axis_factors(blocks, n, centres, sigmas)
+    mass = np.einsum("bg,bg,bg->g", E[0].sum(axis=2), E[1].sum(axis=2), E[2].sum(axis=2))
     amps = amps - mass * (mass @ amps) / (mass @ mass)
-    f = np.zeros(P.shape[:-1])
-    for a, bb in zip(amps, bumps):
-        f += a * bb
-    return f, dict(centres=centres, sigmas=sigmas, amps=amps)
+    return _sum_separable(E, amps), dict(centres=centres, sigmas=sigmas, amps=amps)
 
 
 def _random_rotation(rng):
