@@ -55,7 +55,7 @@ typedef enum {
     LGF_ERR_OOM = 3,     /* device allocation failed                                     */
     LGF_ERR_BUDGET = 4,  /* the plan would exceed the configured device-memory budget    */
     LGF_ERR_DEVICE = 5,  /* a HIP runtime call or kernel launch failed                   */
-    LGF_ERR_BUSY = 6     /* reserved for the request server                              */
+    LGF_ERR_BUSY = 6     /* the request server's queue is full                          */
 } lgf_status;
 
 typedef enum { LGF_F64 = 0, LGF_F32 = 1 } lgf_precision;
@@ -94,6 +94,15 @@ typedef struct {
  */
 lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p,
                            int32_t levels, lgf_precision prec, void* hip_stream, lgf_plan_t* out);
+
+/*
+ * Host-only preview of lgf_plan_create: builds the tree and lists of the layout (no device
+ * work, no allocation on the device) and fills *info as lgf_plan_query would, with
+ * workspace_bytes = the device bytes the plan would own and spectra_bytes = 0.  For
+ * admission decisions and inspection.  Errors: LGF_ERR_ARG, LGF_ERR_LAYOUT, LGF_ERR_OOM.
+ */
+lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p,
+                             int32_t levels, lgf_precision prec, lgf_plan_info* info);
 
 /*
  * u = G * f on the plan's layout (Steps 1-3 of Sec. 3.1).  f, u: DEVICE pointers as
@@ -214,6 +223,76 @@ typedef struct {
 
 lgf_status lgf_profile_enable(lgf_plan_t plan, int32_t max_solves);
 lgf_status lgf_profile_collect(lgf_plan_t plan, lgf_step_profile* out, double* solve_ms, int32_t max_out);
+
+/*
+ * Request server: independent solves submitted one by one (each u = G * f on its own
+ * layout, Sec. 3.1) and run concurrently on one GPU.
+ *   - A dispatcher thread owned by the server takes requests in submission order.  A
+ *     request starts when one of max_slots streams is free and its plan fits the HBM
+ *     budget; it is retired when its completion event has fired.
+ *   - Plans (lists and workspace) stay resident, cached by layout, and are reused by
+ *     later requests with the same block coordinates; kernel spectra are shared by all
+ *     plans with equal (n, p, precision).  A plan that does not fit the budget evicts
+ *     idle cached plans (least recently used first), else waits for running requests.
+ *     A request whose plan alone exceeds the budget fails with LGF_ERR_BUDGET.
+ *   - Results do not depend on what else is running: every request computes exactly
+ *     what lgf_solve computes on a plan of its own layout.
+ * budget_bytes counts the resident plan workspaces plus the shared kernel spectra
+ * (0 = unlimited).  max_queue bounds the waiting requests (0 = unbounded); a submit to
+ * a full queue returns LGF_ERR_BUSY.  The server serves one (n, p, levels, precision).
+ */
+typedef struct lgf_server_s* lgf_server_t;
+
+typedef struct {
+    int64_t budget_bytes;  /* HBM budget of the server's resident state, 0 = unlimited */
+    int32_t max_slots;     /* requests running at once (one stream each), 1..16         */
+    int32_t max_queue;     /* waiting requests accepted, 0 = unbounded                  */
+    int32_t n, p, levels;  /* as for lgf_plan_create                                    */
+    int32_t precision;     /* lgf_precision                                             */
+} lgf_server_config;
+
+typedef struct {
+    int32_t status;     /* LGF_OK, or the error that ended the request             */
+    int64_t nblocks;    /* blocks of the request's layout                          */
+    double latency_ms;  /* submit -> completion observed (host clock)              */
+    double queue_ms;    /* submit -> launch                                        */
+    double device_ms;   /* solve time on the device (events around the solve)      */
+} lgf_request_result;
+
+typedef struct {
+    int64_t completed, failed, queued;  /* requests                                       */
+    int64_t points;                     /* grid points of the completed requests           */
+    int64_t plans_created, plans_evicted;
+    int64_t plan_bytes, spectra_bytes;  /* resident device bytes                           */
+    double latency_p50_ms, latency_p99_ms, latency_max_ms;  /* of the completed requests   */
+    double points_per_s;                /* points / (first submit -> last completion)      */
+} lgf_server_stats_t;
+
+/* Start a server on the current device.  Errors: LGF_ERR_ARG (bad config), LGF_ERR_DEVICE. */
+lgf_status lgf_server_create(const lgf_server_config* cfg, lgf_server_t* out);
+
+/*
+ * Queue one solve.  block_ijk: HOST layout [nblocks][3] (copied); f, u: DEVICE fields of
+ * the server's precision in the layout's order, caller-owned, kept alive and untouched until
+ * the request completes.  *ticket identifies the request.  Non-blocking.
+ * Errors: LGF_ERR_ARG, LGF_ERR_BUSY (queue full).  Layout errors are reported per request.
+ */
+lgf_status lgf_server_submit(lgf_server_t server, const int32_t* block_ijk, int64_t nblocks, const void* f,
+                             void* u, int64_t* ticket);
+
+/* *done = 1 and *result filled (HOST, may be NULL) when the request has finished; a
+ * finished ticket is then released.  Errors: LGF_ERR_ARG (unknown ticket). */
+lgf_status lgf_server_poll(lgf_server_t server, int64_t ticket, int32_t* done, lgf_request_result* result);
+
+/* Block until the request has finished, fill *result and release the ticket. */
+lgf_status lgf_server_wait(lgf_server_t server, int64_t ticket, lgf_request_result* result);
+
+/* Counters and latency percentiles since creation or the last reset. */
+lgf_status lgf_server_stats(lgf_server_t server, lgf_server_stats_t* out);
+lgf_status lgf_server_reset_stats(lgf_server_t server);
+
+/* Finish every queued request, then release the server's plans and streams. */
+lgf_status lgf_server_destroy(lgf_server_t server);
 
 /* Thread-local message for the last failure on this thread ("" if none). */
 const char* lgf_last_error(void);

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/lgf.h"
 #include "lgf_device.h"
 
 namespace lgfdev {
@@ -105,5 +106,11 @@ bool budget_reserve(int64_t bytes);
 void budget_release(int64_t bytes);
 int64_t budget_in_use();
 void budget_set(int64_t bytes);
+
+// Workspace bytes a plan of this layout would own (host-only work: builds the lists).
+lgf_status plan_estimate(const int32_t* ijk, int64_t nblocks, int n, int p, int levels, lgf_precision prec,
+                         int64_t* bytes);
+// Sets the calling thread's lgf_last_error message.
+void set_last_error(const std::string& msg);
 
 }  // namespace lgfdev

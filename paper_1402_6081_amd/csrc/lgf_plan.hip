@@ -310,6 +310,28 @@ struct DevBuf {
     int64_t bytes = 0;
 };
 
+// Device bytes of a plan's workspace (lists, matrices, node values and spectra of every
+// level it solves on); the shared kernel spectra are not included.
+int64_t workspace_need(const HostPlan& H, lgf_precision prec) {
+    const int n = H.n, p = H.p;
+    const int64_t esz = prec == LGF_F64 ? sizeof(double) : sizeof(float);
+    const int64_t usz = 8;
+    const int64_t S0 = spec_padded(2 * n * 2 * n * (n + 1));
+    const int64_t S1 = spec_padded(2 * p * 2 * p * (p + 1));
+    const int64_t p3 = (int64_t)p * p * p;
+    const int64_t nb = H.nb;
+    const int topc = std::min(H.Ltop + 1, H.L);
+    int64_t need = H.ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (2 * nb + 1) * S0 * 2 * esz;
+    for (int l = 1; l <= H.Ltop; ++l) {
+        const HostLevel& h = H.lv[l];
+        need += h.nint * p3 * (esz + usz);
+        if (h.pairs() > 0) need += (2 * h.nint + 1) * S1 * 2 * esz;
+        need += (int64_t)(h.csr_tgt.size() + h.csr_ptr.size() + 2 * h.csr_src.size()) * 4;
+    }
+    for (int l = 2; l <= topc && H.Ltop >= 1; ++l) need += H.lv[l].nint * 224 * 4;
+    return need;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ the plan
@@ -606,14 +628,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     const int64_t p3 = (int64_t)p * p * p;
     const int64_t nb = H.nb;
     const int topc = std::min(pl->Ltop + 1, H.L);  // highest level whose child8 / src216 is used
-    int64_t need = H.ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (2 * nb + 1) * S0 * 2 * esz;
-    for (int l = 1; l <= pl->Ltop; ++l) {
-        const HostLevel& h = H.lv[l];
-        need += h.nint * p3 * (esz + usz);
-        if (h.pairs() > 0) need += (2 * h.nint + 1) * S1 * 2 * esz;
-        need += (int64_t)(h.csr_tgt.size() + h.csr_ptr.size() + 2 * h.csr_src.size()) * 4;
-    }
-    for (int l = 2; l <= topc && pl->Ltop >= 1; ++l) need += H.lv[l].nint * 224 * 4;
+    const int64_t need = workspace_need(H, prec);
     if (!budget_reserve(need)) return fail(LGF_ERR_BUDGET, "plan workspace exceeds the device-memory budget");
     pl->ws_bytes = need;
     bool ok = dev_alloc(pl, &pl->d_g0_tgt8, H.ngroups0 * 8 * 4) &&
@@ -762,6 +777,21 @@ bool budget_reserve(int64_t bytes) {
 void budget_release(int64_t bytes) { g_used.fetch_sub(bytes); }
 int64_t budget_in_use() { return g_used.load(); }
 void budget_set(int64_t bytes) { g_budget.store(bytes); }
+
+lgf_status plan_estimate(const int32_t* ijk, int64_t nblocks, int n, int p, int levels, lgf_precision prec,
+                         int64_t* bytes) {
+    try {
+        HostPlan H;
+        lgf_status st = build_host(ijk, nblocks, n, p, levels, H);
+        if (st != LGF_OK) return st;
+        *bytes = workspace_need(H, prec);
+        return LGF_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LGF_ERR_OOM, "host allocation failed");
+    }
+}
+
+void set_last_error(const std::string& msg) { t_err = msg; }
 }  // namespace lgfdev
 
 // ============================================================== C ABI
@@ -833,6 +863,39 @@ lgf_status lgf_plan_create_batch(const int32_t* const* layouts, const int64_t* n
         return fail(LGF_ERR_OOM, "host allocation failed");
     } catch (...) {
         return fail(LGF_ERR_DEVICE, "unexpected failure while building the batch plan");
+    }
+}
+
+lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
+                             lgf_precision prec, lgf_plan_info* info) {
+    t_err.clear();
+    if (!info || !block_ijk) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_estimate");
+    if (nblocks < 1) return fail(LGF_ERR_LAYOUT, "empty layout");
+    if (nblocks > (int64_t)1 << 30) return fail(LGF_ERR_ARG, "too many blocks");
+    lgf_status st = check_args(n, p, prec);
+    if (st != LGF_OK) return st;
+    try {
+        HostPlan H;
+        st = build_host(block_ijk, nblocks, n, p, levels, H);
+        if (st != LGF_OK) return st;
+        std::memset(info, 0, sizeof(*info));
+        info->nblocks = H.nb;
+        info->npoints = H.nb * (int64_t)n * n * n;
+        info->n = n;
+        info->p = p;
+        info->levels = H.L;
+        info->top_level = H.Ltop;
+        info->near_pairs = H.near_pairs;
+        info->intervals[0] = H.nb;
+        for (int l = 1; l <= H.L && l < 16; ++l) {
+            info->far_pairs[l] = H.lv[l].pairs();
+            info->intervals[l] = H.lv[l].nint;
+        }
+        info->workspace_bytes = workspace_need(H, prec);
+        info->precision = prec;
+        return LGF_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LGF_ERR_OOM, "host allocation failed");
     }
 }
 

@@ -36,6 +36,25 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("p", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("nblocks", ctypes.c_int64), ("latency_ms", ctypes.c_double),
+                ("queue_ms", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("points", ctypes.c_int64), ("plans_created", ctypes.c_int64), ("plans_evicted", ctypes.c_int64),
+                ("plan_bytes", ctypes.c_int64), ("spectra_bytes", ctypes.c_int64),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("points_per_s", ctypes.c_double)]
+
+
 class StepProfile(ctypes.Structure):
     _fields_ = [
         ("nsteps", ctypes.c_int32), ("nsolves", ctypes.c_int32),
@@ -44,9 +63,10 @@ class StepProfile(ctypes.Structure):
     ]
 
 
-EXPORTS = ["lgf_plan_create", "lgf_plan_create_batch", "lgf_plan_solve_offsets", "lgf_solve", "lgf_solve_many",
+EXPORTS = ["lgf_plan_create", "lgf_plan_estimate", "lgf_plan_create_batch", "lgf_plan_solve_offsets", "lgf_solve", "lgf_solve_many",
            "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy", "lgf_plan_autotune", "lgf_plan_get_tuning",
-           "lgf_plan_set_tuning",
+           "lgf_plan_set_tuning", "lgf_server_create", "lgf_server_submit", "lgf_server_poll", "lgf_server_wait",
+           "lgf_server_stats", "lgf_server_reset_stats", "lgf_server_destroy",
            "lgf_plan_query", "lgf_plan_destroy", "lgf_set_memory_budget", "lgf_memory_in_use",
            "lgf_spectra_cache_trim", "lgf_last_error", "lgf_green_table", "lgf_far_kernel", "lgf_profile_enable",
            "lgf_profile_collect"]
@@ -66,6 +86,7 @@ def library():
         L.lgf_plan_create_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32, i32, i32,
                                             ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.lgf_plan_solve_offsets.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)]
+        L.lgf_plan_estimate.argtypes = [vp, i64, i32, i32, i32, ctypes.c_int, ctypes.POINTER(PlanInfo)]
         L.lgf_solve.argtypes = [vp, vp, vp, vp]
         L.lgf_graph_create.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.lgf_graph_launch.argtypes = [vp, vp]
@@ -73,6 +94,13 @@ def library():
         L.lgf_plan_autotune.argtypes = [vp, vp, vp, vp, i32]
         L.lgf_plan_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.lgf_plan_set_tuning.argtypes = [vp, i32, i32, i32]
+        L.lgf_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+        L.lgf_server_submit.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(i64)]
+        L.lgf_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(RequestResult)]
+        L.lgf_server_wait.argtypes = [vp, i64, ctypes.POINTER(RequestResult)]
+        L.lgf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.lgf_server_reset_stats.argtypes = [vp]
+        L.lgf_server_destroy.argtypes = [vp]
         L.lgf_solve_many.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
         L.lgf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.lgf_plan_destroy.argtypes = [vp]
@@ -228,6 +256,22 @@ class Plan:
             pass
 
 
+def _info_dict(inf):
+    d = {k: getattr(inf, k) for k, _ in PlanInfo._fields_}
+    d["far_pairs"] = list(inf.far_pairs)
+    d["intervals"] = list(inf.intervals)
+    return d
+
+
+def plan_estimate(blocks, n, p, levels=0, precision="f64"):
+    """lgf_plan_estimate: the plan summary of a layout, computed on the host only."""
+    b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+    inf = PlanInfo()
+    _check(library().lgf_plan_estimate(b.ctypes.data, b.shape[0], int(n), int(p), int(levels),
+                                       {"f64": F64, "f32": F32}[precision], ctypes.byref(inf)))
+    return _info_dict(inf)
+
+
 class Graph:
     """An executable HIP graph of one solve (lgf_graph_create / launch / destroy).
 
@@ -250,6 +294,74 @@ class Graph:
         if self._h is not None:
             library().lgf_graph_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """lgf_server_*: a request loop with HBM-budget admission and resident plans."""
+
+    def __init__(self, n, p, levels=0, precision="f32", max_slots=4, budget_bytes=0, max_queue=0):
+        _require_gpu()
+        self.n = int(n)
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        cfg = ServerConfig(int(budget_bytes), int(max_slots), int(max_queue), self.n, int(p), int(levels),
+                           {"f64": F64, "f32": F32}[precision])
+        h = ctypes.c_void_p()
+        _check(library().lgf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, blocks, f, u):
+        """Queue u = G * f on `blocks`; returns a ticket.  f, u stay referenced until done."""
+        b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+        shape = (b.shape[0], self.n, self.n, self.n)
+        for x in (f, u):
+            if not (x.is_cuda and x.is_contiguous() and x.dtype == self.dtype and tuple(x.shape) == shape):
+                raise ValueError("fields must be contiguous %s device tensors of shape %s" % (self.dtype, shape))
+        t = ctypes.c_int64()
+        _check(library().lgf_server_submit(self._h, b.ctypes.data, b.shape[0], ctypes.c_void_p(f.data_ptr()),
+                                           ctypes.c_void_p(u.data_ptr()), ctypes.byref(t)))
+        self._keep[t.value] = (f, u)
+        return t.value
+
+    @staticmethod
+    def _result(r):
+        return dict(status=_STATUS.get(r.status, r.status), nblocks=r.nblocks, latency_ms=r.latency_ms,
+                    queue_ms=r.queue_ms, device_ms=r.device_ms)
+
+    def wait(self, ticket):
+        r = RequestResult()
+        _check(library().lgf_server_wait(self._h, int(ticket), ctypes.byref(r)))
+        self._keep.pop(ticket, None)
+        return self._result(r)
+
+    def poll(self, ticket):
+        r = RequestResult()
+        d = ctypes.c_int32()
+        _check(library().lgf_server_poll(self._h, int(ticket), ctypes.byref(d), ctypes.byref(r)))
+        if not d.value:
+            return None
+        self._keep.pop(ticket, None)
+        return self._result(r)
+
+    def stats(self):
+        st = ServerStats()
+        _check(library().lgf_server_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        _check(library().lgf_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h is not None:
+            library().lgf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -1,0 +1,119 @@
+"""Host-side plan logic (tree, lists, workspace estimate) through lgf_plan_estimate, which
+does no device work: checked against the oracle's plain O(N^2) list enumeration and
+against closed forms (runs without a GPU)."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle import flgf
+from paper_1402_6081_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1402_6081_amd", "libpaper_lgf.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch  # noqa: F401  (shares the HIP runtime with the library)
+    from paper_1402_6081_amd import lgf as L
+    L.library()
+    return L
+
+
+CASES = [
+    ("eden60_full", 60, 0),
+    ("eden150_full", 150, 0),
+    ("eden150_L2", 150, 2),
+    ("eden90_L3", 90, 3),
+    ("eden1", 1, 0),
+    ("eden2", 2, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_lists_match_oracle_tree(L, case):
+    label, nb, levels = case
+    rng = np.random.default_rng(len(label) * 1000 + nb)
+    blocks = W.eden_layout(nb, rng)
+    # shift to an arbitrary origin: the plan anchors at the bounding-box minimum
+    blocks = blocks + np.array([-7, 3, 100], dtype=np.int32)
+    info = L.plan_estimate(blocks, 8, 6, levels, "f64")
+    tree = flgf.Tree(blocks, levels)
+    assert info["levels"] == tree.L
+    assert info["near_pairs"] == len(tree.near[0])
+    top = 0
+    for lvl in range(1, tree.L + 1):
+        assert info["intervals"][lvl] == tree.coords[lvl].shape[0], lvl
+        assert info["far_pairs"][lvl] == len(tree.ilist[lvl][0]), lvl
+        if len(tree.ilist[lvl][0]):
+            top = lvl
+    assert info["top_level"] == top
+    assert info["intervals"][0] == nb and info["npoints"] == nb * 512
+
+
+@pytest.mark.parametrize("k,levels,expect", [
+    (4, 2, [1000, 3096, 0]),                     # 32^3 of 8^3 blocks, 2 levels
+    (8, 4, [10648, 53352, 3096, 0, 0]),          # 128^3 of 16^3 blocks, 4 levels
+    (16, 0, [97336, 584136, 53352, 3096, 0]),    # 256^3 of 16^3 blocks, full depth
+])
+def test_cube_pair_counts(L, k, levels, expect):
+    """Near pairs of a k^3 cube of blocks: (3k - 2)^3 (each axis contributes
+    k + 2 (k - 1) ordered pairs with |d| <= 1).  The interaction-list counts per level are
+    the ones the oracle's tree enumerates on the same cubes (checked here for k <= 8)."""
+    info = L.plan_estimate(W.cube_layout(k), 16, 8, levels, "f32")
+    assert info["near_pairs"] == (3 * k - 2) ** 3 == expect[0]
+    for lvl, cnt in enumerate(expect[1:], start=1):
+        assert info["far_pairs"][lvl] == cnt, lvl
+    if k <= 8:
+        tree = flgf.Tree(W.cube_layout(k), levels)
+        for lvl in range(1, tree.L + 1):
+            assert len(tree.ilist[lvl][0]) == info["far_pairs"][lvl]
+
+
+def test_interaction_list_size_bound(L):
+    """No interval has more than 189 = 6^3 - 3^3 interaction-list entries (Sec. 3.1)."""
+    info = L.plan_estimate(W.cube_layout(16), 16, 8, 0, "f32")
+    for lvl in range(1, info["levels"] + 1):
+        assert info["far_pairs"][lvl] <= 189 * info["intervals"][lvl]
+
+
+def test_workspace_estimate_scales(L):
+    a = L.plan_estimate(W.cube_layout(4), 16, 8, 0, "f32")["workspace_bytes"]
+    b = L.plan_estimate(W.cube_layout(4), 16, 8, 0, "f64")["workspace_bytes"]
+    c = L.plan_estimate(W.cube_layout(8), 16, 8, 0, "f32")["workspace_bytes"]
+    # level-0 spectra dominate: 2 N_B + 1 items of 16^2 * 17 (padded to 64) complex values
+    s0 = 32 * 32 * 17
+    assert a > (2 * 64 + 1) * s0 * 8
+    assert 1.6 < b / a < 2.1
+    assert 7.0 < c / a < 9.0
+
+
+def test_layout_errors(L):
+    with pytest.raises(L.LGFError) as e:
+        L.plan_estimate(np.array([[0, 0, 0], [1, 0, 0], [0, 0, 0]]), 8, 6)
+    assert e.value.name == "LGF_ERR_LAYOUT"
+    with pytest.raises(L.LGFError) as e:
+        L.plan_estimate(np.array([[0, 0, 0], [1 << 21, 0, 0]]), 8, 6)
+    assert e.value.name == "LGF_ERR_LAYOUT"
+    with pytest.raises(L.LGFError) as e:
+        L.plan_estimate(np.array([[0, 0, 0]]), 6, 6)
+    assert e.value.name == "LGF_ERR_ARG"
+
+
+def test_server_config_errors(L):
+    lib = L.library()
+    h = ctypes.c_void_p()
+    bad = [L.ServerConfig(0, 0, 0, 16, 8, 0, 1),    # no slots
+           L.ServerConfig(0, 4, 0, 12, 8, 0, 1),    # n unsupported
+           L.ServerConfig(-1, 4, 0, 16, 8, 0, 1),   # negative budget
+           L.ServerConfig(0, 4, 0, 16, 8, 0, 7)]    # unknown precision
+    for cfg in bad:
+        assert lib.lgf_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+    assert lib.lgf_server_submit(None, None, 1, None, None, None) == 1
+    assert lib.lgf_server_destroy(None) == 0
+    assert lib.lgf_graph_create(None, None, None, None, ctypes.byref(h)) == 1
+    assert lib.lgf_plan_set_tuning(None, 0, 4, 8) == 1
+    assert lib.lgf_plan_create_batch(None, None, 0, 8, 6, 0, 0, None, ctypes.byref(h)) == 1
