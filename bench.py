@@ -12,7 +12,9 @@ inputs are resident in HBM before the timed region.  Two passes per precision:
     (lgf_profile_*): per-kernel device times (the roofline entry uses the dominant one);
   * the same solve captured once as a HIP graph (lgf_graph_create) and launched K times:
     the reported rate (value) and per-solve latencies (p50/p99, events around each launch).
-A third pass times the batched workload: 64 independent Eden layouts in one batch plan.
+A third pass times the batched workload: 64 independent Eden layouts in one batch plan;
+a fourth serves a request mix through the request server (closed loop for capacity, then
+Poisson arrivals at 80% of it for p50/p99 latency).
 
 cpu_baseline: the oracle (step-by-step FLGF in numpy, single thread) timed on the host
 on the full workload (plan and pre-computation excluded).
@@ -173,6 +175,60 @@ def batch_bench(L, W, steps, warmup, seed=4):
             "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3)}
 
 
+def serve_bench(L, W, nreq=192, seed=5, slots=4, load=0.8):
+    """Serving: 32 request layouts (bounding box U{2..16} blocks of 16^3, Eden fill
+    U[0.3, 1]), p = 8, FP32, through the request server (resident plans, shared spectra).
+    Closed loop first (all requests queued at once) gives the capacity; then an open loop
+    with Poisson arrivals at `load` x capacity gives the latency percentiles."""
+    import torch
+    rng = np.random.default_rng(seed)
+    mix = W.serving_mix(32, rng)
+    dev = torch.device("cuda:0")
+    fs = [torch.from_numpy(f).to(dev, torch.float32) for _, f in mix]
+    order = rng.integers(0, len(mix), size=nreq)
+    us = [torch.empty_like(fs[k]) for k in order]
+    srv = L.Server(16, 8, 0, "f32", max_slots=slots)
+    # warm-up: every layout's plan becomes resident, every spectrum cached
+    for t in [srv.submit(mix[k][0], fs[k], torch.empty_like(fs[k])) for k in range(len(mix))]:
+        assert srv.wait(t)["status"] == "LGF_OK"
+    srv.reset_stats()
+    tickets = [srv.submit(mix[k][0], fs[k], u) for k, u in zip(order, us)]
+    for t in tickets:
+        assert srv.wait(t)["status"] == "LGF_OK"
+    closed = srv.stats()
+    cap_rps = closed["completed"] / (closed["points"] / closed["points_per_s"])  # requests/s
+    # open loop, Poisson arrivals
+    srv.reset_stats()
+    gaps = rng.exponential(1.0 / (load * cap_rps), size=nreq)
+    t0 = time.perf_counter()
+    due = t0
+    tickets = []
+    for k, u, g in zip(order, us, gaps):
+        due += g
+        while time.perf_counter() < due:
+            pass
+        tickets.append(srv.submit(mix[k][0], fs[k], u))
+    res = [srv.wait(t) for t in tickets]
+    assert all(r["status"] == "LGF_OK" for r in res)
+    st = srv.stats()
+    srv.close()
+    pts_req = [mix[k][1].size for k in order]
+    return {"workload": "%d requests over 32 Eden-box layouts (edge U{2..16} blocks of 16^3, fill U[0.3,1]; "
+                        "seed %d), p=8, f32, %d slots" % (nreq, seed, slots),
+            "points_per_request_mean": round(float(np.mean(pts_req)), 1),
+            "closed_loop": {"value": round(closed["points_per_s"], 1), "unit": "grid points solved/s",
+                            "requests_per_s": round(cap_rps, 1),
+                            "latency_ms": {"p50": round(closed["latency_p50_ms"], 4),
+                                           "p99": round(closed["latency_p99_ms"], 4)}},
+            "open_loop": {"offered_load": load, "value": round(st["points_per_s"], 1),
+                          "unit": "grid points solved/s",
+                          "latency_ms": {"p50": round(st["latency_p50_ms"], 4),
+                                         "p99": round(st["latency_p99_ms"], 4),
+                                         "max": round(st["latency_max_ms"], 4)},
+                          "device_ms_p50": round(float(np.percentile([r["device_ms"] for r in res], 50)), 4)},
+            "resident_plan_bytes": st["plan_bytes"], "spectra_bytes": st["spectra_bytes"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +237,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--breakdown", default=None, help="write the per-step breakdown JSON here")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -253,6 +310,9 @@ def main():
     if not args.no_batch:
         result["batch"] = batch_bench(L, W, max(5, args.steps // 5), 2)
         print("batch measured", flush=True, file=sys.stderr)
+    if not args.no_serve:
+        result["serve"] = serve_bench(L, W)
+        print("serving measured", flush=True, file=sys.stderr)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg)

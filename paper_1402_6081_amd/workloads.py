@@ -75,6 +75,48 @@ def eden_layout(nblocks, rng, max_extent=None):
     return arr.astype(np.int32)
 
 
+def eden_box_layout(edge, fill, rng):
+    """Face-connected Eden cluster of round(fill * edge^3) blocks grown from the centre of
+    an edge^3 box and confined to it (bounding-box edge <= `edge`)."""
+    target = max(1, int(round(fill * edge ** 3)))
+    c = (edge // 2,) * 3
+    cur = {c}
+    frontier = []
+
+    def push(b):
+        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            nb = (b[0] + d[0], b[1] + d[1], b[2] + d[2])
+            if nb not in cur and all(0 <= v < edge for v in nb):
+                frontier.append(nb)
+
+    push(c)
+    while len(cur) < target and frontier:
+        i = int(rng.integers(len(frontier)))
+        b = frontier[i]
+        frontier[i] = frontier[-1]
+        frontier.pop()
+        if b in cur:
+            continue
+        cur.add(b)
+        push(b)
+    arr = np.array(sorted(cur, key=lambda t: (t[2], t[1], t[0])), dtype=np.int64)
+    arr -= arr.min(axis=0)
+    return arr.astype(np.int32)
+
+
+def serving_mix(count, rng, n=16):
+    """Request layouts of the serving workload: bounding-box edge U{2..16} blocks, Eden
+    fill U[0.3, 1.0], each with max(1, N_B / 8) zero-net Gaussians (sigma U[2, 6])."""
+    out = []
+    for _ in range(count):
+        edge = int(rng.integers(2, 17))
+        fill = float(rng.uniform(0.3, 1.0))
+        b = eden_box_layout(edge, fill, rng)
+        f, _ = zero_mean_gaussians(b, n, rng, max(1, b.shape[0] // 8))
+        out.append((b, f))
+    return out
+
+
 def points_of(blocks, n):
     """Grid coordinates [N_B, n, n, n, 3] (x, y, z) of every point of every block."""
     b = np.asarray(blocks, dtype=np.int64)
@@ -100,9 +142,14 @@ def _sum_separable(E, amps):
     """f[b, z, y, x] = sum_g amps[g] ez[b, g, z] ey[b, g, y] ex[b, g, x]."""
     ex, ey, ez = E
     nb, g, n = ex.shape
-    zy = (ez * np.asarray(amps)[None, :, None])[:, :, :, None] * ey[:, :, None, :]  # [N_B, G, z, y]
-    zy = zy.reshape(nb, g, n * n).transpose(0, 2, 1)                               # [N_B, zy, G]
-    return np.matmul(zy, ex).reshape(nb, n, n, n)
+    out = np.empty((nb, n, n, n))
+    a = np.asarray(amps)[None, :, None]
+    for b0 in range(0, nb, 128):  # chunks of blocks bound the [chunk, G, n, n] temporary
+        b1 = min(nb, b0 + 128)
+        zy = (ez[b0:b1] * a)[:, :, :, None] * ey[b0:b1, :, None, :]          # [c, G, z, y]
+        zy = zy.reshape(b1 - b0, g, n * n).transpose(0, 2, 1)                # [c, zy, G]
+        out[b0:b1] = np.matmul(zy, ex[b0:b1]).reshape(b1 - b0, n, n, n)
+    return out
 
 
 def gaussian_source(blocks, n, centres, sigmas, amps):
