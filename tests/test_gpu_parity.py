@@ -176,3 +176,32 @@ def test_deterministic(L):
         a = gpu_solve(L, blocks, f, 16, 8, 0, prec)
         b = gpu_solve(L, blocks, f, 16, 8, 0, prec)
         assert np.array_equal(a, b), prec
+
+
+def test_large_config_vortex_ring(L):
+    """256^3 vortex-ring workload (16^3 blocks of 16^3, p = 8, full depth) at full size:
+    FP64 against the oracle's FLGF and exact direct sum at 64 stored targets
+    (tests/golden/large_config_samples.json, written by make_large_samples.py from the
+    oracle alone), and the FP32 path against FP64 over the whole field."""
+    import json
+    import os
+    _say("case: large config 256^3 vortex ring, FP64 + FP32")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "large_config_samples.json")))
+    c = W.config_large()
+    assert gold["workload"] == c["name"]
+    idx = np.asarray(gold["flat_index"])
+    u64 = gpu_solve(L, c["blocks"], c["f"], c["n"], c["p"], c["levels"], "f64").reshape(-1)
+    scale = gold["max_abs_u"]
+    assert abs(np.max(np.abs(u64)) - scale) <= 1e-12 * scale
+    flgf_ref = np.asarray(gold["flgf"])
+    exact = np.asarray(gold["exact"])
+    err_b = float(np.max(np.abs(u64[idx] - flgf_ref)) / scale)
+    trunc = float(np.max(np.abs(flgf_ref - exact)) / np.max(np.abs(exact)))
+    err_a = float(np.max(np.abs(u64[idx] - exact)) / np.max(np.abs(exact)))
+    _say("  vs oracle FLGF %.3g, vs exact %.3g (oracle FLGF vs exact %.3g)" % (err_b, err_a, trunc))
+    assert err_b <= fp64_tol(c["p"])
+    assert err_a <= trunc + 1e-12
+    u32 = gpu_solve(L, c["blocks"], c["f"], c["n"], c["p"], c["levels"], "f32").reshape(-1)
+    err32 = float(np.max(np.abs(u32 - u64)) / np.max(np.abs(u64)))
+    _say("  FP32 vs FP64 %.3g" % err32)
+    assert err32 <= 1e-6
