@@ -72,7 +72,47 @@ def _time_graph(plan, f, u, steps, warmup):
     return t1 - t0, lat
 
 
-def _roofline(prof, dtype_peak_tflops):
+_SRC = {"prod": ["lgf_prod.hip", "lgf_device.h", "lgf_internal.h"],
+        "fft": ["lgf_fft.hip", "lgf_device.h", "lgf_internal.h"],
+        "interp": ["lgf_interp.hip", "lgf_device.h", "lgf_internal.h"]}
+
+
+def _family(step):
+    if step.startswith("prod"):
+        return "prod"
+    if step.startswith("fft"):
+        return "fft"
+    return "interp"
+
+
+def _src_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1402_6081_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, prec, step):
+    """HBM bytes per launch of `step` from the committed rocprofv3 counter summaries
+    (profiles/*.md, FETCH_SIZE + WRITE_SIZE scaled by a copy kernel), or None when no
+    summary covers it or the kernel's sources changed since the counters were taken."""
+    import glob
+    want = _src_hash(_SRC[_family(step)])
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("TRAFFIC "):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("workload") == workload and kv.get("prec") == prec and kv.get("step") == step:
+                    if kv.get("src") == want:
+                        return float(kv["bytes"]), os.path.basename(path)
+    return None, None
+
+
+def _roofline(prof, dtype_peak_tflops, workload=None, prec=None):
     steps = prof["steps"]
     ns = max(prof["nsolves"], 1)
     dom = max(steps, key=lambda s: s["total_ms"])
@@ -88,8 +128,12 @@ def _roofline(prof, dtype_peak_tflops):
     else:
         roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": dtype_peak_tflops, "unit": "TFLOP/s",
                 "frac": round(tfl / dtype_peak_tflops, 4)}
+    traffic, src = measured_traffic(workload, prec, dom["name"]) if workload else (None, None)
     roof.update({"kernel_step": dom["name"], "avg_ms": round(avg_s * 1e3, 5),
-                 "algorithmic_bytes": dom["bytes"], "algorithmic_flops": dom["flops"], "traffic": None})
+                 "algorithmic_bytes": dom["bytes"], "algorithmic_flops": dom["flops"],
+                 "traffic": traffic})
+    if src:
+        roof["traffic_from"] = src
     return roof
 
 
@@ -119,11 +163,24 @@ def cpu_baseline(cfg, budget_s=30.0):
                       "excluded, %.1f s" % (cfg["name"], npts, dt)}
 
 
-def _measure(plan, f, u, steps, warmup):
+def _measure(plan, f, u, steps, warmup, graph=True):
     """Eager solves with per-step events (breakdown, roofline), then graph launches (rate)."""
     dt_e, prof = _time_solves(plan, f, u, steps, warmup)
+    if not graph:  # counter-collection runs: eager solves only
+        return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_e, lat_graph=np.asarray(prof["solve_ms"]))
     dt_g, lat = _time_graph(plan, f, u, steps, warmup)
     return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat)
+
+
+def copy_calibration(mib):
+    """Three plain device copies of `mib` MiB (a kernel of known traffic: mib MiB read and
+    mib MiB written per launch) so hardware byte counters can be scaled to bytes."""
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
 
 
 def _pct(x):
@@ -238,6 +295,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="eager solves only (counter runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run 3 plain device copies of MIB MiB (counter calibration)")
     ap.add_argument("--breakdown", default=None, help="write the per-step breakdown JSON here")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -249,6 +309,8 @@ def main():
     import paper_1402_6081_amd.lgf as L
     from paper_1402_6081_amd import workloads as W
 
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     cfg = W.config_medium()
     npts = cfg["f"].size
     dev = torch.device("cuda:0")
@@ -258,7 +320,7 @@ def main():
     plan = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], "f64")
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t_plan
-    m = _measure(plan, f64, u64, args.steps, args.warmup)
+    m = _measure(plan, f64, u64, args.steps, args.warmup, graph=not args.no_graph)
     print("fp64 measured", flush=True, file=sys.stderr)
     info = plan.info()
 
@@ -276,7 +338,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "points": int(npts), "blocks": int(info["nblocks"]),
-                   "n": cfg["n"], "p": cfg["p"], "levels": cfg["levels"], "launch": "hip graph per solve",
+                   "n": cfg["n"], "p": cfg["p"], "levels": cfg["levels"],
+                   "launch": "eager lgf_solve" if args.no_graph else "hip graph per solve",
                    "source": "32 seeded Gaussians, sigma U[2,6], zero net source"},
         "latency_ms": _pct(m["lat_graph"]),
         "eager": {"value": round(npts * args.steps / m["dt_eager"], 1),
@@ -284,7 +347,7 @@ def main():
                   "latency_ms": _pct(m["prof"]["solve_ms"]),
                   "note": "lgf_solve per step, with per-step profiling events"},
         "plan_s": round(t_plan, 3),
-        "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS),
+        "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS, cfg["name"], "f64"),
     }
     breakdown = {"fp64": _breakdown(m["prof"])}
     u64_host = u64.cpu().numpy()
@@ -293,7 +356,7 @@ def main():
         f32 = f64.float()
         u32 = torch.empty_like(f32)
         plan32 = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], "f32")
-        m32 = _measure(plan32, f32, u32, args.steps, args.warmup)
+        m32 = _measure(plan32, f32, u32, args.steps, args.warmup, graph=not args.no_graph)
         print("fp32 measured", flush=True, file=sys.stderr)
         u32_host = u32.double().cpu().numpy()
         err = float(np.max(np.abs(u32_host - u64_host)) / np.max(np.abs(u64_host)))
@@ -302,7 +365,7 @@ def main():
                           "rel_linf_err_vs_fp64": err,
                           "latency_ms": _pct(m32["lat_graph"]),
                           "eager_ms_per_step": round(m32["dt_eager"] / args.steps * 1e3, 5),
-                          "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS)}
+                          "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS, cfg["name"], "f32")}
         breakdown["fp32"] = _breakdown(m32["prof"])
         plan32.close()
     plan.close()
