@@ -6,11 +6,14 @@ Workload (the metric's configuration that fits one GPU): a 128^3 cube as 8^3 blo
 workload is also solved on the FP32 path (FP64 tables and final add), whose rate, error
 against the FP64 result and latencies are reported next to the FP64 numbers.
 
-Timing: W untimed warm-up solves, then K solves bracketed by device synchronisation; the
-inputs are resident in HBM before the timed region.  Two passes per precision:
-  * eager lgf_solve calls with every step bracketed by HIP events on the stream it runs on
-    (lgf_profile_*): per-kernel device times (the roofline entry uses the dominant one);
-  * the same solve captured once as a HIP graph (lgf_graph_create) and launched K times:
+Timing: the plan's kernel variants are autotuned first (lgf_plan_autotune, a few dozen
+solves), then W untimed warm-up solves and K timed solves bracketed by device
+synchronisation; the inputs are resident in HBM before the timed region.  Two passes per
+precision:
+  * eager lgf_solve calls on one stream with every step bracketed by HIP events
+    (lgf_profile_*): isolated per-kernel device times (the roofline entry uses the
+    dominant one);
+  * the tuned solve captured once as a HIP graph (lgf_graph_create) and launched K times:
     the reported rate (value) and per-solve latencies (p50/p99, events around each launch).
 A third pass times the batched workload: 64 independent Eden layouts in one batch plan;
 a fourth serves a request mix through the request server (closed loop for capacity, then
@@ -163,13 +166,20 @@ def cpu_baseline(cfg, budget_s=30.0):
                       "excluded, %.1f s" % (cfg["name"], npts, dt)}
 
 
-def _measure(plan, f, u, steps, warmup, graph=True):
-    """Eager solves with per-step events (breakdown, roofline), then graph launches (rate)."""
+def _measure(plan, f, u, steps, warmup, graph=True, tune=True):
+    """Autotune the plan's kernel variants (lgf_plan_autotune), then
+      * eager solves on one stream with per-step events: isolated kernel durations for the
+        breakdown and the roofline;
+      * graph launches with the tuned variants (far field concurrent with the near field
+        when that is faster): the rate and latencies."""
+    choice = plan.autotune(f, u, reps=3) if tune else plan.tuning()
+    plan.set_tuning(**dict(choice, overlap=2))
     dt_e, prof = _time_solves(plan, f, u, steps, warmup)
+    plan.set_tuning(**choice)
     if not graph:  # counter-collection runs: eager solves only
-        return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_e, lat_graph=np.asarray(prof["solve_ms"]))
+        return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_e, lat_graph=np.asarray(prof["solve_ms"]), tuning=choice)
     dt_g, lat = _time_graph(plan, f, u, steps, warmup)
-    return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat)
+    return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat, tuning=choice)
 
 
 def copy_calibration(mib):
@@ -206,6 +216,7 @@ def batch_bench(L, W, steps, warmup, seed=4):
     bp = L.Plan.batch(lays, 16, 8, 0, "f32")
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
+    choice = bp.autotune(fcat, ucat, reps=2)
     dt_g, lat = _time_graph(bp, fcat, ucat, steps, warmup)
     # the same 64 problems as 64 plans enqueued back to back (no batching)
     plans = [L.Plan(b, 16, 8, 0, "f32") for b in lays]
@@ -229,7 +240,7 @@ def batch_bench(L, W, steps, warmup, seed=4):
             "ms_per_batch": round(dt_g / steps * 1e3, 5), "latency_ms": _pct(lat),
             "separate_plans_value": round(npts * steps / dt_sep, 1),
             "separate_plans_ms": round(dt_sep / steps * 1e3, 5),
-            "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3)}
+            "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3), "tuning": choice}
 
 
 def serve_bench(L, W, nreq=192, seed=5, slots=4, load=0.8):
@@ -296,6 +307,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="eager solves only (counter runs)")
+    ap.add_argument("--no-tune", action="store_true", help="default kernel variants, no autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run 3 plain device copies of MIB MiB (counter calibration)")
     ap.add_argument("--breakdown", default=None, help="write the per-step breakdown JSON here")
@@ -320,7 +332,7 @@ def main():
     plan = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], "f64")
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t_plan
-    m = _measure(plan, f64, u64, args.steps, args.warmup, graph=not args.no_graph)
+    m = _measure(plan, f64, u64, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune)
     print("fp64 measured", flush=True, file=sys.stderr)
     info = plan.info()
 
@@ -340,12 +352,13 @@ def main():
         "config": {"workload": cfg["name"], "points": int(npts), "blocks": int(info["nblocks"]),
                    "n": cfg["n"], "p": cfg["p"], "levels": cfg["levels"],
                    "launch": "eager lgf_solve" if args.no_graph else "hip graph per solve",
+                   "tuning": m["tuning"],
                    "source": "32 seeded Gaussians, sigma U[2,6], zero net source"},
         "latency_ms": _pct(m["lat_graph"]),
         "eager": {"value": round(npts * args.steps / m["dt_eager"], 1),
                   "ms_per_step": round(m["dt_eager"] / args.steps * 1e3, 5),
                   "latency_ms": _pct(m["prof"]["solve_ms"]),
-                  "note": "lgf_solve per step, with per-step profiling events"},
+                  "note": "lgf_solve per step on one stream, with per-step profiling events (roofline source)"},
         "plan_s": round(t_plan, 3),
         "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS, cfg["name"], "f64"),
     }
@@ -356,7 +369,7 @@ def main():
         f32 = f64.float()
         u32 = torch.empty_like(f32)
         plan32 = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], "f32")
-        m32 = _measure(plan32, f32, u32, args.steps, args.warmup, graph=not args.no_graph)
+        m32 = _measure(plan32, f32, u32, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune)
         print("fp32 measured", flush=True, file=sys.stderr)
         u32_host = u32.double().cpu().numpy()
         err = float(np.max(np.abs(u32_host - u64_host)) / np.max(np.abs(u64_host)))
@@ -365,6 +378,7 @@ def main():
                           "rel_linf_err_vs_fp64": err,
                           "latency_ms": _pct(m32["lat_graph"]),
                           "eager_ms_per_step": round(m32["dt_eager"] / args.steps * 1e3, 5),
+                          "tuning": m32["tuning"],
                           "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS, cfg["name"], "f32")}
         breakdown["fp32"] = _breakdown(m32["prof"])
         plan32.close()

@@ -42,10 +42,12 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
                             cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, hipStream_t s);
 // Levels >= 1 below the top: over parents (child8 and the 216 candidate sources src216 of
 // each parent), offsets radius 3.
+// waves: parent groups per workgroup (1, 2, 4); cpl: children accumulated per lane (8, 4, 2,
+// 1); 0 = chosen from the level's size.
 template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
-                               int waves, hipStream_t s);
+                               int waves, int cpl, hipStream_t s);
 // Targets tgt[0..ntgt) from CSR lists (the top level of a truncated tree).
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
@@ -56,7 +58,9 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
 struct TuneConfig {
     int fft0_threads = 0;  // 0 = default per tile size, else 128 / 256 / 512
     int near_waves = 4;    // waves per workgroup of the level-0 Prod kernel: 2, 4, 8
-    int far_waves = 8;     // waves per workgroup of the level >= 1 Prod kernel: 4, 8, 16
+    int far_waves = 0;     // parent groups per workgroup of the level >= 1 Prod kernel: 1, 2, 4, 0 = by level size
+    int far_children = 0;  // children per lane of that kernel: 8, 4, 2, 1, or 0 = by level size
+    int overlap = 0;       // far-field chain on a second stream: 1 = yes, 2 = no, 0 = for small plans
 };
 
 // Reg block -> level-1 interval: out[b] = (A x A x A) f[b], A is p x n (row-major)

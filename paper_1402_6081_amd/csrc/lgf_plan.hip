@@ -475,11 +475,12 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     } while (0)
     mark.solve_begin(s);
     const bool far = pl->Ltop >= 1;
-    hipStream_t s2 = pl->overlap ? pl->far_stream : s;
+    const bool overlap = tc.overlap == 0 ? pl->overlap : tc.overlap == 1;
+    hipStream_t s2 = overlap ? pl->far_stream : s;
     if (far) {
         // ---- far field (levels >= 1), on the second stream for small plans: Reg up, FFT,
         //      M2L, IFFT, Interp down
-        if (pl->overlap) {
+        if (overlap) {
             if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(s2, pl->ev_fork, 0)) != hipSuccess) return e;
         }
@@ -504,7 +505,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
                 LGF_STEP(s2,
                          (launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8,
                                                  Pp.d_src216, (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S,
-                                                 tc.far_waves, s2)),
+                                                 tc.far_waves, tc.far_children, s2)),
                          lname("prod_l", l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.sib_pairs * S1 * 8.0);
             }
             if (L.csr_entries > 0)
@@ -531,7 +532,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
                          "interp_l" + std::to_string(l + 1) + "_l" + std::to_string(l),
                          (lvN(l + 1) + 2.0 * lvN(l)) * p3 * us, lvN(l) * 2.0 * 3.0 * p3 * p);
         }
-        if (pl->overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
+        if (overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
     }
     // ---- near field (level 0) on the caller's stream
     LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nb, s, tc.fft0_threads), "fft_fwd_l0",
@@ -543,7 +544,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s, tc.fft0_threads)), "fft_inv_l0",
              nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
     if (far) {
-        if (pl->overlap && (e = hipStreamWaitEvent(s, pl->ev_join, 0)) != hipSuccess) return e;
+        if (overlap && (e = hipStreamWaitEvent(s, pl->ev_join, 0)) != hipSuccess) return e;
         LGF_STEP(s, (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s)), "final_l1_l0",
                  nb * (2.0 * n3 * es + p3 * us), nb * 2.0 * (p3 * n + p * p * n * n + p * n3));
     }
@@ -701,8 +702,11 @@ int bucket_of(int64_t nb) {
 bool valid_tune(const TuneConfig& c) {
     const bool f = c.fft0_threads == 0 || c.fft0_threads == 128 || c.fft0_threads == 256 || c.fft0_threads == 512;
     const bool nw = c.near_waves == 2 || c.near_waves == 4 || c.near_waves == 8;
-    const bool fw = c.far_waves == 4 || c.far_waves == 8 || c.far_waves == 16;
-    return f && nw && fw;
+    const bool fw = c.far_waves == 1 || c.far_waves == 2 || c.far_waves == 4;
+    const bool fc = c.far_children == 0 || c.far_children == 1 || c.far_children == 2 || c.far_children == 4 ||
+                    c.far_children == 8;
+    const bool fw0 = c.far_waves == 0;
+    return f && nw && (fw || fw0) && fc && c.overlap >= 0 && c.overlap <= 2;
 }
 
 void tune_load_file() {
@@ -714,8 +718,8 @@ void tune_load_file() {
     if (!fh) return;
     TuneKey k;
     TuneConfig c;
-    while (std::fscanf(fh, "%d %d %d %d %d %d %d", &k.n, &k.p, &k.prec, &k.bucket, &c.fft0_threads, &c.near_waves,
-                       &c.far_waves) == 7)
+    while (std::fscanf(fh, "%d %d %d %d %d %d %d %d %d", &k.n, &k.p, &k.prec, &k.bucket, &c.fft0_threads,
+                       &c.near_waves, &c.far_waves, &c.far_children, &c.overlap) == 9)
         if (valid_tune(c)) g_tune[k] = c;
     std::fclose(fh);
 }
@@ -726,7 +730,8 @@ void tune_store(const TuneKey& k, const TuneConfig& c) {
     if (!path) return;
     FILE* fh = std::fopen(path, "a");
     if (!fh) return;
-    std::fprintf(fh, "%d %d %d %d %d %d %d\n", k.n, k.p, k.prec, k.bucket, c.fft0_threads, c.near_waves, c.far_waves);
+    std::fprintf(fh, "%d %d %d %d %d %d %d %d %d\n", k.n, k.p, k.prec, k.bucket, c.fft0_threads, c.near_waves,
+                 c.far_waves, c.far_children, c.overlap);
     std::fclose(fh);
 }
 
@@ -977,15 +982,15 @@ lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_
     TuneConfig best = plan->tune;
     float best_ms = time_solves(plan, f, u, s, reps);
     // coordinate search: each knob in turn, keeping the best value of the others
-    const int fft_opts[] = {128, 256, 512};
-    const int near_opts[] = {2, 4, 8};
-    const int far_opts[] = {4, 8, 16};
-    for (int knob = 0; knob < 3; ++knob) {
-        for (int k = 0; k < 3; ++k) {
+    const std::vector<std::vector<int>> opts = {{1, 2}, {128, 256, 512}, {2, 4, 8}, {1, 2, 4}, {8, 4, 2, 1}};
+    for (int knob = 0; knob < 5; ++knob) {
+        for (int v : opts[knob]) {
             TuneConfig c = best;
-            if (knob == 0) c.fft0_threads = fft_opts[k];
-            if (knob == 1) c.near_waves = near_opts[k];
-            if (knob == 2) c.far_waves = far_opts[k];
+            if (knob == 0) c.overlap = v;
+            if (knob == 1) c.fft0_threads = v;
+            if (knob == 2) c.near_waves = v;
+            if (knob == 3) c.far_waves = v;
+            if (knob == 4) c.far_children = v;
             plan->tune = c;
             const float ms = time_solves(plan, f, u, s, reps);
             if (ms < best_ms) {
@@ -1001,20 +1006,26 @@ lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_
     return LGF_OK;
 }
 
-lgf_status lgf_plan_get_tuning(lgf_plan_t plan, int32_t* fft0_threads, int32_t* near_waves, int32_t* far_waves) {
+lgf_status lgf_plan_get_tuning(lgf_plan_t plan, int32_t* fft0_threads, int32_t* near_waves, int32_t* far_waves,
+                               int32_t* far_children, int32_t* overlap) {
     if (!plan) return fail(LGF_ERR_ARG, "NULL plan");
+    if (overlap) *overlap = plan->tune.overlap;
     if (fft0_threads) *fft0_threads = plan->tune.fft0_threads;
     if (near_waves) *near_waves = plan->tune.near_waves;
     if (far_waves) *far_waves = plan->tune.far_waves;
+    if (far_children) *far_children = plan->tune.far_children;
     return LGF_OK;
 }
 
-lgf_status lgf_plan_set_tuning(lgf_plan_t plan, int32_t fft0_threads, int32_t near_waves, int32_t far_waves) {
+lgf_status lgf_plan_set_tuning(lgf_plan_t plan, int32_t fft0_threads, int32_t near_waves, int32_t far_waves,
+                               int32_t far_children, int32_t overlap) {
     if (!plan) return fail(LGF_ERR_ARG, "NULL plan");
     TuneConfig c;
+    c.overlap = overlap;
     c.fft0_threads = fft0_threads;
     c.near_waves = near_waves;
     c.far_waves = far_waves;
+    c.far_children = far_children;
     if (!valid_tune(c)) return fail(LGF_ERR_ARG, "lgf_plan_set_tuning: unsupported variant");
     plan->tune = c;
     return LGF_OK;

@@ -110,77 +110,132 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 // Parents J (level l+1): src216[J][e * 8 + cs] = level-l interval 2(J + e') + cs with
 // e' = (ex-1, ey-1, ez-1), e = ex + 3 ey + 9 ez, or the zero sentinel item (index nitems);
 // child8[J][c] = target 2J + c (or -1).  khat: 343 offsets, id (Dx+3) + 7 (Dy+3) + 49 (Dz+3).
-// Lane = (child c, frequency j of a chunk of 8); one wave per parent, the waves of a
-// workgroup share the [343][8] kernel tile in LDS.  The 8 child lanes of a frequency read
-// the same source coefficient, so each source spectrum is fetched once per parent.
-constexpr int kFarWC = 8;
-constexpr int kFarRow = kFarWC + 1;  // padded tile row (breaks LDS bank aliasing between rows)
-// Tile layout: row ((3 - Dx) + 7 (3 - Dy) + 49 (3 - Dz)), column j holds khat^D at frequency
-// w0 + j, and 0 for the 27 offsets with |D|_inf <= 1 (not interaction-list offsets).  With
-// D = c - cs - 2e the row is base(c, e) + (csx + 7 csy + 49 csz): a compile-time offset for
-// the unrolled source child cs, and near pairs add exact zeros.
-template <typename T, int kFarWaves>
-__global__ void __launch_bounds__(64 * kFarWaves)
+//
+// The target child c receives source child cs of neighbour e at offset D = c - cs - 2e'.
+// Register blocking: a lane owns one frequency of one parent and accumulates CPL of its 8
+// children (the subset Q of the children is fixed per wave, so all its index arithmetic is
+// compile-time).  Per neighbour e the lane loads the 8 source coefficients once; its
+// (child, source child) pairs need only the kernel values at delta = c - cs, each read once
+// from LDS and applied to every pair with that delta.  The delta loop is unrolled; the
+// interaction-list condition |D|_inf >= 2 is a wave-uniform branch.
+// Every child sums its terms in the same order (neighbour e, then delta) whatever CPL and
+// the number of waves, so all variants give identical results.
+// Lanes: F consecutive frequencies (one 128-byte segment of a spectrum) x 64/F parents.
+// The workgroup's waves share the [343][F] kernel tile and the parents' source indices in LDS.
+template <typename T>
+struct M2LShape {
+    static constexpr int F = 128 / (int)sizeof(cplx<T>);  // frequencies per chunk: 8 FP64, 16 FP32
+    static constexpr int PPW = 64 / F;                     // parents per wave
+};
+
+// child i of subset Q when a lane accumulates CPL children (subsets split z, then y, then x)
+template <int CPL, int Q>
+__device__ constexpr int m2l_child(int i) { return Q * CPL + i; }
+
+template <typename T, int CPL, int Q>
+__device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fl, const int32_t* si, const cplx<T>* tk,
+                                         T (&ar)[CPL], T (&ai)[CPL]) {
+    constexpr int F = M2LShape<T>::F;
+    cplx<T> fa[8];
+#pragma unroll
+    for (int cs = 0; cs < 8; ++cs) fa[cs] = fl[(int64_t)si[cs] * 64];
+#pragma unroll 1
+    for (int e = 0; e < 27; ++e) {
+        // the next neighbour's sources are in flight while this one is consumed
+        cplx<T> fb[8];
+        const int en = e + 1 < 27 ? e + 1 : e;
+#pragma unroll
+        for (int cs = 0; cs < 8; ++cs) fb[cs] = fl[(int64_t)si[en * 8 + cs] * 64];
+        const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;  // wave-uniform
+        const cplx<T>* kb = tk + ((3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 - 2 * ez)) * F;
+#pragma unroll
+        for (int d = 0; d < 27; ++d) {
+            const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+            bool used = false;  // compile-time: does a child of this subset pair with delta d?
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) {
+                const int c = m2l_child<CPL, Q>(i);
+                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+                used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
+            }
+            if (!used) continue;
+            const int Dx = dx - 2 * ex, Dy = dy - 2 * ey, Dz = dz - 2 * ez;
+            // near offsets are not in the interaction list (uniform branch)
+            if (Dx >= -1 && Dx <= 1 && Dy >= -1 && Dy <= 1 && Dz >= -1 && Dz <= 1) continue;
+            const cplx<T> k = kb[(dx + 7 * dy + 49 * dz) * F];
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) {
+                const int c = m2l_child<CPL, Q>(i);
+                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+                if (csx < 0 || csx > 1 || csy < 0 || csy > 1 || csz < 0 || csz > 1) continue;  // compile-time
+                cmac(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
+            }
+        }
+#pragma unroll
+        for (int cs = 0; cs < 8; ++cs) fa[cs] = fb[cs];
+    }
+}
+
+template <typename T, int CPL, int Q = 0>
+__device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fl, const int32_t* si, const cplx<T>* tk,
+                                             T (&ar)[CPL], T (&ai)[CPL]) {
+    if constexpr (Q + 1 < 8 / CPL) {
+        if (q != Q) {
+            m2l_dispatch<T, CPL, Q + 1>(q, fl, si, tk, ar, ai);
+            return;
+        }
+    }
+    m2l_lane<T, CPL, Q>(fl, si, tk, ar, ai);
+}
+
+template <typename T, int kFarWaves, int CPL>
+__global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     k_prod_far_sib(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                    const int32_t* __restrict__ child8, const int32_t* __restrict__ src216,
                    cplx<T>* __restrict__ uhat, int S, int nparents, int nitems) {
-    __shared__ cplx<T> tile[343 * kFarRow];
-    const int nchunks = (S + kFarWC - 1) / kFarWC;
+    constexpr int F = M2LShape<T>::F;
+    constexpr int PPW = M2LShape<T>::PPW;
+    constexpr int NQ = 8 / CPL;             // waves per group of parents (one per child subset)
+    constexpr int PPG = PPW * kFarWaves;    // parents per workgroup
+    constexpr int NT = 64 * kFarWaves * NQ;
+    __shared__ cplx<T> tile[343 * F];
+    __shared__ int32_t sidx[PPG * 216];
+    const int nchunks = (S + F - 1) / F;
     int chunk, pb;
-    if (!xcd_tile(nchunks, (nparents + kFarWaves - 1) / kFarWaves, chunk, pb)) return;
-    const int w0 = chunk * kFarWC;
-    for (int i = threadIdx.x; i < 343 * kFarWC; i += 64 * kFarWaves) {
-        const int r = i / kFarWC, j = i - r * kFarWC;
-        const int Dx = 3 - r % 7, Dy = 3 - (r / 7) % 7, Dz = 3 - r / 49;
-        const int o = (Dx + 3) + 7 * (Dy + 3) + 49 * (Dz + 3);
-        const bool near = Dx >= -1 && Dx <= 1 && Dy >= -1 && Dy <= 1 && Dz >= -1 && Dz <= 1;
-        tile[r * kFarRow + j] = (w0 + j < S && !near) ? khat[spec_at(o, w0 + j, 343)] : cplx<T>{T(0), T(0)};
+    if (!xcd_tile(nchunks, (nparents + PPG - 1) / PPG, chunk, pb)) return;
+    const int w0 = chunk * F;
+    for (int i = threadIdx.x; i < 343 * F; i += NT) {
+        const int r = i / F, jj = i - r * F;
+        tile[i] = (w0 + jj < S) ? khat[spec_at(r, w0 + jj, 343)] : cplx<T>{T(0), T(0)};
+    }
+    for (int i = threadIdx.x; i < PPG * 216; i += NT) {
+        const int Jl = i / 216, k = i - Jl * 216;
+        const int J = pb * PPG + Jl;
+        sidx[i] = J < nparents ? src216[(int64_t)J * 216 + k] : nitems;  // padding parents read zeros
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int c = lane >> 3, j = lane & 7;
-    const int w = w0 + j;
-    const bool live = w < S;
-    const int J = wave_uniform(pb * kFarWaves + (threadIdx.x >> 6));
-    if (J >= nparents) return;
-    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-    // this lane's frequency column of the source spectra (padding lanes read column w0)
-    const cplx<T>* fl = fhat + (int64_t)((live ? w : w0) >> 6) * (nitems + 1) * 64 + ((live ? w : w0) & 63);
-    const int32_t* sj = src216 + (int64_t)J * 216;
-    T ar = T(0), ai = T(0);
-    // double-buffered: the 8 source loads of neighbour e+1 are in flight while e is consumed
-    cplx<T> fa[8], fb[8];
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int q = wave % NQ, pw = wave / NQ;
+    const int j = lane % F;
+    const int Jl = pw * PPW + lane / F;
+    const int J = pb * PPG + Jl;
+    const int w = w0 + j;  // may exceed S in the last chunk: computed, never stored
+    const cplx<T>* fl = fhat + (int64_t)(w >> 6) * (nitems + 1) * 64 + (w & 63);
+    T ar[CPL], ai[CPL];
 #pragma unroll
-    for (int cs = 0; cs < 8; ++cs) fa[cs] = fl[(int64_t)sj[cs] * 64];
-#pragma unroll 1
-    for (int e = 0; e < 27; e += 2) {
-        if (e + 1 < 27) {
-#pragma unroll
-            for (int cs = 0; cs < 8; ++cs) fb[cs] = fl[(int64_t)sj[(e + 1) * 8 + cs] * 64];
-        }
-        {
-            const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;
-            const cplx<T>* kb = tile + ((3 - cx + 2 * ex) + 7 * (3 - cy + 2 * ey) + 49 * (3 - cz + 2 * ez)) * kFarRow + j;
-#pragma unroll
-            for (int cs = 0; cs < 8; ++cs)
-                cmac(ar, ai, fa[cs], kb[((cs & 1) + 7 * ((cs >> 1) & 1) + 49 * (cs >> 2)) * kFarRow]);
-        }
-        if (e + 1 >= 27) break;
-        if (e + 2 < 27) {
-#pragma unroll
-            for (int cs = 0; cs < 8; ++cs) fa[cs] = fl[(int64_t)sj[(e + 2) * 8 + cs] * 64];
-        }
-        {
-            const int e1 = e + 1;
-            const int ex = e1 % 3 - 1, ey = (e1 / 3) % 3 - 1, ez = e1 / 9 - 1;
-            const cplx<T>* kb = tile + ((3 - cx + 2 * ex) + 7 * (3 - cy + 2 * ey) + 49 * (3 - cz + 2 * ez)) * kFarRow + j;
-#pragma unroll
-            for (int cs = 0; cs < 8; ++cs)
-                cmac(ar, ai, fb[cs], kb[((cs & 1) + 7 * ((cs >> 1) & 1) + 49 * (cs >> 2)) * kFarRow]);
-        }
+    for (int i = 0; i < CPL; ++i) {
+        ar[i] = T(0);
+        ai[i] = T(0);
     }
-    const int t = child8[(int64_t)J * 8 + c];
-    if (t >= 0 && live) uhat[spec_at(t, w, nitems)] = cplx<T>{ar, ai};
+    m2l_dispatch<T, CPL>(q, fl, sidx + Jl * 216, tile + j, ar, ai);
+    if (J >= nparents || w >= S) return;
+    const int32_t* c8 = child8 + (int64_t)J * 8 + q * CPL;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+        const int t = c8[i];
+        if (t >= 0) uhat[spec_at(t, w, nitems)] = cplx<T>{ar[i], ai[i]};
+    }
 }
 
 // ------------------------------------------------------------------ generic CSR (top level)
@@ -230,24 +285,50 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
     }
 }
 
-template <typename T, int NW>
+template <typename T, int NW, int CPL>
 static hipError_t far_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
                          cplx<T>* uhat, int64_t nparents, int64_t nitems, int S, hipStream_t s) {
-    const unsigned grid = xcd_grid((S + kFarWC - 1) / kFarWC, (int)((nparents + NW - 1) / NW));
-    hipLaunchKernelGGL((k_prod_far_sib<T, NW>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, child8, src216, uhat, S,
-                       (int)nparents, (int)nitems);
+    constexpr int F = M2LShape<T>::F, PPG = M2LShape<T>::PPW * NW;
+    const unsigned grid = xcd_grid((S + F - 1) / F, (int)((nparents + PPG - 1) / PPG));
+    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, fhat, khat,
+                       child8, src216, uhat, S, (int)nparents, (int)nitems);
     return hipGetLastError();
+}
+
+template <typename T, int CPL>
+static hipError_t far_cpl(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
+                          cplx<T>* uhat, int64_t nparents, int64_t nitems, int S, int waves, hipStream_t s) {
+    // at most 16 waves (1024 threads) per workgroup: 2 parent groups when a lane holds one child
+    constexpr int kMaxGroups = 16 / (8 / CPL) < 4 ? 16 / (8 / CPL) : 4;
+    switch (waves < kMaxGroups ? waves : kMaxGroups) {
+        case 1: return far_nw<T, 1, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+        case 4:
+            if constexpr (kMaxGroups >= 4) return far_nw<T, 4, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+            [[fallthrough]];
+        default: return far_nw<T, 2, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+    }
+}
+
+// Variant when the plan leaves it open, from measurements on MI355X: levels with at least
+// 64 parents run 4 children per lane in 4 parent groups per workgroup, smaller levels 2
+// children in 2 groups (more waves for little work).  Every variant computes the same bits.
+void m2l_default(int64_t nparents, int& waves, int& cpl) {
+    const bool big = nparents >= 64;
+    if (waves == 0) waves = big ? 4 : 2;
+    if (cpl == 0) cpl = big ? 4 : 2;
 }
 
 template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
-                               int waves, hipStream_t s) {
+                               int waves, int cpl, hipStream_t s) {
     if (nparents <= 0) return hipSuccess;
-    switch (waves) {
-        case 4: return far_nw<T, 4>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
-        case 16: return far_nw<T, 16>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
-        default: return far_nw<T, 8>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+    m2l_default(nparents, waves, cpl);
+    switch (cpl) {
+        case 8: return far_cpl<T, 8>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
+        case 4: return far_cpl<T, 4>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
+        case 2: return far_cpl<T, 2>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
+        default: return far_cpl<T, 1>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
     }
 }
 
@@ -266,7 +347,7 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
     template hipError_t launch_prod_near<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,      \
                                             cplx<T>*, int64_t, int64_t, int, int, hipStream_t);                  \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
-                                               cplx<T>*, int64_t, int64_t, int, int, hipStream_t);               \
+                                               cplx<T>*, int64_t, int64_t, int, int, int, hipStream_t);          \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \
                                            const int32_t*, const int32_t*, cplx<T>*, int64_t, int64_t, int, int, \
                                            hipStream_t);

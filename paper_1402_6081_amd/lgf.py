@@ -92,8 +92,8 @@ def library():
         L.lgf_graph_launch.argtypes = [vp, vp]
         L.lgf_graph_destroy.argtypes = [vp]
         L.lgf_plan_autotune.argtypes = [vp, vp, vp, vp, i32]
-        L.lgf_plan_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
-        L.lgf_plan_set_tuning.argtypes = [vp, i32, i32, i32]
+        L.lgf_plan_get_tuning.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
+        L.lgf_plan_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32]
         L.lgf_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
         L.lgf_server_submit.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(i64)]
         L.lgf_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(RequestResult)]
@@ -215,12 +215,13 @@ class Plan:
         return self.tuning()
 
     def tuning(self):
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(library().lgf_plan_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return dict(fft0_threads=a.value, near_waves=b.value, far_waves=c.value)
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(library().lgf_plan_get_tuning(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("fft0_threads", "near_waves", "far_waves", "far_children", "overlap"), [x.value for x in v]))
 
-    def set_tuning(self, fft0_threads=0, near_waves=4, far_waves=8):
-        _check(library().lgf_plan_set_tuning(self._h, int(fft0_threads), int(near_waves), int(far_waves)))
+    def set_tuning(self, fft0_threads=0, near_waves=4, far_waves=0, far_children=0, overlap=0):
+        _check(library().lgf_plan_set_tuning(self._h, int(fft0_threads), int(near_waves), int(far_waves),
+                                             int(far_children), int(overlap)))
 
     def info(self):
         inf = PlanInfo()

@@ -177,7 +177,9 @@ def test_autotune_keeps_results(L):
     choice = plan.autotune(f, reps=2)
     assert choice["fft0_threads"] in (0, 128, 256, 512)
     assert choice["near_waves"] in (2, 4, 8)
-    assert choice["far_waves"] in (4, 8, 16)
+    assert choice["far_waves"] in (0, 1, 2, 4)
+    assert choice["far_children"] in (0, 1, 2, 4, 8)
+    assert choice["overlap"] in (0, 1, 2)
     after = plan.solve(f)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
@@ -197,16 +199,17 @@ def test_every_variant_same_bits(L, prec):
         _say("case: kernel variants", prec, "n", n)
         plan = L.Plan(blocks, n, 6, 0, prec)
         f = torch.from_numpy(rng.standard_normal(plan.shape())).to("cuda:0", plan.dtype)
-        plan.set_tuning(0, 4, 8)
+        plan.set_tuning(0, 4, 2, 8, 2)
         ref = plan.solve(f)
         torch.cuda.synchronize()
-        for ft in (0, 128, 256, 512):
-            for nw in (2, 4, 8):
-                for fw in (4, 8, 16):
-                    plan.set_tuning(ft, nw, fw)
-                    got = plan.solve(f)
-                    torch.cuda.synchronize()
-                    assert torch.equal(ref, got), (ft, nw, fw)
+        variants = [(ft, 4, 0, 0, 0) for ft in (0, 128, 256, 512)] + [(0, nw, 0, 0, 0) for nw in (2, 8)]
+        variants += [(0, 4, fw, fc, 0) for fw in (0, 1, 2, 4) for fc in (0, 1, 2, 4, 8)]
+        variants += [(0, 4, 0, 0, ov) for ov in (1, 2)]
+        for v in variants:
+            plan.set_tuning(*v)
+            got = plan.solve(f)
+            torch.cuda.synchronize()
+            assert torch.equal(ref, got), v
         with pytest.raises(L.LGFError):
-            plan.set_tuning(64, 4, 8)
+            plan.set_tuning(64, 4, 2, 0, 0)
         plan.close()
