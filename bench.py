@@ -182,6 +182,25 @@ def _measure(plan, f, u, steps, warmup, graph=True, tune=True):
     return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat, tuning=choice)
 
 
+def hbm_copy_bandwidth(mib=2048, reps=10):
+    """Achievable HBM bandwidth of a plain device copy (read + write bytes / time), for context."""
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * x.numel() * 4 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def copy_calibration(mib):
     """Three plain device copies of `mib` MiB (a kernel of known traffic: mib MiB read and
     mib MiB written per launch) so hardware byte counters can be scaled to bytes."""
@@ -361,6 +380,7 @@ def main():
                   "note": "lgf_solve per step on one stream, with per-step profiling events (roofline source)"},
         "plan_s": round(t_plan, 3),
         "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS, cfg["name"], "f64"),
+        "hbm_copy_GBps": hbm_copy_bandwidth(),
     }
     breakdown = {"fp64": _breakdown(m["prof"])}
     u64_host = u64.cpu().numpy()

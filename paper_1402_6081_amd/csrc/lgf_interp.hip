@@ -15,45 +15,50 @@
 namespace lgfdev {
 
 constexpr int kInterpThreads = 256;
-constexpr int kMaxN = 16, kMaxP = 10;
 
 // ------------------------------------------------------------------ block -> level 1
-template <typename T>
+// One workgroup per block: the block is staged in LDS with coalesced loads, then the
+// three passes run from LDS with compile-time extents.
+template <typename T, int N, int P>
 __global__ void __launch_bounds__(kInterpThreads)
-    k_reg_block(const T* __restrict__ f, const double* __restrict__ A, T* __restrict__ out, int n, int p) {
-    __shared__ T t1[kMaxN * kMaxN * kMaxP], t2[kMaxN * kMaxP * kMaxP];
-    __shared__ T Am[kMaxP * kMaxN];
+    k_reg_block(const T* __restrict__ f, const double* __restrict__ A, T* __restrict__ out) {
+    constexpr int N3 = N * N * N, P3 = P * P * P;
+    __shared__ T X[N3], t1[N * N * P], t2[N * P * P];
+    __shared__ T Am[P * N];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    const int n3 = n * n * n, p3 = p * p * p;
-    for (int i = tid; i < p * n; i += kInterpThreads) Am[i] = (T)A[i];
+    for (int i = tid; i < P * N; i += kInterpThreads) Am[i] = (T)A[i];
+    const T* src = f + b * N3;
+    for (int i = tid; i < N3; i += kInterpThreads) X[i] = src[i];
     __syncthreads();
-    const T* X = f + b * n3;
-    // x: t1[z][y][d] = sum_x A[d][x] f[z][y][x]  (rows read straight from HBM)
-    for (int i = tid; i < n * n * p; i += kInterpThreads) {
-        const int d = i % p, zy = i / p;
-        const T* row = X + zy * n;
-        const T* m = Am + d * n;
-        T s = T(0);
-        for (int x = 0; x < n; ++x) s += m[x] * row[x];
-        t1[i] = s;
+    for (int i = tid; i < N * N * P; i += kInterpThreads) {  // x: t1[z][y][d]
+        const int d = i % P, zy = i / P;
+        const T* row = X + zy * N;
+        const T* m = Am + d * N;
+        T acc = T(0);
+#pragma unroll
+        for (int x = 0; x < N; ++x) acc += m[x] * row[x];
+        t1[i] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < n * p * p; i += kInterpThreads) {  // y: t2[z][c][d]
-        const int d = i % p, c = (i / p) % p, z = i / (p * p);
-        const T* m = Am + c * n;
-        T s = T(0);
-        for (int y = 0; y < n; ++y) s += m[y] * t1[(z * n + y) * p + d];
-        t2[i] = s;
+    for (int i = tid; i < N * P * P; i += kInterpThreads) {  // y: t2[z][c][d]
+        const int d = i % P, c = (i / P) % P, z = i / (P * P);
+        const T* m = Am + c * N;
+        const T* col = t1 + z * N * P + d;
+        T acc = T(0);
+#pragma unroll
+        for (int y = 0; y < N; ++y) acc += m[y] * col[y * P];
+        t2[i] = acc;
     }
     __syncthreads();
-    T* o = out + b * p3;
-    for (int i = tid; i < p3; i += kInterpThreads) {  // z: out[a][c][d]
-        const int cd = i % (p * p), a = i / (p * p);
-        const T* m = Am + a * n;
-        T s = T(0);
-        for (int z = 0; z < n; ++z) s += m[z] * t2[z * (p * p) + cd];
-        o[i] = s;
+    T* o = out + b * P3;
+    for (int i = tid; i < P3; i += kInterpThreads) {  // z: out[a][c][d]
+        const int cd = i % (P * P), a = i / (P * P);
+        const T* m = Am + a * N;
+        T acc = T(0);
+#pragma unroll
+        for (int z = 0; z < N; ++z) acc += m[z] * t2[z * (P * P) + cd];
+        o[i] = acc;
     }
 }
 
@@ -171,54 +176,105 @@ __global__ void __launch_bounds__(kInterpThreads)
 }
 
 // ------------------------------------------------------------------ level 1 -> block, FP64 add-back
-template <typename T, typename U>
+template <typename T, typename U, int N, int P>
 __global__ void __launch_bounds__(kInterpThreads)
-    k_final(const T* vnear, const U* __restrict__ ut, const double* __restrict__ A, T* u, int n, int p) {
-    __shared__ double X[kMaxP * kMaxP * kMaxP], t1[kMaxP * kMaxP * kMaxN], t2[kMaxP * kMaxN * kMaxN];
-    __shared__ double At[kMaxN * kMaxP];  // At[j][k] = A[k][j]
+    k_final(const T* vnear, const U* __restrict__ ut, const double* __restrict__ A, T* u) {
+    constexpr int N3 = N * N * N, P3 = P * P * P;
+    __shared__ double X[P3], t1[P * P * N], t2[P * N * N];
+    __shared__ double At[N * P];  // At[j][k] = A[k][j]
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    const int n3 = n * n * n, p3 = p * p * p;
-    for (int i = tid; i < n * p; i += kInterpThreads) {
-        const int j = i / p, k = i % p;
-        At[i] = A[k * n + j];
+    for (int i = tid; i < N * P; i += kInterpThreads) {
+        const int jj = i / P, k = i % P;
+        At[i] = A[k * N + jj];
     }
-    for (int i = tid; i < p3; i += kInterpThreads) X[i] = to_double(ut[b * p3 + i]);
+    for (int i = tid; i < P3; i += kInterpThreads) X[i] = to_double(ut[b * P3 + i]);
     __syncthreads();
-    for (int i = tid; i < p * p * n; i += kInterpThreads) {  // x: t1[a][c][x]
-        const int x = i % n, ac = i / n;
-        const double* m = At + x * p;
-        const double* row = X + ac * p;
-        double s = 0.0;
-        for (int d = 0; d < p; ++d) s += m[d] * row[d];
-        t1[i] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < p * n * n; i += kInterpThreads) {  // y: t2[a][y][x]
-        const int x = i % n, y = (i / n) % n, a = i / (n * n);
-        const double* m = At + y * p;
-        double s = 0.0;
-        for (int c = 0; c < p; ++c) s += m[c] * t1[(a * p + c) * n + x];
-        t2[i] = s;
+    for (int i = tid; i < P * P * N; i += kInterpThreads) {  // x: t1[a][c][x]
+        const int x = i % N, ac = i / N;
+        const double* m = At + x * P;
+        const double* row = X + ac * P;
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < P; ++d) acc += m[d] * row[d];
+        t1[i] = acc;
     }
     __syncthreads();
-    const T* v = vnear + b * n3;
-    T* o = u + b * n3;
-    for (int i = tid; i < n3; i += kInterpThreads) {  // z: u[z][y][x]
-        const int yx = i % (n * n), z = i / (n * n);
-        const double* m = At + z * p;
-        double s = 0.0;
-        for (int a = 0; a < p; ++a) s += m[a] * t2[a * n * n + yx];
-        o[i] = (T)((double)v[i] + s);
+    for (int i = tid; i < P * N * N; i += kInterpThreads) {  // y: t2[a][y][x]
+        const int x = i % N, y = (i / N) % N, a = i / (N * N);
+        const double* m = At + y * P;
+        const double* col = t1 + a * P * N + x;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) acc += m[c] * col[c * N];
+        t2[i] = acc;
+    }
+    __syncthreads();
+    const T* v = vnear + b * N3;
+    T* o = u + b * N3;
+    for (int i = tid; i < N3; i += kInterpThreads) {  // z: u[z][y][x]
+        const int yx = i % (N * N), z = i / (N * N);
+        const double* m = At + z * P;
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < P; ++a) acc += m[a] * t2[a * N * N + yx];
+        o[i] = (T)((double)v[i] + acc);
     }
 }
 
 // ------------------------------------------------------------------ launchers
+// (n, p) -> compile-time kernel: n in {4, 8, 16}, p in [2, 10]
+template <template <int, int> class K, typename... Args>
+static hipError_t dispatch_np(int n, int p, Args... args) {
+#define LGF_NP(NN)                                          \
+    switch (p) {                                            \
+        case 2: return K<NN, 2>::run(args...);              \
+        case 3: return K<NN, 3>::run(args...);              \
+        case 4: return K<NN, 4>::run(args...);              \
+        case 5: return K<NN, 5>::run(args...);              \
+        case 6: return K<NN, 6>::run(args...);              \
+        case 7: return K<NN, 7>::run(args...);              \
+        case 8: return K<NN, 8>::run(args...);              \
+        case 9: return K<NN, 9>::run(args...);              \
+        case 10: return K<NN, 10>::run(args...);            \
+        default: return hipErrorInvalidValue;               \
+    }
+    switch (n) {
+        case 4: LGF_NP(4)
+        case 8: LGF_NP(8)
+        case 16: LGF_NP(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef LGF_NP
+}
+
+template <typename T>
+struct RegBlockRun {
+    template <int N, int P>
+    struct K {
+        static hipError_t run(const T* f, const double* A, T* out, int64_t nb, hipStream_t s) {
+            hipLaunchKernelGGL((k_reg_block<T, N, P>), dim3((unsigned)nb), dim3(kInterpThreads), 0, s, f, A, out);
+            return hipGetLastError();
+        }
+    };
+};
+
+template <typename T, typename U>
+struct FinalRun {
+    template <int N, int P>
+    struct K {
+        static hipError_t run(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, hipStream_t s) {
+            hipLaunchKernelGGL((k_final<T, U, N, P>), dim3((unsigned)nb), dim3(kInterpThreads), 0, s, vnear, ut, A,
+                               u);
+            return hipGetLastError();
+        }
+    };
+};
+
 template <typename T>
 hipError_t launch_reg_block(const T* f, const double* A, T* out, int64_t nb, int n, int p, hipStream_t s) {
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reg_block<T>, dim3((unsigned)nb), dim3(kInterpThreads), 0, s, f, A, out, n, p);
-    return hipGetLastError();
+    return dispatch_np<RegBlockRun<T>::template K>(n, p, f, A, out, nb, s);
 }
 
 template <typename T, int P>
@@ -273,8 +329,7 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
 template <typename T, typename U>
 hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, int n, int p, hipStream_t s) {
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_final<T, U>), dim3((unsigned)nb), dim3(kInterpThreads), 0, s, vnear, ut, A, u, n, p);
-    return hipGetLastError();
+    return dispatch_np<FinalRun<T, U>::template K>(n, p, vnear, ut, A, u, nb, s);
 }
 
 template hipError_t launch_reg_block<double>(const double*, const double*, double*, int64_t, int, int, hipStream_t);

@@ -132,47 +132,61 @@ struct M2LShape {
 template <int CPL, int Q>
 __device__ constexpr int m2l_child(int i) { return Q * CPL + i; }
 
+// The contribution of neighbour e to this lane's children, with source values fa.
+template <typename T, int CPL, int Q>
+__device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], const cplx<T>* tk, T (&ar)[CPL],
+                                              T (&ai)[CPL]) {
+    constexpr int F = M2LShape<T>::F;
+    const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;  // wave-uniform
+    const cplx<T>* kb = tk + ((3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 - 2 * ez)) * F;
+#pragma unroll
+    for (int d = 0; d < 27; ++d) {
+        const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+        bool used = false;  // compile-time: does a child of this subset pair with delta d?
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            const int c = m2l_child<CPL, Q>(i);
+            const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+            used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
+        }
+        if (!used) continue;
+        const int Dx = dx - 2 * ex, Dy = dy - 2 * ey, Dz = dz - 2 * ez;
+        // near offsets are not in the interaction list (uniform branch)
+        if (Dx >= -1 && Dx <= 1 && Dy >= -1 && Dy <= 1 && Dz >= -1 && Dz <= 1) continue;
+        const cplx<T> k = kb[(dx + 7 * dy + 49 * dz) * F];
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            const int c = m2l_child<CPL, Q>(i);
+            const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+            if (csx < 0 || csx > 1 || csy < 0 || csy > 1 || csz < 0 || csz > 1) continue;  // compile-time
+            cmac(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fl, const int32_t* si, cplx<T> (&f)[8]) {
+    const int ee = e < 27 ? e : 26;  // past the end: a harmless reload of the last neighbour
+#pragma unroll
+    for (int cs = 0; cs < 8; ++cs) f[cs] = fl[(int64_t)si[ee * 8 + cs] * 64];
+}
+
+// Neighbours in order e = 0..26 through a three-buffer pipeline: the sources of e+1 and
+// e+2 are in flight while e is consumed.
 template <typename T, int CPL, int Q>
 __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fl, const int32_t* si, const cplx<T>* tk,
                                          T (&ar)[CPL], T (&ai)[CPL]) {
-    constexpr int F = M2LShape<T>::F;
-    cplx<T> fa[8];
-#pragma unroll
-    for (int cs = 0; cs < 8; ++cs) fa[cs] = fl[(int64_t)si[cs] * 64];
+    cplx<T> fa[8], fb[8], fc[8];
+    m2l_load<T>(0, fl, si, fa);
+    m2l_load<T>(1, fl, si, fb);
 #pragma unroll 1
-    for (int e = 0; e < 27; ++e) {
-        // the next neighbour's sources are in flight while this one is consumed
-        cplx<T> fb[8];
-        const int en = e + 1 < 27 ? e + 1 : e;
-#pragma unroll
-        for (int cs = 0; cs < 8; ++cs) fb[cs] = fl[(int64_t)si[en * 8 + cs] * 64];
-        const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;  // wave-uniform
-        const cplx<T>* kb = tk + ((3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 - 2 * ez)) * F;
-#pragma unroll
-        for (int d = 0; d < 27; ++d) {
-            const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
-            bool used = false;  // compile-time: does a child of this subset pair with delta d?
-#pragma unroll
-            for (int i = 0; i < CPL; ++i) {
-                const int c = m2l_child<CPL, Q>(i);
-                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
-                used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
-            }
-            if (!used) continue;
-            const int Dx = dx - 2 * ex, Dy = dy - 2 * ey, Dz = dz - 2 * ez;
-            // near offsets are not in the interaction list (uniform branch)
-            if (Dx >= -1 && Dx <= 1 && Dy >= -1 && Dy <= 1 && Dz >= -1 && Dz <= 1) continue;
-            const cplx<T> k = kb[(dx + 7 * dy + 49 * dz) * F];
-#pragma unroll
-            for (int i = 0; i < CPL; ++i) {
-                const int c = m2l_child<CPL, Q>(i);
-                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
-                if (csx < 0 || csx > 1 || csy < 0 || csy > 1 || csz < 0 || csz > 1) continue;  // compile-time
-                cmac(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
-            }
-        }
-#pragma unroll
-        for (int cs = 0; cs < 8; ++cs) fa[cs] = fb[cs];
+    for (int e = 0; e < 27; e += 3) {
+        m2l_load<T>(e + 2, fl, si, fc);
+        m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
+        m2l_load<T>(e + 3, fl, si, fa);
+        m2l_neighbour<T, CPL, Q>(e + 1, fb, tk, ar, ai);
+        m2l_load<T>(e + 4, fl, si, fb);
+        m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
     }
 }
 
@@ -298,8 +312,10 @@ static hipError_t far_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t
 template <typename T, int CPL>
 static hipError_t far_cpl(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
                           cplx<T>* uhat, int64_t nparents, int64_t nitems, int S, int waves, hipStream_t s) {
-    // at most 16 waves (1024 threads) per workgroup: 2 parent groups when a lane holds one child
-    constexpr int kMaxGroups = 16 / (8 / CPL) < 4 ? 16 / (8 / CPL) : 4;
+    // at most 16 waves (1024 threads) per workgroup, and at most 8 in FP64, whose pipeline
+    // needs more than the 128 registers a lane gets in a 16-wave workgroup
+    constexpr int kMaxWaves = sizeof(T) == 8 ? 8 : 16;
+    constexpr int kMaxGroups = kMaxWaves / (8 / CPL) < 4 ? kMaxWaves / (8 / CPL) : 4;
     switch (waves < kMaxGroups ? waves : kMaxGroups) {
         case 1: return far_nw<T, 1, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
         case 4:
@@ -310,11 +326,13 @@ static hipError_t far_cpl(const cplx<T>* fhat, const cplx<T>* khat, const int32_
 }
 
 // Variant when the plan leaves it open, from measurements on MI355X: levels with at least
-// 64 parents run 4 children per lane in 4 parent groups per workgroup, smaller levels 2
-// children in 2 groups (more waves for little work).  Every variant computes the same bits.
+// 64 parents run 4 children per lane in 4 parent groups per workgroup; smaller levels run
+// 2 children per lane (more waves for little work) in 1 (FP64) or 2 (FP32) groups.  Every
+// variant computes the same bits.
+template <typename T>
 void m2l_default(int64_t nparents, int& waves, int& cpl) {
     const bool big = nparents >= 64;
-    if (waves == 0) waves = big ? 4 : 2;
+    if (waves == 0) waves = big ? 4 : (sizeof(T) == 8 ? 1 : 2);
     if (cpl == 0) cpl = big ? 4 : 2;
 }
 
@@ -323,7 +341,7 @@ hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const i
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
                                int waves, int cpl, hipStream_t s) {
     if (nparents <= 0) return hipSuccess;
-    m2l_default(nparents, waves, cpl);
+    m2l_default<T>(nparents, waves, cpl);
     switch (cpl) {
         case 8: return far_cpl<T, 8>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
         case 4: return far_cpl<T, 4>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
