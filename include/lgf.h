@@ -159,30 +159,35 @@ lgf_status lgf_graph_launch(lgf_graph_t graph, void* hip_stream);
 lgf_status lgf_graph_destroy(lgf_graph_t graph);
 
 /*
- * Autotuner of the plan's kernel variants: one or two streams for the near and far fields,
- * threads per workgroup of the level-0 transforms (128 / 256 / 512), waves per workgroup of
- * the level-0 Prod kernel (2 / 4 / 8), parent groups per workgroup (1 / 2 / 4) and children
- * accumulated per lane (8 / 4 / 2 / 1) of the level >= 1 Prod kernel.  Runs (1 + reps) solves per candidate on (f, u) (DEVICE
- * buffers of the plan's shape; u is overwritten) in a coordinate search, keeps the fastest
- * median device time, and remembers the choice for later plans of the same (n, p,
- * precision, power-of-two block-count bucket) in this process; if the environment
- * variable LGF_TUNE_FILE names a file the choice is appended there and read by later
- * processes.  Synchronous.  Variants differ in scheduling only: every variant gives the
- * same u bit for bit.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
+ * Kernel variants of a plan.  Variants differ in scheduling only: every variant gives the
+ * same u bit for bit.  0 selects the library's default where listed.
+ */
+typedef struct {
+    int32_t fft0_threads;   /* threads per workgroup of the level-0 transforms: 0, 128, 256, 512    */
+    int32_t near_waves;     /* waves per workgroup of the level-0 Prod: 2, 4, 8                      */
+    int32_t near_prefetch;  /* level-0 Prod issues the next source slab's loads early: 0, 1         */
+    int32_t far_waves;      /* parent groups per workgroup of the level >= 1 Prod: 0, 1, 2, 4       */
+    int32_t far_children;   /* children accumulated per lane of that kernel: 0, 1, 2, 4, 8           */
+    int32_t overlap;        /* far-field levels on a second stream, concurrent with the near field:
+                               1 yes, 2 no, 0 for plans of at most 256 blocks                         */
+} lgf_tuning;
+
+/*
+ * Autotuner: runs (1 + reps) solves per candidate variant on (f, u) (DEVICE buffers of the
+ * plan's shape; u is overwritten) in a coordinate search over the fields of lgf_tuning,
+ * keeps the fastest median device time, and remembers the choice for later plans of the
+ * same (n, p, precision, power-of-two block-count bucket) in this process; if the
+ * environment variable LGF_TUNE_FILE names a file the choice is appended there and read by
+ * later processes.  Synchronous.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
  */
 lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_stream, int32_t reps);
 
-/* The plan's current variant choice (0 = the default for the level or block size). */
-lgf_status lgf_plan_get_tuning(lgf_plan_t plan, int32_t* fft0_threads, int32_t* near_waves,
-                               int32_t* far_waves, int32_t* far_children, int32_t* overlap);
+/* The plan's current variants.  Errors: LGF_ERR_ARG. */
+lgf_status lgf_plan_get_tuning(lgf_plan_t plan, lgf_tuning* out);
 
-/* Pin the plan's variants by hand: fft0_threads in {0, 128, 256, 512}, near_waves in
- * {2, 4, 8}, far_waves in {0, 1, 2, 4}, far_children in {0, 1, 2, 4, 8}, overlap in {0, 1, 2}
- * (1: far-field levels on the plan's second stream, concurrent with the near field;
- * 2: one stream; 0: second stream for plans of at most 256 blocks).
- * Errors: LGF_ERR_ARG (other values). */
-lgf_status lgf_plan_set_tuning(lgf_plan_t plan, int32_t fft0_threads, int32_t near_waves,
-                               int32_t far_waves, int32_t far_children, int32_t overlap);
+/* Pin the plan's variants by hand (HOST struct, read during the call).
+ * Errors: LGF_ERR_ARG (a value outside the lists above). */
+lgf_status lgf_plan_set_tuning(lgf_plan_t plan, const lgf_tuning* tuning);
 
 /* Fill *info (HOST struct).  Errors: LGF_ERR_ARG. */
 lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info);

@@ -37,9 +37,11 @@ template <> struct FarAcc<float> { using type = ff32; };
 // Source spectra (fhat) arrays hold nitems + 1 items per frequency chunk; the last is a zero
 // sentinel that inactive neighbours point to.  Field spectra (uhat) hold nitems items.
 // Level 0 over groups of 2x2x2 target blocks (tgt8) with their 4^3 source neighbourhood (src64).
+// prefetch: 1 = the next source slab's loads are issued before the current slab is used.
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, hipStream_t s);
+                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, int prefetch,
+                            hipStream_t s);
 // Levels >= 1 below the top: over parents (child8 and the 216 candidate sources src216 of
 // each parent), offsets radius 3.
 // waves: parent groups per workgroup (1, 2, 4); cpl: children accumulated per lane (8, 4, 2,
@@ -58,6 +60,7 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
 struct TuneConfig {
     int fft0_threads = 0;  // 0 = default per tile size, else 128 / 256 / 512
     int near_waves = 4;    // waves per workgroup of the level-0 Prod kernel: 2, 4, 8
+    int near_prefetch = 0; // that kernel's source loads one z slab ahead: 0, 1
     int far_waves = 0;     // parent groups per workgroup of the level >= 1 Prod kernel: 1, 2, 4, 0 = by level size
     int far_children = 0;  // children per lane of that kernel: 8, 4, 2, 1, or 0 = by level size
     int overlap = 0;       // far-field chain on a second stream: 1 = yes, 2 = no, 0 = for small plans

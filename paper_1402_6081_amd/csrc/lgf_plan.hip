@@ -539,7 +539,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
              nb * (n3 * es + S0 * cs), nb * fft_flops(2 * n));
     LGF_STEP(s,
              launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8, pl->d_g0_src64,
-                                 (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S, tc.near_waves, s),
+                                 (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S, tc.near_waves,
+                                 tc.near_prefetch, s),
              "prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
     LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s, tc.fft0_threads)), "fft_inv_l0",
              nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
@@ -701,7 +702,8 @@ int bucket_of(int64_t nb) {
 
 bool valid_tune(const TuneConfig& c) {
     const bool f = c.fft0_threads == 0 || c.fft0_threads == 128 || c.fft0_threads == 256 || c.fft0_threads == 512;
-    const bool nw = c.near_waves == 2 || c.near_waves == 4 || c.near_waves == 8;
+    const bool nw = (c.near_waves == 2 || c.near_waves == 4 || c.near_waves == 8) &&
+                    (c.near_prefetch == 0 || c.near_prefetch == 1);
     const bool fw = c.far_waves == 1 || c.far_waves == 2 || c.far_waves == 4;
     const bool fc = c.far_children == 0 || c.far_children == 1 || c.far_children == 2 || c.far_children == 4 ||
                     c.far_children == 8;
@@ -718,8 +720,8 @@ void tune_load_file() {
     if (!fh) return;
     TuneKey k;
     TuneConfig c;
-    while (std::fscanf(fh, "%d %d %d %d %d %d %d %d %d", &k.n, &k.p, &k.prec, &k.bucket, &c.fft0_threads,
-                       &c.near_waves, &c.far_waves, &c.far_children, &c.overlap) == 9)
+    while (std::fscanf(fh, "%d %d %d %d %d %d %d %d %d %d", &k.n, &k.p, &k.prec, &k.bucket, &c.fft0_threads,
+                       &c.near_waves, &c.near_prefetch, &c.far_waves, &c.far_children, &c.overlap) == 10)
         if (valid_tune(c)) g_tune[k] = c;
     std::fclose(fh);
 }
@@ -730,8 +732,8 @@ void tune_store(const TuneKey& k, const TuneConfig& c) {
     if (!path) return;
     FILE* fh = std::fopen(path, "a");
     if (!fh) return;
-    std::fprintf(fh, "%d %d %d %d %d %d %d %d %d\n", k.n, k.p, k.prec, k.bucket, c.fft0_threads, c.near_waves,
-                 c.far_waves, c.far_children, c.overlap);
+    std::fprintf(fh, "%d %d %d %d %d %d %d %d %d %d\n", k.n, k.p, k.prec, k.bucket, c.fft0_threads, c.near_waves,
+                 c.near_prefetch, c.far_waves, c.far_children, c.overlap);
     std::fclose(fh);
 }
 
@@ -982,15 +984,16 @@ lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_
     TuneConfig best = plan->tune;
     float best_ms = time_solves(plan, f, u, s, reps);
     // coordinate search: each knob in turn, keeping the best value of the others
-    const std::vector<std::vector<int>> opts = {{1, 2}, {128, 256, 512}, {2, 4, 8}, {1, 2, 4}, {8, 4, 2, 1}};
-    for (int knob = 0; knob < 5; ++knob) {
+    const std::vector<std::vector<int>> opts = {{1, 2}, {128, 256, 512}, {2, 4, 8}, {0, 1}, {1, 2, 4}, {8, 4, 2, 1}};
+    for (int knob = 0; knob < 6; ++knob) {
         for (int v : opts[knob]) {
             TuneConfig c = best;
             if (knob == 0) c.overlap = v;
             if (knob == 1) c.fft0_threads = v;
             if (knob == 2) c.near_waves = v;
-            if (knob == 3) c.far_waves = v;
-            if (knob == 4) c.far_children = v;
+            if (knob == 3) c.near_prefetch = v;
+            if (knob == 4) c.far_waves = v;
+            if (knob == 5) c.far_children = v;
             plan->tune = c;
             const float ms = time_solves(plan, f, u, s, reps);
             if (ms < best_ms) {
@@ -1006,26 +1009,26 @@ lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_
     return LGF_OK;
 }
 
-lgf_status lgf_plan_get_tuning(lgf_plan_t plan, int32_t* fft0_threads, int32_t* near_waves, int32_t* far_waves,
-                               int32_t* far_children, int32_t* overlap) {
-    if (!plan) return fail(LGF_ERR_ARG, "NULL plan");
-    if (overlap) *overlap = plan->tune.overlap;
-    if (fft0_threads) *fft0_threads = plan->tune.fft0_threads;
-    if (near_waves) *near_waves = plan->tune.near_waves;
-    if (far_waves) *far_waves = plan->tune.far_waves;
-    if (far_children) *far_children = plan->tune.far_children;
+lgf_status lgf_plan_get_tuning(lgf_plan_t plan, lgf_tuning* out) {
+    if (!plan || !out) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_get_tuning");
+    out->fft0_threads = plan->tune.fft0_threads;
+    out->near_waves = plan->tune.near_waves;
+    out->near_prefetch = plan->tune.near_prefetch;
+    out->far_waves = plan->tune.far_waves;
+    out->far_children = plan->tune.far_children;
+    out->overlap = plan->tune.overlap;
     return LGF_OK;
 }
 
-lgf_status lgf_plan_set_tuning(lgf_plan_t plan, int32_t fft0_threads, int32_t near_waves, int32_t far_waves,
-                               int32_t far_children, int32_t overlap) {
-    if (!plan) return fail(LGF_ERR_ARG, "NULL plan");
+lgf_status lgf_plan_set_tuning(lgf_plan_t plan, const lgf_tuning* t) {
+    if (!plan || !t) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_set_tuning");
     TuneConfig c;
-    c.overlap = overlap;
-    c.fft0_threads = fft0_threads;
-    c.near_waves = near_waves;
-    c.far_waves = far_waves;
-    c.far_children = far_children;
+    c.fft0_threads = t->fft0_threads;
+    c.near_waves = t->near_waves;
+    c.near_prefetch = t->near_prefetch;
+    c.far_waves = t->far_waves;
+    c.far_children = t->far_children;
+    c.overlap = t->overlap;
     if (!valid_tune(c)) return fail(LGF_ERR_ARG, "lgf_plan_set_tuning: unsupported variant");
     plan->tune = c;
     return LGF_OK;

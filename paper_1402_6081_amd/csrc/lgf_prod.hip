@@ -52,7 +52,7 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 // One wave = 64 consecutive frequencies of one group; the 4 waves of a workgroup share the
 // frequency chunk and its kernel tile in LDS.  The tile has rows for dz in [-2, 2] (the
 // rows with |dz| = 2 are zero) so the source-slab loop needs no branches.
-template <typename T, int kNearWaves>
+template <typename T, int kNearWaves, bool kPrefetch>
 __global__ void __launch_bounds__(64 * kNearWaves)
     k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                         const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
@@ -78,14 +78,10 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     }
     const int32_t* sg = src64 + (int64_t)g * 64;
     const cplx<T>* fl = fhat + (int64_t)chunk * (nb + 1) * 64 + lane;  // this lane's frequency
-#pragma unroll 1
-    for (int sz = 0; sz < 4; ++sz) {  // source z slab; x and y unrolled
-        cplx<T> f[16];
-#pragma unroll
-        for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = fl[(int64_t)sg[sz * 16 + sxy] * 64];
-        // dz = cz - (sz - 1) in [-2, 2]; row base for cz = 0 and cz = 1
-        const cplx<T>* t0 = tile + (9 * (3 - sz)) * 64 + lane;
-        const cplx<T>* t1 = tile + (9 * (4 - sz)) * 64 + lane;
+    // source z slab sz contributes to target slab cz through kernel rows dz = cz - (sz - 1)
+    auto slab = [&](int sz, const cplx<T>(&f)[16]) {
+        const cplx<T>* t0 = tile + (9 * (3 - sz)) * 64 + lane;  // row base for cz = 0
+        const cplx<T>* t1 = tile + (9 * (4 - sz)) * 64 + lane;  // and cz = 1
 #pragma unroll
         for (int sxy = 0; sxy < 16; ++sxy) {
             const int sx = (sxy & 3) - 1, sy = (sxy >> 2) - 1;
@@ -96,6 +92,30 @@ __global__ void __launch_bounds__(64 * kNearWaves)
                 const cplx<T> k = ((c >> 2) ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
                 cmac(ar[c], ai[c], f[sxy], k);
             }
+        }
+    };
+    if constexpr (kPrefetch) {
+        // the next slab's 16 source values are in flight while this slab is consumed
+        cplx<T> fa[16], fb[16];
+#pragma unroll
+        for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = fl[(int64_t)sg[sxy] * 64];
+#pragma unroll 1
+        for (int sz = 0; sz < 4; sz += 2) {
+#pragma unroll
+            for (int sxy = 0; sxy < 16; ++sxy) fb[sxy] = fl[(int64_t)sg[(sz + 1) * 16 + sxy] * 64];
+            slab(sz, fa);
+            const int sn = sz + 2 < 4 ? sz + 2 : sz;  // past the end: a harmless reload
+#pragma unroll
+            for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = fl[(int64_t)sg[sn * 16 + sxy] * 64];
+            slab(sz + 1, fb);
+        }
+    } else {
+#pragma unroll 1
+        for (int sz = 0; sz < 4; ++sz) {  // source z slab; x and y unrolled
+            cplx<T> f[16];
+#pragma unroll
+            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = fl[(int64_t)sg[sz * 16 + sxy] * 64];
+            slab(sz, f);
         }
     }
     const int32_t* tg = tgt8 + (int64_t)g * 8;
@@ -278,25 +298,33 @@ __global__ void __launch_bounds__(kProdThreads)
     uhat[spec_at(P, w, nitems)] = cplx<T>{ar, ai};
 }
 
-template <typename T, int NW>
+template <typename T, int NW, bool PF>
 static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
                           cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, hipStream_t s) {
     const unsigned grid = xcd_grid(S / 64, (int)((ngroups + NW - 1) / NW));
-    hipLaunchKernelGGL((k_prod_near_grouped<T, NW>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64, uhat, S,
-                       (int)ngroups, (int)nitems);
+    hipLaunchKernelGGL((k_prod_near_grouped<T, NW, PF>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64,
+                       uhat, S, (int)ngroups, (int)nitems);
     return hipGetLastError();
+}
+
+template <typename T, bool PF>
+static hipError_t near_pf(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
+                          cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, hipStream_t s) {
+    switch (waves) {
+        case 2: return near_nw<T, 2, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
+        case 8: return near_nw<T, 8, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
+        default: return near_nw<T, 4, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
+    }
 }
 
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, hipStream_t s) {
+                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, int prefetch,
+                            hipStream_t s) {
     if (ngroups <= 0) return hipSuccess;
     if (S % 64) return hipErrorInvalidValue;
-    switch (waves) {
-        case 2: return near_nw<T, 2>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
-        case 8: return near_nw<T, 8>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
-        default: return near_nw<T, 4>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
-    }
+    return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, waves, s)
+                    : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, waves, s);
 }
 
 template <typename T, int NW, int CPL>
@@ -363,7 +391,7 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
 
 #define LGF_INST(T)                                                                                              \
     template hipError_t launch_prod_near<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,      \
-                                            cplx<T>*, int64_t, int64_t, int, int, hipStream_t);                  \
+                                            cplx<T>*, int64_t, int64_t, int, int, int, hipStream_t);             \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
                                                cplx<T>*, int64_t, int64_t, int, int, int, hipStream_t);          \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \

@@ -36,6 +36,13 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+TUNING_FIELDS = ("fft0_threads", "near_waves", "near_prefetch", "far_waves", "far_children", "overlap")
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in TUNING_FIELDS]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("max_queue", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("p", ctypes.c_int32), ("levels", ctypes.c_int32),
@@ -92,8 +99,8 @@ def library():
         L.lgf_graph_launch.argtypes = [vp, vp]
         L.lgf_graph_destroy.argtypes = [vp]
         L.lgf_plan_autotune.argtypes = [vp, vp, vp, vp, i32]
-        L.lgf_plan_get_tuning.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
-        L.lgf_plan_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.lgf_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.lgf_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.lgf_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
         L.lgf_server_submit.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(i64)]
         L.lgf_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(RequestResult)]
@@ -215,13 +222,14 @@ class Plan:
         return self.tuning()
 
     def tuning(self):
-        v = [ctypes.c_int32() for _ in range(5)]
-        _check(library().lgf_plan_get_tuning(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(("fft0_threads", "near_waves", "far_waves", "far_children", "overlap"), [x.value for x in v]))
+        t = Tuning()
+        _check(library().lgf_plan_get_tuning(self._h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k in TUNING_FIELDS}
 
-    def set_tuning(self, fft0_threads=0, near_waves=4, far_waves=0, far_children=0, overlap=0):
-        _check(library().lgf_plan_set_tuning(self._h, int(fft0_threads), int(near_waves), int(far_waves),
-                                             int(far_children), int(overlap)))
+    def set_tuning(self, fft0_threads=0, near_waves=4, near_prefetch=0, far_waves=0, far_children=0, overlap=0):
+        t = Tuning(int(fft0_threads), int(near_waves), int(near_prefetch), int(far_waves), int(far_children),
+                   int(overlap))
+        _check(library().lgf_plan_set_tuning(self._h, ctypes.byref(t)))
 
     def info(self):
         inf = PlanInfo()

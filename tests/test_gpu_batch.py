@@ -180,6 +180,7 @@ def test_autotune_keeps_results(L):
     assert choice["far_waves"] in (0, 1, 2, 4)
     assert choice["far_children"] in (0, 1, 2, 4, 8)
     assert choice["overlap"] in (0, 1, 2)
+    assert choice["near_prefetch"] in (0, 1)
     after = plan.solve(f)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
@@ -199,17 +200,18 @@ def test_every_variant_same_bits(L, prec):
         _say("case: kernel variants", prec, "n", n)
         plan = L.Plan(blocks, n, 6, 0, prec)
         f = torch.from_numpy(rng.standard_normal(plan.shape())).to("cuda:0", plan.dtype)
-        plan.set_tuning(0, 4, 2, 8, 2)
+        plan.set_tuning(far_waves=2, far_children=8, overlap=2)
         ref = plan.solve(f)
         torch.cuda.synchronize()
-        variants = [(ft, 4, 0, 0, 0) for ft in (0, 128, 256, 512)] + [(0, nw, 0, 0, 0) for nw in (2, 8)]
-        variants += [(0, 4, fw, fc, 0) for fw in (0, 1, 2, 4) for fc in (0, 1, 2, 4, 8)]
-        variants += [(0, 4, 0, 0, ov) for ov in (1, 2)]
+        variants = [dict(fft0_threads=ft) for ft in (0, 128, 256, 512)]
+        variants += [dict(near_waves=nw, near_prefetch=pf) for nw in (2, 4, 8) for pf in (0, 1)]
+        variants += [dict(far_waves=fw, far_children=fc) for fw in (0, 1, 2, 4) for fc in (0, 1, 2, 4, 8)]
+        variants += [dict(overlap=ov) for ov in (1, 2)]
         for v in variants:
-            plan.set_tuning(*v)
+            plan.set_tuning(**v)
             got = plan.solve(f)
             torch.cuda.synchronize()
             assert torch.equal(ref, got), v
         with pytest.raises(L.LGFError):
-            plan.set_tuning(64, 4, 2, 0, 0)
+            plan.set_tuning(fft0_threads=64)
         plan.close()

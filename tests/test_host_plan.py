@@ -115,5 +115,7 @@ def test_server_config_errors(L):
     assert lib.lgf_server_submit(None, None, 1, None, None, None) == 1
     assert lib.lgf_server_destroy(None) == 0
     assert lib.lgf_graph_create(None, None, None, None, ctypes.byref(h)) == 1
-    assert lib.lgf_plan_set_tuning(None, 0, 4, 2, 0, 0) == 1
+    t = L.Tuning(0, 4, 0, 0, 0, 0)
+    assert lib.lgf_plan_set_tuning(None, ctypes.byref(t)) == 1
+    assert lib.lgf_plan_get_tuning(None, ctypes.byref(t)) == 1
     assert lib.lgf_plan_create_batch(None, None, 0, 8, 6, 0, 0, None, ctypes.byref(h)) == 1
