@@ -28,10 +28,10 @@
  * synchronous device work (kernel spectra, list upload) on `hip_stream`.
  * A plan holds one workspace: solves on one plan must not overlap in time (enqueue
  * them on one stream).  Different plans may run concurrently on different streams.
- * For plans of at most 256 blocks the far-field chain (levels >= 1) of a solve runs on a
- * second stream owned by the plan, forked from and joined back into hip_stream with
- * events, so it overlaps the near-field transforms; from the caller's view the solve is
- * ordinary stream work on hip_stream either way.
+ * By default the far-field chain (levels >= 1) of a solve runs on a second stream owned by
+ * the plan, forked from and joined back into hip_stream with events, so it overlaps the
+ * near-field transforms (lgf_tuning.overlap); from the caller's view the solve is ordinary
+ * stream work on hip_stream either way.
  *
  * Errors.  Every entry point returns an lgf_status; nothing is printed and no C++
  * exception crosses the ABI.  lgf_last_error() returns a thread-local message for the
@@ -169,7 +169,7 @@ typedef struct {
     int32_t far_waves;      /* parent groups per workgroup of the level >= 1 Prod: 0, 1, 2, 4       */
     int32_t far_children;   /* children accumulated per lane of that kernel: 0, 1, 2, 4, 8           */
     int32_t overlap;        /* far-field levels on a second stream, concurrent with the near field:
-                               1 yes, 2 no, 0 for plans of at most 256 blocks                         */
+                               1 yes, 2 no, 0 default (yes)                                           */
 } lgf_tuning;
 
 /*

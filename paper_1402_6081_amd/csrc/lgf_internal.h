@@ -63,7 +63,7 @@ struct TuneConfig {
     int near_prefetch = 0; // that kernel's source loads one z slab ahead: 0, 1
     int far_waves = 0;     // parent groups per workgroup of the level >= 1 Prod kernel: 1, 2, 4, 0 = by level size
     int far_children = 0;  // children per lane of that kernel: 8, 4, 2, 1, or 0 = by level size
-    int overlap = 0;       // far-field chain on a second stream: 1 = yes, 2 = no, 0 = for small plans
+    int overlap = 0;       // far-field chain on a second stream: 1 = yes, 2 = no, 0 = default (yes)
 };
 
 // Reg block -> level-1 interval: out[b] = (A x A x A) f[b], A is p x n (row-major)

@@ -28,7 +28,6 @@
 
 using namespace lgfdev;
 
-constexpr int64_t kOverlapMaxBlocks = 256;
 
 namespace {
 
@@ -575,9 +574,10 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
         hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)
         return fail(LGF_ERR_DEVICE, "stream/event creation failed");
-    // Large plans saturate the GPU with either chain alone; measured on MI355X the
-    // concurrent chains then only contend, so overlap is used for small plans only.
-    pl->overlap = H.nb <= kOverlapMaxBlocks;
+    // The far-field chain (small, latency-bound kernels) and the near field (HBM-bound
+    // transforms and products) overlap well: measured on MI355X the concurrent chains are
+    // faster at every plan size tried (64 to 18802 blocks), so it is the default.
+    pl->overlap = true;
     pl->lv.assign(H.L + 1, LevelPlan());
     for (int l = 1; l <= H.L; ++l) {
         pl->lv[l].nint = H.lv[l].nint;
