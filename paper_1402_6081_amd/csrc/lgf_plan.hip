@@ -369,8 +369,8 @@ struct lgf_plan_s {
     int prof_max = 0, prof_solves = 0, prof_cursor = 0;
     bool prof_on = false;
     // far-field chain on a second (default-priority) stream for small plans
-    hipStream_t far_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t far_stream = nullptr, far_stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
     bool overlap = false;
 
     ~lgf_plan_s() {
@@ -378,7 +378,10 @@ struct lgf_plan_s {
         for (auto& e : events) hipEventDestroy(e);
         if (ev_fork) hipEventDestroy(ev_fork);
         if (ev_join) hipEventDestroy(ev_join);
+        if (ev_fork2) hipEventDestroy(ev_fork2);
+        if (ev_join2) hipEventDestroy(ev_join2);
         if (far_stream) hipStreamDestroy(far_stream);
+        if (far_stream2) hipStreamDestroy(far_stream2);
         budget_release(ws_bytes);
     }
 };
@@ -475,61 +478,95 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     mark.solve_begin(s);
     const bool far = pl->Ltop >= 1;
     const bool overlap = tc.overlap == 0 ? pl->overlap : tc.overlap == 1;
+    // streams: s = near field (level 0), s2 = level 1, s3 = levels >= 2 (the coarse levels'
+    // small kernels run beside the level-1 M2L); one stream when overlap is off.
+    // Under graph capture the coarse levels stay on s2: capturing the nested fork (s2 -> s3
+    // -> s2) ended in a host crash inside graph creation on this ROCm stack, so a captured
+    // solve uses the two-stream schedule.
+    const bool split = overlap && !t_capturing;
     hipStream_t s2 = overlap ? pl->far_stream : s;
+    hipStream_t s3 = split ? pl->far_stream2 : s2;
+    // forward work of level l: PadFFT and the M2L products (Steps 1-2)
+    auto level_up = [&](int l, hipStream_t st) -> hipError_t {
+        LevelPlan& L = pl->lv[l];
+        if (L.pairs() == 0) return hipSuccess;
+        LGF_STEP(st, (launch_pad_fft<T>(p, (const T*)L.d_ftil, (C*)L.d_fhat, L.nint, st)), lname("fft_fwd_l", l),
+                 lvN(l) * (p3 * es + S1 * cs), lvN(l) * fft_flops(2 * p));
+        if (L.zero_uhat)
+            LGF_STEP(st, zero_fill(L.d_uhat, L.nint * S1p * 2 * (int64_t)sizeof(T), st), lname("zero_uhat_l", l),
+                     lvN(l) * S1 * cs, 0.0);
+        if (L.sib_pairs > 0) {
+            const LevelPlan& Pp = pl->lv[l + 1];
+            LGF_STEP(st,
+                     (launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216,
+                                             (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S, tc.far_waves,
+                                             tc.far_children, st)),
+                     lname("prod_l", l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.sib_pairs * S1 * 8.0);
+        }
+        if (L.csr_entries > 0)
+            LGF_STEP(st,
+                     (launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra_csr->dev, L.d_csr_ptr, L.d_csr_src,
+                                         L.d_csr_off, L.d_csr_tgt, (C*)L.d_uhat, L.ncsr, L.nint, L.spectra_csr->noff,
+                                         L.spectra_csr->S, st)),
+                     lname("prod_top_l", l), (2.0 * lvN(l) + L.spectra_csr->noff) * S1 * cs,
+                     (double)L.csr_entries * S1 * 8.0);
+        return hipSuccess;
+    };
+    // inverse of level l (IFFT + Trunc, or zero when the level has no list entries)
+    auto level_down = [&](int l, hipStream_t st) -> hipError_t {
+        LevelPlan& L = pl->lv[l];
+        if (L.pairs() == 0) {
+            LGF_STEP(st, zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(U), st), lname("zero_l", l),
+                     lvN(l) * p3 * us, 0.0);
+        } else {
+            LGF_STEP(st, (launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, st)),
+                     lname("fft_inv_l", l), lvN(l) * (S1 * cs + p3 * us), lvN(l) * fft_flops(2 * p));
+        }
+        return hipSuccess;
+    };
+    // Interp from level l + 1 down to level l, accumulated (Step 3)
+    auto interp = [&](int l, hipStream_t st) -> hipError_t {
+        LGF_STEP(st,
+                 (launch_interp_down<U>((const U*)pl->lv[l + 1].d_util, pl->lv[l + 1].d_child8, pl->d_C01,
+                                        (U*)pl->lv[l].d_util, pl->lv[l + 1].nint, p, st)),
+                 "interp_l" + std::to_string(l + 1) + "_l" + std::to_string(l), (lvN(l + 1) + 2.0 * lvN(l)) * p3 * us,
+                 lvN(l) * 2.0 * 3.0 * p3 * p);
+        return hipSuccess;
+    };
     if (far) {
-        // ---- far field (levels >= 1), on the second stream for small plans: Reg up, FFT,
-        //      M2L, IFFT, Interp down
         if (overlap) {
             if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(s2, pl->ev_fork, 0)) != hipSuccess) return e;
         }
         LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nb, n, p, s2)), "reg_l0_l1",
                  nb * (n3 + p3) * es, nb * 2.0 * (p * n3 + p * p * n * n + p3 * n));
-        for (int l = 1; l < pl->Ltop; ++l)
-            LGF_STEP(s2,
-                     (launch_reg_up<T>((const T*)pl->lv[l].d_ftil, pl->lv[l + 1].d_child8, pl->d_C01,
-                                       (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s2)),
-                     "reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1), (lvN(l) + lvN(l + 1)) * p3 * es,
-                     lvN(l) * 2.0 * 3.0 * p3 * p);
-        for (int l = 1; l <= pl->Ltop; ++l) {
-            LevelPlan& L = pl->lv[l];
-            if (L.pairs() == 0) continue;
-            LGF_STEP(s2, (launch_pad_fft<T>(p, (const T*)L.d_ftil, (C*)L.d_fhat, L.nint, s2)), lname("fft_fwd_l", l),
-                     lvN(l) * (p3 * es + S1 * cs), lvN(l) * fft_flops(2 * p));
-            if (L.zero_uhat)
-                LGF_STEP(s2, zero_fill(L.d_uhat, L.nint * S1p * 2 * (int64_t)sizeof(T), s2), lname("zero_uhat_l", l),
-                         lvN(l) * S1 * cs, 0.0);
-            if (L.sib_pairs > 0) {
-                const LevelPlan& Pp = pl->lv[l + 1];
-                LGF_STEP(s2,
-                         (launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8,
-                                                 Pp.d_src216, (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S,
-                                                 tc.far_waves, tc.far_children, s2)),
-                         lname("prod_l", l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.sib_pairs * S1 * 8.0);
+        const bool coarse = pl->Ltop >= 2;
+        if (coarse) {
+            // levels >= 2 on s3: Reg up, their M2L, and the down pass to level 2
+            if (split) {
+                if ((e = hipEventRecord(pl->ev_fork2, s2)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(s3, pl->ev_fork2, 0)) != hipSuccess) return e;
             }
-            if (L.csr_entries > 0)
-                LGF_STEP(s2,
-                         (launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra_csr->dev, L.d_csr_ptr,
-                                             L.d_csr_src, L.d_csr_off, L.d_csr_tgt, (C*)L.d_uhat, L.ncsr, L.nint,
-                                             L.spectra_csr->noff, L.spectra_csr->S, s2)),
-                         lname("prod_top_l", l), (2.0 * lvN(l) + L.spectra_csr->noff) * S1 * cs,
-                         (double)L.csr_entries * S1 * 8.0);
+            for (int l = 1; l < pl->Ltop; ++l)
+                LGF_STEP(s3,
+                         (launch_reg_up<T>((const T*)pl->lv[l].d_ftil, pl->lv[l + 1].d_child8, pl->d_C01,
+                                           (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s3)),
+                         "reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1),
+                         (lvN(l) + lvN(l + 1)) * p3 * es, lvN(l) * 2.0 * 3.0 * p3 * p);
+            for (int l = 2; l <= pl->Ltop; ++l)
+                if ((e = level_up(l, s3)) != hipSuccess) return e;
+            for (int l = pl->Ltop; l >= 2; --l) {
+                if ((e = level_down(l, s3)) != hipSuccess) return e;
+                if (l < pl->Ltop && (e = interp(l, s3)) != hipSuccess) return e;
+            }
+            if (split && (e = hipEventRecord(pl->ev_join2, s3)) != hipSuccess) return e;
         }
-        for (int l = pl->Ltop; l >= 1; --l) {
-            LevelPlan& L = pl->lv[l];
-            if (L.pairs() == 0) {
-                LGF_STEP(s2, zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(U), s2), lname("zero_l", l),
-                         lvN(l) * p3 * us, 0.0);
-            } else {
-                LGF_STEP(s2, (launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, s2)),
-                         lname("fft_inv_l", l), lvN(l) * (S1 * cs + p3 * us), lvN(l) * fft_flops(2 * p));
-            }
-            if (l < pl->Ltop)
-                LGF_STEP(s2,
-                         (launch_interp_down<U>((const U*)pl->lv[l + 1].d_util, pl->lv[l + 1].d_child8, pl->d_C01,
-                                                (U*)L.d_util, pl->lv[l + 1].nint, p, s2)),
-                         "interp_l" + std::to_string(l + 1) + "_l" + std::to_string(l),
-                         (lvN(l + 1) + 2.0 * lvN(l)) * p3 * us, lvN(l) * 2.0 * 3.0 * p3 * p);
+        // level 1 on s2
+        if ((e = level_up(1, s2)) != hipSuccess) return e;
+        if ((e = level_down(1, s2)) != hipSuccess) return e;
+        if (coarse) {
+            if (split && (e = hipStreamWaitEvent(s2, pl->ev_join2, 0)) != hipSuccess) return e;
+            if ((e = interp(1, s2)) != hipSuccess) return e;
         }
         if (overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
     }
@@ -571,8 +608,11 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     pl->solve_offsets = H.solve_offsets;
     hipGetDevice(&pl->device);
     if (hipStreamCreateWithFlags(&pl->far_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&pl->far_stream2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_fork2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming) != hipSuccess)
         return fail(LGF_ERR_DEVICE, "stream/event creation failed");
     // The far-field chain (small, latency-bound kernels) and the near field (HBM-bound
     // transforms and products) overlap well: measured on MI355X the concurrent chains are
