@@ -172,7 +172,7 @@ def _measure(plan, f, u, steps, warmup, graph=True, tune=True):
         breakdown and the roofline;
       * graph launches with the tuned variants (far field concurrent with the near field
         when that is faster): the rate and latencies."""
-    choice = plan.autotune(f, u, reps=5) if tune else plan.tuning()
+    choice = plan.autotune(f, u, reps=10) if tune else plan.tuning()
     plan.set_tuning(**dict(choice, overlap=2))
     dt_e, prof = _time_solves(plan, f, u, steps, warmup)
     plan.set_tuning(**choice)

@@ -28,10 +28,10 @@
  * synchronous device work (kernel spectra, list upload) on `hip_stream`.
  * A plan holds one workspace: solves on one plan must not overlap in time (enqueue
  * them on one stream).  Different plans may run concurrently on different streams.
- * By default the far-field chain (levels >= 1) of a solve runs on a second stream owned by
- * the plan, forked from and joined back into hip_stream with events, so it overlaps the
- * near-field transforms (lgf_tuning.overlap); from the caller's view the solve is ordinary
- * stream work on hip_stream either way.
+ * By default the far-field levels of a solve run on streams owned by the plan (level 1 on
+ * one, levels >= 2 on another), forked from and joined back into hip_stream with events, so
+ * they overlap the near-field transforms (lgf_tuning.overlap); from the caller's view the
+ * solve is ordinary stream work on hip_stream either way.
  *
  * Errors.  Every entry point returns an lgf_status; nothing is printed and no C++
  * exception crosses the ABI.  lgf_last_error() returns a thread-local message for the
@@ -168,13 +168,15 @@ typedef struct {
     int32_t near_prefetch;  /* level-0 Prod issues the next source slab's loads early: 0, 1         */
     int32_t far_waves;      /* parent groups per workgroup of the level >= 1 Prod: 0, 1, 2, 4       */
     int32_t far_children;   /* children accumulated per lane of that kernel: 0, 1, 2, 4, 8           */
-    int32_t overlap;        /* far-field levels on a second stream, concurrent with the near field:
-                               1 yes, 2 no, 0 default (yes)                                           */
+    int32_t overlap;        /* schedule of a solve: 1 three concurrent branches (near field, level 1,
+                               levels >= 2), 3 two (near field, levels >= 1), 2 one stream,
+                               0 default (three)                                                      */
 } lgf_tuning;
 
 /*
  * Autotuner: runs (1 + reps) solves per candidate variant on (f, u) (DEVICE buffers of the
- * plan's shape; u is overwritten) in a coordinate search over the fields of lgf_tuning,
+ * plan's shape; u is overwritten), each as one launch of the solve's HIP graph, in a
+ * coordinate search over the fields of lgf_tuning,
  * keeps the fastest median device time, and remembers the choice for later plans of the
  * same (n, p, precision, power-of-two block-count bucket) in this process; if the
  * environment variable LGF_TUNE_FILE names a file the choice is appended there and read by

@@ -10,6 +10,7 @@
 // Lists: level 0 near neighbours |Q-P|_inf <= 1; level l < L: children of the parent's
 // neighbours with |Q-P|_inf >= 2; top level L: every interval with |Q-P|_inf >= 2.
 #include <algorithm>
+#include <initializer_list>
 #include <array>
 #include <atomic>
 #include <cmath>
@@ -454,8 +455,20 @@ inline double fft_flops(int M) {  // Table 1: 2 (8 N_b) log2(8 N_b) for a padded
     return 2.0 * N * std::log2(N);
 }
 
+// Independent pieces of one solve, for graphs assembled from separately captured parts
+// (lgf_graph_create).  Dependencies: REG1 -> {L1, COARSE} -> JOIN; {NEAR, JOIN} -> FINAL.
+enum : unsigned {
+    kSegNear = 1,     // level 0: PadFFT, Prod, IFFT
+    kSegReg1 = 2,     // Reg block -> level 1
+    kSegL1 = 4,       // level 1: PadFFT, M2L, IFFT
+    kSegCoarse = 8,   // Reg up, levels >= 2 up and down to level 2
+    kSegJoin = 16,    // Interp level 2 -> level 1
+    kSegFinal = 32,   // Interp level 1 -> blocks, add to the near field
+    kSegAll = 63
+};
+
 template <typename T>
-hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
+hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned segs = kSegAll) {
     using C = cplx<T>;
     using U = typename FarAcc<T>::type;
     const int n = pl->n, p = pl->p;
@@ -477,13 +490,19 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     } while (0)
     mark.solve_begin(s);
     const bool far = pl->Ltop >= 1;
-    const bool overlap = tc.overlap == 0 ? pl->overlap : tc.overlap == 1;
+    // a subset of segments is issued in order on s alone (no streams or events of its own)
+    const bool all = segs == kSegAll;
+    // overlap: 1 (and the default 0) three concurrent branches, 3 two (the coarse levels
+    // follow level 1 on one stream), 2 a single stream
+    const int ov = tc.overlap == 0 ? (pl->overlap ? 1 : 2) : tc.overlap;
+    const bool overlap = all && ov != 2;
     // streams: s = near field (level 0), s2 = level 1, s3 = levels >= 2 (the coarse levels'
     // small kernels run beside the level-1 M2L); one stream when overlap is off.
-    // Under graph capture the coarse levels stay on s2: capturing the nested fork (s2 -> s3
-    // -> s2) ended in a host crash inside graph creation on this ROCm stack, so a captured
-    // solve uses the two-stream schedule.
-    const bool split = overlap && !t_capturing;
+    // A whole solve captured on one stream keeps the coarse levels on s2: capturing the
+    // nested fork (s2 -> s3 -> s2) ended in a host crash inside graph creation on this ROCm
+    // stack.  lgf_graph_create builds the concurrent schedule from separately captured
+    // segments instead.
+    const bool split = overlap && ov == 1 && !t_capturing;
     hipStream_t s2 = overlap ? pl->far_stream : s;
     hipStream_t s3 = split ? pl->far_stream2 : s2;
     // forward work of level l: PadFFT and the M2L products (Steps 1-2)
@@ -538,10 +557,11 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
             if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(s2, pl->ev_fork, 0)) != hipSuccess) return e;
         }
-        LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nb, n, p, s2)), "reg_l0_l1",
-                 nb * (n3 + p3) * es, nb * 2.0 * (p * n3 + p * p * n * n + p3 * n));
+        if (segs & kSegReg1)
+            LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nb, n, p, s2)), "reg_l0_l1",
+                     nb * (n3 + p3) * es, nb * 2.0 * (p * n3 + p * p * n * n + p3 * n));
         const bool coarse = pl->Ltop >= 2;
-        if (coarse) {
+        if (coarse && (segs & kSegCoarse)) {
             // levels >= 2 on s3: Reg up, their M2L, and the down pass to level 2
             if (split) {
                 if ((e = hipEventRecord(pl->ev_fork2, s2)) != hipSuccess) return e;
@@ -562,25 +582,29 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
             if (split && (e = hipEventRecord(pl->ev_join2, s3)) != hipSuccess) return e;
         }
         // level 1 on s2
-        if ((e = level_up(1, s2)) != hipSuccess) return e;
-        if ((e = level_down(1, s2)) != hipSuccess) return e;
-        if (coarse) {
+        if (segs & kSegL1) {
+            if ((e = level_up(1, s2)) != hipSuccess) return e;
+            if ((e = level_down(1, s2)) != hipSuccess) return e;
+        }
+        if (coarse && (segs & kSegJoin)) {
             if (split && (e = hipStreamWaitEvent(s2, pl->ev_join2, 0)) != hipSuccess) return e;
             if ((e = interp(1, s2)) != hipSuccess) return e;
         }
         if (overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
     }
     // ---- near field (level 0) on the caller's stream
-    LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nb, s, tc.fft0_threads), "fft_fwd_l0",
-             nb * (n3 * es + S0 * cs), nb * fft_flops(2 * n));
-    LGF_STEP(s,
-             launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8, pl->d_g0_src64,
-                                 (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S, tc.near_waves,
-                                 tc.near_prefetch, s),
-             "prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
-    LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s, tc.fft0_threads)), "fft_inv_l0",
-             nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
-    if (far) {
+    if (segs & kSegNear) {
+        LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nb, s, tc.fft0_threads), "fft_fwd_l0",
+                 nb * (n3 * es + S0 * cs), nb * fft_flops(2 * n));
+        LGF_STEP(s,
+                 launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8,
+                                     pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S,
+                                     tc.near_waves, tc.near_prefetch, s),
+                 "prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
+        LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s, tc.fft0_threads)),
+                 "fft_inv_l0", nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
+    }
+    if (far && (segs & kSegFinal)) {
         if (overlap && (e = hipStreamWaitEvent(s, pl->ev_join, 0)) != hipSuccess) return e;
         LGF_STEP(s, (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s)), "final_l1_l0",
                  nb * (2.0 * n3 * es + p3 * us), nb * 2.0 * (p3 * n + p * p * n * n + p * n3));
@@ -590,9 +614,9 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t solve_dispatch(lgf_plan_s* pl, const void* f, void* u, hipStream_t s) {
-    return pl->prec == LGF_F64 ? run_solve<double>(pl, (const double*)f, (double*)u, s)
-                               : run_solve<float>(pl, (const float*)f, (float*)u, s);
+hipError_t solve_dispatch(lgf_plan_s* pl, const void* f, void* u, hipStream_t s, unsigned segs = kSegAll) {
+    return pl->prec == LGF_F64 ? run_solve<double>(pl, (const double*)f, (double*)u, s, segs)
+                               : run_solve<float>(pl, (const float*)f, (float*)u, s, segs);
 }
 
 lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan_s* pl) {
@@ -720,6 +744,106 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     return LGF_OK;
 }
 
+// Capture the given segments of a solve, issued in order on a private stream, as a graph.
+hipError_t capture_part(lgf_plan_t plan, const void* f, void* u, unsigned segs, hipGraph_t* out) {
+    *out = nullptr;
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        t_capturing = true;
+        const hipError_t es = solve_dispatch(plan, f, u, cap, segs);
+        t_capturing = false;
+        e = hipStreamEndCapture(cap, out);
+        if (es != hipSuccess) e = es;
+    }
+    hipStreamDestroy(cap);
+    return e;
+}
+
+// Copy the kernel nodes of a captured single-stream graph (a chain) into `parent`, the first
+// one depending on `deps`; *last receives the copy of the chain's last node (or stays NULL
+// for an empty chain).
+hipError_t append_chain(hipGraph_t parent, hipGraph_t part, const std::vector<hipGraphNode_t>& deps,
+                               hipGraphNode_t* last) {
+    *last = nullptr;
+    size_t nroots = 0;
+    hipError_t e = hipGraphGetRootNodes(part, nullptr, &nroots);
+    if (e != hipSuccess || nroots == 0) return e;
+    if (nroots != 1) return hipErrorInvalidValue;
+    hipGraphNode_t node = nullptr;
+    if ((e = hipGraphGetRootNodes(part, &node, &nroots)) != hipSuccess) return e;
+    std::vector<hipGraphNode_t> d = deps;
+    for (;;) {
+        hipGraphNodeType type;
+        if ((e = hipGraphNodeGetType(node, &type)) != hipSuccess) return e;
+        if (type != hipGraphNodeTypeKernel) return hipErrorInvalidValue;  // only kernels are captured
+        hipKernelNodeParams kp;
+        if ((e = hipGraphKernelNodeGetParams(node, &kp)) != hipSuccess) return e;
+        hipGraphNode_t copy = nullptr;
+        if ((e = hipGraphAddKernelNode(&copy, parent, d.empty() ? nullptr : d.data(), d.size(), &kp)) != hipSuccess)
+            return e;
+        *last = copy;
+        d.assign(1, copy);
+        size_t nd = 0;
+        if ((e = hipGraphNodeGetDependentNodes(node, nullptr, &nd)) != hipSuccess) return e;
+        if (nd == 0) return hipSuccess;
+        if (nd != 1) return hipErrorInvalidValue;
+        if ((e = hipGraphNodeGetDependentNodes(node, &node, &nd)) != hipSuccess) return e;
+    }
+}
+
+lgf_status make_graph(lgf_plan_t plan, const void* f, void* u, lgf_graph_s** out) {
+    *out = nullptr;
+    lgf_graph_s* g = new lgf_graph_s();
+    hipError_t e = hipSuccess;
+    const int ov = plan->tune.overlap == 0 ? (plan->overlap ? 1 : 2) : plan->tune.overlap;
+    if (ov != 1 || plan->Ltop < 1) {
+        // one stream, or two (fork/join from the capture stream), captured as issued
+        e = capture_part(plan, f, u, kSegAll, &g->graph);
+    } else {
+        // concurrent branches with explicit dependencies:
+        //   near ------------------------------------------\
+        //   reg1 -> level 1 --------------------> join -> final
+        //        \-> coarse levels ----------/
+        // Each branch is captured alone on one stream (a chain of kernel nodes) and its nodes
+        // are copied into one flat graph.
+        e = hipGraphCreate(&g->graph, 0);
+        const bool coarse = plan->Ltop >= 2;
+        hipGraphNode_t last[6] = {};
+        std::vector<hipGraph_t> parts;
+        auto add = [&](int slot, unsigned segs, std::initializer_list<int> deps) {
+            if (e != hipSuccess) return;
+            hipGraph_t part = nullptr;
+            e = capture_part(plan, f, u, segs, &part);
+            if (e != hipSuccess) return;
+            parts.push_back(part);
+            std::vector<hipGraphNode_t> d;
+            for (int k : deps)
+                if (last[k]) d.push_back(last[k]);
+            e = append_chain(g->graph, part, d, &last[slot]);
+        };
+        add(0, kSegNear, {});
+        add(1, kSegReg1, {});
+        add(2, kSegL1, {1});
+        if (coarse) {
+            add(3, kSegCoarse, {1});
+            add(4, kSegJoin, {2, 3});
+        }
+        add(5, kSegFinal, {0, coarse ? 4 : 2});
+        if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        for (hipGraph_t part : parts) hipGraphDestroy(part);
+    }
+    if (e == hipSuccess && !g->exec) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(LGF_ERR_DEVICE, std::string("graph creation failed: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return LGF_OK;
+}
+
 // ------------------------------------------------------------------ autotuner
 // Candidate kernel variants are timed on the plan itself (median of a few solves); the
 // winner is remembered per (n, p, precision, block-count bucket) for the process and, if
@@ -748,7 +872,7 @@ bool valid_tune(const TuneConfig& c) {
     const bool fc = c.far_children == 0 || c.far_children == 1 || c.far_children == 2 || c.far_children == 4 ||
                     c.far_children == 8;
     const bool fw0 = c.far_waves == 0;
-    return f && nw && (fw || fw0) && fc && c.overlap >= 0 && c.overlap <= 2;
+    return f && nw && (fw || fw0) && fc && c.overlap >= 0 && c.overlap <= 3;
 }
 
 void tune_load_file() {
@@ -777,15 +901,18 @@ void tune_store(const TuneKey& k, const TuneConfig& c) {
     std::fclose(fh);
 }
 
-// median device time (ms) of `reps` solves with the plan's current configuration
+// median device time (ms) of `reps` solves with the plan's current configuration, each one
+// launch of the solve's graph (the way solves are usually issued)
 float time_solves(lgf_plan_s* pl, const void* f, void* u, hipStream_t s, int reps) {
+    lgf_graph_s* g = nullptr;
+    if (make_graph(pl, f, u, &g) != LGF_OK) return 1e30f;
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
     std::vector<float> t;
     for (int r = 0; r < reps + 1; ++r) {
         hipEventRecord(a, s);
-        if (solve_dispatch(pl, f, u, s) != hipSuccess) {
+        if (hipGraphLaunch(g->exec, s) != hipSuccess) {
             t.assign(1, 1e30f);
             break;
         }
@@ -797,6 +924,7 @@ float time_solves(lgf_plan_s* pl, const void* f, void* u, hipStream_t s, int rep
     }
     hipEventDestroy(a);
     hipEventDestroy(b);
+    delete g;
     std::sort(t.begin(), t.end());
     return t[t.size() / 2];
 }
@@ -979,30 +1107,9 @@ lgf_status lgf_solve_many(const lgf_plan_t* plans, const void* const* f, void* c
 lgf_status lgf_graph_create(lgf_plan_t plan, const void* f, void* u, void* hip_stream, lgf_graph_t* out) {
     if (!plan || !f || !u || !out) return fail(LGF_ERR_ARG, "NULL argument to lgf_graph_create");
     *out = nullptr;
-    hipStream_t cap = nullptr;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
-        return fail(LGF_ERR_DEVICE, "stream creation failed");
     // the capture must not start while the caller's stream still has work for these buffers
     if (hip_stream) hipStreamSynchronize((hipStream_t)hip_stream);
-    lgf_graph_s* g = new lgf_graph_s();
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        t_capturing = true;
-        hipError_t es = solve_dispatch(plan, f, u, cap);
-        t_capturing = false;
-        hipGraph_t graph = nullptr;
-        e = hipStreamEndCapture(cap, &graph);
-        g->graph = graph;
-        if (es != hipSuccess) e = es;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-    hipStreamDestroy(cap);
-    if (e != hipSuccess) {
-        delete g;
-        return fail(LGF_ERR_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
-    }
-    *out = g;
-    return LGF_OK;
+    return make_graph(plan, f, u, out);
 }
 
 lgf_status lgf_graph_launch(lgf_graph_t graph, void* hip_stream) {
@@ -1019,29 +1126,45 @@ lgf_status lgf_graph_destroy(lgf_graph_t graph) {
 
 lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_stream, int32_t reps) {
     if (!plan || !f || !u) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_autotune");
-    if (reps < 1) reps = 3;
+    if (reps < 1) reps = 5;
     hipStream_t s = (hipStream_t)hip_stream;
-    TuneConfig best = plan->tune;
-    float best_ms = time_solves(plan, f, u, s, reps);
-    // coordinate search: each knob in turn, keeping the best value of the others
-    const std::vector<std::vector<int>> opts = {{1, 2}, {128, 256, 512}, {2, 4, 8}, {0, 1}, {1, 2, 4}, {8, 4, 2, 1}};
-    for (int knob = 0; knob < 6; ++knob) {
-        for (int v : opts[knob]) {
-            TuneConfig c = best;
-            if (knob == 0) c.overlap = v;
-            if (knob == 1) c.fft0_threads = v;
-            if (knob == 2) c.near_waves = v;
-            if (knob == 3) c.near_prefetch = v;
-            if (knob == 4) c.far_waves = v;
-            if (knob == 5) c.far_children = v;
-            plan->tune = c;
-            const float ms = time_solves(plan, f, u, s, reps);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
+    const TuneConfig start = plan->tune;
+    auto timed = [&](const TuneConfig& c) {
+        plan->tune = c;
+        return time_solves(plan, f, u, s, reps);
+    };
+    TuneConfig best = start;
+    float best_ms = timed(best);
+    // coordinate search, two sweeps: each knob in turn, keeping the best value of the others
+    // (0 = the per-level default for the level >= 1 Prod knobs)
+    const std::vector<std::vector<int>> opts = {{1, 3, 2},    {128, 256, 512}, {2, 4, 8},
+                                                {0, 1},       {0, 1, 2, 4},    {0, 8, 4, 2, 1}};
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        for (int knob = 0; knob < 6; ++knob) {
+            for (int v : opts[knob]) {
+                TuneConfig c = best;
+                if (knob == 0) c.overlap = v;
+                if (knob == 1) c.fft0_threads = v;
+                if (knob == 2) c.near_waves = v;
+                if (knob == 3) c.near_prefetch = v;
+                if (knob == 4) c.far_waves = v;
+                if (knob == 5) c.far_children = v;
+                const float ms = timed(c);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
             }
         }
     }
+    // guard against a choice that only won on noise: alternate the starting and the tuned
+    // configuration and keep the tuned one only if it is faster by at least 1%
+    float t_start = 0.f, t_best = 0.f;
+    for (int r = 0; r < 3; ++r) {
+        t_start += timed(start);
+        t_best += timed(best);
+    }
+    if (!(t_best < 0.99f * t_start)) best = start;
     plan->tune = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_file();
