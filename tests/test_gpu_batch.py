@@ -218,3 +218,39 @@ def test_every_variant_same_bits(L, prec):
         with pytest.raises(L.LGFError):
             plan.set_tuning(fft0_threads=64)
         plan.close()
+
+
+def test_batch_workload_fp32_against_fp64_and_exact(L):
+    """The batched workload: 64 Eden layouts of U{8..512} blocks of 16^3, p = 8, one batch
+    plan.  Every solve of the FP32 batch against the FP64 batch (<= 1e-6), and 4 sampled
+    solves against the exact direct sum (oracle) at 256 targets (<= FLGF truncation + 1e-6)."""
+    from oracle import lgf as olgf
+    _say("case: 64-layout batch workload, FP32 vs FP64, 4 solves vs exact")
+    rng = np.random.default_rng(4)
+    sizes = rng.integers(8, 513, size=64)
+    lays = [W.eden_layout(int(s), rng) for s in sizes]
+    fs = [W.zero_mean_gaussians(b, 16, rng, max(1, b.shape[0] // 8))[0] for b in lays]
+    out = {}
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        bp = L.Plan.batch(lays, 16, 8, 0, prec)
+        u = bp.solve(torch.from_numpy(np.concatenate(fs)).to("cuda:0", dt))
+        torch.cuda.synchronize()
+        out[prec] = [x.double().cpu().numpy() for x in bp.split(u)]
+        bp.close()
+    worst = max(rel(a, b) for a, b in zip(out["f32"], out["f64"]))
+    _say("  worst FP32 vs FP64 over 64 solves: %.3g" % worst)
+    assert worst <= 1e-6
+    for k in rng.choice(64, 4, replace=False):
+        # the oracle's FLGF on the whole layout, and the exact sum at 256 sampled targets
+        ref = flgf.solve(lays[k], fs[k], 16, 8, 0).reshape(-1)
+        P = W.points_of(lays[k], 16).reshape(-1, 3)
+        idx = rng.choice(P.shape[0], 256, replace=False)
+        exact = olgf.direct_sum(P, fs[k].reshape(-1), P[idx])
+        got = out["f64"][k].reshape(-1)
+        scale = float(np.max(np.abs(exact)))
+        trunc = float(np.max(np.abs(ref[idx] - exact))) / scale
+        err_a = float(np.max(np.abs(got[idx] - exact))) / scale
+        _say("  solve %d (%d blocks): vs oracle FLGF %.3g, vs exact %.3g (truncation %.3g)"
+             % (k, lays[k].shape[0], rel(got, ref), err_a, trunc))
+        assert rel(got, ref) <= 1e-12
+        assert err_a <= trunc + 1e-12

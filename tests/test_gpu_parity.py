@@ -205,3 +205,28 @@ def test_large_config_vortex_ring(L):
     err32 = float(np.max(np.abs(u32 - u64)) / np.max(np.abs(u64)))
     _say("  FP32 vs FP64 %.3g" % err32)
     assert err32 <= 1e-6
+
+
+def test_medium_config_tuned_graph(L):
+    """The 128^3 workload in the launch configuration the benchmark times: autotuned kernel
+    variants and schedule, one HIP-graph launch per solve.  FP64 against the oracle's FLGF
+    at full size; FP32 against FP64 within 1e-6."""
+    _say("case: medium config, autotuned graph launches, FP64 + FP32")
+    c = W.config_medium()
+    ref = flgf.solve(c["blocks"], c["f"], c["n"], c["p"], c["levels"])
+    out = {}
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        plan = L.Plan(c["blocks"], c["n"], c["p"], c["levels"], prec)
+        f = torch.from_numpy(c["f"]).to("cuda:0", dt)
+        u = torch.empty_like(f)
+        plan.autotune(f, u, reps=2)
+        g = plan.graph(f, u)
+        for _ in range(3):
+            u.fill_(float("nan"))
+            g.launch()
+            torch.cuda.synchronize()
+        out[prec] = u.double().cpu().numpy()
+        g.close()
+        plan.close()
+    assert rel(out["f64"], ref) <= fp64_tol(c["p"])
+    assert rel(out["f32"], out["f64"]) <= 1e-6
