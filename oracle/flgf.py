@@ -26,6 +26,12 @@ Readings taken where the paper is silent or ambiguous (all listed in the design 
   * InflList: at level 0 the (up to) 27 blocks with |Q-P|_inf <= 1; at 1 <= l < L the
     children of the parent's neighbours with |Q-P|_inf >= 2; at the top level L all
     intervals with |Q-P|_inf >= 2.  L = min(levels, 1 + ceil(log2(extent))).
+  * Separate source and evaluation blocks (B_s != B_e in Eq. bconv; the paper's Sec. 3.1
+    takes them equal for brevity): both sets live on one lattice (shifted by the
+    minimum over their union, extent of the union), the upward pass runs on the tree
+    of the source blocks, the downward pass on the tree of the evaluation blocks, and
+    every list pairs an evaluation interval P (target) with a source interval Q under
+    the same geometric rules as above.
   * Kernel: level 0 uses the exact G.  Level l >= 1 uses G at lattice offsets with
     max|x_i| < R_LATTICE when the node spacing h_l is an integer, and the asymptotic
     expansion A^Q_FAR otherwise (the continuous part of Eq. dpsoln).
@@ -43,16 +49,21 @@ Q_FAR = 8        # terms of the asymptotic expansion used as the far kernel
 
 # ----------------------------------------------------------------------------- layout / tree
 
-def normalize_blocks(blocks):
-    """Shift block coordinates so the bounding-box minimum is 0 (translation-invariant
-    tree anchoring)."""
+def _as_blocks(blocks):
+    """[N, 3] integer block coordinates (x, y, z); rejects empty sets and duplicates."""
     b = np.asarray(blocks, dtype=np.int64).reshape(-1, 3)
     if b.shape[0] == 0:
         raise ValueError("empty layout")
-    b = b - b.min(axis=0)
     if len({tuple(r) for r in b.tolist()}) != b.shape[0]:
         raise ValueError("duplicate blocks")
     return b
+
+
+def normalize_blocks(blocks):
+    """Shift block coordinates so the bounding-box minimum is 0 (translation-invariant
+    tree anchoring)."""
+    b = _as_blocks(blocks)
+    return b - b.min(axis=0)
 
 
 def full_depth(blocks):
@@ -65,46 +76,68 @@ def full_depth(blocks):
 
 
 class Tree:
-    """Octree of intervals (Sec. 3.1) plus the lists RegSupp, IntrpSupp and InflList."""
+    """Octree of intervals (Sec. 3.1) plus the lists RegSupp, IntrpSupp and InflList.
 
-    def __init__(self, blocks, levels):
-        self.blocks = normalize_blocks(blocks)
-        fd = full_depth(self.blocks)
+    Source side: `blocks`, `coords[l]`, `parent[l]` (the upward pass).  Evaluation side:
+    `eval_blocks`, `coords_e[l]`, `parent_e[l]` (the downward pass); the same objects as
+    the source side unless `eval_blocks` is given.  List entries are (target index on
+    the evaluation side, source index on the source side, D = P - Q)."""
+
+    def __init__(self, blocks, levels, eval_blocks=None):
+        src = _as_blocks(blocks)
+        ev = src if eval_blocks is None else _as_blocks(eval_blocks)
+        lo = np.minimum(src.min(axis=0), ev.min(axis=0))
+        self.blocks = src - lo
+        self.eval_blocks = ev - lo
+        fd = full_depth(np.vstack([self.blocks, self.eval_blocks]))
         self.L = fd if levels is None or levels <= 0 else min(int(levels), fd)
-        # coords[l] for l = 1..L ; level-1 intervals are the blocks, same order
-        self.coords = {1: self.blocks.copy()}
-        self.parent = {}
-        for l in range(1, self.L):
-            par = self.coords[l] // 2
-            uniq, inv = np.unique(par, axis=0, return_inverse=True)
-            self.coords[l + 1] = uniq
-            self.parent[l] = inv.reshape(-1)
+        self.coords, self.parent = self._levels(self.blocks)
+        if eval_blocks is None:
+            self.coords_e, self.parent_e = self.coords, self.parent
+        else:
+            self.coords_e, self.parent_e = self._levels(self.eval_blocks)
         # near-neighbour list at level 0: (target, source, D = P - Q)
-        self.near = self._pairs(self.blocks, None, near=True)
+        self.near = self._pairs(self.coords_e[1], self.coords[1], None, None, near=True)
         # interaction lists
         self.ilist = {}
         for l in range(1, self.L + 1):
-            C = self.coords[l]
-            pc = self.coords[l + 1][self.parent[l]] if l < self.L else None
-            self.ilist[l] = self._pairs(C, pc, near=False)
+            if l < self.L:
+                pt = self.coords_e[l + 1][self.parent_e[l]]
+                ps = self.coords[l + 1][self.parent[l]]
+            else:
+                pt = ps = None
+            self.ilist[l] = self._pairs(self.coords_e[l], self.coords[l], pt, ps, near=False)
+
+    def _levels(self, blocks):
+        """coords[l] for l = 1..L (level-1 intervals are the blocks, same order) and
+        parent[l][i] = index at level l + 1 of the parent of interval i."""
+        coords = {1: blocks.copy()}
+        parent = {}
+        for l in range(1, self.L):
+            par = coords[l] // 2
+            uniq, inv = np.unique(par, axis=0, return_inverse=True)
+            coords[l + 1] = uniq
+            parent[l] = inv.reshape(-1)
+        return coords, parent
 
     @staticmethod
-    def _pairs(C, parent, near):
-        """All (P, Q, D = P - Q) of a list, by plain O(N^2) enumeration.
+    def _pairs(CT, CS, pt, ps, near):
+        """All (P, Q, D = P - Q) of a list, by plain O(N^2) enumeration over targets CT
+        and sources CS.
         near=True : |D|_inf <= 1 (near neighbours).
-        near=False: |D|_inf >= 2, and if `parent` is given also
-                    |parent(P) - parent(Q)|_inf <= 1 (interaction list)."""
-        n = C.shape[0]
+        near=False: |D|_inf >= 2, and if parent coordinates `pt` (of each target) and `ps`
+                    (of each source) are given also |pt(P) - ps(Q)|_inf <= 1
+                    (interaction list)."""
         tgt, src, off = [], [], []
-        for i in range(n):
-            d = C[i][None, :] - C
+        for i in range(CT.shape[0]):
+            d = CT[i][None, :] - CS
             dinf = np.max(np.abs(d), axis=1)
             if near:
                 mask = dinf <= 1
             else:
                 mask = dinf >= 2
-                if parent is not None:
-                    mask &= np.max(np.abs(parent[i][None, :] - parent), axis=1) <= 1
+                if pt is not None:
+                    mask &= np.max(np.abs(pt[i][None, :] - ps), axis=1) <= 1
             js = np.nonzero(mask)[0]
             tgt.extend([i] * len(js))
             src.extend(js.tolist())
@@ -215,11 +248,12 @@ def ifft_trunc(uhat, M, m):
 # ----------------------------------------------------------------------------- the solver
 
 class FLGF:
-    """Plan + solve for u = G * f on a block layout, evaluated by the FLGF method."""
+    """Plan + solve for u = G * f on a block layout, evaluated by the FLGF method.
+    f lives on `blocks` (B_s); u is evaluated on `eval_blocks` (B_e), default B_s."""
 
-    def __init__(self, blocks, n, p, levels):
+    def __init__(self, blocks, n, p, levels, eval_blocks=None):
         self.n, self.p = int(n), int(p)
-        self.tree = Tree(blocks, levels)
+        self.tree = Tree(blocks, levels, eval_blocks)
         self.A = block_matrix(self.n, self.p)
         self.C = child_matrices(self.p)
         # Step 0: pre-computation of every unique kernel spectrum used in Step 2
@@ -235,10 +269,10 @@ class FLGF:
                 self.khat[(l, D)] = np.fft.rfftn(kernel_block(D, self.p, fn))
         self.M0, self.M1 = M0, M1
 
-    def _prod(self, fhat, pairs, khat_of):
-        """Step 2 for one level: uhat^P = sum_Q Prod(fhat^Q, khat^{P-Q})."""
+    def _prod(self, fhat, pairs, khat_of, ntgt):
+        """Step 2 for one level: uhat^P = sum_Q Prod(fhat^Q, khat^{P-Q}) for ntgt targets."""
         tgt, src, off = pairs
-        uhat = np.zeros_like(fhat)
+        uhat = np.zeros((ntgt,) + fhat.shape[1:], dtype=fhat.dtype)
         if tgt.size == 0:
             return uhat
         keys = [tuple(d) for d in off.tolist()]
@@ -256,11 +290,12 @@ class FLGF:
         return uhat
 
     def solve(self, f, return_levels=False):
-        """f: [N_B, n, n, n] indexed [block, z, y, x]; returns u with the same layout."""
+        """f: [N_s, n, n, n] indexed [block, z, y, x] over the source blocks; returns u
+        [N_e, n, n, n] over the evaluation blocks (the same blocks by default)."""
         t = self.tree
         n, p, L = self.n, self.p, t.L
         f = np.asarray(f, dtype=np.float64)
-        # ---- Step 1: upward pass
+        # ---- Step 1: upward pass (on the source tree)
         ftil = {1: reg_block(self.A, f)}
         for l in range(1, L):
             par = t.parent[l]
@@ -278,17 +313,17 @@ class FLGF:
         fhat0 = pad_fft(f, self.M0)
         fhat = {l: pad_fft(ftil[l], self.M1) for l in range(1, L + 1)}
         # ---- Step 2: level interactions
-        uhat0 = self._prod(fhat0, t.near, lambda D: self.khat0[D])
-        uhat = {l: self._prod(fhat[l], t.ilist[l], lambda D, l=l: self.khat[(l, D)])
+        uhat0 = self._prod(fhat0, t.near, lambda D: self.khat0[D], t.coords_e[1].shape[0])
+        uhat = {l: self._prod(fhat[l], t.ilist[l], lambda D, l=l: self.khat[(l, D)], t.coords_e[l].shape[0])
                 for l in range(1, L + 1)}
-        # ---- Step 3: downward pass
+        # ---- Step 3: downward pass (on the evaluation tree)
         util, vtil = {}, {}
         for l in range(L, 0, -1):
             v = ifft_trunc(uhat[l], self.M1, p)
             vtil[l] = v.copy()
             if l < L:
-                par = t.parent[l]
-                cpos = t.coords[l] - 2 * t.coords[l + 1][par]
+                par = t.parent_e[l]
+                cpos = t.coords_e[l] - 2 * t.coords_e[l + 1][par]
                 for c in range(8):
                     cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1
                     sel = np.nonzero((cpos[:, 0] == cx) & (cpos[:, 1] == cy) & (cpos[:, 2] == cz))[0]
@@ -303,5 +338,5 @@ class FLGF:
         return u
 
 
-def solve(blocks, f, n, p, levels):
-    return FLGF(blocks, n, p, levels).solve(f)
+def solve(blocks, f, n, p, levels, eval_blocks=None):
+    return FLGF(blocks, n, p, levels, eval_blocks).solve(f)
