@@ -262,6 +262,43 @@ def batch_bench(L, W, steps, warmup, seed=4):
             "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3), "tuning": choice}
 
 
+def split_bench(L, W, steps, warmup):
+    """Separate source and evaluation blocks: the vortex ring's 779 source blocks evaluated
+    on the whole 16^3-block cube of 16^3 points (p = 8, full depth), FP64 and FP32, one
+    autotuned graph launch per solve; against the single-set plan of the cube with the
+    sources zero-padded to it (the same u, bit for bit)."""
+    import torch
+    cfg = W.config_split()
+    src, ev, n = cfg["blocks"], cfg["eval_blocks"], cfg["n"]
+    pos = {tuple(b): i for i, b in enumerate(ev.tolist())}
+    at = np.asarray([pos[tuple(b)] for b in src.tolist()])
+    fpad = np.zeros((len(ev), n, n, n))
+    fpad[at] = cfg["f"]
+    npts = len(ev) * n ** 3
+    out = {"workload": cfg["name"], "source_blocks": int(len(src)), "eval_blocks": int(len(ev)),
+           "points": int(npts), "unit": "evaluation points solved/s"}
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        plan = L.Plan(src, n, cfg["p"], cfg["levels"], prec, eval_blocks=ev)
+        f = torch.from_numpy(cfg["f"]).to("cuda:0", dt)
+        u = torch.empty(plan.out_shape(), dtype=dt, device="cuda:0")
+        choice = plan.autotune(f, u, reps=2)
+        dt_s, lat = _time_graph(plan, f, u, steps, warmup)
+        whole = L.Plan(ev, n, cfg["p"], cfg["levels"], prec)
+        fw = torch.from_numpy(fpad).to("cuda:0", dt)
+        uw = torch.empty_like(fw)
+        whole.autotune(fw, uw, reps=2)
+        dt_w, _ = _time_graph(whole, fw, uw, steps, warmup)
+        out[prec] = {"value": round(npts * steps / dt_s, 1), "ms_per_step": round(dt_s / steps * 1e3, 5),
+                     "latency_ms": _pct(lat), "tuning": choice,
+                     "single_set_ms_per_step": round(dt_w / steps * 1e3, 5),
+                     "equal_to_single_set": bool(torch.equal(u, uw))}
+        plan.close()
+        whole.close()
+        del f, u, fw, uw
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_bench(L, W, nreq=192, seed=5, slots=4, load=0.8):
     """Serving: 32 request layouts (bounding box U{2..16} blocks of 16^3, Eden fill
     U[0.3, 1]), p = 8, FP32, through the request server (resident plans, shared spectra).
@@ -325,6 +362,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="eager solves only (counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="default kernel variants, no autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -410,6 +448,9 @@ def main():
     if not args.no_serve:
         result["serve"] = serve_bench(L, W)
         print("serving measured", flush=True, file=sys.stderr)
+    if not args.no_split:
+        result["split"] = split_bench(L, W, max(5, args.steps // 5), 2)
+        print("separate-set solves measured", flush=True, file=sys.stderr)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg)

@@ -5,7 +5,9 @@
  * the 7-point Laplacian [L u](n) = sum_{+-e_i} u(n +- e_i) - 6 u(n) and unit spacing,
  * compute u = G * f, i.e. u(n) = sum_m G(n - m) f(m), where G is the lattice Green's
  * function (Eq. lgf1) and f is supported on a union of equal cubic blocks of n^3
- * points (Sec. 2.3).  u is evaluated on the same blocks (B_e = B_s, Sec. 3.1).
+ * points (Sec. 2.3).  u is evaluated on the same blocks (B_e = B_s, the case Sec. 3.1
+ * describes), or, for a plan from lgf_plan_create_split, on a separate set of evaluation
+ * blocks (B_e != B_s in Eq. bconv).
  * The sum is evaluated with the Fast Lattice Green's Function method of Sec. 3.1:
  * block-wise zero-padded FFT convolutions with the exact G between neighbouring
  * blocks (level 0) and, on an octree of interpolation intervals, Lagrange
@@ -73,6 +75,10 @@ typedef struct {
     int64_t workspace_bytes;  /* device bytes owned by the plan                        */
     int64_t spectra_bytes;    /* device bytes of the (shared) kernel spectra it uses   */
     int32_t precision;        /* lgf_precision                                         */
+    int64_t source_blocks;    /* blocks of f (B_s)                                     */
+    int64_t eval_blocks;      /* blocks of u (B_e); equal to source_blocks and nblocks
+                                 unless the plan has separate sets, where nblocks counts
+                                 the union the tree of levels >= 1 is built on          */
 } lgf_plan_info;
 
 /*
@@ -106,7 +112,8 @@ lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t 
 
 /*
  * u = G * f on the plan's layout (Steps 1-3 of Sec. 3.1).  f, u: DEVICE pointers as
- * described above (may not alias).  u is overwritten entirely.  Asynchronous on
+ * described above (may not alias; f over the source blocks and u over the evaluation
+ * blocks for a plan with separate sets).  u is overwritten entirely.  Asynchronous on
  * hip_stream.  Errors: LGF_ERR_ARG (NULL), LGF_ERR_DEVICE (launch failure).
  */
 lgf_status lgf_solve(lgf_plan_t plan, const void* f, void* u, void* hip_stream);
@@ -136,9 +143,35 @@ lgf_status lgf_plan_create_batch(const int32_t* const* layouts, const int64_t* n
                                  void* hip_stream, lgf_plan_t* out);
 
 /*
+ * Plan with separate source and evaluation blocks (Eq. bconv: u^P = sum over Q in B_s of
+ * conv(k^{Q-P}, f^Q) for every P in B_e; Sec. 3.1 describes the method for B_e = B_s, and
+ * its lists, transfers and transforms apply unchanged to the two sets).
+ *   source_ijk : HOST array [nsource][3] of the source blocks B_s; f is DEVICE
+ *                [nsource][n][n][n] in this order
+ *   eval_ijk   : HOST array [neval][3] of the evaluation blocks B_e; u is DEVICE
+ *                [neval][n][n][n] in this order
+ * Both sets use one lattice (one origin); they may overlap, be disjoint or nest, and
+ * neither may hold duplicates.  The tree of levels >= 1 spans the union of the two
+ * sets (its extent sets the full depth); the near field pairs each evaluation block with
+ * its neighbouring source blocks only.  A set equal to the other gives the same u as
+ * lgf_plan_create.  All other arguments and errors as for lgf_plan_create.  Plans with
+ * separate sets are single problems (not for lgf_plan_create_batch or the server).
+ */
+lgf_status lgf_plan_create_split(const int32_t* source_ijk, int64_t nsource, const int32_t* eval_ijk,
+                                 int64_t neval, int32_t n, int32_t p, int32_t levels, lgf_precision prec,
+                                 void* hip_stream, lgf_plan_t* out);
+
+/* Host-only preview of lgf_plan_create_split (as lgf_plan_estimate). */
+lgf_status lgf_plan_estimate_split(const int32_t* source_ijk, int64_t nsource, const int32_t* eval_ijk,
+                                   int64_t neval, int32_t n, int32_t p, int32_t levels, lgf_precision prec,
+                                   lgf_plan_info* info);
+
+/*
  * Block offsets of the problems of a plan: *count receives the number of problems (1 for
- * a plan from lgf_plan_create) and offsets[0..min(count+1, max_entries)-1] (HOST, may be
- * NULL) the first block of each problem followed by the total block count.
+ * a plan from lgf_plan_create or lgf_plan_create_split) and
+ * offsets[0..min(count+1, max_entries)-1] (HOST, may be NULL) the first block of each
+ * problem followed by the total block count (of u: the evaluation blocks for a plan with
+ * separate sets).
  * Errors: LGF_ERR_ARG.
  */
 lgf_status lgf_plan_solve_offsets(lgf_plan_t plan, int64_t* offsets, int32_t max_entries, int32_t* count);

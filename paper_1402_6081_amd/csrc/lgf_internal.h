@@ -37,11 +37,13 @@ template <> struct FarAcc<float> { using type = ff32; };
 // Source spectra (fhat) arrays hold nitems + 1 items per frequency chunk; the last is a zero
 // sentinel that inactive neighbours point to.  Field spectra (uhat) hold nitems items.
 // Level 0 over groups of 2x2x2 target blocks (tgt8) with their 4^3 source neighbourhood (src64).
+// Sources and targets are numbered separately: fhat holds nsrc + 1 items (sentinel nsrc),
+// uhat ntgt items.
 // prefetch: 1 = the next source slab's loads are issued before the current slab is used.
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, int prefetch,
-                            hipStream_t s);
+                            cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
+                            int prefetch, hipStream_t s);
 // Levels >= 1 below the top: over parents (child8 and the 216 candidate sources src216 of
 // each parent), offsets radius 3.
 // waves: parent groups per workgroup (1, 2, 4); cpl: children accumulated per lane (8, 4, 2,
@@ -77,10 +79,11 @@ hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, 
 template <typename U>
 hipError_t launch_interp_down(const U* par, const int32_t* child8, const double* C01, U* io, int64_t nparent,
                               int p, hipStream_t s);
-// Final: u[b] = vnear[b] + (A^T x A^T x A^T) ut[b], accumulated in FP64 (u may alias vnear)
+// Final: u[b] = vnear[b] + (A^T x A^T x A^T) ut[q(b)], accumulated in FP64 (u may alias
+// vnear); q(b) = l1map[b] (the level-1 interval of evaluation block b), or b when l1map is NULL
 template <typename T, typename U>
 hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, int n, int p,
-                        hipStream_t s);
+                        hipStream_t s, const int32_t* l1map = nullptr);
 
 // ------------------------------------------------------------------ kernel spectra
 struct SpectraKey {

@@ -178,7 +178,8 @@ __global__ void __launch_bounds__(kInterpThreads)
 // ------------------------------------------------------------------ level 1 -> block, FP64 add-back
 template <typename T, typename U, int N, int P>
 __global__ void __launch_bounds__(kInterpThreads)
-    k_final(const T* vnear, const U* __restrict__ ut, const double* __restrict__ A, T* u) {
+    k_final(const T* vnear, const U* __restrict__ ut, const double* __restrict__ A, T* u,
+            const int32_t* __restrict__ l1map) {
     constexpr int N3 = N * N * N, P3 = P * P * P;
     __shared__ double X[P3], t1[P * P * N], t2[P * N * N];
     __shared__ double At[N * P];  // At[j][k] = A[k][j]
@@ -188,7 +189,8 @@ __global__ void __launch_bounds__(kInterpThreads)
         const int jj = i / P, k = i % P;
         At[i] = A[k * N + jj];
     }
-    for (int i = tid; i < P3; i += kInterpThreads) X[i] = to_double(ut[b * P3 + i]);
+    const int64_t q = l1map ? (int64_t)l1map[b] : b;  // level-1 interval of this block
+    for (int i = tid; i < P3; i += kInterpThreads) X[i] = to_double(ut[q * P3 + i]);
     __syncthreads();
     for (int i = tid; i < P * P * N; i += kInterpThreads) {  // x: t1[a][c][x]
         const int x = i % N, ac = i / N;
@@ -263,9 +265,10 @@ template <typename T, typename U>
 struct FinalRun {
     template <int N, int P>
     struct K {
-        static hipError_t run(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, hipStream_t s) {
+        static hipError_t run(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, const int32_t* l1map,
+                              hipStream_t s) {
             hipLaunchKernelGGL((k_final<T, U, N, P>), dim3((unsigned)nb), dim3(kInterpThreads), 0, s, vnear, ut, A,
-                               u);
+                               u, l1map);
             return hipGetLastError();
         }
     };
@@ -327,9 +330,10 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
 }
 
 template <typename T, typename U>
-hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, int n, int p, hipStream_t s) {
+hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, int n, int p, hipStream_t s,
+                        const int32_t* l1map) {
     if (nb <= 0) return hipSuccess;
-    return dispatch_np<FinalRun<T, U>::template K>(n, p, vnear, ut, A, u, nb, s);
+    return dispatch_np<FinalRun<T, U>::template K>(n, p, vnear, ut, A, u, nb, l1map, s);
 }
 
 template hipError_t launch_reg_block<double>(const double*, const double*, double*, int64_t, int, int, hipStream_t);
@@ -343,8 +347,8 @@ template hipError_t launch_interp_down<double>(const double*, const int32_t*, co
 template hipError_t launch_interp_down<ff32>(const ff32*, const int32_t*, const double*, ff32*, int64_t, int,
                                              hipStream_t);
 template hipError_t launch_final<double, double>(const double*, const double*, const double*, double*, int64_t, int,
-                                                 int, hipStream_t);
+                                                 int, hipStream_t, const int32_t*);
 template hipError_t launch_final<float, ff32>(const float*, const ff32*, const double*, float*, int64_t, int, int,
-                                              hipStream_t);
+                                              hipStream_t, const int32_t*);
 
 }  // namespace lgfdev

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <unordered_set>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -102,48 +103,105 @@ struct HostLevel {
 struct HostPlan {
     int n = 0, p = 0, L = 0, Ltop = 0;
     int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
-    std::vector<int32_t> g0_tgt8, g0_src64;  // sentinel = nb
+    int64_t nsrc = 0, neval = 0;              // source / evaluation blocks (both nb unless split)
+    std::vector<int32_t> eval_l1;             // split sets: level-1 interval of each evaluation block
+    std::vector<int32_t> g0_tgt8, g0_src64;  // targets: evaluation numbering; sources: sentinel = nsrc
     std::vector<HostLevel> lv;               // index 0 unused, 1..L
     std::vector<int64_t> solve_offsets{0};   // block offsets of the layouts of a batch
+    // levels >= 1: does an interval hold a source / an evaluation block below it (index = level)
+    std::vector<std::vector<char>> has_src, has_eval;
 };
 
-lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int levels, HostPlan& H) {
+// Source blocks ijk[nblocks] and evaluation blocks (Eq. bconv).  With eval_ijk == NULL the
+// two sets are the same blocks.  Otherwise the levels >= 1 are built over the union of the
+// two sets, sources first (the union index of source block i is i), then the evaluation
+// blocks that are not sources.  An interval with no source below it carries a zero field: the
+// source lists name the zero sentinel instead, so it costs no spectrum reads.  An interval
+// with no evaluation block below it is never interpolated to a block, and the list sizes
+// reported count only pairs with an evaluation target (the lists of the method).  The level-0
+// groups hold evaluation blocks (numbered as given) and their sources (numbered as given).
+lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int levels, HostPlan& H,
+                      const int32_t* eval_ijk = nullptr, int64_t neval = 0) {
+    const bool split = eval_ijk != nullptr;
+    if (!split) {
+        eval_ijk = ijk;
+        neval = nblocks;
+    }
     H.n = n;
     H.p = p;
-    H.nb = nblocks;
-    H.solve_offsets = {0, nblocks};
+    H.nsrc = nblocks;
+    H.neval = neval;
     int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
-    for (int64_t b = 0; b < nblocks; ++b)
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = std::min<int64_t>(lo[d], ijk[3 * b + d]);
-            hi[d] = std::max<int64_t>(hi[d], ijk[3 * b + d]);
-        }
+    auto span = [&](const int32_t* c, int64_t m) {
+        for (int64_t b = 0; b < m; ++b)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min<int64_t>(lo[d], c[3 * b + d]);
+                hi[d] = std::max<int64_t>(hi[d], c[3 * b + d]);
+            }
+    };
+    span(ijk, nblocks);
+    if (split) span(eval_ijk, neval);
     int64_t ext = 1;
     for (int d = 0; d < 3; ++d) {
         if (hi[d] - lo[d] >= (1 << 20)) return fail(LGF_ERR_LAYOUT, "layout spans more than 2^20 blocks");
         ext = std::max<int64_t>(ext, hi[d] - lo[d] + 1);
     }
-    std::vector<int32_t> blocks(3 * nblocks);
-    std::unordered_map<uint64_t, int32_t> idx0;
-    idx0.reserve(nblocks * 2);
+    const int64_t cap = nblocks + (split ? neval : 0);
+    std::vector<int32_t> blocks;  // the union, shifted so the minimum is 0
+    blocks.reserve(3 * cap);
+    std::unordered_map<uint64_t, int32_t> idx0;  // union index of a block
+    idx0.reserve(cap * 2);
     for (int64_t b = 0; b < nblocks; ++b) {
-        for (int d = 0; d < 3; ++d) blocks[3 * b + d] = (int32_t)(ijk[3 * b + d] - lo[d]);
-        const uint64_t key = pack(blocks[3 * b], blocks[3 * b + 1], blocks[3 * b + 2]);
-        if (!idx0.emplace(key, (int32_t)b).second) return fail(LGF_ERR_LAYOUT, "duplicate block in layout");
+        int32_t c[3];
+        for (int d = 0; d < 3; ++d) c[d] = (int32_t)(ijk[3 * b + d] - lo[d]);
+        if (!idx0.emplace(pack(c[0], c[1], c[2]), (int32_t)b).second)
+            return fail(LGF_ERR_LAYOUT, split ? "duplicate source block" : "duplicate block in layout");
+        blocks.insert(blocks.end(), c, c + 3);
     }
+    std::vector<int32_t> ecoords;  // evaluation blocks, shifted (split sets only)
+    if (split) {
+        std::unordered_set<uint64_t> seen;
+        seen.reserve(neval * 2);
+        ecoords.resize(3 * neval);
+        H.eval_l1.resize(neval);
+        for (int64_t j = 0; j < neval; ++j) {
+            int32_t* c = &ecoords[3 * j];
+            for (int d = 0; d < 3; ++d) c[d] = (int32_t)(eval_ijk[3 * j + d] - lo[d]);
+            const uint64_t key = pack(c[0], c[1], c[2]);
+            if (!seen.insert(key).second) return fail(LGF_ERR_LAYOUT, "duplicate evaluation block");
+            auto it = idx0.find(key);
+            int32_t u;
+            if (it == idx0.end()) {
+                u = (int32_t)(blocks.size() / 3);
+                idx0.emplace(key, u);
+                blocks.insert(blocks.end(), c, c + 3);
+            } else {
+                u = it->second;
+            }
+            H.eval_l1[j] = u;
+        }
+    }
+    const int64_t nu = (int64_t)blocks.size() / 3;
+    H.nb = nu;
+    H.solve_offsets = {0, neval};
     int full = 1;
     while ((int64_t(1) << (full - 1)) < ext) ++full;
     H.L = levels <= 0 ? full : std::min(levels, full);
     if (H.L >= kMaxLevels) return fail(LGF_ERR_LAYOUT, "tree deeper than supported");
 
-    // ---- level 0: near pairs and 2x2x2 target groups with their 4^3 sources
+    // ---- level 0: near pairs (evaluation target, source) and 2x2x2 target groups with
+    //      their 4^3 source neighbourhood
+    auto source_at = [&](int64_t qx, int64_t qy, int64_t qz) -> int32_t {
+        if (qx < 0 || qy < 0 || qz < 0) return -1;
+        auto jt = idx0.find(pack(qx, qy, qz));
+        return (jt != idx0.end() && jt->second < nblocks) ? jt->second : -1;
+    };
+    const int32_t* E = split ? ecoords.data() : blocks.data();
     std::unordered_map<uint64_t, int32_t> gidx;
-    for (int64_t b = 0; b < nblocks; ++b) {
-        const int32_t* P = &blocks[3 * b];
-        for (int d = 0; d < 27; ++d) {
-            const int64_t qx = P[0] - (d % 3 - 1), qy = P[1] - ((d / 3) % 3 - 1), qz = P[2] - (d / 9 - 1);
-            if (qx >= 0 && qy >= 0 && qz >= 0 && idx0.count(pack(qx, qy, qz))) ++H.near_pairs;
-        }
+    for (int64_t b = 0; b < neval; ++b) {
+        const int32_t* P = &E[3 * b];
+        for (int d = 0; d < 27; ++d)
+            if (source_at(P[0] - (d % 3 - 1), P[1] - ((d / 3) % 3 - 1), P[2] - (d / 9 - 1)) >= 0) ++H.near_pairs;
         const uint64_t key = pack(P[0] >> 1, P[1] >> 1, P[2] >> 1);
         auto it = gidx.find(key);
         int32_t g;
@@ -153,12 +211,10 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
             H.g0_tgt8.resize(8 * H.ngroups0, -1);
             H.g0_src64.resize(64 * H.ngroups0, (int32_t)nblocks);
             for (int sidx = 0; sidx < 64; ++sidx) {
-                const int64_t qx = 2 * (int64_t)(P[0] >> 1) + (sidx & 3) - 1;
-                const int64_t qy = 2 * (int64_t)(P[1] >> 1) + ((sidx >> 2) & 3) - 1;
-                const int64_t qz = 2 * (int64_t)(P[2] >> 1) + (sidx >> 4) - 1;
-                if (qx < 0 || qy < 0 || qz < 0) continue;
-                auto jt = idx0.find(pack(qx, qy, qz));
-                if (jt != idx0.end()) H.g0_src64[64 * g + sidx] = jt->second;
+                const int32_t q = source_at(2 * (int64_t)(P[0] >> 1) + (sidx & 3) - 1,
+                                            2 * (int64_t)(P[1] >> 1) + ((sidx >> 2) & 3) - 1,
+                                            2 * (int64_t)(P[2] >> 1) + (sidx >> 4) - 1);
+                if (q >= 0) H.g0_src64[64 * g + sidx] = q;
             }
         } else {
             g = it->second;
@@ -166,12 +222,19 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
         H.g0_tgt8[8 * g + ((P[0] & 1) | ((P[1] & 1) << 1) | ((P[2] & 1) << 2))] = (int32_t)b;
     }
 
-    // ---- levels: coordinates, parents, children
+    // ---- levels: coordinates, parents, children, and which intervals hold sources /
+    //      evaluation blocks
     H.lv.assign(H.L + 1, HostLevel());
+    H.has_src.assign(H.L + 1, std::vector<char>());
+    H.has_eval.assign(H.L + 1, std::vector<char>());
     std::vector<std::unordered_map<uint64_t, int32_t>> idx(H.L + 2);
-    H.lv[1].nint = nblocks;
+    H.lv[1].nint = nu;
     H.lv[1].coords = blocks;
     idx[1] = idx0;
+    H.has_src[1].assign(nu, 0);
+    H.has_eval[1].assign(nu, split ? 0 : 1);
+    for (int64_t i = 0; i < nblocks; ++i) H.has_src[1][i] = 1;
+    for (int32_t u : H.eval_l1) H.has_eval[1][u] = 1;
     for (int l = 1; l < H.L; ++l) {
         HostLevel& C = H.lv[l];
         HostLevel& P = H.lv[l + 1];
@@ -194,7 +257,13 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
             cpos[i] = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
         }
         P.child8.assign(8 * P.nint, -1);
-        for (int64_t i = 0; i < C.nint; ++i) P.child8[8 * parent[i] + cpos[i]] = (int32_t)i;
+        H.has_src[l + 1].assign(P.nint, 0);
+        H.has_eval[l + 1].assign(P.nint, 0);
+        for (int64_t i = 0; i < C.nint; ++i) {
+            P.child8[8 * parent[i] + cpos[i]] = (int32_t)i;
+            H.has_src[l + 1][parent[i]] |= H.has_src[l][i];
+            H.has_eval[l + 1][parent[i]] |= H.has_eval[l][i];
+        }
     }
     // ---- levels >= 2: the 216 candidate sources of each parent (children of its neighbours);
     //      the interaction-list size of every child follows from them
@@ -213,12 +282,12 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
                 if (it == idx[l].end()) continue;
                 for (int cs = 0; cs < 8; ++cs) {
                     const int32_t q = Lv.child8[8 * it->second + cs];
-                    if (q >= 0) Lv.src216[216 * i + 8 * e + cs] = q;
+                    if (q >= 0 && H.has_src[l - 1][q]) Lv.src216[216 * i + 8 * e + cs] = q;
                 }
             }
             for (int c = 0; c < 8; ++c) {
                 const int32_t t = Lv.child8[8 * i + c];
-                if (t < 0) continue;
+                if (t < 0 || !H.has_eval[l - 1][t]) continue;
                 for (int s = 0; s < 216; ++s) {
                     const int32_t q = Lv.src216[216 * i + s];
                     if (q == sentinel) continue;
@@ -232,13 +301,15 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
         }
         H.lv[l - 1].sib_pairs = pairs;
     }
-    // ---- top level: every non-adjacent interval (non-empty only below the full depth)
+    // ---- top level: every non-adjacent interval (non-empty only below the full depth); a
+    //      target without evaluation blocks keeps an empty list (its field is written as 0)
     {
         HostLevel& T = H.lv[H.L];
         for (int64_t i = 0; i < T.nint; ++i) {
             const int32_t* P = &T.coords[3 * i];
             T.csr_tgt.push_back((int32_t)i);
-            for (int64_t q = 0; q < T.nint; ++q) {
+            for (int64_t q = 0; q < T.nint && H.has_eval[H.L][i]; ++q) {
+                if (!H.has_src[H.L][q]) continue;
                 const int32_t* Q = &T.coords[3 * q];
                 std::array<int32_t, 3> D{P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
                 if (std::max(std::abs(D[0]), std::max(std::abs(D[1]), std::abs(D[2]))) < 2) continue;
@@ -270,6 +341,8 @@ HostPlan concat(const std::vector<HostPlan>& parts) {
     U.lv.assign(U.L + 1, HostLevel());
     for (const auto& P : parts) {
         U.nb += P.nb;
+        U.nsrc += P.nsrc;  // parts have equal source and evaluation sets
+        U.neval += P.neval;
         U.ngroups0 += P.ngroups0;
         U.near_pairs += P.near_pairs;
         for (int l = 1; l <= P.L; ++l) U.lv[l].nint += P.lv[l].nint;
@@ -279,7 +352,7 @@ HostPlan concat(const std::vector<HostPlan>& parts) {
     for (const auto& P : parts) {
         const int64_t ob = off[1];
         for (int32_t t : P.g0_tgt8) U.g0_tgt8.push_back(t < 0 ? -1 : (int32_t)(t + ob));
-        for (int32_t q : P.g0_src64) U.g0_src64.push_back(q == (int32_t)P.nb ? (int32_t)U.nb : (int32_t)(q + ob));
+        for (int32_t q : P.g0_src64) U.g0_src64.push_back(q == (int32_t)P.nsrc ? (int32_t)U.nsrc : (int32_t)(q + ob));
         for (int l = 1; l <= P.L; ++l) {
             const HostLevel& A = P.lv[l];
             HostLevel& B = U.lv[l];
@@ -319,9 +392,9 @@ int64_t workspace_need(const HostPlan& H, lgf_precision prec) {
     const int64_t S0 = spec_padded(2 * n * 2 * n * (n + 1));
     const int64_t S1 = spec_padded(2 * p * 2 * p * (p + 1));
     const int64_t p3 = (int64_t)p * p * p;
-    const int64_t nb = H.nb;
     const int topc = std::min(H.Ltop + 1, H.L);
-    int64_t need = H.ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (2 * nb + 1) * S0 * 2 * esz;
+    int64_t need = H.ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (H.nsrc + 1 + H.neval) * S0 * 2 * esz +
+                   (int64_t)H.eval_l1.size() * 4;
     for (int l = 1; l <= H.Ltop; ++l) {
         const HostLevel& h = H.lv[l];
         need += h.nint * p3 * (esz + usz);
@@ -350,6 +423,8 @@ struct lgf_plan_s {
     int n = 0, p = 0, L = 0, Ltop = 0;
     lgf_precision prec = LGF_F64;
     int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
+    int64_t nsrc = 0, neval = 0;        // blocks of f / of u (nb for both unless the sets differ)
+    int32_t* d_eval_l1 = nullptr;       // level-1 interval of each evaluation block (split sets)
     std::vector<int64_t> solve_offsets;
     std::vector<LevelPlan> lv;  // index 0 unused, 1..L
     std::shared_ptr<SpectraEntry> spectra0;
@@ -479,7 +554,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     const double n3 = (double)n * n * n, p3 = (double)p * p * p;
     const double S0 = pl->spectra0->S, S1 = (double)(2 * p) * (2 * p) * (p + 1);
     const int64_t S1p = spec_padded(2 * p * 2 * p * (p + 1));
-    const double nb = (double)pl->nb;
+    const double ns = (double)pl->nsrc, ne = (double)pl->neval;  // source / evaluation blocks
     auto lvN = [&](int l) { return (double)pl->lv[l].nint; };
     auto lname = [](const char* a, int l) { return std::string(a) + std::to_string(l); };
 #define LGF_STEP(st, x, name, bytes, flops)                              \
@@ -558,8 +633,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             if ((e = hipStreamWaitEvent(s2, pl->ev_fork, 0)) != hipSuccess) return e;
         }
         if (segs & kSegReg1)
-            LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nb, n, p, s2)), "reg_l0_l1",
-                     nb * (n3 + p3) * es, nb * 2.0 * (p * n3 + p * p * n * n + p3 * n));
+            LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nsrc, n, p, s2)), "reg_l0_l1",
+                     ns * (n3 + p3) * es, ns * 2.0 * (p * n3 + p * p * n * n + p3 * n));
         const bool coarse = pl->Ltop >= 2;
         if (coarse && (segs & kSegCoarse)) {
             // levels >= 2 on s3: Reg up, their M2L, and the down pass to level 2
@@ -594,20 +669,21 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     }
     // ---- near field (level 0) on the caller's stream
     if (segs & kSegNear) {
-        LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nb, s, tc.fft0_threads), "fft_fwd_l0",
-                 nb * (n3 * es + S0 * cs), nb * fft_flops(2 * n));
+        LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nsrc, s, tc.fft0_threads), "fft_fwd_l0",
+                 ns * (n3 * es + S0 * cs), ns * fft_flops(2 * n));
         LGF_STEP(s,
                  launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8,
-                                     pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nb, pl->spectra0->S,
-                                     tc.near_waves, tc.near_prefetch, s),
-                 "prod_l0", (2.0 * nb + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
-        LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->nb, s, tc.fft0_threads)),
-                 "fft_inv_l0", nb * (S0 * cs + n3 * es), nb * fft_flops(2 * n));
+                                     pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nsrc, pl->neval,
+                                     pl->spectra0->S, tc.near_waves, tc.near_prefetch, s),
+                 "prod_l0", (ns + ne + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
+        LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->neval, s, tc.fft0_threads)),
+                 "fft_inv_l0", ne * (S0 * cs + n3 * es), ne * fft_flops(2 * n));
     }
     if (far && (segs & kSegFinal)) {
         if (overlap && (e = hipStreamWaitEvent(s, pl->ev_join, 0)) != hipSuccess) return e;
-        LGF_STEP(s, (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->nb, n, p, s)), "final_l1_l0",
-                 nb * (2.0 * n3 * es + p3 * us), nb * 2.0 * (p3 * n + p * p * n * n + p * n3));
+        LGF_STEP(s,
+                 (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->neval, n, p, s, pl->d_eval_l1)),
+                 "final_l1_l0", ne * (2.0 * n3 * es + p3 * us), ne * 2.0 * (p3 * n + p * p * n * n + p * n3));
     }
     mark.solve_end(s);
 #undef LGF_STEP
@@ -625,6 +701,8 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     pl->p = p;
     pl->prec = prec;
     pl->nb = H.nb;
+    pl->nsrc = H.nsrc;
+    pl->neval = H.neval;
     pl->L = H.L;
     pl->Ltop = H.Ltop;
     pl->near_pairs = H.near_pairs;
@@ -699,8 +777,10 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     pl->ws_bytes = need;
     bool ok = dev_alloc(pl, &pl->d_g0_tgt8, H.ngroups0 * 8 * 4) &&
               dev_alloc(pl, &pl->d_g0_src64, H.ngroups0 * 64 * 4) && dev_alloc(pl, &pl->d_A, p * n * 8) &&
-              dev_alloc(pl, &pl->d_C01, 2 * p * p * 8) && dev_alloc(pl, &pl->d_fhat0, (nb + 1) * S0 * 2 * esz) &&
-              dev_alloc(pl, &pl->d_uhat0, nb * S0 * 2 * esz);
+              dev_alloc(pl, &pl->d_C01, 2 * p * p * 8) &&
+              dev_alloc(pl, &pl->d_fhat0, (H.nsrc + 1) * S0 * 2 * esz) &&
+              dev_alloc(pl, &pl->d_uhat0, H.neval * S0 * 2 * esz);
+    if (ok && !H.eval_l1.empty()) ok = dev_alloc(pl, &pl->d_eval_l1, (int64_t)H.eval_l1.size() * 4);
     for (int l = 1; ok && l <= pl->Ltop; ++l) {
         LevelPlan& Lv = pl->lv[l];
         const HostLevel& h = H.lv[l];
@@ -722,6 +802,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     if (e == hipSuccess) e = upload(pl->d_g0_src64, H.g0_src64, s);
     if (e == hipSuccess) e = upload(pl->d_A, A, s);
     if (e == hipSuccess) e = upload(pl->d_C01, C01, s);
+    if (e == hipSuccess && pl->d_eval_l1) e = upload(pl->d_eval_l1, H.eval_l1, s);
     for (int l = 1; e == hipSuccess && l <= pl->Ltop; ++l) {
         LevelPlan& Lv = pl->lv[l];
         if (Lv.d_csr_tgt) {
@@ -736,7 +817,11 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
         if (e == hipSuccess) e = upload(pl->lv[l].d_src216, H.lv[l].src216, s);
     }
     // the source-spectra arrays start zeroed: their last item is the zero sentinel
-    if (e == hipSuccess) e = zero_fill(pl->d_fhat0, (nb + 1) * S0 * 2 * esz, s);
+    if (e == hipSuccess) e = zero_fill(pl->d_fhat0, (H.nsrc + 1) * S0 * 2 * esz, s);
+    // level-1 fields of the union intervals that are not sources stay zero (Reg writes the
+    // first nsrc only)
+    if (e == hipSuccess && pl->Ltop >= 1 && nb > H.nsrc)
+        e = zero_fill((char*)pl->lv[1].d_ftil + H.nsrc * p3 * esz, (nb - H.nsrc) * p3 * esz, s);
     for (int l = 1; e == hipSuccess && l <= pl->Ltop; ++l)
         if (pl->lv[l].d_fhat) e = zero_fill(pl->lv[l].d_fhat, (pl->lv[l].nint + 1) * S1 * 2 * esz, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -991,19 +1076,27 @@ static lgf_status make_plan(HostPlan& H, lgf_precision prec, void* hip_stream, l
     return LGF_OK;
 }
 
-lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
-                           lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
+static lgf_status check_layout(const int32_t* ijk, int64_t nblocks, const char* what) {
+    if (!ijk) return fail(LGF_ERR_ARG, std::string(what) + " is NULL");
+    if (nblocks < 1) return fail(LGF_ERR_LAYOUT, "empty layout");
+    if (nblocks > (int64_t)1 << 30) return fail(LGF_ERR_ARG, "too many blocks");
+    return LGF_OK;
+}
+
+static lgf_status create_plan(const int32_t* src_ijk, int64_t nsrc, const int32_t* eval_ijk, int64_t neval,
+                              int32_t n, int32_t p, int32_t levels, lgf_precision prec, void* hip_stream,
+                              lgf_plan_t* out) {
     t_err.clear();
     if (!out) return fail(LGF_ERR_ARG, "out is NULL");
     *out = nullptr;
-    if (!block_ijk) return fail(LGF_ERR_ARG, "block_ijk is NULL");
-    if (nblocks < 1) return fail(LGF_ERR_LAYOUT, "empty layout");
-    if (nblocks > (int64_t)1 << 30) return fail(LGF_ERR_ARG, "too many blocks");
-    lgf_status st = check_args(n, p, prec);
+    lgf_status st = check_layout(src_ijk, nsrc, eval_ijk ? "source_ijk" : "block_ijk");
+    if (st == LGF_OK && eval_ijk) st = check_layout(eval_ijk, neval, "eval_ijk");
+    if (st == LGF_OK && nsrc + (eval_ijk ? neval : 0) > (int64_t)1 << 30) st = fail(LGF_ERR_ARG, "too many blocks");
+    if (st == LGF_OK) st = check_args(n, p, prec);
     if (st != LGF_OK) return st;
     try {
         HostPlan H;
-        st = build_host(block_ijk, nblocks, n, p, levels, H);
+        st = build_host(src_ijk, nsrc, n, p, levels, H, eval_ijk, neval);
         if (st != LGF_OK) return st;
         return make_plan(H, prec, hip_stream, out);
     } catch (const std::bad_alloc&) {
@@ -1011,6 +1104,22 @@ lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n,
     } catch (...) {
         return fail(LGF_ERR_DEVICE, "unexpected failure while building the plan");
     }
+}
+
+lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
+                           lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
+    return create_plan(block_ijk, nblocks, nullptr, 0, n, p, levels, prec, hip_stream, out);
+}
+
+lgf_status lgf_plan_create_split(const int32_t* source_ijk, int64_t nsource, const int32_t* eval_ijk,
+                                 int64_t neval, int32_t n, int32_t p, int32_t levels, lgf_precision prec,
+                                 void* hip_stream, lgf_plan_t* out) {
+    if (!eval_ijk) {
+        t_err.clear();
+        if (out) *out = nullptr;
+        return fail(LGF_ERR_ARG, out ? "eval_ijk is NULL" : "out is NULL");
+    }
+    return create_plan(source_ijk, nsource, eval_ijk, neval, n, p, levels, prec, hip_stream, out);
 }
 
 lgf_status lgf_plan_create_batch(const int32_t* const* layouts, const int64_t* nblocks, int32_t count, int32_t n,
@@ -1041,17 +1150,17 @@ lgf_status lgf_plan_create_batch(const int32_t* const* layouts, const int64_t* n
     }
 }
 
-lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
-                             lgf_precision prec, lgf_plan_info* info) {
+static lgf_status estimate_plan(const int32_t* src_ijk, int64_t nsrc, const int32_t* eval_ijk, int64_t neval,
+                                int32_t n, int32_t p, int32_t levels, lgf_precision prec, lgf_plan_info* info) {
     t_err.clear();
-    if (!info || !block_ijk) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_estimate");
-    if (nblocks < 1) return fail(LGF_ERR_LAYOUT, "empty layout");
-    if (nblocks > (int64_t)1 << 30) return fail(LGF_ERR_ARG, "too many blocks");
-    lgf_status st = check_args(n, p, prec);
+    if (!info) return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_estimate");
+    lgf_status st = check_layout(src_ijk, nsrc, eval_ijk ? "source_ijk" : "block_ijk");
+    if (st == LGF_OK && eval_ijk) st = check_layout(eval_ijk, neval, "eval_ijk");
+    if (st == LGF_OK) st = check_args(n, p, prec);
     if (st != LGF_OK) return st;
     try {
         HostPlan H;
-        st = build_host(block_ijk, nblocks, n, p, levels, H);
+        st = build_host(src_ijk, nsrc, n, p, levels, H, eval_ijk, neval);
         if (st != LGF_OK) return st;
         std::memset(info, 0, sizeof(*info));
         info->nblocks = H.nb;
@@ -1068,10 +1177,27 @@ lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t 
         }
         info->workspace_bytes = workspace_need(H, prec);
         info->precision = prec;
+        info->source_blocks = H.nsrc;
+        info->eval_blocks = H.neval;
         return LGF_OK;
     } catch (const std::bad_alloc&) {
         return fail(LGF_ERR_OOM, "host allocation failed");
     }
+}
+
+lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
+                             lgf_precision prec, lgf_plan_info* info) {
+    return estimate_plan(block_ijk, nblocks, nullptr, 0, n, p, levels, prec, info);
+}
+
+lgf_status lgf_plan_estimate_split(const int32_t* source_ijk, int64_t nsource, const int32_t* eval_ijk,
+                                   int64_t neval, int32_t n, int32_t p, int32_t levels, lgf_precision prec,
+                                   lgf_plan_info* info) {
+    if (!eval_ijk) {
+        t_err.clear();
+        return fail(LGF_ERR_ARG, "NULL argument to lgf_plan_estimate_split");
+    }
+    return estimate_plan(source_ijk, nsource, eval_ijk, neval, n, p, levels, prec, info);
 }
 
 lgf_status lgf_plan_solve_offsets(lgf_plan_t plan, int64_t* offsets, int32_t max_entries, int32_t* count) {
@@ -1221,6 +1347,8 @@ lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info) {
     }
     info->spectra_bytes = sb;
     info->precision = plan->prec;
+    info->source_blocks = plan->nsrc;
+    info->eval_blocks = plan->neval;
     return LGF_OK;
 }
 

@@ -47,8 +47,10 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 
 // ------------------------------------------------------------------ level 0
 // Groups g: tgt8[g][c] = block 2J + c (c = cx | cy<<1 | cz<<2) or -1;
-// src64[g][s] = block 2J + (sx-1, sy-1, sz-1), s = sx + 4 sy + 16 sz, or the zero sentinel
-// item (index nb) when that block is not active.  fhat holds nb + 1 items (the last is 0).
+// src64[g][s] = source block 2J + (sx-1, sy-1, sz-1), s = sx + 4 sy + 16 sz, or the zero
+// sentinel item (index nsrc) when that block is not a source.  fhat holds nsrc + 1 items
+// (the last is 0), uhat ntgt items (targets and sources are numbered separately, so the
+// evaluation blocks may differ from the source blocks).
 // One wave = 64 consecutive frequencies of one group; the 4 waves of a workgroup share the
 // frequency chunk and its kernel tile in LDS.  The tile has rows for dz in [-2, 2] (the
 // rows with |dz| = 2 are zero) so the source-slab loop needs no branches.
@@ -56,7 +58,7 @@ template <typename T, int kNearWaves, bool kPrefetch>
 __global__ void __launch_bounds__(64 * kNearWaves)
     k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                         const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
-                        cplx<T>* __restrict__ uhat, int S, int ngroups, int nb) {
+                        cplx<T>* __restrict__ uhat, int S, int ngroups, int nsrc, int ntgt) {
     __shared__ cplx<T> tile[45 * 64];  // row (dx+1) + 3 (dy+1) + 9 (dz+2)
     const int lane = threadIdx.x & 63;
     int chunk, gb;
@@ -77,7 +79,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         ai[c] = T(0);
     }
     const int32_t* sg = src64 + (int64_t)g * 64;
-    const cplx<T>* fl = fhat + (int64_t)chunk * (nb + 1) * 64 + lane;  // this lane's frequency
+    const cplx<T>* fl = fhat + (int64_t)chunk * (nsrc + 1) * 64 + lane;  // this lane's frequency
     // source z slab sz contributes to target slab cz through kernel rows dz = cz - (sz - 1)
     auto slab = [&](int sz, const cplx<T>(&f)[16]) {
         const cplx<T>* t0 = tile + (9 * (3 - sz)) * 64 + lane;  // row base for cz = 0
@@ -122,7 +124,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int t = tg[c];
-        if (t >= 0) uhat[spec_at(t, w, nb)] = cplx<T>{ar[c], ai[c]};
+        if (t >= 0) uhat[spec_at(t, w, ntgt)] = cplx<T>{ar[c], ai[c]};
     }
 }
 
@@ -300,31 +302,32 @@ __global__ void __launch_bounds__(kProdThreads)
 
 template <typename T, int NW, bool PF>
 static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                          cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, hipStream_t s) {
+                          cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, hipStream_t s) {
     const unsigned grid = xcd_grid(S / 64, (int)((ngroups + NW - 1) / NW));
     hipLaunchKernelGGL((k_prod_near_grouped<T, NW, PF>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64,
-                       uhat, S, (int)ngroups, (int)nitems);
+                       uhat, S, (int)ngroups, (int)nsrc, (int)ntgt);
     return hipGetLastError();
 }
 
 template <typename T, bool PF>
 static hipError_t near_pf(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                          cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, hipStream_t s) {
+                          cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
+                          hipStream_t s) {
     switch (waves) {
-        case 2: return near_nw<T, 2, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
-        case 8: return near_nw<T, 8, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
-        default: return near_nw<T, 4, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, s);
+        case 2: return near_nw<T, 2, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s);
+        case 8: return near_nw<T, 8, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s);
+        default: return near_nw<T, 4, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s);
     }
 }
 
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                            cplx<T>* uhat, int64_t ngroups, int64_t nitems, int S, int waves, int prefetch,
-                            hipStream_t s) {
+                            cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
+                            int prefetch, hipStream_t s) {
     if (ngroups <= 0) return hipSuccess;
     if (S % 64) return hipErrorInvalidValue;
-    return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, waves, s)
-                    : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nitems, S, waves, s);
+    return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s)
+                    : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s);
 }
 
 template <typename T, int NW, int CPL>
@@ -391,7 +394,7 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
 
 #define LGF_INST(T)                                                                                              \
     template hipError_t launch_prod_near<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,      \
-                                            cplx<T>*, int64_t, int64_t, int, int, int, hipStream_t);             \
+                                            cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t);    \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
                                                cplx<T>*, int64_t, int64_t, int, int, int, hipStream_t);          \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \

@@ -33,6 +33,7 @@ class PlanInfo(ctypes.Structure):
         ("near_pairs", ctypes.c_int64), ("far_pairs", ctypes.c_int64 * 16),
         ("intervals", ctypes.c_int64 * 16), ("workspace_bytes", ctypes.c_int64),
         ("spectra_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
+        ("source_blocks", ctypes.c_int64), ("eval_blocks", ctypes.c_int64),
     ]
 
 
@@ -70,7 +71,8 @@ class StepProfile(ctypes.Structure):
     ]
 
 
-EXPORTS = ["lgf_plan_create", "lgf_plan_estimate", "lgf_plan_create_batch", "lgf_plan_solve_offsets", "lgf_solve", "lgf_solve_many",
+EXPORTS = ["lgf_plan_create", "lgf_plan_estimate", "lgf_plan_create_split", "lgf_plan_estimate_split",
+           "lgf_plan_create_batch", "lgf_plan_solve_offsets", "lgf_solve", "lgf_solve_many",
            "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy", "lgf_plan_autotune", "lgf_plan_get_tuning",
            "lgf_plan_set_tuning", "lgf_server_create", "lgf_server_submit", "lgf_server_poll", "lgf_server_wait",
            "lgf_server_stats", "lgf_server_reset_stats", "lgf_server_destroy",
@@ -94,6 +96,9 @@ def library():
                                             ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.lgf_plan_solve_offsets.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)]
         L.lgf_plan_estimate.argtypes = [vp, i64, i32, i32, i32, ctypes.c_int, ctypes.POINTER(PlanInfo)]
+        L.lgf_plan_create_split.argtypes = [vp, i64, vp, i64, i32, i32, i32, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.lgf_plan_estimate_split.argtypes = [vp, i64, vp, i64, i32, i32, i32, ctypes.c_int,
+                                              ctypes.POINTER(PlanInfo)]
         L.lgf_solve.argtypes = [vp, vp, vp, vp]
         L.lgf_graph_create.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.lgf_graph_launch.argtypes = [vp, vp]
@@ -142,18 +147,32 @@ def _require_gpu():
         raise RuntimeError("no GPU visible: the LGF solver runs only on the device")
 
 
-class Plan:
-    """lgf_plan_create / lgf_solve / lgf_plan_query / lgf_plan_destroy."""
+def _layout(blocks):
+    return np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
 
-    def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None, _layouts=None):
+
+class Plan:
+    """lgf_plan_create / lgf_solve / lgf_plan_query / lgf_plan_destroy.
+
+    With `eval_blocks` (lgf_plan_create_split) f lives on `blocks` (B_s) and u on
+    `eval_blocks` (B_e)."""
+
+    def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None, _layouts=None, eval_blocks=None):
         _require_gpu()
         self.n, self.p = int(n), int(p)
         self.precision = precision
         prec = {"f64": F64, "f32": F32}[precision]
         self.dtype = torch.float64 if prec == F64 else torch.float32
         h = ctypes.c_void_p()
-        if _layouts is None:
-            b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+        self.eval_blocks = None
+        if _layouts is None and eval_blocks is not None:
+            b, e = _layout(blocks), _layout(eval_blocks)
+            _check(library().lgf_plan_create_split(b.ctypes.data, b.shape[0], e.ctypes.data, e.shape[0], self.n,
+                                                   self.p, int(levels), prec, _stream_handle(stream),
+                                                   ctypes.byref(h)))
+            self.eval_blocks = e
+        elif _layouts is None:
+            b = _layout(blocks)
             _check(library().lgf_plan_create(b.ctypes.data, b.shape[0], self.n, self.p, int(levels), prec,
                                              _stream_handle(stream), ctypes.byref(h)))
         else:
@@ -185,25 +204,32 @@ class Plan:
         return self._h
 
     def shape(self):
+        """Shape of f (the source blocks)."""
         return (self.blocks.shape[0], self.n, self.n, self.n)
 
+    def out_shape(self):
+        """Shape of u (the evaluation blocks; the source blocks unless the sets differ)."""
+        nb = self.blocks.shape[0] if self.eval_blocks is None else self.eval_blocks.shape[0]
+        return (nb, self.n, self.n, self.n)
+
     def solve(self, f, u=None, stream=None):
-        """u = G * f on the plan's layout; f is a contiguous device tensor [N_B, n, n, n]."""
+        """u = G * f on the plan's layout; f is a contiguous device tensor [N_s, n, n, n],
+        u [N_e, n, n, n] (allocated when None)."""
         if self._h is None:
             raise RuntimeError("plan destroyed")
-        if not (f.is_cuda and f.is_contiguous() and f.dtype == self.dtype and tuple(f.shape) == self.shape()):
-            raise ValueError("f must be a contiguous %s device tensor of shape %s" % (self.dtype, self.shape()))
+        self._check_field(f, "f")
         if u is None:
-            u = torch.empty_like(f)
-        elif not (u.is_cuda and u.is_contiguous() and u.dtype == self.dtype and tuple(u.shape) == self.shape()):
-            raise ValueError("u must match f")
+            u = torch.empty(self.out_shape(), dtype=self.dtype, device=f.device)
+        else:
+            self._check_field(u, "u")
         _check(library().lgf_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                    _stream_handle(stream)))
         return u
 
     def _check_field(self, x, name):
-        if not (x.is_cuda and x.is_contiguous() and x.dtype == self.dtype and tuple(x.shape) == self.shape()):
-            raise ValueError("%s must be a contiguous %s device tensor of shape %s" % (name, self.dtype, self.shape()))
+        shape = self.shape() if name == "f" else self.out_shape()
+        if not (x.is_cuda and x.is_contiguous() and x.dtype == self.dtype and tuple(x.shape) == shape):
+            raise ValueError("%s must be a contiguous %s device tensor of shape %s" % (name, self.dtype, shape))
 
     def graph(self, f, u, stream=None):
         """Capture one solve reading f and writing u as a HIP graph (lgf_graph_create)."""
@@ -215,7 +241,7 @@ class Plan:
         """Pick the fastest kernel variants for this plan (lgf_plan_autotune); returns the choice."""
         self._check_field(f, "f")
         if u is None:
-            u = torch.empty_like(f)
+            u = torch.empty(self.out_shape(), dtype=self.dtype, device=f.device)
         self._check_field(u, "u")
         _check(library().lgf_plan_autotune(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                            _stream_handle(stream), int(reps)))
@@ -272,12 +298,19 @@ def _info_dict(inf):
     return d
 
 
-def plan_estimate(blocks, n, p, levels=0, precision="f64"):
-    """lgf_plan_estimate: the plan summary of a layout, computed on the host only."""
-    b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+def plan_estimate(blocks, n, p, levels=0, precision="f64", eval_blocks=None):
+    """lgf_plan_estimate (lgf_plan_estimate_split with eval_blocks): the plan summary of a
+    layout, computed on the host only."""
+    b = _layout(blocks)
     inf = PlanInfo()
-    _check(library().lgf_plan_estimate(b.ctypes.data, b.shape[0], int(n), int(p), int(levels),
-                                       {"f64": F64, "f32": F32}[precision], ctypes.byref(inf)))
+    prec = {"f64": F64, "f32": F32}[precision]
+    if eval_blocks is None:
+        _check(library().lgf_plan_estimate(b.ctypes.data, b.shape[0], int(n), int(p), int(levels), prec,
+                                           ctypes.byref(inf)))
+    else:
+        e = _layout(eval_blocks)
+        _check(library().lgf_plan_estimate_split(b.ctypes.data, b.shape[0], e.ctypes.data, e.shape[0], int(n),
+                                                 int(p), int(levels), prec, ctypes.byref(inf)))
     return _info_dict(inf)
 
 

@@ -16,9 +16,9 @@ vortex-ring-shaped source, and random manufactured solutions (Sec. 4.1).
 import numpy as np
 
 __all__ = [
-    "cube_layout", "sphere_layout", "shell_layout", "eden_layout", "points_of",
+    "cube_layout", "sphere_layout", "shell_layout", "eden_layout", "dilate_layout", "split_sets", "points_of",
     "gaussian_source", "zero_mean_gaussians", "vortex_ring_source", "random_manufactured",
-    "boundary_mask", "config_small", "config_medium", "config_large",
+    "boundary_mask", "config_small", "config_medium", "config_large", "config_split",
 ]
 
 
@@ -115,6 +115,35 @@ def serving_mix(count, rng, n=16):
         f, _ = zero_mean_gaussians(b, n, rng, max(1, b.shape[0] // 8))
         out.append((b, f))
     return out
+
+
+def dilate_layout(blocks, r=1):
+    """Blocks within Chebyshev distance r of a block of the layout (the layout plus an
+    r-block halo), sorted z, y, x."""
+    s = {tuple(b) for b in np.asarray(blocks).tolist()}
+    rng_ = range(-r, r + 1)
+    out = {(x + dx, y + dy, z + dz) for (x, y, z) in s for dx in rng_ for dy in rng_ for dz in rng_}
+    return np.array(sorted(out, key=lambda t: (t[2], t[1], t[0])), dtype=np.int32)
+
+
+def split_sets(kind, rng):
+    """(source blocks, evaluation blocks) of the three shapes separate sets take:
+    "dilated"  sources on a small Eden cluster, evaluation on it plus a one-block halo;
+    "subset"   evaluation on 7 of the 30 blocks of a source cluster;
+    "disjoint" a source cluster and a shifted evaluation cluster with the overlap removed."""
+    if kind == "dilated":
+        src = eden_layout(14, rng)
+        return src, dilate_layout(src, 1)
+    if kind == "subset":
+        src = eden_layout(30, rng)
+        pick = rng.choice(len(src), size=7, replace=False)
+        return src, src[np.sort(pick)]
+    if kind == "disjoint":
+        src = eden_layout(12, rng)
+        ev = eden_layout(10, rng) + np.array([6, 1, -2], dtype=np.int32)
+        s = {tuple(b) for b in src.tolist()}
+        return src, np.asarray([b for b in ev.tolist() if tuple(b) not in s], dtype=np.int32)
+    raise ValueError(kind)
 
 
 def points_of(blocks, n):
@@ -260,3 +289,15 @@ def config_large(seed=2):
     n = 16
     f = vortex_ring_source(blocks, n, rng)
     return dict(blocks=blocks, n=n, p=8, levels=0, f=f, name="cube256_n16_p8_vortexring")
+
+
+def config_split(seed=2):
+    """Separate source and evaluation blocks on the 256^3 vortex-ring workload: sources on
+    the blocks of the 16^3-block cube where the ring's field exceeds 1e-16 of its peak
+    (779 blocks, f restricted to them), evaluation on all 4096 blocks; n = 16, p = 8,
+    full depth."""
+    c = config_large(seed)
+    amp = np.max(np.abs(c["f"]), axis=(1, 2, 3))
+    keep = amp > 1e-16 * amp.max()
+    return dict(blocks=c["blocks"][keep], f=c["f"][keep], eval_blocks=c["blocks"], n=c["n"], p=c["p"],
+                levels=c["levels"], name="ring256_split_n16_p8_full")

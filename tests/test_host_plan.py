@@ -119,3 +119,59 @@ def test_server_config_errors(L):
     assert lib.lgf_plan_set_tuning(None, ctypes.byref(t)) == 1
     assert lib.lgf_plan_get_tuning(None, ctypes.byref(t)) == 1
     assert lib.lgf_plan_create_batch(None, None, 0, 8, 6, 0, 0, None, ctypes.byref(h)) == 1
+
+
+SPLIT_CASES = [(k, lv) for k in ("dilated", "subset", "disjoint") for lv in (0, 2)]
+
+
+@pytest.mark.parametrize("kind,levels", SPLIT_CASES)
+def test_split_lists_match_oracle_tree(L, kind, levels):
+    """Separate source and evaluation blocks: the plan's list sizes are the oracle's lists
+    (evaluation targets x source intervals), its intervals those of the union of the two
+    trees."""
+    rng = np.random.default_rng(21)
+    src, ev = W.split_sets(kind, rng)
+    shift = np.array([4, -9, 31], dtype=np.int32)
+    info = L.plan_estimate(src + shift, 8, 6, levels, "f64", eval_blocks=ev + shift)
+    tree = flgf.Tree(src, levels, ev)
+    assert info["levels"] == tree.L
+    assert info["source_blocks"] == len(src) and info["eval_blocks"] == len(ev)
+    assert info["near_pairs"] == len(tree.near[0])
+    top = 0
+    for lvl in range(1, tree.L + 1):
+        union = np.unique(np.vstack([tree.coords[lvl], tree.coords_e[lvl]]), axis=0)
+        assert info["intervals"][lvl] == union.shape[0], lvl
+        assert info["far_pairs"][lvl] == len(tree.ilist[lvl][0]), lvl
+        if len(tree.ilist[lvl][0]):
+            top = lvl
+    assert info["top_level"] == top
+    assert info["nblocks"] == info["intervals"][1]
+
+
+def test_split_with_equal_sets_matches_single_set(L):
+    rng = np.random.default_rng(22)
+    blocks = W.eden_layout(120, rng)
+    perm = rng.permutation(len(blocks))
+    a = L.plan_estimate(blocks, 8, 6, 0, "f32")
+    b = L.plan_estimate(blocks, 8, 6, 0, "f32", eval_blocks=blocks[perm])
+    for k in ("nblocks", "levels", "top_level", "near_pairs", "far_pairs", "intervals"):
+        assert a[k] == b[k], k
+    # the split plan adds only its evaluation -> level-1 map
+    assert b["workspace_bytes"] == a["workspace_bytes"] + 4 * len(blocks)
+
+
+def test_split_layout_errors(L):
+    src = W.cube_layout(2)
+    for ev, name in ((np.array([[0, 0, 0], [0, 0, 0]]), "LGF_ERR_LAYOUT"),
+                     (np.zeros((0, 3)), "LGF_ERR_LAYOUT"),
+                     (np.array([[0, 0, 0], [1 << 21, 0, 0]]), "LGF_ERR_LAYOUT")):
+        with pytest.raises(L.LGFError) as e:
+            L.plan_estimate(src, 8, 6, eval_blocks=ev)
+        assert e.value.name == name
+    with pytest.raises(L.LGFError) as e:
+        L.plan_estimate(np.array([[1, 1, 1], [1, 1, 1]]), 8, 6, eval_blocks=src)
+    assert e.value.name == "LGF_ERR_LAYOUT"
+    info = L.PlanInfo()
+    lib = L.library()
+    st = lib.lgf_plan_estimate_split(src.ctypes.data, len(src), None, 4, 8, 6, 0, 0, ctypes.byref(info))
+    assert st == 1  # LGF_ERR_ARG

@@ -19,33 +19,12 @@ def _rel(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
-def _sets(kind, rng):
-    """(B_s, B_e) pairs with the shapes that separate sets take in use."""
-    if kind == "dilated":   # evaluate on the source blocks and a one-block halo around them
-        src = W.eden_layout(14, rng)
-        s = {tuple(b) for b in src.tolist()}
-        ev = sorted({(x + dx, y + dy, z + dz) for (x, y, z) in s
-                     for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)})
-        return src, np.asarray(ev, dtype=np.int32)
-    if kind == "subset":    # evaluate on a few of the source blocks
-        src = W.eden_layout(30, rng)
-        pick = rng.choice(len(src), size=7, replace=False)
-        return src, src[np.sort(pick)]
-    if kind == "disjoint":  # a source cluster and a separate evaluation cluster
-        src = W.eden_layout(12, rng)
-        ev = W.eden_layout(10, rng) + np.array([6, 1, -2], dtype=np.int32)
-        s = {tuple(b) for b in src.tolist()}
-        ev = np.asarray([b for b in ev.tolist() if tuple(b) not in s], dtype=np.int32)
-        return src, ev
-    raise ValueError(kind)
-
-
 @pytest.mark.parametrize("kind", ["dilated", "subset", "disjoint"])
 def test_lists_cover_every_eval_source_pair_once(kind):
     # every (evaluation block, source block) pair is reached by exactly one list entry:
     # the near list at level 0, or the interaction list of one level (via the ancestors)
     rng = np.random.default_rng(11)
-    src, ev = _sets(kind, rng)
+    src, ev = W.split_sets(kind, rng)
     for levels in (0, 2):
         t = flgf.Tree(src, levels, ev)
         ns, ne = len(t.blocks), len(t.eval_blocks)
@@ -68,7 +47,7 @@ def test_lattice_single_level_is_exact(kind):
     # p = n + 1 and one level: Reg/Interp are the identity and the level-1 kernel is the
     # exact G, so the FLGF equals Eq. bconv to rounding
     rng = np.random.default_rng(12)
-    src, ev = _sets(kind, rng)
+    src, ev = W.split_sets(kind, rng)
     n = 4
     f = rng.standard_normal((len(src), n, n, n))
     u = flgf.solve(src, f, n, n + 1, 1, eval_blocks=ev)
@@ -82,7 +61,7 @@ def test_full_depth_within_interpolation_error(kind):
     # geometrically in p, as in the same-set case (Sec. 2.5): a wrong list, tree or
     # transfer on either side leaves an O(1) error instead
     rng = np.random.default_rng(13)
-    src, ev = _sets(kind, rng)
+    src, ev = W.split_sets(kind, rng)
     n = 8
     f = rng.standard_normal((len(src), n, n, n))
     exact = _exact(src, ev, n, f)
@@ -108,7 +87,7 @@ def test_evaluation_restricts_and_source_order_is_free():
     # restriction of u on B_e (targets do not interact), and permuting the source blocks
     # together with their fields changes nothing
     rng = np.random.default_rng(15)
-    src, ev = _sets("dilated", rng)
+    src, ev = W.split_sets("dilated", rng)
     n, p = 4, 3
     f = rng.standard_normal((len(src), n, n, n))
     u = flgf.solve(src, f, n, p, 0, eval_blocks=ev)
@@ -127,7 +106,7 @@ def test_sources_absent_from_evaluation_are_superposed():
     # linearity across the two sets: sources split into two parts give the sum of the
     # two solves on the same evaluation blocks (same anchor and extent)
     rng = np.random.default_rng(16)
-    src, ev = _sets("dilated", rng)
+    src, ev = W.split_sets("dilated", rng)
     n, p = 4, 3
     f = rng.standard_normal((len(src), n, n, n))
     fa, fb = f.copy(), f.copy()
