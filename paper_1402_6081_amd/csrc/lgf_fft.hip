@@ -16,7 +16,7 @@ namespace lgfdev {
 
 template <typename T, int m, int M, int NT>
 __global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                int64_t nbatch) {
+                                                int64_t nout) {
     constexpr int H = M / 2 + 1;
     constexpr int PLANE = M * H;
     static_assert(M == 2 * m, "padded length is twice the tile edge");
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T
         T Xr[M], Xi[M];
         pencil_fwd<T, m, M>(xr, xi, Xr, Xi);
 #pragma unroll
-        for (int k = 0; k < M; ++k) out[spec_at(b, k * PLANE + col, nbatch + 1)] = cplx<T>{Xr[k], Xi[k]};
+        for (int k = 0; k < M; ++k) out[spec_at(b, k * PLANE + col, nout)] = cplx<T>{Xr[k], Xi[k]};
     }
 }
 
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T
 // inverted in float-float arithmetic and written as float-float node values.)
 template <typename Tin, typename A, typename Tout, int m, int M, int NT>
 __global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__ in, Tout* __restrict__ out,
-                                                   int64_t nbatch) {
+                                                   int64_t nbatch, const int32_t* __restrict__ out_map) {
     constexpr int H = M / 2 + 1;
     constexpr int PLANE = M * H;
     static_assert(M == 2 * m, "padded length is twice the tile edge");
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__
         for (int j = 0; j < m; ++j) d[j] = x[j];
     }
     __syncthreads();
-    Tout* dst = out + b * (m * m * m);
+    Tout* dst = out + (out_map ? (size_t)out_map[b] : b) * (m * m * m);
     for (int i = tid; i < m * m * m; i += NT) {
         const int z = i / (m * m), r = i - z * (m * m);
         dst[i] = (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[r];
@@ -155,84 +155,90 @@ __global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__
 // among {128, 256, 512} for the level-0 tiles (m = 8, 16).  512 threads are not offered for
 // the FP64 16^3 tile, whose 32-point pencils then no longer fit the register file.
 template <typename T, int m, int NT>
-static hipError_t fwd_mnt(const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s) {
-    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out, nbatch);
+static hipError_t fwd_mnt(const T* in, cplx<T>* out, int64_t nbatch, int64_t nout, hipStream_t s) {
+    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out, nout);
     return hipGetLastError();
 }
 
 template <typename T, int m>
-static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt = 0) {
+static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, int64_t nout, hipStream_t s,
+                               int nt = 0) {
     if constexpr (m == 8 || m == 16) {
         if constexpr (!(m == 16 && sizeof(T) == 8))
-            if (nt == 512) return fwd_mnt<T, m, 512>(in, out, nbatch, s);
-        if (nt == 128 && m >= 12) return fwd_mnt<T, m, 128>(in, out, nbatch, s);
-        if (nt == 256 && m < 12) return fwd_mnt<T, m, 256>(in, out, nbatch, s);
+            if (nt == 512) return fwd_mnt<T, m, 512>(in, out, nbatch, nout, s);
+        if (nt == 128 && m >= 12) return fwd_mnt<T, m, 128>(in, out, nbatch, nout, s);
+        if (nt == 256 && m < 12) return fwd_mnt<T, m, 256>(in, out, nbatch, nout, s);
     }
-    return fwd_mnt<T, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, s);
+    return fwd_mnt<T, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, nout, s);
 }
 
 template <typename Tin, typename A, typename Tout, int m, int NT>
-static hipError_t inv_mnt(const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s) {
+static hipError_t inv_mnt(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, hipStream_t s) {
     hipLaunchKernelGGL((k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out,
-                       nbatch);
+                       nbatch, out_map);
     return hipGetLastError();
 }
 
 template <typename Tin, typename A, typename Tout, int m>
-static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0) {
+static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, hipStream_t s,
+                               int nt = 0) {
     if constexpr ((m == 8 || m == 16) && !std::is_same<A, ff32>::value) {
         if constexpr (!(m == 16 && sizeof(A) == 8))
-            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(in, out, nbatch, s);
-        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(in, out, nbatch, s);
-        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(in, out, nbatch, s);
+            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(in, out, nbatch, out_map, s);
+        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(in, out, nbatch, out_map, s);
+        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(in, out, nbatch, out_map, s);
     }
-    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, s);
+    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, out_map, s);
 }
 
 template <typename T>
-hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt) {
+hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt, int64_t nout) {
     if (nbatch <= 0) return hipSuccess;
+    if (nout <= 0) nout = nbatch + 1;
     switch (m) {
-        case 2: return launch_fwd_m<T, 2>(in, out, nbatch, s);
-        case 3: return launch_fwd_m<T, 3>(in, out, nbatch, s);
-        case 4: return launch_fwd_m<T, 4>(in, out, nbatch, s);
-        case 5: return launch_fwd_m<T, 5>(in, out, nbatch, s);
-        case 6: return launch_fwd_m<T, 6>(in, out, nbatch, s);
-        case 7: return launch_fwd_m<T, 7>(in, out, nbatch, s);
-        case 8: return launch_fwd_m<T, 8>(in, out, nbatch, s, nt);
-        case 9: return launch_fwd_m<T, 9>(in, out, nbatch, s);
-        case 10: return launch_fwd_m<T, 10>(in, out, nbatch, s);
-        case 16: return launch_fwd_m<T, 16>(in, out, nbatch, s, nt);
+        case 2: return launch_fwd_m<T, 2>(in, out, nbatch, nout, s);
+        case 3: return launch_fwd_m<T, 3>(in, out, nbatch, nout, s);
+        case 4: return launch_fwd_m<T, 4>(in, out, nbatch, nout, s);
+        case 5: return launch_fwd_m<T, 5>(in, out, nbatch, nout, s);
+        case 6: return launch_fwd_m<T, 6>(in, out, nbatch, nout, s);
+        case 7: return launch_fwd_m<T, 7>(in, out, nbatch, nout, s);
+        case 8: return launch_fwd_m<T, 8>(in, out, nbatch, nout, s, nt);
+        case 9: return launch_fwd_m<T, 9>(in, out, nbatch, nout, s);
+        case 10: return launch_fwd_m<T, 10>(in, out, nbatch, nout, s);
+        case 16: return launch_fwd_m<T, 16>(in, out, nbatch, nout, s, nt);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename Tin, typename A, typename Tout>
-hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt) {
+hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt,
+                             const int32_t* out_map) {
     if (nbatch <= 0) return hipSuccess;
     switch (m) {
-        case 2: return launch_inv_m<Tin, A, Tout, 2>(in, out, nbatch, s);
-        case 3: return launch_inv_m<Tin, A, Tout, 3>(in, out, nbatch, s);
-        case 4: return launch_inv_m<Tin, A, Tout, 4>(in, out, nbatch, s);
-        case 5: return launch_inv_m<Tin, A, Tout, 5>(in, out, nbatch, s);
-        case 6: return launch_inv_m<Tin, A, Tout, 6>(in, out, nbatch, s);
-        case 7: return launch_inv_m<Tin, A, Tout, 7>(in, out, nbatch, s);
-        case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, s, nt);
-        case 9: return launch_inv_m<Tin, A, Tout, 9>(in, out, nbatch, s);
-        case 10: return launch_inv_m<Tin, A, Tout, 10>(in, out, nbatch, s);
+        case 2: return launch_inv_m<Tin, A, Tout, 2>(in, out, nbatch, out_map, s);
+        case 3: return launch_inv_m<Tin, A, Tout, 3>(in, out, nbatch, out_map, s);
+        case 4: return launch_inv_m<Tin, A, Tout, 4>(in, out, nbatch, out_map, s);
+        case 5: return launch_inv_m<Tin, A, Tout, 5>(in, out, nbatch, out_map, s);
+        case 6: return launch_inv_m<Tin, A, Tout, 6>(in, out, nbatch, out_map, s);
+        case 7: return launch_inv_m<Tin, A, Tout, 7>(in, out, nbatch, out_map, s);
+        case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, out_map, s, nt);
+        case 9: return launch_inv_m<Tin, A, Tout, 9>(in, out, nbatch, out_map, s);
+        case 10: return launch_inv_m<Tin, A, Tout, 10>(in, out, nbatch, out_map, s);
         case 16:
-            if constexpr (!std::is_same<A, ff32>::value) return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, s, nt);
+            if constexpr (!std::is_same<A, ff32>::value)
+                return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, out_map, s, nt);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t, int);
-template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t, int);
+template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t, int, int64_t);
+template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t, int, int64_t);
 template hipError_t launch_ifft_trunc<double, double, double>(int, const cplx<double>*, double*, int64_t,
-                                                               hipStream_t, int);
+                                                               hipStream_t, int, const int32_t*);
 template hipError_t launch_ifft_trunc<float, float, float>(int, const cplx<float>*, float*, int64_t, hipStream_t,
-                                                             int);
-template hipError_t launch_ifft_trunc<float, ff32, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t, int);
+                                                             int, const int32_t*);
+template hipError_t launch_ifft_trunc<float, ff32, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t, int,
+                                                         const int32_t*);
 
 }  // namespace lgfdev

@@ -21,12 +21,16 @@ constexpr int kFarTerms = 8;
 constexpr int kMaxLevels = 16;
 
 // ------------------------------------------------------------------ launchers (device code)
-// out: chunk-major spectra with nbatch + 1 items (the last, a zero sentinel, is not written)
+// out: chunk-major spectra of nout items, of which the first nbatch are written (nout = 0:
+// nbatch + 1, the last a zero sentinel that is not written)
 // nt: threads per workgroup variant (0 = default; tunable for level-0 tiles)
 template <typename T>
-hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt = 0);
+hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt = 0,
+                          int64_t nout = 0);
+// out_map: output tile of each transformed item (NULL = the item's own index)
 template <typename Tin, typename A, typename Tout>
-hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0);
+hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0,
+                             const int32_t* out_map = nullptr);
 
 // Far-field node values of the down pass: double on the FP64 path, float-float on the
 // FP32 path (8 bytes either way).
@@ -80,10 +84,11 @@ template <typename U>
 hipError_t launch_interp_down(const U* par, const int32_t* child8, const double* C01, U* io, int64_t nparent,
                               int p, hipStream_t s);
 // Final: u[b] = vnear[b] + (A^T x A^T x A^T) ut[q(b)], accumulated in FP64 (u may alias
-// vnear); q(b) = l1map[b] (the level-1 interval of evaluation block b), or b when l1map is NULL
+// vnear); q(b) = l1map[b] (the level-1 interval of evaluation block b), or b when l1map is
+// NULL; vnear[b] is taken as 0 (and not read) where near_flag[b] == 0 (NULL: every block)
 template <typename T, typename U>
 hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, int n, int p,
-                        hipStream_t s, const int32_t* l1map = nullptr);
+                        hipStream_t s, const int32_t* l1map = nullptr, const int32_t* near_flag = nullptr);
 
 // ------------------------------------------------------------------ kernel spectra
 struct SpectraKey {

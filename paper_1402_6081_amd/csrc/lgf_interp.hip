@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kInterpThreads)
 template <typename T, typename U, int N, int P>
 __global__ void __launch_bounds__(kInterpThreads)
     k_final(const T* vnear, const U* __restrict__ ut, const double* __restrict__ A, T* u,
-            const int32_t* __restrict__ l1map) {
+            const int32_t* __restrict__ l1map, const int32_t* __restrict__ near_flag) {
     constexpr int N3 = N * N * N, P3 = P * P * P;
     __shared__ double X[P3], t1[P * P * N], t2[P * N * N];
     __shared__ double At[N * P];  // At[j][k] = A[k][j]
@@ -213,6 +213,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
     __syncthreads();
     const T* v = vnear + b * N3;
+    const bool has_near = !near_flag || near_flag[b];  // no near field: v is not read
     T* o = u + b * N3;
     for (int i = tid; i < N3; i += kInterpThreads) {  // z: u[z][y][x]
         const int yx = i % (N * N), z = i / (N * N);
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(kInterpThreads)
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < P; ++a) acc += m[a] * t2[a * N * N + yx];
-        o[i] = (T)((double)v[i] + acc);
+        o[i] = (T)((has_near ? (double)v[i] : 0.0) + acc);
     }
 }
 
@@ -266,9 +267,9 @@ struct FinalRun {
     template <int N, int P>
     struct K {
         static hipError_t run(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, const int32_t* l1map,
-                              hipStream_t s) {
+                              const int32_t* near_flag, hipStream_t s) {
             hipLaunchKernelGGL((k_final<T, U, N, P>), dim3((unsigned)nb), dim3(kInterpThreads), 0, s, vnear, ut, A,
-                               u, l1map);
+                               u, l1map, near_flag);
             return hipGetLastError();
         }
     };
@@ -331,9 +332,9 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
 
 template <typename T, typename U>
 hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, int n, int p, hipStream_t s,
-                        const int32_t* l1map) {
+                        const int32_t* l1map, const int32_t* near_flag) {
     if (nb <= 0) return hipSuccess;
-    return dispatch_np<FinalRun<T, U>::template K>(n, p, vnear, ut, A, u, nb, l1map, s);
+    return dispatch_np<FinalRun<T, U>::template K>(n, p, vnear, ut, A, u, nb, l1map, near_flag, s);
 }
 
 template hipError_t launch_reg_block<double>(const double*, const double*, double*, int64_t, int, int, hipStream_t);
@@ -347,8 +348,8 @@ template hipError_t launch_interp_down<double>(const double*, const int32_t*, co
 template hipError_t launch_interp_down<ff32>(const ff32*, const int32_t*, const double*, ff32*, int64_t, int,
                                              hipStream_t);
 template hipError_t launch_final<double, double>(const double*, const double*, const double*, double*, int64_t, int,
-                                                 int, hipStream_t, const int32_t*);
+                                                 int, hipStream_t, const int32_t*, const int32_t*);
 template hipError_t launch_final<float, ff32>(const float*, const ff32*, const double*, float*, int64_t, int, int,
-                                              hipStream_t, const int32_t*);
+                                              hipStream_t, const int32_t*, const int32_t*);
 
 }  // namespace lgfdev

@@ -105,6 +105,9 @@ struct HostPlan {
     int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
     int64_t nsrc = 0, neval = 0;              // source / evaluation blocks (both nb unless split)
     std::vector<int32_t> eval_l1;             // split sets: level-1 interval of each evaluation block
+    int64_t ntgt0 = 0;                        // level-0 targets transformed (near-active blocks)
+    std::vector<int32_t> near_out;            // split sets: evaluation block of each level-0 target
+    std::vector<int32_t> near_flag;           // split sets: 1 if the evaluation block has a near field
     std::vector<int32_t> g0_tgt8, g0_src64;  // targets: evaluation numbering; sources: sentinel = nsrc
     std::vector<HostLevel> lv;               // index 0 unused, 1..L
     std::vector<int64_t> solve_offsets{0};   // block offsets of the layouts of a batch
@@ -188,39 +191,6 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
     while ((int64_t(1) << (full - 1)) < ext) ++full;
     H.L = levels <= 0 ? full : std::min(levels, full);
     if (H.L >= kMaxLevels) return fail(LGF_ERR_LAYOUT, "tree deeper than supported");
-
-    // ---- level 0: near pairs (evaluation target, source) and 2x2x2 target groups with
-    //      their 4^3 source neighbourhood
-    auto source_at = [&](int64_t qx, int64_t qy, int64_t qz) -> int32_t {
-        if (qx < 0 || qy < 0 || qz < 0) return -1;
-        auto jt = idx0.find(pack(qx, qy, qz));
-        return (jt != idx0.end() && jt->second < nblocks) ? jt->second : -1;
-    };
-    const int32_t* E = split ? ecoords.data() : blocks.data();
-    std::unordered_map<uint64_t, int32_t> gidx;
-    for (int64_t b = 0; b < neval; ++b) {
-        const int32_t* P = &E[3 * b];
-        for (int d = 0; d < 27; ++d)
-            if (source_at(P[0] - (d % 3 - 1), P[1] - ((d / 3) % 3 - 1), P[2] - (d / 9 - 1)) >= 0) ++H.near_pairs;
-        const uint64_t key = pack(P[0] >> 1, P[1] >> 1, P[2] >> 1);
-        auto it = gidx.find(key);
-        int32_t g;
-        if (it == gidx.end()) {
-            g = (int32_t)H.ngroups0++;
-            gidx.emplace(key, g);
-            H.g0_tgt8.resize(8 * H.ngroups0, -1);
-            H.g0_src64.resize(64 * H.ngroups0, (int32_t)nblocks);
-            for (int sidx = 0; sidx < 64; ++sidx) {
-                const int32_t q = source_at(2 * (int64_t)(P[0] >> 1) + (sidx & 3) - 1,
-                                            2 * (int64_t)(P[1] >> 1) + ((sidx >> 2) & 3) - 1,
-                                            2 * (int64_t)(P[2] >> 1) + (sidx >> 4) - 1);
-                if (q >= 0) H.g0_src64[64 * g + sidx] = q;
-            }
-        } else {
-            g = it->second;
-        }
-        H.g0_tgt8[8 * g + ((P[0] & 1) | ((P[1] & 1) << 1) | ((P[2] & 1) << 2))] = (int32_t)b;
-    }
 
     // ---- levels: coordinates, parents, children, and which intervals hold sources /
     //      evaluation blocks
@@ -325,7 +295,90 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
     }
     for (int l = 1; l <= H.L; ++l)
         if (H.lv[l].pairs() > 0) H.Ltop = l;
+
+    // ---- level 0: near pairs (evaluation target, source) and 2x2x2 target groups with
+    //      their 4^3 source neighbourhood.  With separate sets and a far field, evaluation
+    //      blocks with no source among their 27 neighbours have a zero near field: they get
+    //      no level-0 target (the final pass adds the far field alone), so the level-0
+    //      targets are the near-active blocks, numbered in evaluation order.
+    auto source_at = [&](int64_t qx, int64_t qy, int64_t qz) -> int32_t {
+        if (qx < 0 || qy < 0 || qz < 0) return -1;
+        auto jt = idx0.find(pack(qx, qy, qz));
+        return (jt != idx0.end() && jt->second < nblocks) ? jt->second : -1;
+    };
+    const int32_t* E = split ? ecoords.data() : blocks.data();
+    const bool trim = split && H.Ltop >= 1;
+    std::vector<int32_t> act(neval, -1);
+    for (int64_t b = 0; b < neval; ++b) {
+        const int32_t* P = &E[3 * b];
+        int cnt = 0;
+        for (int d = 0; d < 27; ++d)
+            if (source_at(P[0] - (d % 3 - 1), P[1] - ((d / 3) % 3 - 1), P[2] - (d / 9 - 1)) >= 0) ++cnt;
+        H.near_pairs += cnt;
+        if (!trim || cnt > 0) {
+            act[b] = (int32_t)H.ntgt0++;
+            if (trim) H.near_out.push_back((int32_t)b);
+        }
+    }
+    if (trim && H.ntgt0 == neval) {
+        H.near_out.clear();  // every evaluation block is near-active: identity
+    } else if (trim) {
+        H.near_flag.assign(neval, 0);
+        for (int64_t b = 0; b < neval; ++b) H.near_flag[b] = act[b] >= 0;
+    }
+    std::unordered_map<uint64_t, int32_t> gidx;
+    for (int64_t b = 0; b < neval; ++b) {
+        if (act[b] < 0) continue;
+        const int32_t* P = &E[3 * b];
+        const uint64_t key = pack(P[0] >> 1, P[1] >> 1, P[2] >> 1);
+        auto it = gidx.find(key);
+        int32_t g;
+        if (it == gidx.end()) {
+            g = (int32_t)H.ngroups0++;
+            gidx.emplace(key, g);
+            H.g0_tgt8.resize(8 * H.ngroups0, -1);
+            H.g0_src64.resize(64 * H.ngroups0, (int32_t)nblocks);
+            for (int sidx = 0; sidx < 64; ++sidx) {
+                const int32_t q = source_at(2 * (int64_t)(P[0] >> 1) + (sidx & 3) - 1,
+                                            2 * (int64_t)(P[1] >> 1) + ((sidx >> 2) & 3) - 1,
+                                            2 * (int64_t)(P[2] >> 1) + (sidx >> 4) - 1);
+                if (q >= 0) H.g0_src64[64 * g + sidx] = q;
+            }
+        } else {
+            g = it->second;
+        }
+        H.g0_tgt8[8 * g + ((P[0] & 1) | ((P[1] & 1) << 1) | ((P[2] & 1) << 2))] = act[b];
+    }
     return LGF_OK;
+}
+
+// Every index a kernel will follow lies inside the buffer it addresses (checked on the host
+// before upload): level-0 targets < ntgt0, sources <= nsrc (the sentinel), output maps inside
+// the caller's u and the level-1 fields, children and candidate sources inside their level.
+lgf_status check_host(const HostPlan& H) {
+    auto within = [](const std::vector<int32_t>& v, int64_t lo, int64_t hi) {
+        for (int32_t x : v)
+            if (x < lo || x > hi) return false;
+        return true;
+    };
+    bool ok = within(H.g0_tgt8, -1, H.ntgt0 - 1) && within(H.g0_src64, 0, H.nsrc) &&
+              within(H.eval_l1, 0, H.nb - 1) && within(H.near_out, 0, H.neval - 1) &&
+              (H.near_out.empty() || (int64_t)H.near_out.size() == H.ntgt0) &&
+              (H.near_flag.empty() || (int64_t)H.near_flag.size() == H.neval) &&
+              (int64_t)H.g0_tgt8.size() == 8 * H.ngroups0 && (int64_t)H.g0_src64.size() == 64 * H.ngroups0 &&
+              H.ntgt0 <= H.neval && H.nsrc <= H.nb && (H.eval_l1.empty() || (int64_t)H.eval_l1.size() == H.neval);
+    for (int l = 2; ok && l <= H.L && l < (int)H.lv.size(); ++l) {
+        const HostLevel& Lv = H.lv[l];
+        const int64_t nc = H.lv[l - 1].nint;
+        ok = within(Lv.child8, -1, nc - 1) && within(Lv.src216, 0, nc) &&
+             (Lv.src216.empty() || (int64_t)Lv.src216.size() == 216 * Lv.nint);
+    }
+    for (int l = 1; ok && l <= H.L && l < (int)H.lv.size(); ++l) {
+        const HostLevel& Lv = H.lv[l];
+        ok = within(Lv.csr_tgt, 0, Lv.nint - 1) && within(Lv.csr_src, 0, Lv.nint - 1) &&
+             Lv.csr_ptr.size() == Lv.csr_tgt.size() + 1 && (int64_t)Lv.csr_ptr.back() == (int64_t)Lv.csr_src.size();
+    }
+    return ok ? LGF_OK : fail(LGF_ERR_LAYOUT, "internal error: plan list index out of range");
 }
 
 // Union of independent layouts: every index is offset by the items of the earlier
@@ -343,6 +396,7 @@ HostPlan concat(const std::vector<HostPlan>& parts) {
         U.nb += P.nb;
         U.nsrc += P.nsrc;  // parts have equal source and evaluation sets
         U.neval += P.neval;
+        U.ntgt0 += P.ntgt0;
         U.ngroups0 += P.ngroups0;
         U.near_pairs += P.near_pairs;
         for (int l = 1; l <= P.L; ++l) U.lv[l].nint += P.lv[l].nint;
@@ -393,8 +447,8 @@ int64_t workspace_need(const HostPlan& H, lgf_precision prec) {
     const int64_t S1 = spec_padded(2 * p * 2 * p * (p + 1));
     const int64_t p3 = (int64_t)p * p * p;
     const int topc = std::min(H.Ltop + 1, H.L);
-    int64_t need = H.ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (H.nsrc + 1 + H.neval) * S0 * 2 * esz +
-                   (int64_t)H.eval_l1.size() * 4;
+    int64_t need = H.ngroups0 * 72 * 4 + (p * n + 2 * p * p) * 8 + (H.nsrc + 1 + H.ntgt0) * S0 * 2 * esz +
+                   (int64_t)(H.eval_l1.size() + H.near_out.size() + H.near_flag.size()) * 4;
     for (int l = 1; l <= H.Ltop; ++l) {
         const HostLevel& h = H.lv[l];
         need += h.nint * p3 * (esz + usz);
@@ -424,7 +478,10 @@ struct lgf_plan_s {
     lgf_precision prec = LGF_F64;
     int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
     int64_t nsrc = 0, neval = 0;        // blocks of f / of u (nb for both unless the sets differ)
+    int64_t ntgt0 = 0;                  // level-0 targets (evaluation blocks with a near field)
     int32_t* d_eval_l1 = nullptr;       // level-1 interval of each evaluation block (split sets)
+    int32_t* d_near_out = nullptr;      // evaluation block of each level-0 target (split sets)
+    int32_t* d_near_flag = nullptr;     // near field present, per evaluation block (split sets)
     std::vector<int64_t> solve_offsets;
     std::vector<LevelPlan> lv;  // index 0 unused, 1..L
     std::shared_ptr<SpectraEntry> spectra0;
@@ -554,7 +611,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     const double n3 = (double)n * n * n, p3 = (double)p * p * p;
     const double S0 = pl->spectra0->S, S1 = (double)(2 * p) * (2 * p) * (p + 1);
     const int64_t S1p = spec_padded(2 * p * 2 * p * (p + 1));
-    const double ns = (double)pl->nsrc, ne = (double)pl->neval;  // source / evaluation blocks
+    // source / evaluation blocks, and the evaluation blocks with a near field
+    const double ns = (double)pl->nsrc, ne = (double)pl->neval, nt0 = (double)pl->ntgt0;
     auto lvN = [&](int l) { return (double)pl->lv[l].nint; };
     auto lname = [](const char* a, int l) { return std::string(a) + std::to_string(l); };
 #define LGF_STEP(st, x, name, bytes, flops)                              \
@@ -584,8 +642,10 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     auto level_up = [&](int l, hipStream_t st) -> hipError_t {
         LevelPlan& L = pl->lv[l];
         if (L.pairs() == 0) return hipSuccess;
-        LGF_STEP(st, (launch_pad_fft<T>(p, (const T*)L.d_ftil, (C*)L.d_fhat, L.nint, st)), lname("fft_fwd_l", l),
-                 lvN(l) * (p3 * es + S1 * cs), lvN(l) * fft_flops(2 * p));
+        // level 1: the sources come first and are the only intervals the lists read
+        const int64_t nfwd = l == 1 ? pl->nsrc : L.nint;
+        LGF_STEP(st, (launch_pad_fft<T>(p, (const T*)L.d_ftil, (C*)L.d_fhat, nfwd, st, 0, L.nint + 1)),
+                 lname("fft_fwd_l", l), (double)nfwd * (p3 * es + S1 * cs), (double)nfwd * fft_flops(2 * p));
         if (L.zero_uhat)
             LGF_STEP(st, zero_fill(L.d_uhat, L.nint * S1p * 2 * (int64_t)sizeof(T), st), lname("zero_uhat_l", l),
                      lvN(l) * S1 * cs, 0.0);
@@ -673,17 +733,20 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                  ns * (n3 * es + S0 * cs), ns * fft_flops(2 * n));
         LGF_STEP(s,
                  launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8,
-                                     pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nsrc, pl->neval,
+                                     pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nsrc, pl->ntgt0,
                                      pl->spectra0->S, tc.near_waves, tc.near_prefetch, s),
-                 "prod_l0", (ns + ne + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
-        LGF_STEP(s, (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->neval, s, tc.fft0_threads)),
-                 "fft_inv_l0", ne * (S0 * cs + n3 * es), ne * fft_flops(2 * n));
+                 "prod_l0", (ns + nt0 + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
+        LGF_STEP(s,
+                 (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->ntgt0, s, tc.fft0_threads,
+                                             pl->d_near_out)),
+                 "fft_inv_l0", nt0 * (S0 * cs + n3 * es), nt0 * fft_flops(2 * n));
     }
     if (far && (segs & kSegFinal)) {
         if (overlap && (e = hipStreamWaitEvent(s, pl->ev_join, 0)) != hipSuccess) return e;
         LGF_STEP(s,
-                 (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->neval, n, p, s, pl->d_eval_l1)),
-                 "final_l1_l0", ne * (2.0 * n3 * es + p3 * us), ne * 2.0 * (p3 * n + p * p * n * n + p * n3));
+                 (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->neval, n, p, s, pl->d_eval_l1,
+                                     pl->d_near_flag)),
+                 "final_l1_l0", (ne + nt0) * n3 * es + ne * p3 * us, ne * 2.0 * (p3 * n + p * p * n * n + p * n3));
     }
     mark.solve_end(s);
 #undef LGF_STEP
@@ -703,6 +766,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     pl->nb = H.nb;
     pl->nsrc = H.nsrc;
     pl->neval = H.neval;
+    pl->ntgt0 = H.ntgt0;
     pl->L = H.L;
     pl->Ltop = H.Ltop;
     pl->near_pairs = H.near_pairs;
@@ -779,8 +843,10 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
               dev_alloc(pl, &pl->d_g0_src64, H.ngroups0 * 64 * 4) && dev_alloc(pl, &pl->d_A, p * n * 8) &&
               dev_alloc(pl, &pl->d_C01, 2 * p * p * 8) &&
               dev_alloc(pl, &pl->d_fhat0, (H.nsrc + 1) * S0 * 2 * esz) &&
-              dev_alloc(pl, &pl->d_uhat0, H.neval * S0 * 2 * esz);
-    if (ok && !H.eval_l1.empty()) ok = dev_alloc(pl, &pl->d_eval_l1, (int64_t)H.eval_l1.size() * 4);
+              dev_alloc(pl, &pl->d_uhat0, H.ntgt0 * S0 * 2 * esz) &&
+              dev_alloc(pl, &pl->d_eval_l1, (int64_t)H.eval_l1.size() * 4) &&
+              dev_alloc(pl, &pl->d_near_out, (int64_t)H.near_out.size() * 4) &&
+              dev_alloc(pl, &pl->d_near_flag, (int64_t)H.near_flag.size() * 4);
     for (int l = 1; ok && l <= pl->Ltop; ++l) {
         LevelPlan& Lv = pl->lv[l];
         const HostLevel& h = H.lv[l];
@@ -802,7 +868,9 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     if (e == hipSuccess) e = upload(pl->d_g0_src64, H.g0_src64, s);
     if (e == hipSuccess) e = upload(pl->d_A, A, s);
     if (e == hipSuccess) e = upload(pl->d_C01, C01, s);
-    if (e == hipSuccess && pl->d_eval_l1) e = upload(pl->d_eval_l1, H.eval_l1, s);
+    if (e == hipSuccess) e = upload(pl->d_eval_l1, H.eval_l1, s);
+    if (e == hipSuccess) e = upload(pl->d_near_out, H.near_out, s);
+    if (e == hipSuccess) e = upload(pl->d_near_flag, H.near_flag, s);
     for (int l = 1; e == hipSuccess && l <= pl->Ltop; ++l) {
         LevelPlan& Lv = pl->lv[l];
         if (Lv.d_csr_tgt) {
@@ -1065,8 +1133,10 @@ static lgf_status check_args(int32_t n, int32_t p, lgf_precision prec) {
 }
 
 static lgf_status make_plan(HostPlan& H, lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
+    lgf_status st = check_host(H);
+    if (st != LGF_OK) return st;
     lgf_plan_s* pl = new lgf_plan_s();
-    lgf_status st = setup_device(H, prec, (hipStream_t)hip_stream, pl);
+    st = setup_device(H, prec, (hipStream_t)hip_stream, pl);
     if (st != LGF_OK) {
         delete pl;
         return st;
@@ -1161,6 +1231,7 @@ static lgf_status estimate_plan(const int32_t* src_ijk, int64_t nsrc, const int3
     try {
         HostPlan H;
         st = build_host(src_ijk, nsrc, n, p, levels, H, eval_ijk, neval);
+        if (st == LGF_OK) st = check_host(H);
         if (st != LGF_OK) return st;
         std::memset(info, 0, sizeof(*info));
         info->nblocks = H.nb;
