@@ -262,7 +262,7 @@ def batch_bench(L, W, steps, warmup, seed=4):
             "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3), "tuning": choice}
 
 
-def split_bench(L, W, steps, warmup):
+def split_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None):
     """Separate source and evaluation blocks: the vortex ring's 779 source blocks evaluated
     on the whole 16^3-block cube of 16^3 points (p = 8, full depth), FP64 and FP32, one
     autotuned graph launch per solve; against the single-set plan of the cube with the
@@ -277,24 +277,31 @@ def split_bench(L, W, steps, warmup):
     npts = len(ev) * n ** 3
     out = {"workload": cfg["name"], "source_blocks": int(len(src)), "eval_blocks": int(len(ev)),
            "points": int(npts), "unit": "evaluation points solved/s"}
-    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+    for prec, dt, peak in (("f64", torch.float64, FP64_PEAK_TFLOPS), ("f32", torch.float32, FP32_PEAK_TFLOPS)):
         plan = L.Plan(src, n, cfg["p"], cfg["levels"], prec, eval_blocks=ev)
         f = torch.from_numpy(cfg["f"]).to("cuda:0", dt)
         u = torch.empty(plan.out_shape(), dtype=dt, device="cuda:0")
-        choice = plan.autotune(f, u, reps=2)
-        dt_s, lat = _time_graph(plan, f, u, steps, warmup)
-        whole = L.Plan(ev, n, cfg["p"], cfg["levels"], prec)
-        fw = torch.from_numpy(fpad).to("cuda:0", dt)
-        uw = torch.empty_like(fw)
-        whole.autotune(fw, uw, reps=2)
-        dt_w, _ = _time_graph(whole, fw, uw, steps, warmup)
-        out[prec] = {"value": round(npts * steps / dt_s, 1), "ms_per_step": round(dt_s / steps * 1e3, 5),
-                     "latency_ms": _pct(lat), "tuning": choice,
-                     "single_set_ms_per_step": round(dt_w / steps * 1e3, 5),
-                     "equal_to_single_set": bool(torch.equal(u, uw))}
+        m = _measure(plan, f, u, steps, warmup, graph=graph, tune=tune)
+        res = {"value": round(npts * steps / m["dt_graph"], 1), "ms_per_step": round(m["dt_graph"] / steps * 1e3, 5),
+               "latency_ms": _pct(m["lat_graph"]), "tuning": m["tuning"],
+               "eager_ms_per_step": round(m["dt_eager"] / steps * 1e3, 5),
+               "roofline": _roofline(m["prof"], peak, cfg["name"], prec)}
+        if breakdown is not None:
+            breakdown["split_fp64" if prec == "f64" else "split_fp32"] = _breakdown(m["prof"])
         plan.close()
-        whole.close()
-        del f, u, fw, uw
+        if graph:
+            whole = L.Plan(ev, n, cfg["p"], cfg["levels"], prec)
+            fw = torch.from_numpy(fpad).to("cuda:0", dt)
+            uw = torch.empty_like(fw)
+            if tune:
+                whole.autotune(fw, uw, reps=2)
+            dt_w, _ = _time_graph(whole, fw, uw, steps, warmup)
+            res["single_set_ms_per_step"] = round(dt_w / steps * 1e3, 5)
+            res["equal_to_single_set"] = bool(torch.equal(u, uw))
+            whole.close()
+            del fw, uw
+        out[prec] = res
+        del f, u
         torch.cuda.empty_cache()
     return out
 
@@ -363,6 +370,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--split-only", action="store_true",
+                    help="only the separate-set workload (profiling runs); prints its JSON object")
     ap.add_argument("--no-graph", action="store_true", help="eager solves only (counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="default kernel variants, no autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -380,6 +389,15 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+    if args.split_only:
+        breakdown = {}
+        out = split_bench(L, W, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune,
+                          breakdown=breakdown)
+        if args.breakdown:
+            with open(args.breakdown, "w") as fh:
+                json.dump(breakdown, fh, indent=1)
+        print(json.dumps({"split": out}), flush=True)
+        return
     cfg = W.config_medium()
     npts = cfg["f"].size
     dev = torch.device("cuda:0")
@@ -449,7 +467,8 @@ def main():
         result["serve"] = serve_bench(L, W)
         print("serving measured", flush=True, file=sys.stderr)
     if not args.no_split:
-        result["split"] = split_bench(L, W, max(5, args.steps // 5), 2)
+        result["split"] = split_bench(L, W, max(5, args.steps // 5), 2, graph=not args.no_graph,
+                                      tune=not args.no_tune, breakdown=breakdown)
         print("separate-set solves measured", flush=True, file=sys.stderr)
 
     if not args.no_cpu_baseline:

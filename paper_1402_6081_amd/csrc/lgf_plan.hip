@@ -89,6 +89,7 @@ hipError_t checked(hipError_t e, const char* what, hipStream_t s) {
 // ------------------------------------------------------------------ host description of a plan
 struct HostLevel {
     int64_t nint = 0;
+    int64_t nsrc_int = 0;         // intervals holding a source (the spectra the lists read)
     std::vector<int32_t> coords;  // [nint][3] (single layouts only; empty in unions)
     std::vector<int32_t> child8;  // [nint][8] children at level l-1 (levels >= 2)
     std::vector<int32_t> src216;  // [nint][216] children of the 27 neighbours, sentinel = N_{l-1}
@@ -293,8 +294,10 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
             T.csr_ptr = {0};
         }
     }
-    for (int l = 1; l <= H.L; ++l)
+    for (int l = 1; l <= H.L; ++l) {
         if (H.lv[l].pairs() > 0) H.Ltop = l;
+        for (char c : H.has_src[l]) H.lv[l].nsrc_int += c;
+    }
 
     // ---- level 0: near pairs (evaluation target, source) and 2x2x2 target groups with
     //      their 4^3 source neighbourhood.  With separate sets and a far field, evaluation
@@ -399,7 +402,10 @@ HostPlan concat(const std::vector<HostPlan>& parts) {
         U.ntgt0 += P.ntgt0;
         U.ngroups0 += P.ngroups0;
         U.near_pairs += P.near_pairs;
-        for (int l = 1; l <= P.L; ++l) U.lv[l].nint += P.lv[l].nint;
+        for (int l = 1; l <= P.L; ++l) {
+            U.lv[l].nint += P.lv[l].nint;
+            U.lv[l].nsrc_int += P.lv[l].nsrc_int;
+        }
     }
     U.solve_offsets = {0};
     std::vector<int64_t> off(U.L + 1, 0);  // running item offset per level (level 1 = blocks)
@@ -463,7 +469,7 @@ int64_t workspace_need(const HostPlan& H, lgf_precision prec) {
 
 // ------------------------------------------------------------------ the plan
 struct LevelPlan {
-    int64_t nint = 0;
+    int64_t nint = 0, nsrc_int = 0;
     int64_t sib_pairs = 0, csr_entries = 0, ncsr = 0;
     bool zero_uhat = false;
     std::shared_ptr<SpectraEntry> spectra, spectra_csr;  // radius 3 / radius of the CSR offsets
@@ -655,14 +661,15 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                      (launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216,
                                              (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S, tc.far_waves,
                                              tc.far_children, st)),
-                     lname("prod_l", l), (2.0 * lvN(l) + 316.0) * S1 * cs, (double)L.sib_pairs * S1 * 8.0);
+                     lname("prod_l", l), ((double)L.nsrc_int + lvN(l) + 316.0) * S1 * cs,
+                     (double)L.sib_pairs * S1 * 8.0);
         }
         if (L.csr_entries > 0)
             LGF_STEP(st,
                      (launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra_csr->dev, L.d_csr_ptr, L.d_csr_src,
                                          L.d_csr_off, L.d_csr_tgt, (C*)L.d_uhat, L.ncsr, L.nint, L.spectra_csr->noff,
                                          L.spectra_csr->S, st)),
-                     lname("prod_top_l", l), (2.0 * lvN(l) + L.spectra_csr->noff) * S1 * cs,
+                     lname("prod_top_l", l), ((double)L.nsrc_int + lvN(l) + L.spectra_csr->noff) * S1 * cs,
                      (double)L.csr_entries * S1 * 8.0);
         return hipSuccess;
     };
@@ -787,6 +794,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     pl->lv.assign(H.L + 1, LevelPlan());
     for (int l = 1; l <= H.L; ++l) {
         pl->lv[l].nint = H.lv[l].nint;
+        pl->lv[l].nsrc_int = H.lv[l].nsrc_int;
         pl->lv[l].sib_pairs = H.lv[l].sib_pairs;
         pl->lv[l].csr_entries = (int64_t)H.lv[l].csr_src.size();
         pl->lv[l].ncsr = (int64_t)H.lv[l].csr_tgt.size();

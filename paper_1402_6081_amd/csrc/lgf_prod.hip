@@ -141,7 +141,9 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 // from LDS and applied to every pair with that delta.  The delta loop is unrolled; the
 // interaction-list condition |D|_inf >= 2 is a wave-uniform branch.
 // Every child sums its terms in the same order (neighbour e, then delta) whatever CPL and
-// the number of waves, so all variants give identical results.
+// the number of waves, so all variants give identical results.  A neighbour whose children
+// are all the zero sentinel for every parent of a wave (absent intervals, or intervals
+// without sources) is skipped by that wave: the terms it would add are exact zeros.
 // Lanes: F consecutive frequencies (one 128-byte segment of a spectrum) x 64/F parents.
 // The workgroup's waves share the [343][F] kernel tile and the parents' source indices in LDS.
 template <typename T>
@@ -195,33 +197,35 @@ __device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fl, 
 
 // Neighbours in order e = 0..26 through a three-buffer pipeline: the sources of e+1 and
 // e+2 are in flight while e is consumed.
+// live: wave-uniform mask, bit e set when neighbour e holds a source for some parent of
+// the wave.
 template <typename T, int CPL, int Q>
 __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fl, const int32_t* si, const cplx<T>* tk,
-                                         T (&ar)[CPL], T (&ai)[CPL]) {
+                                         uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
     cplx<T> fa[8], fb[8], fc[8];
     m2l_load<T>(0, fl, si, fa);
     m2l_load<T>(1, fl, si, fb);
 #pragma unroll 1
     for (int e = 0; e < 27; e += 3) {
         m2l_load<T>(e + 2, fl, si, fc);
-        m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
+        if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
         m2l_load<T>(e + 3, fl, si, fa);
-        m2l_neighbour<T, CPL, Q>(e + 1, fb, tk, ar, ai);
+        if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fb, tk, ar, ai);
         m2l_load<T>(e + 4, fl, si, fb);
-        m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
+        if (live & (4u << e)) m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
     }
 }
 
 template <typename T, int CPL, int Q = 0>
 __device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fl, const int32_t* si, const cplx<T>* tk,
-                                             T (&ar)[CPL], T (&ai)[CPL]) {
+                                             uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
     if constexpr (Q + 1 < 8 / CPL) {
         if (q != Q) {
-            m2l_dispatch<T, CPL, Q + 1>(q, fl, si, tk, ar, ai);
+            m2l_dispatch<T, CPL, Q + 1>(q, fl, si, tk, live, ar, ai);
             return;
         }
     }
-    m2l_lane<T, CPL, Q>(fl, si, tk, ar, ai);
+    m2l_lane<T, CPL, Q>(fl, si, tk, live, ar, ai);
 }
 
 template <typename T, int kFarWaves, int CPL>
@@ -236,6 +240,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     constexpr int NT = 64 * kFarWaves * NQ;
     __shared__ cplx<T> tile[343 * F];
     __shared__ int32_t sidx[PPG * 216];
+    __shared__ uint32_t live[kFarWaves];  // per group of PPW parents: neighbours holding a source
     const int nchunks = (S + F - 1) / F;
     int chunk, pb;
     if (!xcd_tile(nchunks, (nparents + PPG - 1) / PPG, chunk, pb)) return;
@@ -248,6 +253,16 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
         const int Jl = i / 216, k = i - Jl * 216;
         const int J = pb * PPG + Jl;
         sidx[i] = J < nparents ? src216[(int64_t)J * 216 + k] : nitems;  // padding parents read zeros
+    }
+    if (threadIdx.x < kFarWaves) live[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kFarWaves * 27; i += NT) {
+        const int g = i / 27, e = i - g * 27;
+        bool any = false;
+        for (int jl = g * PPW; jl < (g + 1) * PPW; ++jl)
+#pragma unroll
+            for (int cs = 0; cs < 8; ++cs) any |= sidx[jl * 216 + e * 8 + cs] != nitems;
+        if (any) atomicOr(&live[g], 1u << e);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -264,7 +279,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
         ar[i] = T(0);
         ai[i] = T(0);
     }
-    m2l_dispatch<T, CPL>(q, fl, sidx + Jl * 216, tile + j, ar, ai);
+    m2l_dispatch<T, CPL>(q, fl, sidx + Jl * 216, tile + j, (uint32_t)wave_uniform((int)live[pw]), ar, ai);
     if (J >= nparents || w >= S) return;
     const int32_t* c8 = child8 + (int64_t)J * 8 + q * CPL;
 #pragma unroll
