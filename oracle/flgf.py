@@ -21,8 +21,10 @@ Readings taken where the paper is silent or ambiguous (all listed in the design 
   * Interval I at level l >= 1 spans [I s_l, (I+1) s_l]^3 with s_l = n 2^(l-1); its
     p^3 nodes are x_{I,k} = I s_l + k h_l, h_l = s_l/(p-1) (one-node overlap on the
     + side, Sec. 4 footnote; p = n+1 gives the paper's own scheme).
-  * Interpolation is global Lagrange on the p nodes of an interval (n_max = p,
-    Sec. 2.5); Reg is its adjoint.
+  * Interpolation is Lagrange on the p nodes of an interval; with p > n_max = 10 each
+    point uses only its n_max closest nodes (Sec. 2.5's hybrid p/h refinement; window
+    start ceil(t - n_max/2), ties to the lower window, clamped to the interval).  Reg is
+    the adjoint of Interp.
   * InflList: at level 0 the (up to) 27 blocks with |Q-P|_inf <= 1; at 1 <= l < L the
     children of the parent's neighbours with |Q-P|_inf >= 2; at the top level L all
     intervals with |Q-P|_inf >= 2.  L = min(levels, 1 + ceil(log2(extent))).
@@ -45,6 +47,7 @@ from . import lgf as _lgf
 
 R_LATTICE = 32   # exact-G region for lattice kernels at levels >= 1
 Q_FAR = 8        # terms of the asymptotic expansion used as the far kernel
+N_MAX = 10       # most nodes one interpolation stencil uses (the paper's n_max)
 
 
 # ----------------------------------------------------------------------------- layout / tree
@@ -148,25 +151,43 @@ class Tree:
 
 # ----------------------------------------------------------------------------- interpolation
 
-def lagrange(p, t):
-    """phi_k(t) = prod_{j != k} (t - j)/(k - j) on the nodes 0..p-1; returns [p, len(t)]."""
-    t = np.asarray(t, dtype=np.float64)
-    out = np.ones((p, t.size))
-    for k in range(p):
-        for j in range(p):
-            if j != k:
-                out[k] *= (t - j) / (k - j)
+def stencil_start(p, t, nmax=N_MAX):
+    """First node of the nmax consecutive nodes among 0..p-1 closest to t (Sec. 2.5: with
+    more than n_max nodes only the n_max closest are used).  Every included node is at
+    least as close as every excluded one when the window starts at ceil(t - nmax/2); a tie
+    (t - nmax/2 an integer) goes to the lower window.  Clamped to the interval."""
+    if p <= nmax:
+        return 0
+    return int(min(max(int(np.ceil(t - nmax / 2.0)), 0), p - nmax))
+
+
+def lagrange(p, t, nmax=N_MAX):
+    """phi_k(t) for the nodes 0..p-1, returned as [p, len(t)].  With p <= nmax this is the
+    global Lagrange basis prod_{j != k} (t - j)/(k - j).  With p > nmax (hybrid p/h
+    refinement, Sec. 2.5) each t uses the Lagrange basis of its nmax closest nodes, and
+    phi_k(t) = 0 for the nodes outside that window."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    out = np.zeros((p, t.size))
+    for i, ti in enumerate(t.tolist()):
+        lo = stencil_start(p, ti, nmax)
+        win = range(lo, lo + min(p, nmax))
+        for k in win:
+            v = 1.0
+            for j in win:
+                if j != k:
+                    v *= (ti - j) / (k - j)
+            out[k, i] = v
     return out
 
 
-def block_matrix(n, p):
+def block_matrix(n, p, nmax=N_MAX):
     """A[k, j] = phi_k(j (p-1)/n): node k of a level-1 interval -> grid point j of its block."""
-    return lagrange(p, np.arange(n) * (p - 1) / n)
+    return lagrange(p, np.arange(n) * (p - 1) / n, nmax)
 
 
-def child_matrices(p):
+def child_matrices(p, nmax=N_MAX):
     """C_c[m, k] = phi_m((c (p-1) + k)/2): parent node m -> node k of child c in {0, 1}."""
-    return [lagrange(p, (c * (p - 1) + np.arange(p)) / 2.0) for c in (0, 1)]
+    return [lagrange(p, (c * (p - 1) + np.arange(p)) / 2.0, nmax) for c in (0, 1)]
 
 
 def _apply3(Mz, My, Mx, X):

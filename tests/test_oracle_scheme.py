@@ -1,0 +1,111 @@
+"""Pins of the oracle's hybrid p/h-refined interpolation (Sec. 2.5: at most n_max = 10
+nodes per stencil, the closest ones) and of the paper's own scheme family n_I = n + 1
+(Sec. 4), against facts fixed by the mathematics and by the paper's convergence claims."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import flgf, lgf
+from paper_1402_6081_amd import workloads as W
+
+
+def test_window_holds_the_closest_nodes():
+    # brute force: no node outside the chosen window is closer to t than a node inside
+    p, nmax = 17, 10
+    for t in np.linspace(0.0, p - 1.0, 641):
+        lo = flgf.stencil_start(p, t, nmax)
+        inside = np.arange(lo, lo + nmax)
+        outside = np.setdiff1d(np.arange(p), inside)
+        assert np.max(np.abs(inside - t)) <= np.min(np.abs(outside - t)) + 1e-12, t
+    # ties (t - nmax/2 an integer) go to the lower window; midpoints get centred windows
+    assert flgf.stencil_start(p, 8.0, nmax) == 3
+    assert flgf.stencil_start(p, 8.5, nmax) == 4
+    assert flgf.stencil_start(p, 0.5, nmax) == 0 and flgf.stencil_start(p, 15.5, nmax) == 7
+
+
+@pytest.mark.parametrize("p", [11, 13, 17])
+def test_local_stencils_reproduce_polynomials_of_degree_below_nmax(p):
+    rng = np.random.default_rng(p)
+    t = np.concatenate([rng.uniform(0, p - 1, 200), np.arange(p) + 0.5])
+    t = t[t <= p - 1]
+    phi = flgf.lagrange(p, t)
+    assert np.all(np.count_nonzero(phi, axis=0) <= flgf.N_MAX)
+    nodes = np.arange(p, dtype=np.float64)
+    for deg in range(flgf.N_MAX):
+        c = rng.standard_normal(deg + 1)
+        q = np.polyval(c, nodes)
+        scale = np.max(np.abs(np.polyval(c, np.linspace(0, p - 1, 101))))
+        assert np.max(np.abs(q @ phi - np.polyval(c, t))) < 1e-9 * scale, deg
+    # but not degree n_max in general: the stencil is local
+    q = nodes ** flgf.N_MAX
+    assert np.max(np.abs(q @ phi - t ** flgf.N_MAX)) > 1e-3
+
+
+def test_lattice_scheme_transfers():
+    # n_I = n + 1 = 17: level-1 nodes are the block's grid points (Interp 1 -> 0 is
+    # [I; 0]); a child node either sits on a parent node (identity) or halfway between two
+    # (a centred 10-node stencil away from the interval ends)
+    A = flgf.block_matrix(16, 17)
+    assert np.array_equal(A[:16], np.eye(16)) and np.all(A[16] == 0.0)
+    C = flgf.child_matrices(17)
+    for c in (0, 1):
+        for k in range(17):
+            col = C[c][:, k]
+            if k % 2 == 0:
+                assert np.array_equal(col, np.eye(17)[c * 8 + k // 2])
+            else:
+                t = c * 8 + k / 2.0
+                nz = np.nonzero(col)[0]
+                assert len(nz) == 10 and nz[0] == flgf.stencil_start(17, t)
+                if 4.5 <= t <= 11.5:  # centred window: symmetric weights
+                    m = int(t - 0.5)
+                    assert np.allclose(col[m - 4:m + 1], col[m + 1:m + 6][::-1], rtol=1e-13, atol=0)
+
+
+def test_reg_is_adjoint_of_interp_with_local_stencils():
+    rng = np.random.default_rng(4)
+    C = flgf.child_matrices(17)
+    x = rng.standard_normal((1, 17, 17, 17))
+    y = rng.standard_normal((1, 17, 17, 17))
+    for cz, cy, cx in itertools.product((0, 1), repeat=3):
+        up = flgf._apply3(C[cz], C[cy], C[cx], x)          # Reg: child -> parent
+        down = flgf._apply3(C[cz].T, C[cy].T, C[cx].T, y)  # Interp: parent -> child
+        assert abs(np.sum(up * y) - np.sum(x * down)) < 1e-12 * np.sum(np.abs(up * y))
+
+
+def _dense(blocks, n, vals):
+    b = np.asarray(blocks) - np.min(blocks, axis=0)
+    ext = b.max(axis=0) + 1
+    D = np.zeros((ext[2] * n, ext[1] * n, ext[0] * n))
+    for i, (bx, by, bz) in enumerate(b.tolist()):
+        D[bz * n:(bz + 1) * n, by * n:(by + 1) * n, bx * n:(bx + 1) * n] = vals[i]
+    return D
+
+
+def _blocks(blocks, n, D):
+    b = np.asarray(blocks) - np.min(blocks, axis=0)
+    out = np.zeros((len(b), n, n, n))
+    for i, (bx, by, bz) in enumerate(b.tolist()):
+        out[i] = D[bz * n:(bz + 1) * n, by * n:(by + 1) * n, bx * n:(bx + 1) * n]
+    return out
+
+
+def test_paper_scheme_converges_like_n_I_to_minus_10():
+    # one active grid (an Eden cluster of 24 blocks of 16^3 = 192 blocks of 8^3) and one
+    # manufactured solution (Sec. 4.1): the n_I = 17 scheme (n = 16, stencils of 10 nodes)
+    # against the n_I = 9 scheme (n = 8, global): the paper reports error ~ n_I^-10.7
+    # for n_I in [11, 28], (17/9)^10.7 ~ 900
+    rng = np.random.default_rng(3)
+    b16 = W.eden_layout(24, rng)
+    b8 = (2 * b16[:, None, :] + W.cube_layout(2)[None]).reshape(-1, 3)
+    u16 = W.random_manufactured(b16, 16, rng)
+    D = _dense(b16, 16, u16)
+    LD = lgf.laplacian(D)[1:-1, 1:-1, 1:-1]
+    err = {}
+    for n, b in ((16, b16), (8, b8)):
+        u, f = _blocks(b, n, D), _blocks(b, n, LD)
+        assert flgf.Tree(b, 0).L >= 3  # interpolation at two levels or more
+        got = flgf.solve(b, f, n, n + 1, 0)
+        err[n] = np.max(np.abs(got - u)) / np.max(np.abs(u))
+    assert err[16] < 2e-9 and err[8] > 300 * err[16], err
