@@ -292,6 +292,78 @@ __device__ __forceinline__ void pencil_inv(const T (&Xr)[M], const T (&Xi)[M], T
     }
 }
 
+// Twiddle table for the runtime-indexed DFTs below: tw[r] = (cos, sin)(2 pi r / M), r < M,
+// from the compile-time roots (staged in LDS by the caller).
+template <int M>
+__device__ __forceinline__ void stage_roots(double2* tw, int tid, int nthreads) {
+    constexpr RootTable<M> R{};
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+        if (r % nthreads == tid) tw[r] = make_double2(R.c[r], R.s[r]);
+}
+
+// a * (wr + i wi) with runtime twiddles (exact for w in {1, -1, i, -i} as well: the FMA
+// forms give a product of 0 or a copy in each term)
+template <typename T>
+__device__ __forceinline__ void cmul_rt(T ar, T ai, double wr, double wi, T& orr, T& oi) {
+    if constexpr (std::is_floating_point<T>::value) {
+        const T r = (T)wr, i = (T)wi;
+        orr = fma(ar, r, -(ai * i));
+        oi = fma(ar, i, ai * r);
+    } else {
+        const T r = (T)wr, i = (T)wi;
+        orr = ar * r - ai * i;
+        oi = ar * i + ai * r;
+    }
+}
+
+// Direct DFT handing each output to `put` as soon as it is formed, outputs in a runtime
+// loop and twiddles read from tw (large prime-factor pencils: compile-time 64-bit roots and
+// all outputs live at once would spill):
+//   put(k, X_k) for k < nout,  X_k = sum_{j < nin} x_j e^{SIGN 2 pi i jk / M}.
+template <typename T, int nin, int M, int SIGN, int nout, typename Put>
+__device__ __forceinline__ void dft_each(const T (&xr)[nin], const T (&xi)[nin], const double2* tw, Put put) {
+#pragma unroll 1
+    for (int k = 0; k < nout; ++k) {
+        T sr = xr[0], si = xi[0];
+        int idx = 0;
+#pragma unroll
+        for (int j = 1; j < nin; ++j) {
+            idx += k;
+            if (idx >= M) idx -= M;  // idx = j k mod M
+            const double2 w = tw[idx];
+            T tr, ti;
+            cmul_rt<T>(xr[j], xi[j], w.x, SIGN * w.y, tr, ti);
+            sr += tr;
+            si += ti;
+        }
+        put(k, sr, si);
+    }
+}
+
+// Real truncated inverse of a Hermitian spectrum from its first H = M/2 + 1 coefficients,
+// one output at a time: x_j = Y_0 + (-1)^j Y_{M/2} + 2 Re sum_{0<k<M/2} Y_k e^{+2 pi i jk/M}.
+template <typename T, int m, int M, typename Put>
+__device__ __forceinline__ void c2r_each(const T (&Yr)[M / 2 + 1], const T (&Yi)[M / 2 + 1], const double2* tw,
+                                         Put put) {
+#pragma unroll 1
+    for (int j = 0; j < m; ++j) {
+        T acc = T(0);
+        int idx = 0;
+#pragma unroll
+        for (int k = 1; k < M / 2; ++k) {
+            idx += j;
+            if (idx >= M) idx -= M;  // idx = j k mod M
+            const double2 w = tw[idx];
+            T tr, ti;
+            cmul_rt<T>(Yr[k], Yi[k], w.x, w.y, tr, ti);
+            acc += tr;
+        }
+        const T nyq = (j & 1) ? -Yr[M / 2] : Yr[M / 2];
+        put(j, Yr[0] + nyq + (acc + acc));
+    }
+}
+
 // Real part only of the truncated inverse of a Hermitian spectrum given by its first
 // H = M/2 + 1 coefficients (C2R): x[j] = sum_{k<M} Z[k] e^{+2 pi i jk/M}, Z[M-k] = conj Z[k].
 template <typename T, int m, int M>

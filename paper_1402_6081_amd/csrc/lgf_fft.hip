@@ -86,7 +86,8 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T
 // inverted in float-float arithmetic and written as float-float node values.)
 template <typename Tin, typename A, typename Tout, int m, int M, int NT>
 __global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__ in, Tout* __restrict__ out,
-                                                   int64_t nbatch, const int32_t* __restrict__ out_map) {
+                                                   int64_t nbatch, const int32_t* __restrict__ out_map,
+                                                   int opitch) {
     constexpr int H = M / 2 + 1;
     constexpr int PLANE = M * H;
     static_assert(M == 2 * m, "padded length is twice the tile edge");
@@ -144,11 +145,180 @@ __global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__
         for (int j = 0; j < m; ++j) d[j] = x[j];
     }
     __syncthreads();
-    Tout* dst = out + (out_map ? (size_t)out_map[b] : b) * (m * m * m);
-    for (int i = tid; i < m * m * m; i += NT) {
-        const int z = i / (m * m), r = i - z * (m * m);
-        dst[i] = (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[r];
+    // output tiles of opitch^3 values: the m^3 results, zeros in the planes beyond them
+    Tout* dst = out + (out_map ? (size_t)out_map[b] : b) * (size_t)(opitch * opitch * opitch);
+    if (opitch == m) {
+        for (int i = tid; i < m * m * m; i += NT) {
+            const int z = i / (m * m), r = i - z * (m * m);
+            dst[i] = (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[r];
+        }
+    } else {
+        for (int i = tid; i < opitch * opitch * opitch; i += NT) {
+            const int x = i % opitch, y = (i / opitch) % opitch, z = i / (opitch * opitch);
+            dst[i] = (z < m && y < m && x < m) ? (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[y * m + x]
+                                               : Tout(0);
+        }
     }
+}
+
+// ------------------------------------------------------------------ two-phase transforms
+// For tiles whose one-workgroup LDS tile [m][M][M/2+1] exceeds the 160 KB of a workgroup
+// (m = 17: 166 KB of complex doubles), the transforms run in two kernels through an HBM
+// intermediate [z < m][ky < M][kx <= M/2] per item (`scratch`, complex of 16 bytes):
+//   forward  k_fft2_xy (stage, x pass, y pass -> scratch), k_fft2_z (z pass -> spectrum);
+//   inverse  k_ifft2_z (z pass -> scratch), k_ifft2_yx (y pass, x pass -> real tile).
+template <typename T, int m, int M, int NT>
+__global__ void __launch_bounds__(NT) k_fft2_xy(const T* __restrict__ in, cplx<T>* __restrict__ scratch) {
+    constexpr int H = M / 2 + 1;
+    __shared__ T tile[m * m * m];
+    __shared__ cplx<T> buf[m * m * H];  // [z][y][kx]
+    __shared__ double2 tw[M];
+    const int tid = threadIdx.x;
+    const size_t b = blockIdx.x;
+    const T* src = in + b * (m * m * m);
+    stage_roots<M>(tw, tid, NT);
+    for (int i = tid; i < m * m * m; i += NT) tile[i] = src[i];
+    __syncthreads();
+    for (int row = tid; row < m * m; row += NT) {  // x pass: real rows (z, y)
+        T xr[m], xi[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            xr[j] = tile[row * m + j];
+            xi[j] = T(0);
+        }
+        cplx<T>* d = buf + row * H;
+        dft_each<T, m, M, -1, H>(xr, xi, tw, [&](int k, T re, T im) { d[k] = cplx<T>{re, im}; });
+    }
+    __syncthreads();
+    cplx<T>* dst = scratch + b * (m * M * H);
+    for (int col = tid; col < m * H; col += NT) {  // y pass: columns (z, kx) -> [z][ky][kx]
+        const int z = col / H, kx = col - z * H;
+        T xr[m], xi[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            const cplx<T> v = buf[(z * m + j) * H + kx];
+            xr[j] = v.x;
+            xi[j] = v.y;
+        }
+        cplx<T>* d = dst + z * M * H + kx;
+        dft_each<T, m, M, -1, M>(xr, xi, tw, [&](int k, T re, T im) { d[k * H] = cplx<T>{re, im}; });
+    }
+}
+
+// z pass of the forward two-phase transform: one thread per column (ky, kx) of one item
+template <typename T, int m, int M, int NT>
+__global__ void __launch_bounds__(NT) k_fft2_z(const cplx<T>* __restrict__ scratch, cplx<T>* __restrict__ out,
+                                               int64_t nout) {
+    constexpr int H = M / 2 + 1;
+    constexpr int PLANE = M * H;
+    __shared__ double2 tw[M];
+    stage_roots<M>(tw, threadIdx.x, NT);
+    __syncthreads();
+    const size_t b = blockIdx.y;
+    const int col = blockIdx.x * NT + threadIdx.x;
+    if (col >= PLANE) return;
+    const cplx<T>* s = scratch + b * (m * PLANE) + col;
+    T xr[m], xi[m];
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+        const cplx<T> v = s[j * PLANE];
+        xr[j] = v.x;
+        xi[j] = v.y;
+    }
+    dft_each<T, m, M, -1, M>(xr, xi, tw,
+                             [&](int k, T re, T im) { out[spec_at(b, k * PLANE + col, nout)] = cplx<T>{re, im}; });
+}
+
+// z pass of the inverse two-phase transform: spectrum (Tin) -> scratch (arithmetic type A)
+template <typename Tin, typename A, int m, int M, int NT>
+__global__ void __launch_bounds__(NT) k_ifft2_z(const cplx<Tin>* __restrict__ in, cplx<A>* __restrict__ scratch,
+                                                int64_t nbatch) {
+    constexpr int H = M / 2 + 1;
+    constexpr int PLANE = M * H;
+    __shared__ double2 tw[M];
+    stage_roots<M>(tw, threadIdx.x, NT);
+    __syncthreads();
+    const size_t b = blockIdx.y;
+    const int col = blockIdx.x * NT + threadIdx.x;
+    if (col >= PLANE) return;
+    A Xr[M], Xi[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const cplx<Tin> v = in[spec_at(b, k * PLANE + col, nbatch)];
+        Xr[k] = A(v.x);
+        Xi[k] = A(v.y);
+    }
+    cplx<A>* d = scratch + b * (m * PLANE) + col;
+    dft_each<A, M, M, +1, m>(Xr, Xi, tw, [&](int j, A re, A im) { d[j * PLANE] = cplx<A>{re, im}; });
+}
+
+// y and x passes of the inverse two-phase transform: scratch -> real tile (Tout)
+template <typename A, typename Tout, int m, int M, int NT>
+__global__ void __launch_bounds__(NT) k_ifft2_yx(const cplx<A>* __restrict__ scratch, Tout* __restrict__ out,
+                                                 const int32_t* __restrict__ out_map) {
+    constexpr int H = M / 2 + 1;
+    __shared__ cplx<A> buf[m * m * H];  // [z][y][kx]
+    __shared__ A tile[m * m * m];
+    __shared__ double2 tw[M];
+    const int tid = threadIdx.x;
+    const size_t b = blockIdx.x;
+    const cplx<A>* s = scratch + b * (m * M * H);
+    stage_roots<M>(tw, tid, NT);
+    __syncthreads();
+    for (int col = tid; col < m * H; col += NT) {  // y pass: columns (z, kx), ky < M -> y < m
+        const int z = col / H, kx = col - z * H;
+        A Xr[M], Xi[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const cplx<A> v = s[(z * M + k) * H + kx];
+            Xr[k] = v.x;
+            Xi[k] = v.y;
+        }
+        cplx<A>* d = buf + z * m * H + kx;
+        dft_each<A, M, M, +1, m>(Xr, Xi, tw, [&](int j, A re, A im) { d[j * H] = cplx<A>{re, im}; });
+    }
+    __syncthreads();
+    for (int row = tid; row < m * m; row += NT) {  // x pass: Hermitian rows (z, y) -> real x < m
+        A Yr[H], Yi[H];
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const cplx<A> v = buf[row * H + k];
+            Yr[k] = v.x;
+            Yi[k] = v.y;
+        }
+        A* d = tile + row * m;
+        c2r_each<A, m, M>(Yr, Yi, tw, [&](int j, A v) { d[j] = v; });
+    }
+    __syncthreads();
+    Tout* dst = out + (out_map ? (size_t)out_map[b] : b) * (m * m * m);
+    for (int i = tid; i < m * m * m; i += NT) dst[i] = (Tout)tile[i];
+}
+
+template <typename T, int m>
+static hipError_t fwd_two_phase(const T* in, cplx<T>* out, int64_t nbatch, int64_t nout, void* scratch,
+                                hipStream_t s) {
+    constexpr int M = 2 * m, PLANE = M * (M / 2 + 1), NT = 256;
+    if (!scratch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_fft2_xy<T, m, M, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, (cplx<T>*)scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fft2_z<T, m, M, NT>), dim3((PLANE + NT - 1) / NT, (unsigned)nbatch), dim3(NT), 0, s,
+                       (const cplx<T>*)scratch, out, nout);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename A, typename Tout, int m>
+static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map,
+                                void* scratch, hipStream_t s) {
+    constexpr int M = 2 * m, PLANE = M * (M / 2 + 1), NT = 256;
+    if (!scratch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_ifft2_z<Tin, A, m, M, NT>), dim3((PLANE + NT - 1) / NT, (unsigned)nbatch), dim3(NT), 0, s,
+                       in, (cplx<A>*)scratch, nbatch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ifft2_yx<A, Tout, m, M, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s,
+                       (const cplx<A>*)scratch, out, out_map);
+    return hipGetLastError();
 }
 
 // nt: threads per workgroup (0 = default: 256 for m >= 12, else 128); the autotuner picks
@@ -173,29 +343,33 @@ static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, int64_
 }
 
 template <typename Tin, typename A, typename Tout, int m, int NT>
-static hipError_t inv_mnt(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, hipStream_t s) {
+static hipError_t inv_mnt(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, int opitch,
+                          hipStream_t s) {
     hipLaunchKernelGGL((k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out,
-                       nbatch, out_map);
+                       nbatch, out_map, opitch);
     return hipGetLastError();
 }
 
 template <typename Tin, typename A, typename Tout, int m>
-static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, hipStream_t s,
-                               int nt = 0) {
+static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, int opitch,
+                               hipStream_t s, int nt = 0) {
+    if (opitch <= 0) opitch = m;
     if constexpr ((m == 8 || m == 16) && !std::is_same<A, ff32>::value) {
         if constexpr (!(m == 16 && sizeof(A) == 8))
-            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(in, out, nbatch, out_map, s);
-        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(in, out, nbatch, out_map, s);
-        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(in, out, nbatch, out_map, s);
+            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(in, out, nbatch, out_map, opitch, s);
+        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(in, out, nbatch, out_map, opitch, s);
+        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(in, out, nbatch, out_map, opitch, s);
     }
-    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, out_map, s);
+    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, out_map, opitch, s);
 }
 
 template <typename T>
-hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt, int64_t nout) {
+hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt, int64_t nout,
+                          void* scratch) {
     if (nbatch <= 0) return hipSuccess;
     if (nout <= 0) nout = nbatch + 1;
     switch (m) {
+        case 17: return fwd_two_phase<T, 17>(in, out, nbatch, nout, scratch, s);
         case 2: return launch_fwd_m<T, 2>(in, out, nbatch, nout, s);
         case 3: return launch_fwd_m<T, 3>(in, out, nbatch, nout, s);
         case 4: return launch_fwd_m<T, 4>(in, out, nbatch, nout, s);
@@ -212,33 +386,39 @@ hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipS
 
 template <typename Tin, typename A, typename Tout>
 hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt,
-                             const int32_t* out_map) {
+                             const int32_t* out_map, void* scratch, int opitch) {
     if (nbatch <= 0) return hipSuccess;
+    if (opitch > 0 && opitch != m && m != 16) return hipErrorInvalidValue;  // pitched output: 16^3 tiles only
     switch (m) {
-        case 2: return launch_inv_m<Tin, A, Tout, 2>(in, out, nbatch, out_map, s);
-        case 3: return launch_inv_m<Tin, A, Tout, 3>(in, out, nbatch, out_map, s);
-        case 4: return launch_inv_m<Tin, A, Tout, 4>(in, out, nbatch, out_map, s);
-        case 5: return launch_inv_m<Tin, A, Tout, 5>(in, out, nbatch, out_map, s);
-        case 6: return launch_inv_m<Tin, A, Tout, 6>(in, out, nbatch, out_map, s);
-        case 7: return launch_inv_m<Tin, A, Tout, 7>(in, out, nbatch, out_map, s);
-        case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, out_map, s, nt);
-        case 9: return launch_inv_m<Tin, A, Tout, 9>(in, out, nbatch, out_map, s);
-        case 10: return launch_inv_m<Tin, A, Tout, 10>(in, out, nbatch, out_map, s);
+        case 17: return inv_two_phase<Tin, A, Tout, 17>(in, out, nbatch, out_map, scratch, s);
+        case 2: return launch_inv_m<Tin, A, Tout, 2>(in, out, nbatch, out_map, opitch, s);
+        case 3: return launch_inv_m<Tin, A, Tout, 3>(in, out, nbatch, out_map, opitch, s);
+        case 4: return launch_inv_m<Tin, A, Tout, 4>(in, out, nbatch, out_map, opitch, s);
+        case 5: return launch_inv_m<Tin, A, Tout, 5>(in, out, nbatch, out_map, opitch, s);
+        case 6: return launch_inv_m<Tin, A, Tout, 6>(in, out, nbatch, out_map, opitch, s);
+        case 7: return launch_inv_m<Tin, A, Tout, 7>(in, out, nbatch, out_map, opitch, s);
+        case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, out_map, opitch, s, nt);
+        case 9: return launch_inv_m<Tin, A, Tout, 9>(in, out, nbatch, out_map, opitch, s);
+        case 10: return launch_inv_m<Tin, A, Tout, 10>(in, out, nbatch, out_map, opitch, s);
         case 16:
             if constexpr (!std::is_same<A, ff32>::value)
-                return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, out_map, s, nt);
+                return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, out_map, opitch, s, nt);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t, int, int64_t);
-template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t, int, int64_t);
+template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t, int, int64_t,
+                                           void*);
+template hipError_t launch_pad_fft<float>(int, const float*, cplx<float>*, int64_t, hipStream_t, int, int64_t,
+                                          void*);
 template hipError_t launch_ifft_trunc<double, double, double>(int, const cplx<double>*, double*, int64_t,
-                                                               hipStream_t, int, const int32_t*);
+                                                               hipStream_t, int, const int32_t*, void*, int);
 template hipError_t launch_ifft_trunc<float, float, float>(int, const cplx<float>*, float*, int64_t, hipStream_t,
-                                                             int, const int32_t*);
+                                                             int, const int32_t*, void*, int);
 template hipError_t launch_ifft_trunc<float, ff32, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t, int,
-                                                         const int32_t*);
+                                                         const int32_t*, void*, int);
+template hipError_t launch_ifft_trunc<float, float, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t, int,
+                                                          const int32_t*, void*, int);
 
 }  // namespace lgfdev

@@ -19,18 +19,26 @@ namespace lgfdev {
 constexpr int kLatticeRadius = 32;
 constexpr int kFarTerms = 8;
 constexpr int kMaxLevels = 16;
+constexpr int kNmax = 10;  // most nodes one interpolation stencil uses (the paper's n_max)
 
 // ------------------------------------------------------------------ launchers (device code)
 // out: chunk-major spectra of nout items, of which the first nbatch are written (nout = 0:
 // nbatch + 1, the last a zero sentinel that is not written)
 // nt: threads per workgroup variant (0 = default; tunable for level-0 tiles)
 template <typename T>
+// scratch: HBM intermediate for the two-phase tiles (m = 17): nbatch * m * 2m * (m + 1)
+// complex values of 16 bytes (two_phase_scratch_bytes); unused otherwise
 hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipStream_t s, int nt = 0,
-                          int64_t nout = 0);
-// out_map: output tile of each transformed item (NULL = the item's own index)
+                          int64_t nout = 0, void* scratch = nullptr);
+// out_map: output tile of each transformed item (NULL = the item's own index); opitch:
+// edge of the output tiles (0 = m; larger pads the m^3 results with zero planes, m = 16)
 template <typename Tin, typename A, typename Tout>
 hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0,
-                             const int32_t* out_map = nullptr);
+                             const int32_t* out_map = nullptr, void* scratch = nullptr, int opitch = 0);
+inline bool two_phase_tile(int m) { return m == 17; }
+inline int64_t two_phase_scratch_bytes(int m, int64_t nbatch) {
+    return two_phase_tile(m) ? nbatch * (int64_t)m * (2 * m) * (m + 1) * 16 : 0;
+}
 
 // Far-field node values of the down pass: double on the FP64 path, float-float on the
 // FP32 path (8 bytes either way).
@@ -53,14 +61,17 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
 // waves: parent groups per workgroup (1, 2, 4); cpl: children accumulated per lane (8, 4, 2,
 // 1); 0 = chosen from the level's size.
 template <typename T>
+// fhat holds nsrc + 1 items (sentinel nsrc), uhat nitems items; nsrc = nitems unless the
+// level reads another level's spectra (level 1 of the lattice scheme reads the blocks').
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
-                               const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
-                               int waves, int cpl, hipStream_t s);
-// Targets tgt[0..ntgt) from CSR lists (the top level of a truncated tree).
+                               const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc,
+                               int S, int waves, int cpl, hipStream_t s);
+// Targets tgt[0..ntgt) from CSR lists (the top level of a truncated tree); fhat holds
+// nsrc + 1 items (nsrc < 0: nitems).
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
                            const int32_t* off, const int32_t* tgt, cplx<T>* uhat, int64_t ntgt, int64_t nitems,
-                           int noff, int S, hipStream_t s);
+                           int noff, int S, hipStream_t s, int64_t nsrc = -1);
 
 // Kernel variants picked per plan (by the autotuner, or defaults).
 struct TuneConfig {
@@ -95,6 +106,7 @@ struct SpectraKey {
     int n, p, level;   // level 0 = near field
     int radius;        // offsets D in [-radius, radius]^3, id = (Dx+R) + (2R+1)((Dy+R) + (2R+1)(Dz+R))
     int prec;          // 0 = f64, 1 = f32
+    int m = 0;         // tile edge (0: n at level 0, p above; n at level 1 of the lattice scheme)
     bool operator<(const SpectraKey& o) const;
 };
 

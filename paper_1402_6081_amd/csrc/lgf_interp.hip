@@ -175,6 +175,115 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
 }
 
+// ------------------------------------------------------------------ large intervals (P = 17)
+// The children are taken one at a time (the kernels above hold 8 children, or a parent's
+// 2 + 4 partial passes, in LDS: 629 / 275 KB at P = 17).  Same sums in the same order per
+// output node: children in order c = 0..7, each through its x, y, z passes.
+template <typename T, int P>
+__global__ void __launch_bounds__(kInterpThreads)
+    k_reg_up_seq(const T* __restrict__ in, const int32_t* __restrict__ child8, const double* __restrict__ C01,
+                 T* __restrict__ out) {
+    constexpr int P3 = P * P * P;
+    __shared__ T X[P3], t1[P3], acc[P3];
+    __shared__ T Cm[2 * P * P];
+    __shared__ int32_t ch[8];
+    const int tid = threadIdx.x;
+    const int64_t J = blockIdx.x;
+    for (int i = tid; i < 2 * P * P; i += kInterpThreads) Cm[i] = (T)C01[i];
+    if (tid < 8) ch[tid] = child8[J * 8 + tid];
+    for (int i = tid; i < P3; i += kInterpThreads) acc[i] = T(0);
+    __syncthreads();
+    for (int c = 0; c < 8; ++c) {
+        const int q = ch[c];  // uniform
+        if (q < 0) continue;
+        for (int i = tid; i < P3; i += kInterpThreads) X[i] = in[(int64_t)q * P3 + i];
+        __syncthreads();
+        for (int i = tid; i < P3; i += kInterpThreads) {  // x: t1[z][y][d]
+            const int d = i % P, rest = i / P;
+            const T* m = Cm + (c & 1) * P * P + d * P;
+            const T* row = X + rest * P;
+            T sum = T(0);
+#pragma unroll
+            for (int x = 0; x < P; ++x) sum += m[x] * row[x];
+            t1[i] = sum;
+        }
+        __syncthreads();
+        for (int i = tid; i < P3; i += kInterpThreads) {  // y: X[z][b][d]
+            const int d = i % P, bb = (i / P) % P, z = i / (P * P);
+            const T* m = Cm + ((c >> 1) & 1) * P * P + bb * P;
+            T sum = T(0);
+#pragma unroll
+            for (int y = 0; y < P; ++y) sum += m[y] * t1[(z * P + y) * P + d];
+            X[i] = sum;
+        }
+        __syncthreads();
+        for (int i = tid; i < P3; i += kInterpThreads) {  // z, accumulated over the children
+            const int bd = i % (P * P), a = i / (P * P);
+            const T* m = Cm + ((c >> 2) & 1) * P * P + a * P;
+            T sum = T(0);
+#pragma unroll
+            for (int z = 0; z < P; ++z) sum += m[z] * X[z * P * P + bd];
+            acc[i] += sum;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < P3; i += kInterpThreads) out[J * P3 + i] = acc[i];
+}
+
+template <typename U, int P>
+__global__ void __launch_bounds__(kInterpThreads)
+    k_interp_down_seq(const U* __restrict__ par, const int32_t* __restrict__ child8, const double* __restrict__ C01,
+                      U* __restrict__ io) {
+    constexpr int P3 = P * P * P;
+    __shared__ U X[P3], t1[P3], t2[P3];
+    __shared__ U Ct[2 * P * P];  // Ct_c[k][m] = C_c[m][k]
+    __shared__ int32_t ch[8];
+    const int tid = threadIdx.x;
+    const int64_t J = blockIdx.x;
+    for (int i = tid; i < 2 * P * P; i += kInterpThreads) {
+        const int c = i / (P * P), r = i % (P * P), k = r / P, m = r % P;
+        Ct[i] = U(C01[c * P * P + m * P + k]);
+    }
+    if (tid < 8) ch[tid] = child8[J * 8 + tid];
+    for (int i = tid; i < P3; i += kInterpThreads) X[i] = par[J * P3 + i];
+    __syncthreads();
+    for (int c = 0; c < 8; ++c) {
+        const int q = ch[c];  // uniform
+        if (q < 0) continue;
+        const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+        for (int i = tid; i < P3; i += kInterpThreads) {  // x: t1[a][b][x']
+            const int xo = i % P, ab = i / P;
+            const U* m = Ct + cx * P * P + xo * P;
+            const U* row = X + ab * P;
+            U sum = U(0);
+#pragma unroll
+            for (int d = 0; d < P; ++d) sum += m[d] * row[d];
+            t1[i] = sum;
+        }
+        __syncthreads();
+        for (int i = tid; i < P3; i += kInterpThreads) {  // y: t2[a][y'][x']
+            const int xo = i % P, yo = (i / P) % P, a = i / (P * P);
+            const U* m = Ct + cy * P * P + yo * P;
+            const U* src = t1 + a * P * P + xo;
+            U sum = U(0);
+#pragma unroll
+            for (int bb = 0; bb < P; ++bb) sum += m[bb] * src[bb * P];
+            t2[i] = sum;
+        }
+        __syncthreads();
+        for (int i = tid; i < P3; i += kInterpThreads) {  // z, accumulated into the child
+            const int yx = i % (P * P), zo = i / (P * P);
+            const U* m = Ct + cz * P * P + zo * P;
+            U sum = U(0);
+#pragma unroll
+            for (int a = 0; a < P; ++a) sum += m[a] * t2[a * P * P + yx];
+            U* dst = io + (int64_t)q * P3 + i;
+            *dst = *dst + sum;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ level 1 -> block, FP64 add-back
 template <typename T, typename U, int N, int P>
 __global__ void __launch_bounds__(kInterpThreads)
@@ -226,7 +335,7 @@ __global__ void __launch_bounds__(kInterpThreads)
 }
 
 // ------------------------------------------------------------------ launchers
-// (n, p) -> compile-time kernel: n in {4, 8, 16}, p in [2, 10]
+// (n, p) -> compile-time kernel: n in {4, 8, 16}, p in [2, 10], and (16, 17)
 template <template <int, int> class K, typename... Args>
 static hipError_t dispatch_np(int n, int p, Args... args) {
 #define LGF_NP(NN)                                          \
@@ -245,7 +354,9 @@ static hipError_t dispatch_np(int n, int p, Args... args) {
     switch (n) {
         case 4: LGF_NP(4)
         case 8: LGF_NP(8)
-        case 16: LGF_NP(16)
+        case 16:
+            if (p == 17) return K<16, 17>::run(args...);  // the lattice scheme n_I = n + 1
+            LGF_NP(16)
         default: return hipErrorInvalidValue;
     }
 #undef LGF_NP
@@ -301,6 +412,10 @@ hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, 
         case 8: return reg_up_p<T, 8>(in, child8, C01, out, np, s);
         case 9: return reg_up_p<T, 9>(in, child8, C01, out, np, s);
         case 10: return reg_up_p<T, 10>(in, child8, C01, out, np, s);
+        case 17:
+            hipLaunchKernelGGL((k_reg_up_seq<T, 17>), dim3((unsigned)np), dim3(kInterpThreads), 0, s, in, child8, C01,
+                               out);
+            return hipGetLastError();
         default: return hipErrorInvalidValue;
     }
 }
@@ -326,6 +441,10 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
         case 8: return interp_down_p<U, 8>(par, child8, C01, io, nparent, s);
         case 9: return interp_down_p<U, 9>(par, child8, C01, io, nparent, s);
         case 10: return interp_down_p<U, 10>(par, child8, C01, io, nparent, s);
+        case 17:
+            hipLaunchKernelGGL((k_interp_down_seq<U, 17>), dim3((unsigned)nparent), dim3(kInterpThreads), 0, s, par,
+                               child8, C01, io);
+            return hipGetLastError();
         default: return hipErrorInvalidValue;
     }
 }

@@ -44,10 +44,20 @@ inline uint64_t pack(int64_t x, int64_t y, int64_t z) {
     return (uint64_t)x | ((uint64_t)y << 21) | ((uint64_t)z << 42);
 }
 
-// Lagrange basis on nodes 0..p-1 evaluated at t
+// Lagrange basis of node k among the nodes 0..p-1 at t (Sec. 2.5).  With more than
+// kNmax nodes only the kNmax consecutive nodes closest to t are used (hybrid p/h
+// refinement): the window starts at ceil(t - kNmax/2), ties going to the lower window,
+// clamped to the interval, and nodes outside it get 0.
 long double lagrange(int p, int k, long double t) {
+    int lo = 0, hi = p;
+    if (p > kNmax) {
+        lo = (int)std::ceil(t - kNmax / 2.0L);
+        lo = std::min(std::max(lo, 0), p - kNmax);
+        hi = lo + kNmax;
+    }
+    if (k < lo || k >= hi) return 0.0L;
     long double v = 1.0L;
-    for (int j = 0; j < p; ++j)
+    for (int j = lo; j < hi; ++j)
         if (j != k) v *= (t - j) / (long double)(k - j);
     return v;
 }
@@ -103,6 +113,9 @@ struct HostLevel {
 
 struct HostPlan {
     int n = 0, p = 0, L = 0, Ltop = 0;
+    // the lattice scheme with local stencils (p = n + 1 > n_max): level-1 nodes are the
+    // blocks' grid points, and level 1 works on the blocks' own spectra (tiles of n)
+    bool lat1 = false;
     int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
     int64_t nsrc = 0, neval = 0;              // source / evaluation blocks (both nb unless split)
     std::vector<int32_t> eval_l1;             // split sets: level-1 interval of each evaluation block
@@ -133,6 +146,7 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
     }
     H.n = n;
     H.p = p;
+    H.lat1 = p == n + 1 && p > kNmax;
     H.nsrc = nblocks;
     H.neval = neval;
     int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
@@ -241,7 +255,9 @@ lgf_status build_host(const int32_t* ijk, int64_t nblocks, int n, int p, int lev
     for (int l = 2; l <= H.L; ++l) {
         HostLevel& Lv = H.lv[l];
         const HostLevel& Ch = H.lv[l - 1];
-        const int32_t sentinel = (int32_t)Ch.nint;
+        // the zero sentinel of the spectra the lists index: level 1 of the lattice scheme
+        // reads the level-0 source spectra (nsrc items and the sentinel)
+        const int32_t sentinel = (int32_t)(l == 2 && H.lat1 ? H.nsrc : Ch.nint);
         Lv.src216.assign(216 * Lv.nint, sentinel);
         int64_t pairs = 0;
         for (int64_t i = 0; i < Lv.nint; ++i) {
@@ -373,12 +389,15 @@ lgf_status check_host(const HostPlan& H) {
     for (int l = 2; ok && l <= H.L && l < (int)H.lv.size(); ++l) {
         const HostLevel& Lv = H.lv[l];
         const int64_t nc = H.lv[l - 1].nint;
-        ok = within(Lv.child8, -1, nc - 1) && within(Lv.src216, 0, nc) &&
+        // level 1 of the lattice scheme reads the level-0 source spectra (nsrc and the sentinel)
+        const int64_t ns = l == 2 && H.lat1 ? H.nsrc : nc;
+        ok = within(Lv.child8, -1, nc - 1) && within(Lv.src216, 0, ns) &&
              (Lv.src216.empty() || (int64_t)Lv.src216.size() == 216 * Lv.nint);
     }
     for (int l = 1; ok && l <= H.L && l < (int)H.lv.size(); ++l) {
         const HostLevel& Lv = H.lv[l];
-        ok = within(Lv.csr_tgt, 0, Lv.nint - 1) && within(Lv.csr_src, 0, Lv.nint - 1) &&
+        const int64_t ns = l == 1 && H.lat1 ? H.nsrc : Lv.nint;
+        ok = within(Lv.csr_tgt, 0, Lv.nint - 1) && within(Lv.csr_src, 0, ns - 1) &&
              Lv.csr_ptr.size() == Lv.csr_tgt.size() + 1 && (int64_t)Lv.csr_ptr.back() == (int64_t)Lv.csr_src.size();
     }
     return ok ? LGF_OK : fail(LGF_ERR_LAYOUT, "internal error: plan list index out of range");
@@ -390,6 +409,7 @@ HostPlan concat(const std::vector<HostPlan>& parts) {
     HostPlan U;
     U.n = parts[0].n;
     U.p = parts[0].p;
+    U.lat1 = parts[0].lat1;
     for (const auto& P : parts) {
         U.L = std::max(U.L, P.L);
         U.Ltop = std::max(U.Ltop, P.Ltop);
@@ -443,6 +463,15 @@ struct DevBuf {
     int64_t bytes = 0;
 };
 
+// HBM intermediate of the two-phase transforms (levels >= 2 of a tile that does not fit one
+// workgroup's LDS); the levels run one after another on one stream and share it.
+int64_t scratch_need(const HostPlan& H) {
+    int64_t nmax = 0;
+    for (int l = 1; l <= H.Ltop; ++l)
+        if (H.lv[l].pairs() > 0 && !(l == 1 && H.lat1)) nmax = std::max(nmax, H.lv[l].nint);
+    return two_phase_scratch_bytes(H.p, nmax);
+}
+
 // Device bytes of a plan's workspace (lists, matrices, node values and spectra of every
 // level it solves on); the shared kernel spectra are not included.
 int64_t workspace_need(const HostPlan& H, lgf_precision prec) {
@@ -458,11 +487,16 @@ int64_t workspace_need(const HostPlan& H, lgf_precision prec) {
     for (int l = 1; l <= H.Ltop; ++l) {
         const HostLevel& h = H.lv[l];
         need += h.nint * p3 * (esz + usz);
-        if (h.pairs() > 0) need += (2 * h.nint + 1) * S1 * 2 * esz;
+        if (h.pairs() > 0) {
+            if (l == 1 && H.lat1)
+                need += h.nint * S0 * 2 * esz;  // products only: the sources are the level-0 spectra
+            else
+                need += (2 * h.nint + 1) * S1 * 2 * esz;
+        }
         need += (int64_t)(h.csr_tgt.size() + h.csr_ptr.size() + 2 * h.csr_src.size()) * 4;
     }
     for (int l = 2; l <= topc && H.Ltop >= 1; ++l) need += H.lv[l].nint * 224 * 4;
-    return need;
+    return need + scratch_need(H);
 }
 
 }  // namespace
@@ -488,6 +522,8 @@ struct lgf_plan_s {
     int32_t* d_eval_l1 = nullptr;       // level-1 interval of each evaluation block (split sets)
     int32_t* d_near_out = nullptr;      // evaluation block of each level-0 target (split sets)
     int32_t* d_near_flag = nullptr;     // near field present, per evaluation block (split sets)
+    bool lat1 = false;                  // lattice scheme with local stencils (p = n + 1 > n_max)
+    void* d_scratch = nullptr;          // two-phase transform intermediate (levels >= 2, p = 17)
     std::vector<int64_t> solve_offsets;
     std::vector<LevelPlan> lv;  // index 0 unused, 1..L
     std::shared_ptr<SpectraEntry> spectra0;
@@ -594,15 +630,18 @@ inline double fft_flops(int M) {  // Table 1: 2 (8 N_b) log2(8 N_b) for a padded
 }
 
 // Independent pieces of one solve, for graphs assembled from separately captured parts
-// (lgf_graph_create).  Dependencies: REG1 -> {L1, COARSE} -> JOIN; {NEAR, JOIN} -> FINAL.
+// (lgf_graph_create).  Dependencies: FWD0 -> NEAR; REG1 -> {L1, COARSE} -> JOIN;
+// {NEAR, JOIN} -> FINAL; and FWD0 -> L1 when level 1 reads the level-0 spectra (lattice
+// scheme).
 enum : unsigned {
-    kSegNear = 1,     // level 0: PadFFT, Prod, IFFT
+    kSegNear = 1,     // level 0: Prod, IFFT
     kSegReg1 = 2,     // Reg block -> level 1
     kSegL1 = 4,       // level 1: PadFFT, M2L, IFFT
     kSegCoarse = 8,   // Reg up, levels >= 2 up and down to level 2
     kSegJoin = 16,    // Interp level 2 -> level 1
     kSegFinal = 32,   // Interp level 1 -> blocks, add to the near field
-    kSegAll = 63
+    kSegFwd0 = 64,    // level 0: PadFFT
+    kSegAll = 127
 };
 
 template <typename T>
@@ -615,8 +654,11 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     Marker mark(pl);
     const double es = sizeof(T), cs = 2.0 * sizeof(T), us = sizeof(U);
     const double n3 = (double)n * n * n, p3 = (double)p * p * p;
-    const double S0 = pl->spectra0->S, S1 = (double)(2 * p) * (2 * p) * (p + 1);
-    const int64_t S1p = spec_padded(2 * p * 2 * p * (p + 1));
+    const double S0 = pl->spectra0->S;
+    // spectrum size of level l: tiles of p nodes, or of n at level 1 of the lattice scheme
+    auto tile = [&](int l) { return l == 1 && pl->lat1 ? n : p; };
+    auto Sl = [&](int l) { const double m = tile(l); return (2 * m) * (2 * m) * (m + 1); };
+    auto Slp = [&](int l) { const int m = tile(l); return (int64_t)spec_padded(2 * m * 2 * m * (m + 1)); };
     // source / evaluation blocks, and the evaluation blocks with a near field
     const double ns = (double)pl->nsrc, ne = (double)pl->neval, nt0 = (double)pl->ntgt0;
     auto lvN = [&](int l) { return (double)pl->lv[l].nint; };
@@ -648,27 +690,36 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     auto level_up = [&](int l, hipStream_t st) -> hipError_t {
         LevelPlan& L = pl->lv[l];
         if (L.pairs() == 0) return hipSuccess;
-        // level 1: the sources come first and are the only intervals the lists read
-        const int64_t nfwd = l == 1 ? pl->nsrc : L.nint;
-        LGF_STEP(st, (launch_pad_fft<T>(p, (const T*)L.d_ftil, (C*)L.d_fhat, nfwd, st, 0, L.nint + 1)),
-                 lname("fft_fwd_l", l), (double)nfwd * (p3 * es + S1 * cs), (double)nfwd * fft_flops(2 * p));
+        const double S1 = Sl(l);
+        // level 1 of the lattice scheme: the intervals' nodes are the blocks' grid points and
+        // the last node plane of Reg is zero, so its spectra are the level-0 block spectra
+        const bool reuse0 = l == 1 && pl->lat1;
+        const C* fhat = reuse0 ? (const C*)pl->d_fhat0 : (const C*)L.d_fhat;
+        const int64_t nsrc_items = reuse0 ? pl->nsrc : L.nint;
+        if (!reuse0) {
+            // level 1: the sources come first and are the only intervals the lists read
+            const int64_t nfwd = l == 1 ? pl->nsrc : L.nint;
+            LGF_STEP(st,
+                     (launch_pad_fft<T>(p, (const T*)L.d_ftil, (C*)L.d_fhat, nfwd, st, 0, L.nint + 1, pl->d_scratch)),
+                     lname("fft_fwd_l", l), (double)nfwd * (p3 * es + S1 * cs), (double)nfwd * fft_flops(2 * p));
+        }
         if (L.zero_uhat)
-            LGF_STEP(st, zero_fill(L.d_uhat, L.nint * S1p * 2 * (int64_t)sizeof(T), st), lname("zero_uhat_l", l),
+            LGF_STEP(st, zero_fill(L.d_uhat, L.nint * Slp(l) * 2 * (int64_t)sizeof(T), st), lname("zero_uhat_l", l),
                      lvN(l) * S1 * cs, 0.0);
         if (L.sib_pairs > 0) {
             const LevelPlan& Pp = pl->lv[l + 1];
             LGF_STEP(st,
-                     (launch_prod_far_sib<T>((const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216,
-                                             (C*)L.d_uhat, Pp.nint, L.nint, L.spectra->S, tc.far_waves,
+                     (launch_prod_far_sib<T>(fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216, (C*)L.d_uhat,
+                                             Pp.nint, L.nint, nsrc_items, L.spectra->S, tc.far_waves,
                                              tc.far_children, st)),
                      lname("prod_l", l), ((double)L.nsrc_int + lvN(l) + 316.0) * S1 * cs,
                      (double)L.sib_pairs * S1 * 8.0);
         }
         if (L.csr_entries > 0)
             LGF_STEP(st,
-                     (launch_prod_far<T>((const C*)L.d_fhat, (const C*)L.spectra_csr->dev, L.d_csr_ptr, L.d_csr_src,
-                                         L.d_csr_off, L.d_csr_tgt, (C*)L.d_uhat, L.ncsr, L.nint, L.spectra_csr->noff,
-                                         L.spectra_csr->S, st)),
+                     (launch_prod_far<T>(fhat, (const C*)L.spectra_csr->dev, L.d_csr_ptr, L.d_csr_src, L.d_csr_off,
+                                         L.d_csr_tgt, (C*)L.d_uhat, L.ncsr, L.nint, L.spectra_csr->noff,
+                                         L.spectra_csr->S, st, nsrc_items)),
                      lname("prod_top_l", l), ((double)L.nsrc_int + lvN(l) + L.spectra_csr->noff) * S1 * cs,
                      (double)L.csr_entries * S1 * 8.0);
         return hipSuccess;
@@ -679,9 +730,18 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
         if (L.pairs() == 0) {
             LGF_STEP(st, zero_fill(L.d_util, L.nint * (int64_t)p * p * p * sizeof(U), st), lname("zero_l", l),
                      lvN(l) * p3 * us, 0.0);
+        } else if (l == 1 && pl->lat1) {
+            // n^3 results into tiles of p = n + 1 nodes (the last node plane is not used by
+            // the final pass); plain precision: these values are not interpolated further
+            LGF_STEP(st,
+                     (launch_ifft_trunc<T, T, U>(n, (const C*)L.d_uhat, (U*)L.d_util, L.nint, st, 0, nullptr, nullptr,
+                                                 p)),
+                     lname("fft_inv_l", l), lvN(l) * (Sl(l) * cs + p3 * us), lvN(l) * fft_flops(2 * n));
         } else {
-            LGF_STEP(st, (launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, st)),
-                     lname("fft_inv_l", l), lvN(l) * (S1 * cs + p3 * us), lvN(l) * fft_flops(2 * p));
+            LGF_STEP(st,
+                     (launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, st, 0, nullptr,
+                                                 pl->d_scratch)),
+                     lname("fft_inv_l", l), lvN(l) * (Sl(l) * cs + p3 * us), lvN(l) * fft_flops(2 * p));
         }
         return hipSuccess;
     };
@@ -694,6 +754,14 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                  lvN(l) * 2.0 * 3.0 * p3 * p);
         return hipSuccess;
     };
+    // level-0 PadFFT: first when level 1 reads its spectra (the lattice scheme), else at the
+    // head of the near field
+    auto fwd0 = [&]() -> hipError_t {
+        LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nsrc, s, tc.fft0_threads), "fft_fwd_l0",
+                 ns * (n3 * es + S0 * cs), ns * fft_flops(2 * n));
+        return hipSuccess;
+    };
+    if (pl->lat1 && (segs & kSegFwd0) && (e = fwd0()) != hipSuccess) return e;
     if (far) {
         if (overlap) {
             if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
@@ -735,9 +803,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
         if (overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
     }
     // ---- near field (level 0) on the caller's stream
+    if (!pl->lat1 && (segs & kSegFwd0) && (e = fwd0()) != hipSuccess) return e;
     if (segs & kSegNear) {
-        LGF_STEP(s, launch_pad_fft<T>(n, f, (C*)pl->d_fhat0, pl->nsrc, s, tc.fft0_threads), "fft_fwd_l0",
-                 ns * (n3 * es + S0 * cs), ns * fft_flops(2 * n));
         LGF_STEP(s,
                  launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8,
                                      pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nsrc, pl->ntgt0,
@@ -771,6 +838,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     pl->p = p;
     pl->prec = prec;
     pl->nb = H.nb;
+    pl->lat1 = H.lat1;
     pl->nsrc = H.nsrc;
     pl->neval = H.neval;
     pl->ntgt0 = H.ntgt0;
@@ -812,8 +880,9 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     std::vector<std::vector<int32_t>> csr_off(H.L + 1);
     for (int l = 1; l <= pl->Ltop; ++l) {
         LevelPlan& L = pl->lv[l];
+        const int mt = l == 1 && H.lat1 ? n : 0;  // tile edge of the level's spectra (0: p)
         if (L.sib_pairs > 0) {
-            L.spectra = get_spectra(SpectraKey{n, p, l, 3, ip}, s, err);
+            L.spectra = get_spectra(SpectraKey{n, p, l, 3, ip, mt}, s, err);
             if (!L.spectra) return err_status(err);
         }
         if (L.csr_entries > 0) {
@@ -824,7 +893,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
             if ((int64_t)W * W * W > 300000)
                 return fail(LGF_ERR_LAYOUT, "top-level offsets too large: use more levels");
             for (const auto& D : H.lv[l].csr_D) csr_off[l].push_back((D[0] + R) + W * ((D[1] + R) + W * (D[2] + R)));
-            L.spectra_csr = get_spectra(SpectraKey{n, p, l, R, ip}, s, err);
+            L.spectra_csr = get_spectra(SpectraKey{n, p, l, R, ip, mt}, s, err);
             if (!L.spectra_csr) return err_status(err);
         }
     }
@@ -859,7 +928,9 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
         LevelPlan& Lv = pl->lv[l];
         const HostLevel& h = H.lv[l];
         ok = dev_alloc(pl, &Lv.d_ftil, Lv.nint * p3 * esz) && dev_alloc(pl, &Lv.d_util, Lv.nint * p3 * usz);
-        if (ok && h.pairs() > 0)
+        if (ok && h.pairs() > 0 && l == 1 && H.lat1)
+            ok = dev_alloc(pl, &Lv.d_uhat, Lv.nint * S0 * 2 * esz);  // sources: the level-0 spectra
+        else if (ok && h.pairs() > 0)
             ok = dev_alloc(pl, &Lv.d_fhat, (Lv.nint + 1) * S1 * 2 * esz) &&
                  dev_alloc(pl, &Lv.d_uhat, Lv.nint * S1 * 2 * esz);
         if (ok && !h.csr_src.empty())
@@ -871,6 +942,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     for (int l = 2; ok && l <= topc && pl->Ltop >= 1; ++l)
         ok = dev_alloc(pl, &pl->lv[l].d_child8, H.lv[l].nint * 32) &&
              dev_alloc(pl, &pl->lv[l].d_src216, H.lv[l].nint * 216 * 4);
+    if (ok) ok = dev_alloc(pl, &pl->d_scratch, scratch_need(H));
     if (!ok) return fail(LGF_ERR_OOM, "device allocation failed for the plan workspace");
     hipError_t e = upload(pl->d_g0_tgt8, H.g0_tgt8, s);
     if (e == hipSuccess) e = upload(pl->d_g0_src64, H.g0_src64, s);
@@ -965,14 +1037,15 @@ lgf_status make_graph(lgf_plan_t plan, const void* f, void* u, lgf_graph_s** out
         e = capture_part(plan, f, u, kSegAll, &g->graph);
     } else {
         // concurrent branches with explicit dependencies:
-        //   near ------------------------------------------\
+        //   fwd0 -> near ----------------------------------\
         //   reg1 -> level 1 --------------------> join -> final
         //        \-> coarse levels ----------/
+        // (fwd0 -> level 1 as well in the lattice scheme)
         // Each branch is captured alone on one stream (a chain of kernel nodes) and its nodes
         // are copied into one flat graph.
         e = hipGraphCreate(&g->graph, 0);
         const bool coarse = plan->Ltop >= 2;
-        hipGraphNode_t last[6] = {};
+        hipGraphNode_t last[7] = {};
         std::vector<hipGraph_t> parts;
         auto add = [&](int slot, unsigned segs, std::initializer_list<int> deps) {
             if (e != hipSuccess) return;
@@ -985,9 +1058,13 @@ lgf_status make_graph(lgf_plan_t plan, const void* f, void* u, lgf_graph_s** out
                 if (last[k]) d.push_back(last[k]);
             e = append_chain(g->graph, part, d, &last[slot]);
         };
-        add(0, kSegNear, {});
+        add(6, kSegFwd0, {});
+        add(0, kSegNear, {6});
         add(1, kSegReg1, {});
-        add(2, kSegL1, {1});
+        if (plan->lat1)
+            add(2, kSegL1, {1, 6});
+        else
+            add(2, kSegL1, {1});
         if (coarse) {
             add(3, kSegCoarse, {1});
             add(4, kSegJoin, {2, 3});
@@ -1135,7 +1212,8 @@ extern "C" {
 
 static lgf_status check_args(int32_t n, int32_t p, lgf_precision prec) {
     if (n != 4 && n != 8 && n != 16) return fail(LGF_ERR_ARG, "n must be 4, 8 or 16");
-    if (p < 2 || p > 10) return fail(LGF_ERR_ARG, "p must lie in [2, 10]");
+    if (p < 2 || (p > kNmax && !(n == 16 && p == n + 1)))
+        return fail(LGF_ERR_ARG, "p must lie in [2, 10], or be n + 1 = 17 for n = 16 (stencils of 10 nodes)");
     if (prec != LGF_F64 && prec != LGF_F32) return fail(LGF_ERR_ARG, "unknown precision");
     return LGF_OK;
 }

@@ -232,7 +232,7 @@ template <typename T, int kFarWaves, int CPL>
 __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     k_prod_far_sib(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                    const int32_t* __restrict__ child8, const int32_t* __restrict__ src216,
-                   cplx<T>* __restrict__ uhat, int S, int nparents, int nitems) {
+                   cplx<T>* __restrict__ uhat, int S, int nparents, int nitems, int nsrc) {
     constexpr int F = M2LShape<T>::F;
     constexpr int PPW = M2LShape<T>::PPW;
     constexpr int NQ = 8 / CPL;             // waves per group of parents (one per child subset)
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     for (int i = threadIdx.x; i < PPG * 216; i += NT) {
         const int Jl = i / 216, k = i - Jl * 216;
         const int J = pb * PPG + Jl;
-        sidx[i] = J < nparents ? src216[(int64_t)J * 216 + k] : nitems;  // padding parents read zeros
+        sidx[i] = J < nparents ? src216[(int64_t)J * 216 + k] : nsrc;  // padding parents read zeros
     }
     if (threadIdx.x < kFarWaves) live[threadIdx.x] = 0u;
     __syncthreads();
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
         bool any = false;
         for (int jl = g * PPW; jl < (g + 1) * PPW; ++jl)
 #pragma unroll
-            for (int cs = 0; cs < 8; ++cs) any |= sidx[jl * 216 + e * 8 + cs] != nitems;
+            for (int cs = 0; cs < 8; ++cs) any |= sidx[jl * 216 + e * 8 + cs] != nsrc;
         if (any) atomicOr(&live[g], 1u << e);
     }
     __syncthreads();
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     const int Jl = pw * PPW + lane / F;
     const int J = pb * PPG + Jl;
     const int w = w0 + j;  // may exceed S in the last chunk: computed, never stored
-    const cplx<T>* fl = fhat + (int64_t)(w >> 6) * (nitems + 1) * 64 + (w & 63);
+    const cplx<T>* fl = fhat + (int64_t)(w >> 6) * (nsrc + 1) * 64 + (w & 63);
     T ar[CPL], ai[CPL];
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kProdThreads)
     k_prod_far(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
                const int32_t* __restrict__ off, const int32_t* __restrict__ tgt, cplx<T>* __restrict__ uhat, int S,
-               int nitems, int noff) {
+               int nitems, int noff, int nsrc) {
     const int w = blockIdx.y * kProdThreads + threadIdx.x;
     const int64_t i = blockIdx.x;
     if (w >= S) return;
@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(kProdThreads)
     for (int e = e0; e < e1; ++e) {
         const int q = src[e];
         const int o = off[e];
-        const cplx<T> f = fhat[spec_at(q, w, nitems + 1)];
+        const cplx<T> f = fhat[spec_at(q, w, nsrc + 1)];
         const cplx<T> k = khat[spec_at(o, w, noff)];
         cmac(ar, ai, f, k);
     }
@@ -347,27 +347,29 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
 
 template <typename T, int NW, int CPL>
 static hipError_t far_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
-                         cplx<T>* uhat, int64_t nparents, int64_t nitems, int S, hipStream_t s) {
+                         cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc, int S, hipStream_t s) {
     constexpr int F = M2LShape<T>::F, PPG = M2LShape<T>::PPW * NW;
     const unsigned grid = xcd_grid((S + F - 1) / F, (int)((nparents + PPG - 1) / PPG));
     hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, fhat, khat,
-                       child8, src216, uhat, S, (int)nparents, (int)nitems);
+                       child8, src216, uhat, S, (int)nparents, (int)nitems, (int)nsrc);
     return hipGetLastError();
 }
 
 template <typename T, int CPL>
 static hipError_t far_cpl(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
-                          cplx<T>* uhat, int64_t nparents, int64_t nitems, int S, int waves, hipStream_t s) {
+                          cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc, int S, int waves,
+                          hipStream_t s) {
     // at most 16 waves (1024 threads) per workgroup, and at most 8 in FP64, whose pipeline
     // needs more than the 128 registers a lane gets in a 16-wave workgroup
     constexpr int kMaxWaves = sizeof(T) == 8 ? 8 : 16;
     constexpr int kMaxGroups = kMaxWaves / (8 / CPL) < 4 ? kMaxWaves / (8 / CPL) : 4;
     switch (waves < kMaxGroups ? waves : kMaxGroups) {
-        case 1: return far_nw<T, 1, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+        case 1: return far_nw<T, 1, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, s);
         case 4:
-            if constexpr (kMaxGroups >= 4) return far_nw<T, 4, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+            if constexpr (kMaxGroups >= 4)
+                return far_nw<T, 4, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, s);
             [[fallthrough]];
-        default: return far_nw<T, 2, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, S, s);
+        default: return far_nw<T, 2, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, s);
     }
 }
 
@@ -384,26 +386,27 @@ void m2l_default(int64_t nparents, int& waves, int& cpl) {
 
 template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
-                               const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int S,
-                               int waves, int cpl, hipStream_t s) {
+                               const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc,
+                               int S, int waves, int cpl, hipStream_t s) {
     if (nparents <= 0) return hipSuccess;
     m2l_default<T>(nparents, waves, cpl);
     switch (cpl) {
-        case 8: return far_cpl<T, 8>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
-        case 4: return far_cpl<T, 4>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
-        case 2: return far_cpl<T, 2>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
-        default: return far_cpl<T, 1>(fhat, khat, child8, src216, uhat, nparents, nitems, S, waves, s);
+        case 8: return far_cpl<T, 8>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
+        case 4: return far_cpl<T, 4>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
+        case 2: return far_cpl<T, 2>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
+        default: return far_cpl<T, 1>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
     }
 }
 
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
                            const int32_t* off, const int32_t* tgt, cplx<T>* uhat, int64_t ntgt, int64_t nitems,
-                           int noff, int S, hipStream_t s) {
+                           int noff, int S, hipStream_t s, int64_t nsrc) {
     if (ntgt <= 0) return hipSuccess;
+    if (nsrc < 0) nsrc = nitems;
     dim3 grid((unsigned)ntgt, (unsigned)((S + kProdThreads - 1) / kProdThreads));
     hipLaunchKernelGGL(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, tgt, uhat, S,
-                       (int)nitems, noff);
+                       (int)nitems, noff, (int)nsrc);
     return hipGetLastError();
 }
 
@@ -411,10 +414,10 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
     template hipError_t launch_prod_near<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,      \
                                             cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t);    \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
-                                               cplx<T>*, int64_t, int64_t, int, int, int, hipStream_t);          \
+                                               cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t); \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \
                                            const int32_t*, const int32_t*, cplx<T>*, int64_t, int64_t, int, int, \
-                                           hipStream_t);
+                                           hipStream_t, int64_t);
 LGF_INST(double)
 LGF_INST(float)
 #undef LGF_INST

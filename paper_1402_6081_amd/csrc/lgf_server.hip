@@ -295,7 +295,8 @@ lgf_status lgf_server_create(const lgf_server_config* cfg, lgf_server_t* out) {
         set_last_error("n must be 4, 8 or 16");
         return LGF_ERR_ARG;
     }
-    if (cfg->p < 2 || cfg->p > 10 || (cfg->precision != LGF_F64 && cfg->precision != LGF_F32) ||
+    if (cfg->p < 2 || (cfg->p > 10 && !(cfg->n == 16 && cfg->p == 17)) ||
+        (cfg->precision != LGF_F64 && cfg->precision != LGF_F32) ||
         cfg->max_slots < 1 || cfg->max_slots > 16 || cfg->budget_bytes < 0 || cfg->max_queue < 0) {
         set_last_error("lgf_server_create: p in [2, 10], precision, max_slots in [1, 16], budget >= 0");
         return LGF_ERR_ARG;

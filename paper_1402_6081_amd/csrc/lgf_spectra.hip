@@ -457,7 +457,7 @@ int current_device() {
 }  // namespace
 
 bool SpectraKey::operator<(const SpectraKey& o) const {
-    return std::make_tuple(n, p, level, radius, prec) < std::make_tuple(o.n, o.p, o.level, o.radius, o.prec);
+    return std::make_tuple(n, p, level, radius, prec, m) < std::make_tuple(o.n, o.p, o.level, o.radius, o.prec, o.m);
 }
 
 SpectraEntry::~SpectraEntry() {
@@ -524,7 +524,7 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
     const int dev = current_device();
     if (!upload_asym(g_asym[dev], err)) return nullptr;
 
-    const int m = key.level == 0 ? key.n : key.p;
+    const int m = key.m > 0 ? key.m : (key.level == 0 ? key.n : key.p);
     const int M = 2 * m;
     const int H = M / 2 + 1;
     const int S = M * M * H;

@@ -1,0 +1,167 @@
+"""GPU parity of the paper's own scheme family at n = 16: n_I = n + 1 = 17 nodes per interval
+edge at every level, interpolation stencils of the n_max = 10 closest nodes (Sec. 2.5 and
+Sec. 4).  Level 1 works on the blocks' own spectra (its nodes are the blocks' grid points);
+levels >= 2 use 34-point transforms in two phases.
+
+Tolerances: FP64 against the oracle's FLGF within max(1e-12, 2 Lambda^3 eps_64), Lambda the
+Lebesgue constant of the 10-node local stencils; FP64 against the exact sum within the
+oracle's own truncation error + 1e-12 (manufactured solution, Sec. 4.1); graphs, batches and
+kernel variants bit for bit."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import flgf, lgf as olgf
+from paper_1402_6081_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+N, P = 16, 17
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_1402_6081_amd.lgf as L
+    L.library()
+    return L
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def fp64_tol():
+    t = np.linspace(0, P - 1, 20001)
+    leb = float(np.max(np.sum(np.abs(flgf.lagrange(P, t)), axis=0)))
+    return max(1e-12, 2.0 * leb ** 3 * 2.22e-16)
+
+
+def _dev(x, prec):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0", torch.float64 if prec == "f64" else torch.float32)
+
+
+def gpu_solve(L, blocks, f, levels, prec="f64", eval_blocks=None):
+    plan = L.Plan(blocks, N, P, levels, prec, eval_blocks=eval_blocks)
+    u = plan.solve(_dev(f, prec))
+    torch.cuda.synchronize()
+    out = u.double().cpu().numpy()
+    plan.close()
+    return out
+
+
+CASES = [
+    ("cube4_L0", lambda r: W.cube_layout(4), 0),            # level 1 only carries pairs
+    ("eden24_L0", lambda r: W.eden_layout(24, r), 0),       # levels 1-2 (local stencils)
+    ("eden40_L0", lambda r: W.eden_layout(40, r), 0),
+    ("eden40_L2_truncated", lambda r: W.eden_layout(40, r), 2),
+    ("eden30_L1_truncated", lambda r: W.eden_layout(30, r), 1),  # CSR lists on the blocks' spectra
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_lattice_scheme_fp64_matches_oracle(L, case):
+    label, mk, levels = case
+    rng = np.random.default_rng(zlib.crc32(label.encode()))
+    blocks = mk(rng)
+    f = rng.standard_normal((len(blocks), N, N, N))
+    _say("case: n_I = 17,", label, "blocks", len(blocks))
+    ref = flgf.solve(blocks, f, N, P, levels)
+    got = gpu_solve(L, blocks, f, levels)
+    e = rel(got, ref)
+    _say("   rel Linf vs oracle = %.3e (tol %.1e)" % (e, fp64_tol()))
+    assert e < fp64_tol()
+
+
+def _manufactured(blocks, rng):
+    b = np.asarray(blocks) - np.min(blocks, axis=0)
+    ext = b.max(axis=0) + 1
+    u = W.random_manufactured(blocks, N, rng)
+    D = np.zeros((ext[2] * N, ext[1] * N, ext[0] * N))
+    for i, (bx, by, bz) in enumerate(b.tolist()):
+        D[bz * N:(bz + 1) * N, by * N:(by + 1) * N, bx * N:(bx + 1) * N] = u[i]
+    LD = olgf.laplacian(D)[1:-1, 1:-1, 1:-1]
+    f = np.stack([LD[bz * N:(bz + 1) * N, by * N:(by + 1) * N, bx * N:(bx + 1) * N] for bx, by, bz in b.tolist()])
+    return u, f
+
+
+def test_lattice_scheme_against_manufactured_solution(L):
+    # Sec. 4.1: f = L u_rand with u_rand random and zero on the grid's boundary points; the
+    # device's error against u_rand is the oracle's FLGF error (n_I = 17) plus rounding
+    rng = np.random.default_rng(61)
+    blocks = W.eden_layout(40, rng)
+    u, f = _manufactured(blocks, rng)
+    ref = flgf.solve(blocks, f, N, P, 0)
+    got = gpu_solve(L, blocks, f, 0)
+    eps = rel(ref, u)
+    _say("case: manufactured, oracle error %.3e, device error %.3e" % (eps, rel(got, u)))
+    assert eps < 2e-9
+    assert rel(got, u) <= eps + 1e-12
+
+
+def test_lattice_scheme_fp32(L):
+    # FP32 path of the scheme: reported against FP64 (local 10-node stencils: Lambda^3 of
+    # ~3e4 bounds the amplification of FP32 rounding through Interp, the float-float down
+    # pass keeps it far below that)
+    rng = np.random.default_rng(62)
+    blocks = W.eden_layout(40, rng)
+    f, _ = W.zero_mean_gaussians(blocks, N, rng, 6)
+    u64 = gpu_solve(L, blocks, f, 0, "f64")
+    u32 = gpu_solve(L, blocks, f, 0, "f32")
+    e = rel(u32, u64)
+    _say("case: n_I = 17 FP32 vs FP64 rel Linf = %.3e" % e)
+    assert e < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lattice_scheme_graph_batch_and_variants(L, prec):
+    # the graph adds a dependency of level 1 on the level-0 transform; replays with eager
+    # work between them, a batch of two layouts and every kernel variant give the same bits
+    rng = np.random.default_rng(63)
+    lays = [W.eden_layout(40, rng), W.eden_layout(30, rng)]
+    fs = [rng.standard_normal((len(b), N, N, N)) for b in lays]
+    plan = L.Plan(lays[0], N, P, 0, prec)
+    f = _dev(fs[0], prec)
+    ref = plan.solve(f).clone()
+    u = torch.empty_like(f)
+    for ov in (1, 3, 2):
+        plan.set_tuning(overlap=ov)
+        g = plan.graph(f, u)
+        for _ in range(3):
+            u.fill_(float("nan"))
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(u, ref), ov
+            _ = plan.solve(f)  # eager work between replays
+            torch.cuda.synchronize()
+        g.close()
+    plan.set_tuning()
+    plan.autotune(f, u, reps=1)
+    assert torch.equal(plan.solve(f), ref)
+    bp = L.Plan.batch(lays, N, P, 0, prec)
+    ub = bp.solve(torch.cat([f, _dev(fs[1], prec)]))
+    other = L.Plan(lays[1], N, P, 0, prec)
+    assert torch.equal(bp.split(ub)[0], ref)
+    assert torch.equal(bp.split(ub)[1], other.solve(_dev(fs[1], prec)))
+    for pl in (plan, bp, other):
+        pl.close()
+
+
+def test_lattice_scheme_separate_sets(L):
+    rng = np.random.default_rng(64)
+    src = W.eden_layout(20, rng)
+    ev = W.dilate_layout(src, 1)
+    f = rng.standard_normal((len(src), N, N, N))
+    ref = flgf.solve(src, f, N, P, 0, eval_blocks=ev)
+    got = gpu_solve(L, src, f, 0, eval_blocks=ev)
+    e = rel(got, ref)
+    _say("case: n_I = 17 separate sets, rel Linf vs oracle = %.3e" % e)
+    assert e < fp64_tol()

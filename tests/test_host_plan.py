@@ -175,3 +175,33 @@ def test_split_layout_errors(L):
     lib = L.library()
     st = lib.lgf_plan_estimate_split(src.ctypes.data, len(src), None, 4, 8, 6, 0, 0, ctypes.byref(info))
     assert st == 1  # LGF_ERR_ARG
+
+
+def test_lattice_scheme_arguments(L):
+    """p = n + 1 = 17 (the paper's scheme at n = 16, stencils of n_max = 10 nodes) is
+    accepted; other p above 10 are not."""
+    blocks = W.cube_layout(4)
+    info = L.plan_estimate(blocks, 16, 17, 0, "f64")
+    tree = flgf.Tree(blocks, 0)
+    assert info["near_pairs"] == len(tree.near[0])
+    for lvl in range(1, tree.L + 1):
+        assert info["far_pairs"][lvl] == len(tree.ilist[lvl][0])
+    for n, p in ((8, 17), (16, 11), (16, 16), (16, 18), (4, 17)):
+        with pytest.raises(L.LGFError) as e:
+            L.plan_estimate(blocks, n, p)
+        assert e.value.name == "LGF_ERR_ARG", (n, p)
+
+
+def test_lattice_scheme_workspace(L):
+    """Level 1 of the lattice scheme keeps no spectra of its own (it reads the blocks'), and
+    levels >= 2 add a two-phase transform intermediate: 17 * 34 * 18 complex per interval
+    of the largest such level."""
+    blocks = W.cube_layout(8)
+    info = L.plan_estimate(blocks, 16, 17, 0, "f64")
+    nb, n2 = info["intervals"][1], info["intervals"][2]
+    S0 = 32 * 32 * 17
+    S2 = (34 * 34 * 18 + 63) // 64 * 64
+    spectra_part = (2 * nb + 1) * S0 * 16 + nb * S0 * 16 + (2 * n2 + 1) * S2 * 16
+    scratch = n2 * 17 * 34 * 18 * 16
+    assert info["workspace_bytes"] > spectra_part + scratch
+    assert info["workspace_bytes"] < 1.2 * (spectra_part + scratch)
