@@ -306,6 +306,35 @@ def split_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None):
     return out
 
 
+def scheme_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None):
+    """The paper's own scheme family: n_I = n + 1 = 17 nodes per interval edge with stencils of
+    the n_max = 10 closest nodes, on the 128^3 cube of 16^3 blocks, full depth; a random
+    manufactured solution, so the error against the exact u is reported with the rate."""
+    import torch
+    cfg = W.config_scheme()
+    npts = int(cfg["f"].size)
+    out = {"workload": cfg["name"], "points": npts, "n": cfg["n"], "n_I": cfg["p"], "n_max": 10,
+           "unit": "grid points solved/s"}
+    scale = float(np.max(np.abs(cfg["u_exact"])))
+    for prec, dt, peak in (("f64", torch.float64, FP64_PEAK_TFLOPS), ("f32", torch.float32, FP32_PEAK_TFLOPS)):
+        plan = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], prec)
+        f = torch.from_numpy(cfg["f"]).to("cuda:0", dt)
+        u = torch.empty_like(f)
+        m = _measure(plan, f, u, steps, warmup, graph=graph, tune=tune)
+        err = float(np.max(np.abs(u.double().cpu().numpy() - cfg["u_exact"])) / scale)
+        out[prec] = {"value": round(npts * steps / m["dt_graph"], 1), "ms_per_step": round(m["dt_graph"] / steps * 1e3, 5),
+                     "latency_ms": _pct(m["lat_graph"]), "tuning": m["tuning"],
+                     "eager_ms_per_step": round(m["dt_eager"] / steps * 1e3, 5),
+                     "rel_linf_err_vs_exact": err, "workspace_bytes": plan.info()["workspace_bytes"],
+                     "roofline": _roofline(m["prof"], peak, cfg["name"], prec)}
+        if breakdown is not None:
+            breakdown["scheme_fp64" if prec == "f64" else "scheme_fp32"] = _breakdown(m["prof"])
+        plan.close()
+        del f, u
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_bench(L, W, nreq=192, seed=5, slots=4, load=0.8):
     """Serving: 32 request layouts (bounding box U{2..16} blocks of 16^3, Eden fill
     U[0.3, 1]), p = 8, FP32, through the request server (resident plans, shared spectra).
@@ -370,8 +399,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-scheme", action="store_true")
     ap.add_argument("--split-only", action="store_true",
                     help="only the separate-set workload (profiling runs); prints its JSON object")
+    ap.add_argument("--scheme-only", action="store_true",
+                    help="only the n_I = n + 1 scheme workload (profiling runs); prints its JSON object")
     ap.add_argument("--no-graph", action="store_true", help="eager solves only (counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="default kernel variants, no autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -389,14 +421,14 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
-    if args.split_only:
+    if args.split_only or args.scheme_only:
         breakdown = {}
-        out = split_bench(L, W, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune,
-                          breakdown=breakdown)
+        leg, fn = ("split", split_bench) if args.split_only else ("scheme", scheme_bench)
+        out = fn(L, W, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune, breakdown=breakdown)
         if args.breakdown:
             with open(args.breakdown, "w") as fh:
                 json.dump(breakdown, fh, indent=1)
-        print(json.dumps({"split": out}), flush=True)
+        print(json.dumps({leg: out}), flush=True)
         return
     cfg = W.config_medium()
     npts = cfg["f"].size
@@ -470,6 +502,10 @@ def main():
         result["split"] = split_bench(L, W, max(5, args.steps // 5), 2, graph=not args.no_graph,
                                       tune=not args.no_tune, breakdown=breakdown)
         print("separate-set solves measured", flush=True, file=sys.stderr)
+    if not args.no_scheme:
+        result["scheme"] = scheme_bench(L, W, max(5, args.steps // 5), 2, graph=not args.no_graph,
+                                        tune=not args.no_tune, breakdown=breakdown)
+        print("n_I = n + 1 scheme measured", flush=True, file=sys.stderr)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg)

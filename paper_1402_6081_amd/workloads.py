@@ -18,7 +18,8 @@ import numpy as np
 __all__ = [
     "cube_layout", "sphere_layout", "shell_layout", "eden_layout", "dilate_layout", "split_sets", "points_of",
     "gaussian_source", "zero_mean_gaussians", "vortex_ring_source", "random_manufactured",
-    "boundary_mask", "config_small", "config_medium", "config_large", "config_split",
+    "boundary_mask", "manufactured_pair", "config_small", "config_medium", "config_large", "config_split",
+    "config_scheme",
 ]
 
 
@@ -257,6 +258,25 @@ def random_manufactured(blocks, n, rng):
     return u
 
 
+def manufactured_pair(blocks, n, rng):
+    """(u_rand, f = L u_rand) of Sec. 4.1: u_rand ~ U[-1, 1] on the active grid, 0 on its
+    boundary points, and f its 7-point Laplacian [L u](x) = sum_{+-e_i} u(x +- e_i) - 6 u(x),
+    which vanishes off the active grid, so G * f = u_rand exactly."""
+    b = np.asarray(blocks, dtype=np.int64)
+    lo = b.min(axis=0)
+    ext = b.max(axis=0) - lo + 1
+    u = random_manufactured(blocks, n, rng)
+    D = np.zeros((ext[2] * n + 2, ext[1] * n + 2, ext[0] * n + 2))
+    for i, (bx, by, bz) in enumerate((b - lo).tolist()):
+        D[1 + bz * n:1 + (bz + 1) * n, 1 + by * n:1 + (by + 1) * n, 1 + bx * n:1 + (bx + 1) * n] = u[i]
+    Lu = (D[2:, 1:-1, 1:-1] + D[:-2, 1:-1, 1:-1] + D[1:-1, 2:, 1:-1] + D[1:-1, :-2, 1:-1]
+          + D[1:-1, 1:-1, 2:] + D[1:-1, 1:-1, :-2] - 6.0 * D[1:-1, 1:-1, 1:-1])
+    f = np.empty_like(u)
+    for i, (bx, by, bz) in enumerate((b - lo).tolist()):
+        f[i] = Lu[bz * n:(bz + 1) * n, by * n:(by + 1) * n, bx * n:(bx + 1) * n]
+    return u, f
+
+
 # ----------------------------------------------------------------------------- named workloads
 
 def config_small(seed=0):
@@ -301,3 +321,13 @@ def config_split(seed=2):
     keep = amp > 1e-16 * amp.max()
     return dict(blocks=c["blocks"][keep], f=c["f"][keep], eval_blocks=c["blocks"], n=c["n"], p=c["p"],
                 levels=c["levels"], name="ring256_split_n16_p8_full")
+
+
+def config_scheme(seed=6):
+    """The paper's own scheme family on the 128^3 cube (8^3 blocks of 16^3): n_I = n + 1 = 17
+    nodes per interval edge, n_max = 10, full depth; a random manufactured solution
+    (Sec. 4.1), so the exact u is known."""
+    rng = np.random.default_rng(seed)
+    blocks = cube_layout(8)
+    u, f = manufactured_pair(blocks, 16, rng)
+    return dict(blocks=blocks, n=16, p=17, levels=0, f=f, u_exact=u, name="cube128_n16_nI17_manufactured")

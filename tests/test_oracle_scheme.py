@@ -109,3 +109,14 @@ def test_paper_scheme_converges_like_n_I_to_minus_10():
         got = flgf.solve(b, f, n, n + 1, 0)
         err[n] = np.max(np.abs(got - u)) / np.max(np.abs(u))
     assert err[16] < 2e-9 and err[8] > 300 * err[16], err
+
+
+def test_manufactured_pair_is_the_laplacian_of_u():
+    # the shared input generator's f = L u_rand agrees with the oracle's own Laplacian
+    rng = np.random.default_rng(9)
+    blocks = W.eden_layout(12, rng)
+    u, f = W.manufactured_pair(blocks, 8, rng)
+    D = _dense(blocks, 8, u)
+    LD = lgf.laplacian(D)[1:-1, 1:-1, 1:-1]
+    ref = _blocks(blocks, 8, LD)
+    assert np.max(np.abs(f - ref)) <= 4e-16 * np.max(np.abs(ref))  # summation order only
