@@ -321,10 +321,12 @@ __device__ __forceinline__ void cmul_rt(T ar, T ai, double wr, double wi, T& orr
 // loop and twiddles read from tw (large prime-factor pencils: compile-time 64-bit roots and
 // all outputs live at once would spill):
 //   put(k, X_k) for k < nout,  X_k = sum_{j < nin} x_j e^{SIGN 2 pi i jk / M}.
+// Outputs k = k0, k0 + kstep, ... (several threads may share one pencil).
 template <typename T, int nin, int M, int SIGN, int nout, typename Put>
-__device__ __forceinline__ void dft_each(const T (&xr)[nin], const T (&xi)[nin], const double2* tw, Put put) {
+__device__ __forceinline__ void dft_each(const T (&xr)[nin], const T (&xi)[nin], const double2* tw, Put put,
+                                         int k0 = 0, int kstep = 1) {
 #pragma unroll 1
-    for (int k = 0; k < nout; ++k) {
+    for (int k = k0; k < nout; k += kstep) {
         T sr = xr[0], si = xi[0];
         int idx = 0;
 #pragma unroll
@@ -345,9 +347,9 @@ __device__ __forceinline__ void dft_each(const T (&xr)[nin], const T (&xi)[nin],
 // one output at a time: x_j = Y_0 + (-1)^j Y_{M/2} + 2 Re sum_{0<k<M/2} Y_k e^{+2 pi i jk/M}.
 template <typename T, int m, int M, typename Put>
 __device__ __forceinline__ void c2r_each(const T (&Yr)[M / 2 + 1], const T (&Yi)[M / 2 + 1], const double2* tw,
-                                         Put put) {
+                                         Put put, int j0 = 0, int jstep = 1) {
 #pragma unroll 1
-    for (int j = 0; j < m; ++j) {
+    for (int j = j0; j < m; j += jstep) {
         T acc = T(0);
         int idx = 0;
 #pragma unroll

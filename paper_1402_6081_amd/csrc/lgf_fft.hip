@@ -2,10 +2,11 @@
 // (FFT^-1 + Trunc, Eq. alg_dwfft) of one block or interval per workgroup.
 //
 // Data: an m^3 real tile [z][y][x] <-> its padded M^3 real-to-complex spectrum
-// [kz][ky][kx], M = 2m, kx in [0, M/2], stored chunk-major (spec_at) across the batch.  One workgroup per tile; the tile lives in a
-// [z < m][ky < M][kx <= M/2] LDS array (the largest intermediate of either direction),
-// the real input/output is staged in the not-yet-used upper ky half of each z plane
-// so that HBM reads and writes are fully coalesced.  Passes: x (real rows), y (complex
+// [kz][ky][kx], M = 2m, kx in [0, M/2], stored chunk-major (spec_at) across the batch.
+// One workgroup per tile; the tile lives in a [z < m][ky < M][kx <= M/2] LDS array (the
+// largest intermediate of either direction), the real input/output is staged in the
+// not-yet-used upper ky half of each z plane so that HBM reads and writes are fully
+// coalesced.  Passes: x (real rows), y (complex
 // columns of the z < m planes), z (complex columns, straight to/from HBM).
 #include <type_traits>
 
@@ -162,46 +163,50 @@ __global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__
 }
 
 // ------------------------------------------------------------------ two-phase transforms
+constexpr int kShare = 3;  // threads sharing one pencil (each forms every third output)
 // For tiles whose one-workgroup LDS tile [m][M][M/2+1] exceeds the 160 KB of a workgroup
 // (m = 17: 166 KB of complex doubles), the transforms run in two kernels through an HBM
 // intermediate [z < m][ky < M][kx <= M/2] per item (`scratch`, complex of 16 bytes):
-//   forward  k_fft2_xy (stage, x pass, y pass -> scratch), k_fft2_z (z pass -> spectrum);
-//   inverse  k_ifft2_z (z pass -> scratch), k_ifft2_yx (y pass, x pass -> real tile).
+//   forward  k_fft2_xy (per z plane: x pass, y pass -> scratch), k_fft2_z (z pass -> spectrum);
+//   inverse  k_ifft2_z (z pass -> scratch), k_ifft2_yx (per z plane: y pass, x pass -> tile).
 template <typename T, int m, int M, int NT>
 __global__ void __launch_bounds__(NT) k_fft2_xy(const T* __restrict__ in, cplx<T>* __restrict__ scratch) {
+    // one workgroup per z plane of an item: the x and y passes do not mix planes
     constexpr int H = M / 2 + 1;
-    __shared__ T tile[m * m * m];
-    __shared__ cplx<T> buf[m * m * H];  // [z][y][kx]
+    __shared__ T tile[m * m];
+    __shared__ cplx<T> buf[m * H];  // [y][kx]
     __shared__ double2 tw[M];
     const int tid = threadIdx.x;
-    const size_t b = blockIdx.x;
-    const T* src = in + b * (m * m * m);
+    const size_t b = blockIdx.x / m;
+    const int z = blockIdx.x - (int)b * m;
+    const T* src = in + b * (m * m * m) + z * (m * m);
     stage_roots<M>(tw, tid, NT);
-    for (int i = tid; i < m * m * m; i += NT) tile[i] = src[i];
+    for (int i = tid; i < m * m; i += NT) tile[i] = src[i];
     __syncthreads();
-    for (int row = tid; row < m * m; row += NT) {  // x pass: real rows (z, y)
+    for (int t = tid; t < kShare * m; t += NT) {  // x pass: real rows, kShare threads per row
+        const int y = t / kShare, k0 = t - y * kShare;
         T xr[m], xi[m];
 #pragma unroll
         for (int j = 0; j < m; ++j) {
-            xr[j] = tile[row * m + j];
+            xr[j] = tile[y * m + j];
             xi[j] = T(0);
         }
-        cplx<T>* d = buf + row * H;
-        dft_each<T, m, M, -1, H>(xr, xi, tw, [&](int k, T re, T im) { d[k] = cplx<T>{re, im}; });
+        cplx<T>* d = buf + y * H;
+        dft_each<T, m, M, -1, H>(xr, xi, tw, [&](int k, T re, T im) { d[k] = cplx<T>{re, im}; }, k0, kShare);
     }
     __syncthreads();
-    cplx<T>* dst = scratch + b * (m * M * H);
-    for (int col = tid; col < m * H; col += NT) {  // y pass: columns (z, kx) -> [z][ky][kx]
-        const int z = col / H, kx = col - z * H;
+    cplx<T>* dst = scratch + b * (m * M * H) + z * (M * H);
+    for (int t = tid; t < kShare * H; t += NT) {  // y pass: columns kx -> [ky][kx] of plane z
+        const int kx = t / kShare, k0 = t - kx * kShare;
         T xr[m], xi[m];
 #pragma unroll
         for (int j = 0; j < m; ++j) {
-            const cplx<T> v = buf[(z * m + j) * H + kx];
+            const cplx<T> v = buf[j * H + kx];
             xr[j] = v.x;
             xi[j] = v.y;
         }
-        cplx<T>* d = dst + z * M * H + kx;
-        dft_each<T, m, M, -1, M>(xr, xi, tw, [&](int k, T re, T im) { d[k * H] = cplx<T>{re, im}; });
+        cplx<T>* d = dst + kx;
+        dft_each<T, m, M, -1, M>(xr, xi, tw, [&](int k, T re, T im) { d[k * H] = cplx<T>{re, im}; }, k0, kShare);
     }
 }
 
@@ -215,8 +220,9 @@ __global__ void __launch_bounds__(NT) k_fft2_z(const cplx<T>* __restrict__ scrat
     stage_roots<M>(tw, threadIdx.x, NT);
     __syncthreads();
     const size_t b = blockIdx.y;
-    const int col = blockIdx.x * NT + threadIdx.x;
-    if (col >= PLANE) return;
+    const int t = blockIdx.x * NT + threadIdx.x;
+    if (t >= kShare * PLANE) return;
+    const int col = t / kShare, k0 = t - col * kShare;
     const cplx<T>* s = scratch + b * (m * PLANE) + col;
     T xr[m], xi[m];
 #pragma unroll
@@ -225,8 +231,9 @@ __global__ void __launch_bounds__(NT) k_fft2_z(const cplx<T>* __restrict__ scrat
         xr[j] = v.x;
         xi[j] = v.y;
     }
-    dft_each<T, m, M, -1, M>(xr, xi, tw,
-                             [&](int k, T re, T im) { out[spec_at(b, k * PLANE + col, nout)] = cplx<T>{re, im}; });
+    dft_each<T, m, M, -1, M>(
+        xr, xi, tw, [&](int k, T re, T im) { out[spec_at(b, k * PLANE + col, nout)] = cplx<T>{re, im}; }, k0,
+        kShare);
 }
 
 // z pass of the inverse two-phase transform: spectrum (Tin) -> scratch (arithmetic type A)
@@ -239,8 +246,9 @@ __global__ void __launch_bounds__(NT) k_ifft2_z(const cplx<Tin>* __restrict__ in
     stage_roots<M>(tw, threadIdx.x, NT);
     __syncthreads();
     const size_t b = blockIdx.y;
-    const int col = blockIdx.x * NT + threadIdx.x;
-    if (col >= PLANE) return;
+    const int t = blockIdx.x * NT + threadIdx.x;
+    if (t >= kShare * PLANE) return;
+    const int col = t / kShare, j0 = t - col * kShare;
     A Xr[M], Xi[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -249,49 +257,52 @@ __global__ void __launch_bounds__(NT) k_ifft2_z(const cplx<Tin>* __restrict__ in
         Xi[k] = A(v.y);
     }
     cplx<A>* d = scratch + b * (m * PLANE) + col;
-    dft_each<A, M, M, +1, m>(Xr, Xi, tw, [&](int j, A re, A im) { d[j * PLANE] = cplx<A>{re, im}; });
+    dft_each<A, M, M, +1, m>(Xr, Xi, tw, [&](int j, A re, A im) { d[j * PLANE] = cplx<A>{re, im}; }, j0, kShare);
 }
 
-// y and x passes of the inverse two-phase transform: scratch -> real tile (Tout)
+// y and x passes of the inverse two-phase transform: scratch -> real tile (Tout); one
+// workgroup per z plane of an item
 template <typename A, typename Tout, int m, int M, int NT>
 __global__ void __launch_bounds__(NT) k_ifft2_yx(const cplx<A>* __restrict__ scratch, Tout* __restrict__ out,
                                                  const int32_t* __restrict__ out_map) {
     constexpr int H = M / 2 + 1;
-    __shared__ cplx<A> buf[m * m * H];  // [z][y][kx]
-    __shared__ A tile[m * m * m];
+    __shared__ cplx<A> buf[m * H];  // [y][kx]
+    __shared__ A tile[m * m];
     __shared__ double2 tw[M];
     const int tid = threadIdx.x;
-    const size_t b = blockIdx.x;
-    const cplx<A>* s = scratch + b * (m * M * H);
+    const size_t b = blockIdx.x / m;
+    const int z = blockIdx.x - (int)b * m;
+    const cplx<A>* s = scratch + b * (m * M * H) + z * (M * H);
     stage_roots<M>(tw, tid, NT);
     __syncthreads();
-    for (int col = tid; col < m * H; col += NT) {  // y pass: columns (z, kx), ky < M -> y < m
-        const int z = col / H, kx = col - z * H;
+    for (int t = tid; t < kShare * H; t += NT) {  // y pass: ky < M -> y < m, kShare threads per column
+        const int kx = t / kShare, j0 = t - kx * kShare;
         A Xr[M], Xi[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            const cplx<A> v = s[(z * M + k) * H + kx];
+            const cplx<A> v = s[k * H + kx];
             Xr[k] = v.x;
             Xi[k] = v.y;
         }
-        cplx<A>* d = buf + z * m * H + kx;
-        dft_each<A, M, M, +1, m>(Xr, Xi, tw, [&](int j, A re, A im) { d[j * H] = cplx<A>{re, im}; });
+        cplx<A>* d = buf + kx;
+        dft_each<A, M, M, +1, m>(Xr, Xi, tw, [&](int j, A re, A im) { d[j * H] = cplx<A>{re, im}; }, j0, kShare);
     }
     __syncthreads();
-    for (int row = tid; row < m * m; row += NT) {  // x pass: Hermitian rows (z, y) -> real x < m
+    for (int t = tid; t < kShare * m; t += NT) {  // x pass: Hermitian rows -> real x < m
+        const int y = t / kShare, j0 = t - y * kShare;
         A Yr[H], Yi[H];
 #pragma unroll
         for (int k = 0; k < H; ++k) {
-            const cplx<A> v = buf[row * H + k];
+            const cplx<A> v = buf[y * H + k];
             Yr[k] = v.x;
             Yi[k] = v.y;
         }
-        A* d = tile + row * m;
-        c2r_each<A, m, M>(Yr, Yi, tw, [&](int j, A v) { d[j] = v; });
+        A* d = tile + y * m;
+        c2r_each<A, m, M>(Yr, Yi, tw, [&](int j, A v) { d[j] = v; }, j0, kShare);
     }
     __syncthreads();
-    Tout* dst = out + (out_map ? (size_t)out_map[b] : b) * (m * m * m);
-    for (int i = tid; i < m * m * m; i += NT) dst[i] = (Tout)tile[i];
+    Tout* dst = out + (out_map ? (size_t)out_map[b] : b) * (m * m * m) + z * (m * m);
+    for (int i = tid; i < m * m; i += NT) dst[i] = (Tout)tile[i];
 }
 
 template <typename T, int m>
@@ -299,11 +310,12 @@ static hipError_t fwd_two_phase(const T* in, cplx<T>* out, int64_t nbatch, int64
                                 hipStream_t s) {
     constexpr int M = 2 * m, PLANE = M * (M / 2 + 1), NT = 256;
     if (!scratch) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_fft2_xy<T, m, M, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, (cplx<T>*)scratch);
+    hipLaunchKernelGGL((k_fft2_xy<T, m, M, 64>), dim3((unsigned)(nbatch * m)), dim3(64), 0, s, in,
+                       (cplx<T>*)scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fft2_z<T, m, M, NT>), dim3((PLANE + NT - 1) / NT, (unsigned)nbatch), dim3(NT), 0, s,
-                       (const cplx<T>*)scratch, out, nout);
+    const dim3 grid((kShare * PLANE + NT - 1) / NT, (unsigned)nbatch);
+    hipLaunchKernelGGL((k_fft2_z<T, m, M, NT>), grid, dim3(NT), 0, s, (const cplx<T>*)scratch, out, nout);
     return hipGetLastError();
 }
 
@@ -312,11 +324,11 @@ static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, 
                                 void* scratch, hipStream_t s) {
     constexpr int M = 2 * m, PLANE = M * (M / 2 + 1), NT = 256;
     if (!scratch) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ifft2_z<Tin, A, m, M, NT>), dim3((PLANE + NT - 1) / NT, (unsigned)nbatch), dim3(NT), 0, s,
-                       in, (cplx<A>*)scratch, nbatch);
+    const dim3 grid((kShare * PLANE + NT - 1) / NT, (unsigned)nbatch);
+    hipLaunchKernelGGL((k_ifft2_z<Tin, A, m, M, NT>), grid, dim3(NT), 0, s, in, (cplx<A>*)scratch, nbatch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_ifft2_yx<A, Tout, m, M, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s,
+    hipLaunchKernelGGL((k_ifft2_yx<A, Tout, m, M, 64>), dim3((unsigned)(nbatch * m)), dim3(64), 0, s,
                        (const cplx<A>*)scratch, out, out_map);
     return hipGetLastError();
 }

@@ -88,8 +88,12 @@ template <typename T>
 hipError_t launch_reg_block(const T* f, const double* A, T* out, int64_t nb, int n, int p, hipStream_t s);
 // Reg children -> parent: out[J] = sum_c (C_cz x C_cy x C_cx) in[child_c(J)]
 template <typename T>
+// scratch: p = 17 only, nparent * 8 * p^3 values of T (the children's partial sums)
 hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, T* out, int64_t nparent, int p,
-                         hipStream_t s);
+                         hipStream_t s, void* scratch = nullptr);
+// Level-1 node values of the lattice scheme: out[b] (p^3) = f[b] (n^3) padded with zeros
+template <typename T>
+hipError_t launch_pad_copy(const T* f, T* out, int64_t nb, int n, int p, hipStream_t s);
 // Interp parent -> its children, accumulate: io[child8[J][c]] += (C_c^T x C_c^T x C_c^T) par[J]
 template <typename U>
 hipError_t launch_interp_down(const U* par, const int32_t* child8, const double* C01, U* io, int64_t nparent,

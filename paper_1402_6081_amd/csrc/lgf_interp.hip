@@ -176,112 +176,132 @@ __global__ void __launch_bounds__(kInterpThreads)
 }
 
 // ------------------------------------------------------------------ large intervals (P = 17)
-// The children are taken one at a time (the kernels above hold 8 children, or a parent's
-// 2 + 4 partial passes, in LDS: 629 / 275 KB at P = 17).  Same sums in the same order per
-// output node: children in order c = 0..7, each through its x, y, z passes.
+// The kernels above hold 8 children, or a parent's 2 + 4 partial passes, in LDS (629 /
+// 275 KB at P = 17).  Here one workgroup handles one (parent, child) pair, which also
+// gives levels with few parents eight times the workgroups:
+//   Reg up:      k_reg_up_part writes each child's contribution to `part` (scratch), then
+//                k_reg_up_sum adds them in child order c = 0..7 (as one workgroup would);
+//   Interp down: each child accumulates its own values (no two workgroups write one child).
 template <typename T, int P>
 __global__ void __launch_bounds__(kInterpThreads)
-    k_reg_up_seq(const T* __restrict__ in, const int32_t* __restrict__ child8, const double* __restrict__ C01,
-                 T* __restrict__ out) {
+    k_reg_up_part(const T* __restrict__ in, const int32_t* __restrict__ child8, const double* __restrict__ C01,
+                  T* __restrict__ part) {
     constexpr int P3 = P * P * P;
-    __shared__ T X[P3], t1[P3], acc[P3];
+    __shared__ T X[P3], t1[P3];
     __shared__ T Cm[2 * P * P];
-    __shared__ int32_t ch[8];
     const int tid = threadIdx.x;
-    const int64_t J = blockIdx.x;
+    const int64_t J = blockIdx.x >> 3;
+    const int c = blockIdx.x & 7;
+    const int q = child8[J * 8 + c];  // uniform
+    if (q < 0) return;
     for (int i = tid; i < 2 * P * P; i += kInterpThreads) Cm[i] = (T)C01[i];
-    if (tid < 8) ch[tid] = child8[J * 8 + tid];
-    for (int i = tid; i < P3; i += kInterpThreads) acc[i] = T(0);
+    for (int i = tid; i < P3; i += kInterpThreads) X[i] = in[(int64_t)q * P3 + i];
     __syncthreads();
-    for (int c = 0; c < 8; ++c) {
-        const int q = ch[c];  // uniform
-        if (q < 0) continue;
-        for (int i = tid; i < P3; i += kInterpThreads) X[i] = in[(int64_t)q * P3 + i];
-        __syncthreads();
-        for (int i = tid; i < P3; i += kInterpThreads) {  // x: t1[z][y][d]
-            const int d = i % P, rest = i / P;
-            const T* m = Cm + (c & 1) * P * P + d * P;
-            const T* row = X + rest * P;
-            T sum = T(0);
+    for (int i = tid; i < P3; i += kInterpThreads) {  // x: t1[z][y][d]
+        const int d = i % P, rest = i / P;
+        const T* m = Cm + (c & 1) * P * P + d * P;
+        const T* row = X + rest * P;
+        T sum = T(0);
 #pragma unroll
-            for (int x = 0; x < P; ++x) sum += m[x] * row[x];
-            t1[i] = sum;
-        }
-        __syncthreads();
-        for (int i = tid; i < P3; i += kInterpThreads) {  // y: X[z][b][d]
-            const int d = i % P, bb = (i / P) % P, z = i / (P * P);
-            const T* m = Cm + ((c >> 1) & 1) * P * P + bb * P;
-            T sum = T(0);
-#pragma unroll
-            for (int y = 0; y < P; ++y) sum += m[y] * t1[(z * P + y) * P + d];
-            X[i] = sum;
-        }
-        __syncthreads();
-        for (int i = tid; i < P3; i += kInterpThreads) {  // z, accumulated over the children
-            const int bd = i % (P * P), a = i / (P * P);
-            const T* m = Cm + ((c >> 2) & 1) * P * P + a * P;
-            T sum = T(0);
-#pragma unroll
-            for (int z = 0; z < P; ++z) sum += m[z] * X[z * P * P + bd];
-            acc[i] += sum;
-        }
-        __syncthreads();
+        for (int x = 0; x < P; ++x) sum += m[x] * row[x];
+        t1[i] = sum;
     }
-    for (int i = tid; i < P3; i += kInterpThreads) out[J * P3 + i] = acc[i];
+    __syncthreads();
+    for (int i = tid; i < P3; i += kInterpThreads) {  // y: X[z][b][d]
+        const int d = i % P, bb = (i / P) % P, z = i / (P * P);
+        const T* m = Cm + ((c >> 1) & 1) * P * P + bb * P;
+        T sum = T(0);
+#pragma unroll
+        for (int y = 0; y < P; ++y) sum += m[y] * t1[(z * P + y) * P + d];
+        X[i] = sum;
+    }
+    __syncthreads();
+    T* o = part + (J * 8 + c) * P3;
+    for (int i = tid; i < P3; i += kInterpThreads) {  // z
+        const int bd = i % (P * P), a = i / (P * P);
+        const T* m = Cm + ((c >> 2) & 1) * P * P + a * P;
+        T sum = T(0);
+#pragma unroll
+        for (int z = 0; z < P; ++z) sum += m[z] * X[z * P * P + bd];
+        o[i] = sum;
+    }
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(kInterpThreads)
+    k_reg_up_sum(const T* __restrict__ part, const int32_t* __restrict__ child8, T* __restrict__ out, int64_t np) {
+    constexpr int P3 = P * P * P;
+    const int64_t g = (int64_t)blockIdx.x * kInterpThreads + threadIdx.x;
+    if (g >= np * P3) return;
+    const int64_t J = g / P3;
+    const int i = (int)(g - J * P3);
+    T acc = T(0);
+    for (int c = 0; c < 8; ++c)
+        if (child8[J * 8 + c] >= 0) acc += part[(J * 8 + c) * P3 + i];
+    out[g] = acc;
 }
 
 template <typename U, int P>
 __global__ void __launch_bounds__(kInterpThreads)
-    k_interp_down_seq(const U* __restrict__ par, const int32_t* __restrict__ child8, const double* __restrict__ C01,
+    k_interp_down_one(const U* __restrict__ par, const int32_t* __restrict__ child8, const double* __restrict__ C01,
                       U* __restrict__ io) {
     constexpr int P3 = P * P * P;
     __shared__ U X[P3], t1[P3], t2[P3];
     __shared__ U Ct[2 * P * P];  // Ct_c[k][m] = C_c[m][k]
-    __shared__ int32_t ch[8];
     const int tid = threadIdx.x;
-    const int64_t J = blockIdx.x;
+    const int64_t J = blockIdx.x >> 3;
+    const int c = blockIdx.x & 7;
+    const int q = child8[J * 8 + c];  // uniform
+    if (q < 0) return;
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
     for (int i = tid; i < 2 * P * P; i += kInterpThreads) {
-        const int c = i / (P * P), r = i % (P * P), k = r / P, m = r % P;
-        Ct[i] = U(C01[c * P * P + m * P + k]);
+        const int cc = i / (P * P), r = i % (P * P), k = r / P, m = r % P;
+        Ct[i] = U(C01[cc * P * P + m * P + k]);
     }
-    if (tid < 8) ch[tid] = child8[J * 8 + tid];
     for (int i = tid; i < P3; i += kInterpThreads) X[i] = par[J * P3 + i];
     __syncthreads();
-    for (int c = 0; c < 8; ++c) {
-        const int q = ch[c];  // uniform
-        if (q < 0) continue;
-        const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-        for (int i = tid; i < P3; i += kInterpThreads) {  // x: t1[a][b][x']
-            const int xo = i % P, ab = i / P;
-            const U* m = Ct + cx * P * P + xo * P;
-            const U* row = X + ab * P;
-            U sum = U(0);
+    for (int i = tid; i < P3; i += kInterpThreads) {  // x: t1[a][b][x']
+        const int xo = i % P, ab = i / P;
+        const U* m = Ct + cx * P * P + xo * P;
+        const U* row = X + ab * P;
+        U sum = U(0);
 #pragma unroll
-            for (int d = 0; d < P; ++d) sum += m[d] * row[d];
-            t1[i] = sum;
-        }
-        __syncthreads();
-        for (int i = tid; i < P3; i += kInterpThreads) {  // y: t2[a][y'][x']
-            const int xo = i % P, yo = (i / P) % P, a = i / (P * P);
-            const U* m = Ct + cy * P * P + yo * P;
-            const U* src = t1 + a * P * P + xo;
-            U sum = U(0);
-#pragma unroll
-            for (int bb = 0; bb < P; ++bb) sum += m[bb] * src[bb * P];
-            t2[i] = sum;
-        }
-        __syncthreads();
-        for (int i = tid; i < P3; i += kInterpThreads) {  // z, accumulated into the child
-            const int yx = i % (P * P), zo = i / (P * P);
-            const U* m = Ct + cz * P * P + zo * P;
-            U sum = U(0);
-#pragma unroll
-            for (int a = 0; a < P; ++a) sum += m[a] * t2[a * P * P + yx];
-            U* dst = io + (int64_t)q * P3 + i;
-            *dst = *dst + sum;
-        }
-        __syncthreads();
+        for (int d = 0; d < P; ++d) sum += m[d] * row[d];
+        t1[i] = sum;
     }
+    __syncthreads();
+    for (int i = tid; i < P3; i += kInterpThreads) {  // y: t2[a][y'][x']
+        const int xo = i % P, yo = (i / P) % P, a = i / (P * P);
+        const U* m = Ct + cy * P * P + yo * P;
+        const U* src = t1 + a * P * P + xo;
+        U sum = U(0);
+#pragma unroll
+        for (int bb = 0; bb < P; ++bb) sum += m[bb] * src[bb * P];
+        t2[i] = sum;
+    }
+    __syncthreads();
+    for (int i = tid; i < P3; i += kInterpThreads) {  // z, accumulated into the child
+        const int yx = i % (P * P), zo = i / (P * P);
+        const U* m = Ct + cz * P * P + zo * P;
+        U sum = U(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) sum += m[a] * t2[a * P * P + yx];
+        U* dst = io + (int64_t)q * P3 + i;
+        *dst = *dst + sum;
+    }
+}
+
+// Level-1 node values of the lattice scheme (p = n + 1 nodes on the grid points, Reg the
+// identity on n^3 and a zero last plane): a padded copy, out[b] = [f[b]; 0] in each axis.
+template <typename T>
+__global__ void k_pad_copy(const T* __restrict__ f, T* __restrict__ out, int64_t nb, int n, int p) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p3 = (int64_t)p * p * p;
+    if (g >= nb * p3) return;
+    const int64_t b = g / p3;
+    const int r = (int)(g - b * p3);
+    const int x = r % p, y = (r / p) % p, z = r / (p * p);
+    out[g] = (x < n && y < n && z < n) ? f[((b * n + z) * n + y) * n + x] : T(0);
 }
 
 // ------------------------------------------------------------------ level 1 -> block, FP64 add-back
@@ -400,7 +420,7 @@ static hipError_t reg_up_p(const T* in, const int32_t* child8, const double* C01
 
 template <typename T>
 hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, T* out, int64_t np, int p,
-                         hipStream_t s) {
+                         hipStream_t s, void* scratch) {
     if (np <= 0) return hipSuccess;
     switch (p) {
         case 2: return reg_up_p<T, 2>(in, child8, C01, out, np, s);
@@ -412,10 +432,17 @@ hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, 
         case 8: return reg_up_p<T, 8>(in, child8, C01, out, np, s);
         case 9: return reg_up_p<T, 9>(in, child8, C01, out, np, s);
         case 10: return reg_up_p<T, 10>(in, child8, C01, out, np, s);
-        case 17:
-            hipLaunchKernelGGL((k_reg_up_seq<T, 17>), dim3((unsigned)np), dim3(kInterpThreads), 0, s, in, child8, C01,
-                               out);
+        case 17: {
+            constexpr int P3 = 17 * 17 * 17;
+            if (!scratch) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_reg_up_part<T, 17>), dim3((unsigned)(np * 8)), dim3(kInterpThreads), 0, s, in,
+                               child8, C01, (T*)scratch);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_reg_up_sum<T, 17>), dim3((unsigned)((np * P3 + kInterpThreads - 1) / kInterpThreads)),
+                               dim3(kInterpThreads), 0, s, (const T*)scratch, child8, out, np);
             return hipGetLastError();
+        }
         default: return hipErrorInvalidValue;
     }
 }
@@ -442,11 +469,19 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
         case 9: return interp_down_p<U, 9>(par, child8, C01, io, nparent, s);
         case 10: return interp_down_p<U, 10>(par, child8, C01, io, nparent, s);
         case 17:
-            hipLaunchKernelGGL((k_interp_down_seq<U, 17>), dim3((unsigned)nparent), dim3(kInterpThreads), 0, s, par,
-                               child8, C01, io);
+            hipLaunchKernelGGL((k_interp_down_one<U, 17>), dim3((unsigned)(nparent * 8)), dim3(kInterpThreads), 0, s,
+                               par, child8, C01, io);
             return hipGetLastError();
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T>
+hipError_t launch_pad_copy(const T* f, T* out, int64_t nb, int n, int p, hipStream_t s) {
+    if (nb <= 0) return hipSuccess;
+    const int64_t tot = nb * (int64_t)p * p * p;
+    hipLaunchKernelGGL(k_pad_copy<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f, out, nb, n, p);
+    return hipGetLastError();
 }
 
 template <typename T, typename U>
@@ -457,11 +492,13 @@ hipError_t launch_final(const T* vnear, const U* ut, const double* A, T* u, int6
 }
 
 template hipError_t launch_reg_block<double>(const double*, const double*, double*, int64_t, int, int, hipStream_t);
+template hipError_t launch_pad_copy<double>(const double*, double*, int64_t, int, int, hipStream_t);
+template hipError_t launch_pad_copy<float>(const float*, float*, int64_t, int, int, hipStream_t);
 template hipError_t launch_reg_block<float>(const float*, const double*, float*, int64_t, int, int, hipStream_t);
 template hipError_t launch_reg_up<double>(const double*, const int32_t*, const double*, double*, int64_t, int,
-                                          hipStream_t);
+                                         hipStream_t, void*);
 template hipError_t launch_reg_up<float>(const float*, const int32_t*, const double*, float*, int64_t, int,
-                                         hipStream_t);
+                                         hipStream_t, void*);
 template hipError_t launch_interp_down<double>(const double*, const int32_t*, const double*, double*, int64_t, int,
                                                hipStream_t);
 template hipError_t launch_interp_down<ff32>(const ff32*, const int32_t*, const double*, ff32*, int64_t, int,

@@ -466,10 +466,13 @@ struct DevBuf {
 // HBM intermediate of the two-phase transforms (levels >= 2 of a tile that does not fit one
 // workgroup's LDS); the levels run one after another on one stream and share it.
 int64_t scratch_need(const HostPlan& H) {
-    int64_t nmax = 0;
+    int64_t nmax = 0, pmax = 0;
     for (int l = 1; l <= H.Ltop; ++l)
         if (H.lv[l].pairs() > 0 && !(l == 1 && H.lat1)) nmax = std::max(nmax, H.lv[l].nint);
-    return two_phase_scratch_bytes(H.p, nmax);
+    for (int l = 2; l <= H.Ltop; ++l) pmax = std::max(pmax, H.lv[l].nint);  // Reg up: children's partials
+    const int64_t p3 = (int64_t)H.p * H.p * H.p;
+    const int64_t reg = H.p == 17 ? pmax * 8 * p3 * 8 : 0;
+    return std::max(two_phase_scratch_bytes(H.p, nmax), reg);
 }
 
 // Device bytes of a plan's workspace (lists, matrices, node values and spectra of every
@@ -767,7 +770,10 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(s2, pl->ev_fork, 0)) != hipSuccess) return e;
         }
-        if (segs & kSegReg1)
+        if ((segs & kSegReg1) && pl->lat1)  // identity on the grid points: a padded copy
+            LGF_STEP(s2, (launch_pad_copy<T>(f, (T*)pl->lv[1].d_ftil, pl->nsrc, n, p, s2)), "reg_l0_l1",
+                     ns * (n3 + p3) * es, 0.0);
+        else if (segs & kSegReg1)
             LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nsrc, n, p, s2)), "reg_l0_l1",
                      ns * (n3 + p3) * es, ns * 2.0 * (p * n3 + p * p * n * n + p3 * n));
         const bool coarse = pl->Ltop >= 2;
@@ -780,7 +786,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             for (int l = 1; l < pl->Ltop; ++l)
                 LGF_STEP(s3,
                          (launch_reg_up<T>((const T*)pl->lv[l].d_ftil, pl->lv[l + 1].d_child8, pl->d_C01,
-                                           (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s3)),
+                                           (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s3, pl->d_scratch)),
                          "reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1),
                          (lvN(l) + lvN(l + 1)) * p3 * es, lvN(l) * 2.0 * 3.0 * p3 * p);
             for (int l = 2; l <= pl->Ltop; ++l)
