@@ -114,7 +114,10 @@ lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t 
  * u = G * f on the plan's layout (Steps 1-3 of Sec. 3.1).  f, u: DEVICE pointers as
  * described above (may not alias; f over the source blocks and u over the evaluation
  * blocks for a plan with separate sets).  u is overwritten entirely.  Asynchronous on
- * hip_stream.  Errors: LGF_ERR_ARG (NULL), LGF_ERR_DEVICE (launch failure).
+ * hip_stream.  Errors: LGF_ERR_ARG (NULL), LGF_ERR_BUSY (the plan's previous solve was
+ * issued on another stream and has not finished: its one workspace would be shared),
+ * LGF_ERR_DEVICE (launch failure).  With LGF_CHECK_FINITE=1 in the environment the input
+ * is scanned first (synchronising hip_stream) and non-finite values give LGF_ERR_ARG.
  */
 lgf_status lgf_solve(lgf_plan_t plan, const void* f, void* u, void* hip_stream);
 
@@ -184,7 +187,8 @@ lgf_status lgf_plan_solve_offsets(lgf_plan_t plan, int64_t* offsets, int32_t max
  * lgf_graph_launch enqueues the whole solve as one graph launch on hip_stream, with the
  * same result as lgf_solve; the plan's single-workspace rule applies (no overlap with
  * other solves or graph launches of the same plan).  The graph must be destroyed
- * before its plan.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
+ * before its plan.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE, and for lgf_graph_launch
+ * LGF_ERR_BUSY as for lgf_solve (graph launches and solves of one plan share its workspace).
  */
 typedef struct lgf_graph_s* lgf_graph_t;
 lgf_status lgf_graph_create(lgf_plan_t plan, const void* f, void* u, void* hip_stream, lgf_graph_t* out);
@@ -207,8 +211,9 @@ typedef struct {
 } lgf_tuning;
 
 /*
- * Autotuner: runs (1 + reps) solves per candidate variant on (f, u) (DEVICE buffers of the
- * plan's shape; u is overwritten), each as one launch of the solve's HIP graph, in a
+ * Autotuner: times each candidate variant on (f, u) (DEVICE buffers of the plan's shape; u is
+ * overwritten) as the median over `reps` rounds of 4 solves issued back to back on
+ * hip_stream (with the same kernels, streams and dependencies as the solve's graph), in a
  * coordinate search over the fields of lgf_tuning,
  * keeps the fastest median device time, and remembers the choice for later plans of the
  * same (n, p, precision, power-of-two block-count bucket) in this process; if the

@@ -549,6 +549,11 @@ struct lgf_plan_s {
     // far-field chain on a second (default-priority) stream for small plans
     hipStream_t far_stream = nullptr, far_stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
+    // the last solve's completion (one workspace: solves on other streams must wait for it)
+    hipEvent_t ev_done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool done_valid = false;
+    int32_t* d_flag = nullptr;  // debug check of the input (LGF_CHECK_FINITE=1)
     bool overlap = false;
 
     ~lgf_plan_s() {
@@ -558,6 +563,7 @@ struct lgf_plan_s {
         if (ev_join) hipEventDestroy(ev_join);
         if (ev_fork2) hipEventDestroy(ev_fork2);
         if (ev_join2) hipEventDestroy(ev_join2);
+        if (ev_done) hipEventDestroy(ev_done);
         if (far_stream) hipStreamDestroy(far_stream);
         if (far_stream2) hipStreamDestroy(far_stream2);
         budget_release(ws_bytes);
@@ -567,9 +573,12 @@ struct lgf_plan_s {
 struct lgf_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    lgf_plan_s* plan = nullptr;     // the plan whose workspace the graph uses
+    std::vector<hipGraph_t> parts;  // captured pieces whose kernel nodes were copied into graph
     ~lgf_graph_s() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
+        for (hipGraph_t p : parts) hipGraphDestroy(p);  // outlive every copy of their nodes
     }
 };
 
@@ -859,7 +868,8 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
         hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_fork2, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_done, hipEventDisableTiming) != hipSuccess)
         return fail(LGF_ERR_DEVICE, "stream/event creation failed");
     // The far-field chain (small, latency-bound kernels) and the near field (HBM-bound
     // transforms and products) overlap well: measured on MI355X the concurrent chains are
@@ -949,6 +959,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
         ok = dev_alloc(pl, &pl->lv[l].d_child8, H.lv[l].nint * 32) &&
              dev_alloc(pl, &pl->lv[l].d_src216, H.lv[l].nint * 216 * 4);
     if (ok) ok = dev_alloc(pl, &pl->d_scratch, scratch_need(H));
+    if (ok) ok = dev_alloc(pl, &pl->d_flag, 4);
     if (!ok) return fail(LGF_ERR_OOM, "device allocation failed for the plan workspace");
     hipError_t e = upload(pl->d_g0_tgt8, H.g0_tgt8, s);
     if (e == hipSuccess) e = upload(pl->d_g0_src64, H.g0_src64, s);
@@ -1018,7 +1029,9 @@ hipError_t append_chain(hipGraph_t parent, hipGraph_t part, const std::vector<hi
         hipGraphNodeType type;
         if ((e = hipGraphNodeGetType(node, &type)) != hipSuccess) return e;
         if (type != hipGraphNodeTypeKernel) return hipErrorInvalidValue;  // only kernels are captured
-        hipKernelNodeParams kp;
+        // value-initialised: any field the getter leaves unwritten (extra) must read as NULL
+        // when the copy is added, not as whatever the stack held
+        hipKernelNodeParams kp{};
         if ((e = hipGraphKernelNodeGetParams(node, &kp)) != hipSuccess) return e;
         hipGraphNode_t copy = nullptr;
         if ((e = hipGraphAddKernelNode(&copy, parent, d.empty() ? nullptr : d.data(), d.size(), &kp)) != hipSuccess)
@@ -1036,6 +1049,7 @@ hipError_t append_chain(hipGraph_t parent, hipGraph_t part, const std::vector<hi
 lgf_status make_graph(lgf_plan_t plan, const void* f, void* u, lgf_graph_s** out) {
     *out = nullptr;
     lgf_graph_s* g = new lgf_graph_s();
+    g->plan = plan;
     hipError_t e = hipSuccess;
     const int ov = plan->tune.overlap == 0 ? (plan->overlap ? 1 : 2) : plan->tune.overlap;
     if (ov != 1 || plan->Ltop < 1) {
@@ -1052,13 +1066,12 @@ lgf_status make_graph(lgf_plan_t plan, const void* f, void* u, lgf_graph_s** out
         e = hipGraphCreate(&g->graph, 0);
         const bool coarse = plan->Ltop >= 2;
         hipGraphNode_t last[7] = {};
-        std::vector<hipGraph_t> parts;
         auto add = [&](int slot, unsigned segs, std::initializer_list<int> deps) {
             if (e != hipSuccess) return;
             hipGraph_t part = nullptr;
             e = capture_part(plan, f, u, segs, &part);
+            if (part) g->parts.push_back(part);  // freed with the graph, also after a failure
             if (e != hipSuccess) return;
-            parts.push_back(part);
             std::vector<hipGraphNode_t> d;
             for (int k : deps)
                 if (last[k]) d.push_back(last[k]);
@@ -1077,7 +1090,6 @@ lgf_status make_graph(lgf_plan_t plan, const void* f, void* u, lgf_graph_s** out
         }
         add(5, kSegFinal, {0, coarse ? 4 : 2});
         if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-        for (hipGraph_t part : parts) hipGraphDestroy(part);
     }
     if (e == hipSuccess && !g->exec) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -1145,30 +1157,34 @@ void tune_store(const TuneKey& k, const TuneConfig& c) {
     std::fclose(fh);
 }
 
-// median device time (ms) of `reps` solves with the plan's current configuration, each one
-// launch of the solve's graph (the way solves are usually issued)
+// median device time (ms) per solve with the plan's current configuration: `reps` rounds of
+// kRound solves issued back to back (eagerly: the same kernels, streams and fork/join as a
+// solve's graph, and the rounds keep the device busy past the host's issue time).  Graphs
+// are not built here: building hundreds of them per tuning run ended in host crashes inside
+// graph creation and launch on this ROCm stack.
 float time_solves(lgf_plan_s* pl, const void* f, void* u, hipStream_t s, int reps) {
-    lgf_graph_s* g = nullptr;
-    if (make_graph(pl, f, u, &g) != LGF_OK) return 1e30f;
+    constexpr int kRound = 4;
+    if (solve_dispatch(pl, f, u, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return 1e30f;
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
     std::vector<float> t;
-    for (int r = 0; r < reps + 1; ++r) {
+    for (int r = 0; r < reps; ++r) {
         hipEventRecord(a, s);
-        if (hipGraphLaunch(g->exec, s) != hipSuccess) {
+        bool ok = true;
+        for (int k = 0; k < kRound && ok; ++k) ok = solve_dispatch(pl, f, u, s) == hipSuccess;
+        hipEventRecord(b, s);
+        hipEventSynchronize(b);
+        if (!ok) {
             t.assign(1, 1e30f);
             break;
         }
-        hipEventRecord(b, s);
-        hipEventSynchronize(b);
         float ms = 0.f;
         hipEventElapsedTime(&ms, a, b);
-        if (r > 0) t.push_back(ms);  // the first solve warms caches and code objects
+        t.push_back(ms / kRound);
     }
     hipEventDestroy(a);
     hipEventDestroy(b);
-    delete g;
     std::sort(t.begin(), t.end());
     return t[t.size() / 2];
 }
@@ -1214,6 +1230,48 @@ void set_last_error(const std::string& msg) { t_err = msg; }
 }  // namespace lgfdev
 
 // ============================================================== C ABI
+namespace {
+// One workspace per plan: a solve issued on another stream while the plan's previous solve
+// is still running would race on it.  Same-stream solves are ordered by the stream.
+lgf_status check_idle(lgf_plan_s* pl, hipStream_t s) {
+    if (pl->done_valid && s != pl->last_stream && hipEventQuery(pl->ev_done) == hipErrorNotReady)
+        return fail(LGF_ERR_BUSY, "plan busy: its previous solve on another stream has not finished");
+    return LGF_OK;
+}
+
+void mark_issued(lgf_plan_s* pl, hipStream_t s) {
+    if (hipEventRecord(pl->ev_done, s) == hipSuccess) {
+        pl->last_stream = s;
+        pl->done_valid = true;
+    }
+}
+
+__global__ void k_nonfinite(const void* f, int64_t count, int is_f64, int32_t* flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = is_f64 ? ((const double*)f)[i] : (double)((const float*)f)[i];
+        if (!isfinite(v)) flag[0] = 1;  // every writer stores the same value
+    }
+}
+
+// LGF_CHECK_FINITE=1 in the environment: refuse inputs holding NaN or Inf (debugging aid;
+// synchronises the stream, so off by default)
+lgf_status check_finite(lgf_plan_s* pl, const void* f, hipStream_t s) {
+    const char* v = std::getenv("LGF_CHECK_FINITE");
+    if (!v || v[0] != '1') return LGF_OK;
+    const int64_t count = pl->nsrc * (int64_t)pl->n * pl->n * pl->n;
+    int32_t flag = 0;
+    hipError_t e = zero_fill(pl->d_flag, 4, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_nonfinite, dim3(1024), dim3(256), 0, s, f, count, pl->prec == LGF_F64 ? 1 : 0, pl->d_flag);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, pl->d_flag, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(LGF_ERR_DEVICE, std::string("input check failed: ") + hipGetErrorString(e));
+    return flag ? fail(LGF_ERR_ARG, "f holds non-finite values") : LGF_OK;
+}
+}  // namespace
+
 extern "C" {
 
 static lgf_status check_args(int32_t n, int32_t p, lgf_precision prec) {
@@ -1375,8 +1433,13 @@ lgf_status lgf_plan_solve_offsets(lgf_plan_t plan, int64_t* offsets, int32_t max
 lgf_status lgf_solve(lgf_plan_t plan, const void* f, void* u, void* hip_stream) {
     if (!plan || !f || !u) return fail(LGF_ERR_ARG, "NULL argument to lgf_solve");
     t_err.clear();
-    hipError_t e = solve_dispatch(plan, f, u, (hipStream_t)hip_stream);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    lgf_status st = check_idle(plan, s);
+    if (st == LGF_OK) st = check_finite(plan, f, s);
+    if (st != LGF_OK) return st;
+    hipError_t e = solve_dispatch(plan, f, u, s);
     if (e != hipSuccess) return fail(LGF_ERR_DEVICE, std::string("solve failed at ") + t_err);
+    mark_issued(plan, s);
     return LGF_OK;
 }
 
@@ -1403,8 +1466,12 @@ lgf_status lgf_graph_create(lgf_plan_t plan, const void* f, void* u, void* hip_s
 
 lgf_status lgf_graph_launch(lgf_graph_t graph, void* hip_stream) {
     if (!graph || !graph->exec) return fail(LGF_ERR_ARG, "NULL graph");
-    hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)hip_stream);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    lgf_status st = check_idle(graph->plan, s);
+    if (st != LGF_OK) return st;
+    hipError_t e = hipGraphLaunch(graph->exec, s);
     if (e != hipSuccess) return fail(LGF_ERR_DEVICE, std::string("graph launch failed: ") + hipGetErrorString(e));
+    mark_issued(graph->plan, s);
     return LGF_OK;
 }
 

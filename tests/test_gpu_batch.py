@@ -254,3 +254,51 @@ def test_batch_workload_fp32_against_fp64_and_exact(L):
              % (k, lays[k].shape[0], rel(got, ref), err_a, trunc))
         assert rel(got, ref) <= 1e-12
         assert err_a <= trunc + 1e-12
+
+
+def test_plan_busy_on_another_stream(L):
+    """One workspace per plan: a solve on a second stream while the first stream's solve is
+    still queued is refused (LGF_ERR_BUSY); the same stream, or the second stream once the
+    first solve is done, is accepted.  A bounded GPU spin holds the first solve back."""
+    rng = np.random.default_rng(71)
+    blocks = W.eden_layout(64, rng)
+    plan = L.Plan(blocks, 8, 6, 0, "f64")
+    f = torch.from_numpy(rng.standard_normal((len(blocks), 8, 8, 8))).to("cuda:0")
+    ref = plan.solve(f).clone()
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ua, ub = torch.empty_like(f), torch.empty_like(f)
+    with torch.cuda.stream(sa):
+        torch.cuda._sleep(50_000_000)  # bounded spin (tens of milliseconds)
+    plan.solve(f, ua, stream=sa)
+    with pytest.raises(L.LGFError) as e:
+        plan.solve(f, ub, stream=sb)
+    assert e.value.name == "LGF_ERR_BUSY"
+    g = plan.graph(f, ub)  # graph creation synchronises its own stream only
+    plan.solve(f, ua, stream=sa)  # same stream: ordered, accepted
+    torch.cuda.synchronize()
+    plan.solve(f, ub, stream=sb)  # idle again
+    g.launch(stream=sb)
+    torch.cuda.synchronize()
+    assert torch.equal(ua, ref) and torch.equal(ub, ref)
+    g.close()
+    plan.close()
+
+
+def test_nonfinite_input_check(L, monkeypatch):
+    rng = np.random.default_rng(72)
+    blocks = W.eden_layout(20, rng)
+    plan = L.Plan(blocks, 8, 6, 0, "f32")
+    f = torch.from_numpy(rng.standard_normal((len(blocks), 8, 8, 8))).to("cuda:0", torch.float32)
+    good = plan.solve(f).clone()
+    f[3, 1, 2, 3] = float("nan")
+    monkeypatch.setenv("LGF_CHECK_FINITE", "1")
+    with pytest.raises(L.LGFError) as e:
+        plan.solve(f)
+    assert e.value.name == "LGF_ERR_ARG"
+    f[3, 1, 2, 3] = 0.0
+    f2 = torch.from_numpy(rng.standard_normal((len(blocks), 8, 8, 8))).to("cuda:0", torch.float32)
+    assert torch.isfinite(plan.solve(f2)).all()
+    monkeypatch.delenv("LGF_CHECK_FINITE")
+    plan.close()
+    assert torch.isfinite(good).all()
