@@ -7,7 +7,7 @@ workload is also solved on the FP32 path (FP64 tables and final add), whose rate
 against the FP64 result and latencies are reported next to the FP64 numbers.
 
 Timing: the plan's kernel variants are autotuned first (lgf_plan_autotune, a few dozen
-solves), then W untimed warm-up solves and K timed solves bracketed by device
+eager solves), the graph schedule is chosen by timing one graph of each schedule, then W untimed warm-up solves and K timed solves bracketed by device
 synchronisation; the inputs are resident in HBM before the timed region.  Two passes per
 precision:
   * eager lgf_solve calls on one stream with every step bracketed by HIP events
@@ -166,20 +166,37 @@ def cpu_baseline(cfg, budget_s=30.0):
                       "excluded, %.1f s" % (cfg["name"], npts, dt)}
 
 
+def _graph_schedule(plan, f, u, choice, launches=20):
+    """The autotuner times eager solves; a graph runs the same schedules with other costs
+    (the device's own dependency handling instead of host-side events), so the schedule a
+    graph is built with is chosen by timing one graph of each (overlap 1, 3, 2) with the
+    tuned kernel variants.  Returns the choice (set on the plan) and the per-launch times."""
+    ms = {}
+    for ov in (1, 3, 2):
+        plan.set_tuning(**dict(choice, overlap=ov))
+        dt, _ = _time_graph(plan, f, u, launches, 3)
+        ms[ov] = dt / launches * 1e3
+    best = dict(choice, overlap=min(ms, key=ms.get))
+    plan.set_tuning(**best)
+    return best, {str(k): round(v, 5) for k, v in ms.items()}
+
+
 def _measure(plan, f, u, steps, warmup, graph=True, tune=True):
-    """Autotune the plan's kernel variants (lgf_plan_autotune), then
+    """Autotune the plan's kernel variants and eager schedule (lgf_plan_autotune), then
       * eager solves on one stream with per-step events: isolated kernel durations for the
         breakdown and the roofline;
-      * graph launches with the tuned variants (far field concurrent with the near field
-        when that is faster): the rate and latencies."""
+      * graph launches with the tuned variants, in the schedule whose graph is fastest
+        (_graph_schedule): the rate and latencies."""
     choice = plan.autotune(f, u, reps=10) if tune else plan.tuning()
     plan.set_tuning(**dict(choice, overlap=2))
     dt_e, prof = _time_solves(plan, f, u, steps, warmup)
     plan.set_tuning(**choice)
     if not graph:  # counter-collection runs: eager solves only
         return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_e, lat_graph=np.asarray(prof["solve_ms"]), tuning=choice)
+    gchoice, sched = _graph_schedule(plan, f, u, choice) if tune else (choice, None)
     dt_g, lat = _time_graph(plan, f, u, steps, warmup)
-    return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat, tuning=choice)
+    return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat, tuning=gchoice, eager_tuning=choice,
+                graph_schedule_ms=sched)
 
 
 def hbm_copy_bandwidth(mib=2048, reps=10):
@@ -235,7 +252,7 @@ def batch_bench(L, W, steps, warmup, seed=4):
     bp = L.Plan.batch(lays, 16, 8, 0, "f32")
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
-    choice = bp.autotune(fcat, ucat, reps=2)
+    choice, sched = _graph_schedule(bp, fcat, ucat, bp.autotune(fcat, ucat, reps=2), launches=5)
     dt_g, lat = _time_graph(bp, fcat, ucat, steps, warmup)
     # the same 64 problems as 64 plans enqueued back to back (no batching)
     plans = [L.Plan(b, 16, 8, 0, "f32") for b in lays]
@@ -259,7 +276,8 @@ def batch_bench(L, W, steps, warmup, seed=4):
             "ms_per_batch": round(dt_g / steps * 1e3, 5), "latency_ms": _pct(lat),
             "separate_plans_value": round(npts * steps / dt_sep, 1),
             "separate_plans_ms": round(dt_sep / steps * 1e3, 5),
-            "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3), "tuning": choice}
+            "batch_equals_separate": bool(same), "plan_s": round(t_plan, 3), "tuning": choice,
+            "graph_schedule_ms": sched}
 
 
 def split_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None):
@@ -459,7 +477,7 @@ def main():
         "config": {"workload": cfg["name"], "points": int(npts), "blocks": int(info["nblocks"]),
                    "n": cfg["n"], "p": cfg["p"], "levels": cfg["levels"],
                    "launch": "eager lgf_solve" if args.no_graph else "hip graph per solve",
-                   "tuning": m["tuning"],
+                   "tuning": m["tuning"], "graph_schedule_ms": m["graph_schedule_ms"],
                    "source": "32 seeded Gaussians, sigma U[2,6], zero net source"},
         "latency_ms": _pct(m["lat_graph"]),
         "eager": {"value": round(npts * args.steps / m["dt_eager"], 1),
@@ -486,7 +504,7 @@ def main():
                           "rel_linf_err_vs_fp64": err,
                           "latency_ms": _pct(m32["lat_graph"]),
                           "eager_ms_per_step": round(m32["dt_eager"] / args.steps * 1e3, 5),
-                          "tuning": m32["tuning"],
+                          "tuning": m32["tuning"], "graph_schedule_ms": m32["graph_schedule_ms"],
                           "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS, cfg["name"], "f32")}
         breakdown["fp32"] = _breakdown(m32["prof"])
         plan32.close()

@@ -211,14 +211,18 @@ typedef struct {
 } lgf_tuning;
 
 /*
- * Autotuner: times each candidate variant on (f, u) (DEVICE buffers of the plan's shape; u is
- * overwritten) as the median over `reps` rounds of 4 solves issued back to back on
- * hip_stream (with the same kernels, streams and dependencies as the solve's graph), in a
- * coordinate search over the fields of lgf_tuning,
- * keeps the fastest median device time, and remembers the choice for later plans of the
- * same (n, p, precision, power-of-two block-count bucket) in this process; if the
- * environment variable LGF_TUNE_FILE names a file the choice is appended there and read by
- * later processes.  Synchronous.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
+ * Autotuner for eager solves (lgf_solve): times each candidate on (f, u) (DEVICE buffers of
+ * the plan's shape; u is overwritten) as the median over `reps` rounds of 4 solves issued
+ * back to back on hip_stream.  The kernel variants are chosen first, on one stream
+ * (overlap 2: the sum of the kernels' durations), in a coordinate search over the other
+ * fields of lgf_tuning; then the schedule (overlap 1, 3 or 2) of an eager solve with those
+ * variants.  The choice replaces the plan's variants only if it is at least 1% faster than
+ * the variants the call started from, and is remembered for later plans of the same (n, p,
+ * precision, power-of-two block-count bucket) in this process; if the environment variable
+ * LGF_TUNE_FILE names a file the choice is appended there and read by later processes.
+ * A graph runs the schedules with other costs (dependencies resolved on the device instead
+ * of host events), so a caller that launches graphs picks the overlap its graph is built
+ * with by timing one graph per schedule.  Synchronous.  Errors: LGF_ERR_ARG, LGF_ERR_DEVICE.
  */
 lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_stream, int32_t reps);
 

@@ -1489,28 +1489,39 @@ lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_
         plan->tune = c;
         return time_solves(plan, f, u, s, reps);
     };
-    TuneConfig best = start;
-    float best_ms = timed(best);
-    // coordinate search, two sweeps: each knob in turn, keeping the best value of the others
+    // kernel variants first, on one stream (overlap 2): the sum of the kernels' durations,
+    // which is what a variant changes, without the scheduling noise of concurrent branches.
+    // Coordinate search, two sweeps: each knob in turn, keeping the best value of the others
     // (0 = the per-level default for the level >= 1 Prod knobs)
-    const std::vector<std::vector<int>> opts = {{1, 3, 2},    {128, 256, 512}, {2, 4, 8},
-                                                {0, 1},       {0, 1, 2, 4},    {0, 8, 4, 2, 1}};
+    TuneConfig best = start;
+    best.overlap = 2;
+    float best_ms = timed(best);
+    const std::vector<std::vector<int>> opts = {{128, 256, 512}, {2, 4, 8}, {0, 1}, {0, 1, 2, 4}, {0, 8, 4, 2, 1}};
     for (int sweep = 0; sweep < 2; ++sweep) {
-        for (int knob = 0; knob < 6; ++knob) {
+        for (int knob = 0; knob < 5; ++knob) {
             for (int v : opts[knob]) {
                 TuneConfig c = best;
-                if (knob == 0) c.overlap = v;
-                if (knob == 1) c.fft0_threads = v;
-                if (knob == 2) c.near_waves = v;
-                if (knob == 3) c.near_prefetch = v;
-                if (knob == 4) c.far_waves = v;
-                if (knob == 5) c.far_children = v;
+                if (knob == 0) c.fft0_threads = v;
+                if (knob == 1) c.near_waves = v;
+                if (knob == 2) c.near_prefetch = v;
+                if (knob == 3) c.far_waves = v;
+                if (knob == 4) c.far_children = v;
                 const float ms = timed(c);
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = c;
                 }
             }
+        }
+    }
+    // then the schedule of an eager solve with those variants
+    for (int ov : {1, 3}) {
+        TuneConfig c = best;
+        c.overlap = ov;
+        const float ms = timed(c);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
         }
     }
     // guard against a choice that only won on noise: alternate the starting and the tuned
