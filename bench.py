@@ -140,6 +140,23 @@ def _roofline(prof, dtype_peak_tflops, workload=None, prec=None):
     return roof
 
 
+def _solve_hbm(prof, ms_per_solve, copy_gbps, workload, prec):
+    """HBM rate of a whole solve: the bytes of all its steps (algorithmic, and the
+    rocprofv3-measured traffic when every step has a committed counter entry) over the
+    solve time, against the measured device-copy bandwidth and the 8 TB/s peak."""
+    alg = sum(s["bytes"] for s in prof["steps"])  # per solve
+    tr = [measured_traffic(workload, prec, s["name"])[0] for s in prof["steps"]]
+    traffic = sum(tr) if tr and all(t is not None for t in tr) else None
+    t = ms_per_solve / 1e3
+    bytes_ = traffic if traffic is not None else alg
+    gbs = bytes_ / t / 1e9
+    return {"algorithmic_bytes": round(alg), "traffic": round(traffic) if traffic is not None else None,
+            "ms": round(ms_per_solve, 5), "GBps": round(gbs, 1),
+            "frac_of_copy": round(gbs / copy_gbps, 4) if copy_gbps else None,
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_from": "traffic" if traffic is not None else "algorithmic"}
+
+
 def _breakdown(prof):
     ns = max(prof["nsolves"], 1)
     out = []
@@ -488,6 +505,7 @@ def main():
         "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS, cfg["name"], "f64"),
         "hbm_copy_GBps": hbm_copy_bandwidth(),
     }
+    result["solve_hbm"] = _solve_hbm(m["prof"], result["ms_per_step"], result["hbm_copy_GBps"], cfg["name"], "f64")
     breakdown = {"fp64": _breakdown(m["prof"])}
     u64_host = u64.cpu().numpy()
 
@@ -506,6 +524,8 @@ def main():
                           "eager_ms_per_step": round(m32["dt_eager"] / args.steps * 1e3, 5),
                           "tuning": m32["tuning"], "graph_schedule_ms": m32["graph_schedule_ms"],
                           "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS, cfg["name"], "f32")}
+        result["fp32"]["solve_hbm"] = _solve_hbm(m32["prof"], result["fp32"]["ms_per_step"],
+                                                 result["hbm_copy_GBps"], cfg["name"], "f32")
         breakdown["fp32"] = _breakdown(m32["prof"])
         plan32.close()
     plan.close()
