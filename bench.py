@@ -209,7 +209,8 @@ def _measure(plan, f, u, steps, warmup, graph=True, tune=True):
     dt_e, prof = _time_solves(plan, f, u, steps, warmup)
     plan.set_tuning(**choice)
     if not graph:  # counter-collection runs: eager solves only
-        return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_e, lat_graph=np.asarray(prof["solve_ms"]), tuning=choice)
+        return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_e, lat_graph=np.asarray(prof["solve_ms"]), tuning=choice,
+                    eager_tuning=choice, graph_schedule_ms=None)
     gchoice, sched = _graph_schedule(plan, f, u, choice) if tune else (choice, None)
     dt_g, lat = _time_graph(plan, f, u, steps, warmup)
     return dict(dt_eager=dt_e, prof=prof, dt_graph=dt_g, lat_graph=lat, tuning=gchoice, eager_tuning=choice,

@@ -207,7 +207,8 @@ typedef struct {
     int32_t far_children;   /* children accumulated per lane of that kernel: 0, 1, 2, 4, 8           */
     int32_t overlap;        /* schedule of a solve: 1 three concurrent branches (near field, level 1,
                                levels >= 2), 3 two (near field, levels >= 1), 2 one stream,
-                               0 default (three)                                                      */
+                               0 default (three).  With 3 and 2 the M2L of all levels with one
+                               tile size is one launch                                                */
 } lgf_tuning;
 
 /*

@@ -699,7 +699,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     hipStream_t s2 = overlap ? pl->far_stream : s;
     hipStream_t s3 = split ? pl->far_stream2 : s2;
     // forward work of level l: PadFFT and the M2L products (Steps 1-2)
-    auto level_up = [&](int l, hipStream_t st) -> hipError_t {
+    auto level_up = [&](int l, hipStream_t st, bool sib = true) -> hipError_t {
         LevelPlan& L = pl->lv[l];
         if (L.pairs() == 0) return hipSuccess;
         const double S1 = Sl(l);
@@ -718,7 +718,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
         if (L.zero_uhat)
             LGF_STEP(st, zero_fill(L.d_uhat, L.nint * Slp(l) * 2 * (int64_t)sizeof(T), st), lname("zero_uhat_l", l),
                      lvN(l) * S1 * cs, 0.0);
-        if (L.sib_pairs > 0) {
+        if (sib && L.sib_pairs > 0) {
             const LevelPlan& Pp = pl->lv[l + 1];
             LGF_STEP(st,
                      (launch_prod_far_sib<T>(fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216, (C*)L.d_uhat,
@@ -774,6 +774,11 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
         return hipSuccess;
     };
     if (pl->lat1 && (segs & kSegFwd0) && (e = fwd0()) != hipSuccess) return e;
+    // two branches: the level-0 transform goes first and the far field starts behind it.
+    // Its 16^3 tiles take most of a CU's LDS, so it cannot share CUs with the M2L; the
+    // far field then overlaps the level-0 Prod, whose LDS tile is small.
+    const bool fwd0_first = far && overlap && !split && !pl->lat1;
+    if (fwd0_first && (e = fwd0()) != hipSuccess) return e;
     if (far) {
         if (overlap) {
             if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
@@ -786,7 +791,52 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nsrc, n, p, s2)), "reg_l0_l1",
                      ns * (n3 + p3) * es, ns * 2.0 * (p * n3 + p * p * n * n + p3 * n));
         const bool coarse = pl->Ltop >= 2;
-        if (coarse && (segs & kSegCoarse)) {
+        // with one far stream and one tile size on every level, the coarse levels' M2L joins
+        // level 1's in one launch after all the levels' transforms (their small kernels would
+        // otherwise run nearly alone before the near field's large ones start)
+        const bool merge = all && !split && !pl->lat1 && coarse;
+        if (merge) {
+            for (int l = 1; l < pl->Ltop; ++l)
+                LGF_STEP(s2,
+                         (launch_reg_up<T>((const T*)pl->lv[l].d_ftil, pl->lv[l + 1].d_child8, pl->d_C01,
+                                           (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s2, pl->d_scratch)),
+                         "reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1),
+                         (lvN(l) + lvN(l + 1)) * p3 * es, lvN(l) * 2.0 * 3.0 * p3 * p);
+            for (int l = pl->Ltop; l >= 1; --l)
+                if ((e = level_up(l, s2, false)) != hipSuccess) return e;
+            std::vector<FarLevel<T>> fl;
+            double bytes = 0.0, flops = 0.0;
+            int lo = 0, hi = 0, S = 0;
+            for (int l = 1; l <= pl->Ltop; ++l) {
+                LevelPlan& L = pl->lv[l];
+                if (L.pairs() == 0 || L.sib_pairs == 0) continue;
+                if (S == 0) S = L.spectra->S;
+                if (L.spectra->S != S) return hipErrorInvalidValue;  // one tile size for all levels
+                const LevelPlan& Pp = pl->lv[l + 1];
+                fl.push_back(FarLevel<T>{(const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216,
+                                         (C*)L.d_uhat, Pp.nint, L.nint, L.nint});
+                bytes += ((double)L.nsrc_int + lvN(l) + 316.0) * Sl(l) * cs;
+                flops += (double)L.sib_pairs * Sl(l) * 8.0;
+                if (!lo) lo = l;
+                hi = l;
+            }
+            for (size_t k0 = 0; k0 < fl.size(); k0 += kMaxFarSegs) {
+                const int nk = (int)std::min<size_t>(kMaxFarSegs, fl.size() - k0);
+                const std::string nm = fl.size() == 1 ? lname("prod_l", lo)
+                                                      : "prod_l" + std::to_string(lo) + "-" + std::to_string(hi);
+                LGF_STEP(s2,
+                         (launch_prod_far_sib_levels<T>(fl.data() + k0, nk, S, tc.far_waves,
+                                                        tc.far_children, s2)),
+                         nm, k0 == 0 ? bytes : 0.0, k0 == 0 ? flops : 0.0);
+            }
+            for (int l = pl->Ltop; l >= 2; --l) {
+                if ((e = level_down(l, s2)) != hipSuccess) return e;
+                if (l < pl->Ltop && (e = interp(l, s2)) != hipSuccess) return e;
+            }
+            if ((e = level_down(1, s2)) != hipSuccess) return e;
+            if ((e = interp(1, s2)) != hipSuccess) return e;
+        }
+        if (!merge && coarse && (segs & kSegCoarse)) {
             // levels >= 2 on s3: Reg up, their M2L, and the down pass to level 2
             if (split) {
                 if ((e = hipEventRecord(pl->ev_fork2, s2)) != hipSuccess) return e;
@@ -807,18 +857,18 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             if (split && (e = hipEventRecord(pl->ev_join2, s3)) != hipSuccess) return e;
         }
         // level 1 on s2
-        if (segs & kSegL1) {
+        if (!merge && (segs & kSegL1)) {
             if ((e = level_up(1, s2)) != hipSuccess) return e;
             if ((e = level_down(1, s2)) != hipSuccess) return e;
         }
-        if (coarse && (segs & kSegJoin)) {
+        if (!merge && coarse && (segs & kSegJoin)) {
             if (split && (e = hipStreamWaitEvent(s2, pl->ev_join2, 0)) != hipSuccess) return e;
             if ((e = interp(1, s2)) != hipSuccess) return e;
         }
         if (overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
     }
     // ---- near field (level 0) on the caller's stream
-    if (!pl->lat1 && (segs & kSegFwd0) && (e = fwd0()) != hipSuccess) return e;
+    if (!pl->lat1 && !fwd0_first && (segs & kSegFwd0) && (e = fwd0()) != hipSuccess) return e;
     if (segs & kSegNear) {
         LGF_STEP(s,
                  launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8,

@@ -22,6 +22,12 @@ namespace lgfdev {
 // {c : c % 8 == x}, walking every group of such a chunk back to back: all reuse of a source
 // spectrum within a chunk then stays in one L2.  Returns false for padding workgroups.
 constexpr int kXcds = 8;
+__device__ __forceinline__ bool xcd_tile_at(int L, int nchunks, int ngroupblocks, int& chunk, int& gblock) {
+    const int xcd = L % kXcds, k = L / kXcds;
+    chunk = (k / ngroupblocks) * kXcds + xcd;
+    gblock = k % ngroupblocks;
+    return chunk < nchunks;
+}
 __device__ __forceinline__ bool xcd_tile(int nchunks, int ngroupblocks, int& chunk, int& gblock) {
     const int L = blockIdx.x;
     const int xcd = L % kXcds, k = L / kXcds;
@@ -228,11 +234,29 @@ __device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fl, const int
     m2l_lane<T, CPL, Q>(fl, si, tk, live, ar, ai);
 }
 
+// One launch may cover several levels (segments of the grid, each with its own spectra,
+// lists and kernel spectra, all with the same spectrum size S): the coarse levels' small
+// M2L then runs inside the level-1 launch instead of as latency-bound launches of its own.
+// Segment k owns the workgroups [start_k, start_{k+1}); each start is a multiple of the
+// XCD count, so every segment keeps the XCD-aware chunk mapping.
+template <typename T>
+struct FarSeg {
+    const cplx<T>* fhat;
+    const cplx<T>* khat;
+    const int32_t* child8;
+    const int32_t* src216;
+    cplx<T>* uhat;
+    int nparents, nitems, nsrc, ngroupblocks, start;
+};
+template <typename T>
+struct FarSegs {
+    FarSeg<T> s[kMaxFarSegs];
+    int n;
+};
+
 template <typename T, int kFarWaves, int CPL>
 __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
-    k_prod_far_sib(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
-                   const int32_t* __restrict__ child8, const int32_t* __restrict__ src216,
-                   cplx<T>* __restrict__ uhat, int S, int nparents, int nitems, int nsrc) {
+    k_prod_far_sib(const FarSegs<T> segs, int S) {
     constexpr int F = M2LShape<T>::F;
     constexpr int PPW = M2LShape<T>::PPW;
     constexpr int NQ = 8 / CPL;             // waves per group of parents (one per child subset)
@@ -241,9 +265,20 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     __shared__ cplx<T> tile[343 * F];
     __shared__ int32_t sidx[PPG * 216];
     __shared__ uint32_t live[kFarWaves];  // per group of PPW parents: neighbours holding a source
+    // this workgroup's segment (uniform selects over the kernel arguments)
+    FarSeg<T> g = segs.s[0];
+#pragma unroll
+    for (int k = 1; k < kMaxFarSegs; ++k)
+        if (k < segs.n && (int)blockIdx.x >= segs.s[k].start) g = segs.s[k];
+    const cplx<T>* __restrict__ fhat = g.fhat;
+    const cplx<T>* __restrict__ khat = g.khat;
+    const int32_t* __restrict__ child8 = g.child8;
+    const int32_t* __restrict__ src216 = g.src216;
+    cplx<T>* __restrict__ uhat = g.uhat;
+    const int nparents = g.nparents, nitems = g.nitems, nsrc = g.nsrc;
     const int nchunks = (S + F - 1) / F;
     int chunk, pb;
-    if (!xcd_tile(nchunks, (nparents + PPG - 1) / PPG, chunk, pb)) return;
+    if (!xcd_tile_at((int)blockIdx.x - g.start, nchunks, g.ngroupblocks, chunk, pb)) return;
     const int w0 = chunk * F;
     for (int i = threadIdx.x; i < 343 * F; i += NT) {
         const int r = i / F, jj = i - r * F;
@@ -346,37 +381,43 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
 }
 
 template <typename T, int NW, int CPL>
-static hipError_t far_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
-                         cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc, int S, hipStream_t s) {
+static hipError_t far_nw(const FarLevel<T>* lv, int nlev, int S, hipStream_t s) {
     constexpr int F = M2LShape<T>::F, PPG = M2LShape<T>::PPW * NW;
-    const unsigned grid = xcd_grid((S + F - 1) / F, (int)((nparents + PPG - 1) / PPG));
-    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, fhat, khat,
-                       child8, src216, uhat, S, (int)nparents, (int)nitems, (int)nsrc);
+    const int nchunks = (S + F - 1) / F;
+    FarSegs<T> segs{};
+    unsigned grid = 0;
+    for (int k = 0; k < nlev; ++k) {
+        const int ngb = (int)((lv[k].nparents + PPG - 1) / PPG);
+        segs.s[k] = FarSeg<T>{lv[k].fhat,          lv[k].khat,         lv[k].child8, lv[k].src216,
+                              lv[k].uhat,          (int)lv[k].nparents, (int)lv[k].nitems,
+                              (int)lv[k].nsrc,     ngb,                 (int)grid};
+        grid += xcd_grid(nchunks, ngb);  // a multiple of the XCD count
+    }
+    segs.n = nlev;
+    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs, S);
     return hipGetLastError();
 }
 
 template <typename T, int CPL>
-static hipError_t far_cpl(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8, const int32_t* src216,
-                          cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc, int S, int waves,
-                          hipStream_t s) {
+static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int S, int waves, hipStream_t s) {
     // at most 16 waves (1024 threads) per workgroup, and at most 8 in FP64, whose pipeline
     // needs more than the 128 registers a lane gets in a 16-wave workgroup
     constexpr int kMaxWaves = sizeof(T) == 8 ? 8 : 16;
     constexpr int kMaxGroups = kMaxWaves / (8 / CPL) < 4 ? kMaxWaves / (8 / CPL) : 4;
     switch (waves < kMaxGroups ? waves : kMaxGroups) {
-        case 1: return far_nw<T, 1, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, s);
+        case 1: return far_nw<T, 1, CPL>(lv, nlev, S, s);
         case 4:
-            if constexpr (kMaxGroups >= 4)
-                return far_nw<T, 4, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, s);
+            if constexpr (kMaxGroups >= 4) return far_nw<T, 4, CPL>(lv, nlev, S, s);
             [[fallthrough]];
-        default: return far_nw<T, 2, CPL>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, s);
+        default: return far_nw<T, 2, CPL>(lv, nlev, S, s);
     }
 }
 
 // Variant when the plan leaves it open, from measurements on MI355X: levels with at least
 // 64 parents run 4 children per lane in 4 parent groups per workgroup; smaller levels run
-// 2 children per lane (more waves for little work) in 1 (FP64) or 2 (FP32) groups.  Every
-// variant computes the same bits.
+// 2 children per lane (more waves for little work) in 1 (FP64) or 2 (FP32) groups.  A
+// launch over several levels takes the variant of its largest level.  Every variant
+// computes the same bits.
 template <typename T>
 void m2l_default(int64_t nparents, int& waves, int& cpl) {
     const bool big = nparents >= 64;
@@ -385,17 +426,33 @@ void m2l_default(int64_t nparents, int& waves, int& cpl) {
 }
 
 template <typename T>
+hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int S, int waves, int cpl, hipStream_t s) {
+    int64_t most = 0;
+    int k = 0;
+    for (int i = 0; i < nlev; ++i) {
+        if (lv[i].nparents <= 0) continue;
+        if (k != i) return hipErrorInvalidValue;  // empty levels only at the end
+        most = lv[i].nparents > most ? lv[i].nparents : most;
+        ++k;
+    }
+    if (k == 0) return hipSuccess;
+    if (k > kMaxFarSegs) return hipErrorInvalidValue;
+    m2l_default<T>(most, waves, cpl);
+    switch (cpl) {
+        case 8: return far_cpl<T, 8>(lv, k, S, waves, s);
+        case 4: return far_cpl<T, 4>(lv, k, S, waves, s);
+        case 2: return far_cpl<T, 2>(lv, k, S, waves, s);
+        default: return far_cpl<T, 1>(lv, k, S, waves, s);
+    }
+}
+
+template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc,
                                int S, int waves, int cpl, hipStream_t s) {
     if (nparents <= 0) return hipSuccess;
-    m2l_default<T>(nparents, waves, cpl);
-    switch (cpl) {
-        case 8: return far_cpl<T, 8>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
-        case 4: return far_cpl<T, 4>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
-        case 2: return far_cpl<T, 2>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
-        default: return far_cpl<T, 1>(fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, waves, s);
-    }
+    const FarLevel<T> one{fhat, khat, child8, src216, uhat, nparents, nitems, nsrc};
+    return launch_prod_far_sib_levels<T>(&one, 1, S, waves, cpl, s);
 }
 
 template <typename T>
@@ -415,6 +472,7 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
                                             cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t);    \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
                                                cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t); \
+    template hipError_t launch_prod_far_sib_levels<T>(const FarLevel<T>*, int, int, int, int, hipStream_t);      \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \
                                            const int32_t*, const int32_t*, cplx<T>*, int64_t, int64_t, int, int, \
                                            hipStream_t, int64_t);
