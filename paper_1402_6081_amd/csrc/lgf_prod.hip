@@ -51,6 +51,20 @@ __device__ __forceinline__ void cmac(T& ar, T& ai, const cplx<T>& f, const cplx<
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Coefficient lane_off of item `item` in a frequency chunk whose items start at the
+// wave-uniform `base` (64 coefficients per item).  A 32-bit byte offset from a uniform base
+// lets the gather use a scalar base register plus one vector offset instead of 64-bit
+// address arithmetic per load (the launchers check that a chunk spans less than 4 GiB).
+template <typename T>
+__device__ __forceinline__ cplx<T> load_item(const cplx<T>* base, int item, int lane_off) {
+    const uint32_t off = ((uint32_t)item * 64u + (uint32_t)lane_off) * (uint32_t)sizeof(cplx<T>);
+    return *reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__host__ __forceinline__ bool chunk_fits_u32(int64_t items) {
+    return items * 64 * (int64_t)sizeof(cplx<T>) <= (int64_t)UINT32_MAX;
+}
+
 // ------------------------------------------------------------------ level 0
 // Groups g: tgt8[g][c] = block 2J + c (c = cx | cy<<1 | cz<<2) or -1;
 // src64[g][s] = source block 2J + (sx-1, sy-1, sz-1), s = sx + 4 sy + 16 sz, or the zero
@@ -85,7 +99,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         ai[c] = T(0);
     }
     const int32_t* sg = src64 + (int64_t)g * 64;
-    const cplx<T>* fl = fhat + (int64_t)chunk * (nsrc + 1) * 64 + lane;  // this lane's frequency
+    const cplx<T>* fbase = fhat + (int64_t)chunk * (nsrc + 1) * 64;  // this chunk's items (uniform)
     // source z slab sz contributes to target slab cz through kernel rows dz = cz - (sz - 1)
     auto slab = [&](int sz, const cplx<T>(&f)[16]) {
         const cplx<T>* t0 = tile + (9 * (3 - sz)) * 64 + lane;  // row base for cz = 0
@@ -106,15 +120,15 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         // the next slab's 16 source values are in flight while this slab is consumed
         cplx<T> fa[16], fb[16];
 #pragma unroll
-        for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = fl[(int64_t)sg[sxy] * 64];
+        for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load_item(fbase, sg[sxy], lane);
 #pragma unroll 1
         for (int sz = 0; sz < 4; sz += 2) {
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) fb[sxy] = fl[(int64_t)sg[(sz + 1) * 16 + sxy] * 64];
+            for (int sxy = 0; sxy < 16; ++sxy) fb[sxy] = load_item(fbase, sg[(sz + 1) * 16 + sxy], lane);
             slab(sz, fa);
             const int sn = sz + 2 < 4 ? sz + 2 : sz;  // past the end: a harmless reload
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = fl[(int64_t)sg[sn * 16 + sxy] * 64];
+            for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load_item(fbase, sg[sn * 16 + sxy], lane);
             slab(sz + 1, fb);
         }
     } else {
@@ -122,7 +136,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         for (int sz = 0; sz < 4; ++sz) {  // source z slab; x and y unrolled
             cplx<T> f[16];
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = fl[(int64_t)sg[sz * 16 + sxy] * 64];
+            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load_item(fbase, sg[sz * 16 + sxy], lane);
             slab(sz, f);
         }
     }
@@ -195,10 +209,11 @@ __device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], con
 }
 
 template <typename T>
-__device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fl, const int32_t* si, cplx<T> (&f)[8]) {
+__device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fb, int wl, const int32_t* si,
+                                         cplx<T> (&f)[8]) {
     const int ee = e < 27 ? e : 26;  // past the end: a harmless reload of the last neighbour
 #pragma unroll
-    for (int cs = 0; cs < 8; ++cs) f[cs] = fl[(int64_t)si[ee * 8 + cs] * 64];
+    for (int cs = 0; cs < 8; ++cs) f[cs] = load_item(fb, si[ee * 8 + cs], wl);
 }
 
 // Neighbours in order e = 0..26 through a three-buffer pipeline: the sources of e+1 and
@@ -206,32 +221,32 @@ __device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fl, 
 // live: wave-uniform mask, bit e set when neighbour e holds a source for some parent of
 // the wave.
 template <typename T, int CPL, int Q>
-__device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fl, const int32_t* si, const cplx<T>* tk,
-                                         uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
-    cplx<T> fa[8], fb[8], fc[8];
-    m2l_load<T>(0, fl, si, fa);
-    m2l_load<T>(1, fl, si, fb);
+__device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl, const int32_t* si,
+                                         const cplx<T>* tk, uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
+    cplx<T> fa[8], fbuf[8], fc[8];
+    m2l_load<T>(0, fb, wl, si, fa);
+    m2l_load<T>(1, fb, wl, si, fbuf);
 #pragma unroll 1
     for (int e = 0; e < 27; e += 3) {
-        m2l_load<T>(e + 2, fl, si, fc);
+        m2l_load<T>(e + 2, fb, wl, si, fc);
         if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
-        m2l_load<T>(e + 3, fl, si, fa);
-        if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fb, tk, ar, ai);
-        m2l_load<T>(e + 4, fl, si, fb);
+        m2l_load<T>(e + 3, fb, wl, si, fa);
+        if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
+        m2l_load<T>(e + 4, fb, wl, si, fbuf);
         if (live & (4u << e)) m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
     }
 }
 
 template <typename T, int CPL, int Q = 0>
-__device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fl, const int32_t* si, const cplx<T>* tk,
-                                             uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
+__device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fb, int wl, const int32_t* si,
+                                             const cplx<T>* tk, uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
     if constexpr (Q + 1 < 8 / CPL) {
         if (q != Q) {
-            m2l_dispatch<T, CPL, Q + 1>(q, fl, si, tk, live, ar, ai);
+            m2l_dispatch<T, CPL, Q + 1>(q, fb, wl, si, tk, live, ar, ai);
             return;
         }
     }
-    m2l_lane<T, CPL, Q>(fl, si, tk, live, ar, ai);
+    m2l_lane<T, CPL, Q>(fb, wl, si, tk, live, ar, ai);
 }
 
 // One launch may cover several levels (segments of the grid, each with its own spectra,
@@ -307,14 +322,15 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     const int Jl = pw * PPW + lane / F;
     const int J = pb * PPG + Jl;
     const int w = w0 + j;  // may exceed S in the last chunk: computed, never stored
-    const cplx<T>* fl = fhat + (int64_t)(w >> 6) * (nsrc + 1) * 64 + (w & 63);
+    const cplx<T>* fb = fhat + (int64_t)(w0 >> 6) * (nsrc + 1) * 64;  // this chunk's items (uniform)
     T ar[CPL], ai[CPL];
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
         ar[i] = T(0);
         ai[i] = T(0);
     }
-    m2l_dispatch<T, CPL>(q, fl, sidx + Jl * 216, tile + j, (uint32_t)wave_uniform((int)live[pw]), ar, ai);
+    m2l_dispatch<T, CPL>(q, fb, w & 63, sidx + Jl * 216, tile + j, (uint32_t)wave_uniform((int)live[pw]), ar,
+                         ai);
     if (J >= nparents || w >= S) return;
     const int32_t* c8 = child8 + (int64_t)J * 8 + q * CPL;
 #pragma unroll
@@ -375,7 +391,7 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
                             cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
                             int prefetch, hipStream_t s) {
     if (ngroups <= 0) return hipSuccess;
-    if (S % 64) return hipErrorInvalidValue;
+    if (S % 64 || !chunk_fits_u32<T>(nsrc + 1)) return hipErrorInvalidValue;
     return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s)
                     : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s);
 }
@@ -431,7 +447,7 @@ hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int S, in
     int k = 0;
     for (int i = 0; i < nlev; ++i) {
         if (lv[i].nparents <= 0) continue;
-        if (k != i) return hipErrorInvalidValue;  // empty levels only at the end
+        if (k != i || !chunk_fits_u32<T>(lv[i].nsrc + 1)) return hipErrorInvalidValue;  // empty levels only at the end
         most = lv[i].nparents > most ? lv[i].nparents : most;
         ++k;
     }
