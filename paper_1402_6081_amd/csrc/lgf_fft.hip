@@ -85,16 +85,38 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T
 // Inverse: spectrum elements of type Tin, arithmetic in A, real output of type Tout.
 // (FP64 path: all double.  FP32 path: float at level 0; at levels >= 1 float spectra are
 // inverted in float-float arithmetic and written as float-float node values.)
+// One launch may invert several levels' spectra (segments of the grid with their own
+// input, output and item count; one workgroup per item).
+template <typename Tin, typename Tout>
+struct InvSegs {
+    const cplx<Tin>* in[kMaxFarSegs];
+    Tout* out[kMaxFarSegs];
+    int64_t nbatch[kMaxFarSegs];
+    int64_t start[kMaxFarSegs];
+    int n;
+};
+
 template <typename Tin, typename A, typename Tout, int m, int M, int NT>
-__global__ void __launch_bounds__(NT) k_ifft_trunc(const cplx<Tin>* __restrict__ in, Tout* __restrict__ out,
-                                                   int64_t nbatch, const int32_t* __restrict__ out_map,
+__global__ void __launch_bounds__(NT) k_ifft_trunc(const InvSegs<Tin, Tout> segs, const int32_t* __restrict__ out_map,
                                                    int opitch) {
     constexpr int H = M / 2 + 1;
     constexpr int PLANE = M * H;
     static_assert(M == 2 * m, "padded length is twice the tile edge");
     __shared__ cplx<A> buf[m * PLANE];
     const int tid = threadIdx.x;
-    const size_t b = blockIdx.x;
+    // this workgroup's segment (uniform selects over the kernel arguments)
+    const cplx<Tin>* __restrict__ in = segs.in[0];
+    Tout* __restrict__ out = segs.out[0];
+    int64_t nbatch = segs.nbatch[0], b0 = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxFarSegs; ++k)
+        if (k < segs.n && (int64_t)blockIdx.x >= segs.start[k]) {
+            in = segs.in[k];
+            out = segs.out[k];
+            nbatch = segs.nbatch[k];
+            b0 = segs.start[k];
+        }
+    const size_t b = (size_t)((int64_t)blockIdx.x - b0);
 
     // z pass: HBM columns (ky, kx), kz < M -> z < m
     for (int col = tid; col < PLANE; col += NT) {
@@ -355,24 +377,35 @@ static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, int64_
 }
 
 template <typename Tin, typename A, typename Tout, int m, int NT>
-static hipError_t inv_mnt(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, int opitch,
+static hipError_t inv_mnt(const InvSegs<Tin, Tout>& segs, int64_t nblocks, const int32_t* out_map, int opitch,
                           hipStream_t s) {
-    hipLaunchKernelGGL((k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out,
-                       nbatch, out_map, opitch);
+    hipLaunchKernelGGL((k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>), dim3((unsigned)nblocks), dim3(NT), 0, s, segs,
+                       out_map, opitch);
     return hipGetLastError();
+}
+
+template <typename Tin, typename A, typename Tout, int m>
+static hipError_t launch_inv_segs(const InvSegs<Tin, Tout>& segs, int64_t nblocks, const int32_t* out_map,
+                                  int opitch, hipStream_t s, int nt = 0) {
+    if (opitch <= 0) opitch = m;
+    if constexpr ((m == 8 || m == 16) && !std::is_same<A, ff32>::value) {
+        if constexpr (!(m == 16 && sizeof(A) == 8))
+            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(segs, nblocks, out_map, opitch, s);
+        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(segs, nblocks, out_map, opitch, s);
+        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(segs, nblocks, out_map, opitch, s);
+    }
+    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(segs, nblocks, out_map, opitch, s);
 }
 
 template <typename Tin, typename A, typename Tout, int m>
 static hipError_t launch_inv_m(const cplx<Tin>* in, Tout* out, int64_t nbatch, const int32_t* out_map, int opitch,
                                hipStream_t s, int nt = 0) {
-    if (opitch <= 0) opitch = m;
-    if constexpr ((m == 8 || m == 16) && !std::is_same<A, ff32>::value) {
-        if constexpr (!(m == 16 && sizeof(A) == 8))
-            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(in, out, nbatch, out_map, opitch, s);
-        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(in, out, nbatch, out_map, opitch, s);
-        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(in, out, nbatch, out_map, opitch, s);
-    }
-    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, out_map, opitch, s);
+    InvSegs<Tin, Tout> segs{};
+    segs.in[0] = in;
+    segs.out[0] = out;
+    segs.nbatch[0] = nbatch;
+    segs.n = 1;
+    return launch_inv_segs<Tin, A, Tout, m>(segs, nbatch, out_map, opitch, s, nt);
 }
 
 template <typename T>
@@ -419,6 +452,39 @@ hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbat
         default: return hipErrorInvalidValue;
     }
 }
+
+template <typename Tin, typename A, typename Tout>
+hipError_t launch_ifft_trunc_levels(int m, const InvLevel<Tin, Tout>* lv, int nlev, hipStream_t s) {
+    if (nlev <= 0) return hipSuccess;
+    if (nlev > kMaxFarSegs) return hipErrorInvalidValue;
+    InvSegs<Tin, Tout> segs{};
+    int64_t nblocks = 0;
+    for (int k = 0; k < nlev; ++k) {
+        if (lv[k].nbatch <= 0) return hipErrorInvalidValue;
+        segs.in[k] = lv[k].in;
+        segs.out[k] = lv[k].out;
+        segs.nbatch[k] = lv[k].nbatch;
+        segs.start[k] = nblocks;
+        nblocks += lv[k].nbatch;
+    }
+    segs.n = nlev;
+    switch (m) {
+        case 2: return launch_inv_segs<Tin, A, Tout, 2>(segs, nblocks, nullptr, 0, s);
+        case 3: return launch_inv_segs<Tin, A, Tout, 3>(segs, nblocks, nullptr, 0, s);
+        case 4: return launch_inv_segs<Tin, A, Tout, 4>(segs, nblocks, nullptr, 0, s);
+        case 5: return launch_inv_segs<Tin, A, Tout, 5>(segs, nblocks, nullptr, 0, s);
+        case 6: return launch_inv_segs<Tin, A, Tout, 6>(segs, nblocks, nullptr, 0, s);
+        case 7: return launch_inv_segs<Tin, A, Tout, 7>(segs, nblocks, nullptr, 0, s);
+        case 8: return launch_inv_segs<Tin, A, Tout, 8>(segs, nblocks, nullptr, 0, s);
+        case 9: return launch_inv_segs<Tin, A, Tout, 9>(segs, nblocks, nullptr, 0, s);
+        case 10: return launch_inv_segs<Tin, A, Tout, 10>(segs, nblocks, nullptr, 0, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_ifft_trunc_levels<double, double, double>(int, const InvLevel<double, double>*, int,
+                                                                      hipStream_t);
+template hipError_t launch_ifft_trunc_levels<float, ff32, ff32>(int, const InvLevel<float, ff32>*, int, hipStream_t);
 
 template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t, int, int64_t,
                                            void*);

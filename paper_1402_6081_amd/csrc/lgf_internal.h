@@ -35,6 +35,16 @@ hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipS
 template <typename Tin, typename A, typename Tout>
 hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0,
                              const int32_t* out_map = nullptr, void* scratch = nullptr, int opitch = 0);
+// The same for several levels' spectra in one launch (tiles of m <= 10, outputs in item
+// order, at most kMaxFarSegs levels, each with nbatch > 0).
+template <typename Tin, typename Tout>
+struct InvLevel {
+    const cplx<Tin>* in;
+    Tout* out;
+    int64_t nbatch;
+};
+template <typename Tin, typename A, typename Tout>
+hipError_t launch_ifft_trunc_levels(int m, const InvLevel<Tin, Tout>* lv, int nlev, hipStream_t s);
 inline bool two_phase_tile(int m) { return m == 17; }
 inline int64_t two_phase_scratch_bytes(int m, int64_t nbatch) {
     return two_phase_tile(m) ? nbatch * (int64_t)m * (2 * m) * (m + 1) * 16 : 0;

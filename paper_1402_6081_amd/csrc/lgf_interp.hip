@@ -175,7 +175,8 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
 }
 
-// ------------------------------------------------------------------ large intervals (P = 17)
+// ------------------------------------------------------------------ one (parent, child) per workgroup
+// (every P = 17 level, and the Interp of levels with few parents at any P)
 // The kernels above hold 8 children, or a parent's 2 + 4 partial passes, in LDS (629 /
 // 275 KB at P = 17).  Here one workgroup handles one (parent, child) pair, which also
 // gives levels with few parents eight times the workgroups:
@@ -450,7 +451,14 @@ hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, 
 template <typename U, int P>
 static hipError_t interp_down_p(const U* par, const int32_t* child8, const double* C01, U* io, int64_t np,
                                 hipStream_t s) {
-    hipLaunchKernelGGL((k_interp_down<U, P>), dim3((unsigned)np), dim3(kInterpThreads), 0, s, par, child8, C01, io);
+    // levels with few parents: one workgroup per (parent, child), eight times the
+    // workgroups (the same sums in the same order, so the same bits as one per parent)
+    if (np <= 256)
+        hipLaunchKernelGGL((k_interp_down_one<U, P>), dim3((unsigned)(np * 8)), dim3(kInterpThreads), 0, s, par,
+                           child8, C01, io);
+    else
+        hipLaunchKernelGGL((k_interp_down<U, P>), dim3((unsigned)np), dim3(kInterpThreads), 0, s, par, child8, C01,
+                           io);
     return hipGetLastError();
 }
 

@@ -829,12 +829,32 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                                                         tc.far_children, s2)),
                          nm, k0 == 0 ? bytes : 0.0, k0 == 0 ? flops : 0.0);
             }
-            for (int l = pl->Ltop; l >= 2; --l) {
-                if ((e = level_down(l, s2)) != hipSuccess) return e;
-                if (l < pl->Ltop && (e = interp(l, s2)) != hipSuccess) return e;
+            // every level's inverse in one launch too (levels without list entries are zeroed),
+            // then Interp from the top down
+            std::vector<InvLevel<T, U>> il;
+            double ibytes = 0.0, iflops = 0.0;
+            int ilo = 0, ihi = 0;
+            for (int l = pl->Ltop; l >= 1; --l) {
+                LevelPlan& L = pl->lv[l];
+                if (L.pairs() == 0) {
+                    if ((e = level_down(l, s2)) != hipSuccess) return e;
+                    continue;
+                }
+                il.push_back(InvLevel<T, U>{(const C*)L.d_uhat, (U*)L.d_util, L.nint});
+                ibytes += lvN(l) * (Sl(l) * cs + p3 * us);
+                iflops += lvN(l) * fft_flops(2 * p);
+                ilo = l;
+                if (!ihi) ihi = l;
             }
-            if ((e = level_down(1, s2)) != hipSuccess) return e;
-            if ((e = interp(1, s2)) != hipSuccess) return e;
+            for (size_t k0 = 0; k0 < il.size(); k0 += kMaxFarSegs) {
+                const int nk = (int)std::min<size_t>(kMaxFarSegs, il.size() - k0);
+                const std::string nm = il.size() == 1 ? lname("fft_inv_l", ilo)
+                                                      : "fft_inv_l" + std::to_string(ilo) + "-" + std::to_string(ihi);
+                LGF_STEP(s2, (launch_ifft_trunc_levels<T, U, U>(p, il.data() + k0, nk, s2)), nm,
+                         k0 == 0 ? ibytes : 0.0, k0 == 0 ? iflops : 0.0);
+            }
+            for (int l = pl->Ltop - 1; l >= 1; --l)
+                if ((e = interp(l, s2)) != hipSuccess) return e;
         }
         if (!merge && coarse && (segs & kSegCoarse)) {
             // levels >= 2 on s3: Reg up, their M2L, and the down pass to level 2
