@@ -18,23 +18,25 @@ constexpr int kInterpThreads = 256;
 
 // ------------------------------------------------------------------ block -> level 1
 // One workgroup per block: the block is staged in LDS with coalesced loads, then the
-// three passes run from LDS with compile-time extents.
+// three passes run from LDS with compile-time extents.  Rows that a wave reads at several
+// indices at once (the block's x rows, the matrix rows) are padded to N + 1 values, so
+// the reads fall into different LDS banks.
 template <typename T, int N, int P>
 __global__ void __launch_bounds__(kInterpThreads)
     k_reg_block(const T* __restrict__ f, const double* __restrict__ A, T* __restrict__ out) {
-    constexpr int N3 = N * N * N, P3 = P * P * P;
-    __shared__ T X[N3], t1[N * N * P], t2[N * P * P];
-    __shared__ T Am[P * N];
+    constexpr int N3 = N * N * N, P3 = P * P * P, NR = N + 1;
+    __shared__ T X[N * N * NR], t1[N * N * P], t2[N * P * P];
+    __shared__ T Am[P * NR];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    for (int i = tid; i < P * N; i += kInterpThreads) Am[i] = (T)A[i];
+    for (int i = tid; i < P * N; i += kInterpThreads) Am[(i / N) * NR + i % N] = (T)A[i];
     const T* src = f + b * N3;
-    for (int i = tid; i < N3; i += kInterpThreads) X[i] = src[i];
+    for (int i = tid; i < N3; i += kInterpThreads) X[(i / N) * NR + i % N] = src[i];
     __syncthreads();
     for (int i = tid; i < N * N * P; i += kInterpThreads) {  // x: t1[z][y][d]
         const int d = i % P, zy = i / P;
-        const T* row = X + zy * N;
-        const T* m = Am + d * N;
+        const T* row = X + zy * NR;
+        const T* m = Am + d * NR;
         T acc = T(0);
 #pragma unroll
         for (int x = 0; x < N; ++x) acc += m[x] * row[x];
@@ -43,7 +45,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     __syncthreads();
     for (int i = tid; i < N * P * P; i += kInterpThreads) {  // y: t2[z][c][d]
         const int d = i % P, c = (i / P) % P, z = i / (P * P);
-        const T* m = Am + c * N;
+        const T* m = Am + c * NR;
         const T* col = t1 + z * N * P + d;
         T acc = T(0);
 #pragma unroll
@@ -54,7 +56,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     T* o = out + b * P3;
     for (int i = tid; i < P3; i += kInterpThreads) {  // z: out[a][c][d]
         const int cd = i % (P * P), a = i / (P * P);
-        const T* m = Am + a * N;
+        const T* m = Am + a * NR;
         T acc = T(0);
 #pragma unroll
         for (int z = 0; z < N; ++z) acc += m[z] * t2[z * (P * P) + cd];
@@ -310,22 +312,23 @@ template <typename T, typename U, int N, int P>
 __global__ void __launch_bounds__(kInterpThreads)
     k_final(const T* vnear, const U* __restrict__ ut, const double* __restrict__ A, T* u,
             const int32_t* __restrict__ l1map, const int32_t* __restrict__ near_flag) {
-    constexpr int N3 = N * N * N, P3 = P * P * P;
-    __shared__ double X[P3], t1[P * P * N], t2[P * N * N];
-    __shared__ double At[N * P];  // At[j][k] = A[k][j]
+    constexpr int N3 = N * N * N, P3 = P * P * P, PR = P + 1;
+    // rows read at several indices at once by a wave are padded to P + 1 values (LDS banks)
+    __shared__ double X[P * P * PR], t1[P * P * N], t2[P * N * N];
+    __shared__ double At[N * PR];  // At[j][k] = A[k][j]
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     for (int i = tid; i < N * P; i += kInterpThreads) {
         const int jj = i / P, k = i % P;
-        At[i] = A[k * N + jj];
+        At[jj * PR + k] = A[k * N + jj];
     }
     const int64_t q = l1map ? (int64_t)l1map[b] : b;  // level-1 interval of this block
-    for (int i = tid; i < P3; i += kInterpThreads) X[i] = to_double(ut[q * P3 + i]);
+    for (int i = tid; i < P3; i += kInterpThreads) X[(i / P) * PR + i % P] = to_double(ut[q * P3 + i]);
     __syncthreads();
     for (int i = tid; i < P * P * N; i += kInterpThreads) {  // x: t1[a][c][x]
         const int x = i % N, ac = i / N;
-        const double* m = At + x * P;
-        const double* row = X + ac * P;
+        const double* m = At + x * PR;
+        const double* row = X + ac * PR;
         double acc = 0.0;
 #pragma unroll
         for (int d = 0; d < P; ++d) acc += m[d] * row[d];
@@ -334,7 +337,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     __syncthreads();
     for (int i = tid; i < P * N * N; i += kInterpThreads) {  // y: t2[a][y][x]
         const int x = i % N, y = (i / N) % N, a = i / (N * N);
-        const double* m = At + y * P;
+        const double* m = At + y * PR;
         const double* col = t1 + a * P * N + x;
         double acc = 0.0;
 #pragma unroll
@@ -347,7 +350,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     T* o = u + b * N3;
     for (int i = tid; i < N3; i += kInterpThreads) {  // z: u[z][y][x]
         const int yx = i % (N * N), z = i / (N * N);
-        const double* m = At + z * P;
+        const double* m = At + z * PR;
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < P; ++a) acc += m[a] * t2[a * N * N + yx];
