@@ -15,15 +15,37 @@
 
 namespace lgfdev {
 
+// One launch may transform several levels' tiles (segments of the grid with their own
+// input, output and output item count; one workgroup per item).
+template <typename T>
+struct FwdSegs {
+    const T* in[kMaxFarSegs];
+    cplx<T>* out[kMaxFarSegs];
+    int64_t nout[kMaxFarSegs];
+    int64_t start[kMaxFarSegs];
+    int n;
+};
+
 template <typename T, int m, int M, int NT>
-__global__ void __launch_bounds__(NT) k_pad_fft(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                int64_t nout) {
+__global__ void __launch_bounds__(NT) k_pad_fft(const FwdSegs<T> segs) {
     constexpr int H = M / 2 + 1;
     constexpr int PLANE = M * H;
     static_assert(M == 2 * m, "padded length is twice the tile edge");
     __shared__ cplx<T> buf[m * PLANE];
     const int tid = threadIdx.x;
-    const size_t b = blockIdx.x;
+    // this workgroup's segment (uniform selects over the kernel arguments)
+    const T* __restrict__ in = segs.in[0];
+    cplx<T>* __restrict__ out = segs.out[0];
+    int64_t nout = segs.nout[0], b0 = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxFarSegs; ++k)
+        if (k < segs.n && (int64_t)blockIdx.x >= segs.start[k]) {
+            in = segs.in[k];
+            out = segs.out[k];
+            nout = segs.nout[k];
+            b0 = segs.start[k];
+        }
+    const size_t b = (size_t)((int64_t)blockIdx.x - b0);
     const T* src = in + b * (m * m * m);
 
     // stage the real tile: plane z -> upper ky half of LDS plane z
@@ -359,21 +381,31 @@ static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, 
 // among {128, 256, 512} for the level-0 tiles (m = 8, 16).  512 threads are not offered for
 // the FP64 16^3 tile, whose 32-point pencils then no longer fit the register file.
 template <typename T, int m, int NT>
-static hipError_t fwd_mnt(const T* in, cplx<T>* out, int64_t nbatch, int64_t nout, hipStream_t s) {
-    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nbatch), dim3(NT), 0, s, in, out, nout);
+static hipError_t fwd_mnt(const FwdSegs<T>& segs, int64_t nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nblocks), dim3(NT), 0, s, segs);
     return hipGetLastError();
+}
+
+template <typename T, int m>
+static hipError_t launch_fwd_segs(const FwdSegs<T>& segs, int64_t nblocks, hipStream_t s, int nt = 0) {
+    if constexpr (m == 8 || m == 16) {
+        if constexpr (!(m == 16 && sizeof(T) == 8))
+            if (nt == 512) return fwd_mnt<T, m, 512>(segs, nblocks, s);
+        if (nt == 128 && m >= 12) return fwd_mnt<T, m, 128>(segs, nblocks, s);
+        if (nt == 256 && m < 12) return fwd_mnt<T, m, 256>(segs, nblocks, s);
+    }
+    return fwd_mnt<T, m, (m >= 12 ? 256 : 128)>(segs, nblocks, s);
 }
 
 template <typename T, int m>
 static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, int64_t nout, hipStream_t s,
                                int nt = 0) {
-    if constexpr (m == 8 || m == 16) {
-        if constexpr (!(m == 16 && sizeof(T) == 8))
-            if (nt == 512) return fwd_mnt<T, m, 512>(in, out, nbatch, nout, s);
-        if (nt == 128 && m >= 12) return fwd_mnt<T, m, 128>(in, out, nbatch, nout, s);
-        if (nt == 256 && m < 12) return fwd_mnt<T, m, 256>(in, out, nbatch, nout, s);
-    }
-    return fwd_mnt<T, m, (m >= 12 ? 256 : 128)>(in, out, nbatch, nout, s);
+    FwdSegs<T> segs{};
+    segs.in[0] = in;
+    segs.out[0] = out;
+    segs.nout[0] = nout;
+    segs.n = 1;
+    return launch_fwd_segs<T, m>(segs, nbatch, s, nt);
 }
 
 template <typename Tin, typename A, typename Tout, int m, int NT>
@@ -452,6 +484,38 @@ hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbat
         default: return hipErrorInvalidValue;
     }
 }
+
+template <typename T>
+hipError_t launch_pad_fft_levels(int m, const FwdLevel<T>* lv, int nlev, hipStream_t s) {
+    if (nlev <= 0) return hipSuccess;
+    if (nlev > kMaxFarSegs) return hipErrorInvalidValue;
+    FwdSegs<T> segs{};
+    int64_t nblocks = 0;
+    for (int k = 0; k < nlev; ++k) {
+        if (lv[k].nbatch <= 0) return hipErrorInvalidValue;
+        segs.in[k] = lv[k].in;
+        segs.out[k] = lv[k].out;
+        segs.nout[k] = lv[k].nout > 0 ? lv[k].nout : lv[k].nbatch + 1;
+        segs.start[k] = nblocks;
+        nblocks += lv[k].nbatch;
+    }
+    segs.n = nlev;
+    switch (m) {
+        case 2: return launch_fwd_segs<T, 2>(segs, nblocks, s);
+        case 3: return launch_fwd_segs<T, 3>(segs, nblocks, s);
+        case 4: return launch_fwd_segs<T, 4>(segs, nblocks, s);
+        case 5: return launch_fwd_segs<T, 5>(segs, nblocks, s);
+        case 6: return launch_fwd_segs<T, 6>(segs, nblocks, s);
+        case 7: return launch_fwd_segs<T, 7>(segs, nblocks, s);
+        case 8: return launch_fwd_segs<T, 8>(segs, nblocks, s);
+        case 9: return launch_fwd_segs<T, 9>(segs, nblocks, s);
+        case 10: return launch_fwd_segs<T, 10>(segs, nblocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_pad_fft_levels<double>(int, const FwdLevel<double>*, int, hipStream_t);
+template hipError_t launch_pad_fft_levels<float>(int, const FwdLevel<float>*, int, hipStream_t);
 
 template <typename Tin, typename A, typename Tout>
 hipError_t launch_ifft_trunc_levels(int m, const InvLevel<Tin, Tout>* lv, int nlev, hipStream_t s) {

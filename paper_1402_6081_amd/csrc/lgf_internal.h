@@ -35,6 +35,16 @@ hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipS
 template <typename Tin, typename A, typename Tout>
 hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt = 0,
                              const int32_t* out_map = nullptr, void* scratch = nullptr, int opitch = 0);
+// Forward transforms of several levels in one launch (tiles of m <= 10; nout as above,
+// 0 = nbatch + 1; at most kMaxFarSegs levels, each with nbatch > 0).
+template <typename T>
+struct FwdLevel {
+    const T* in;
+    cplx<T>* out;
+    int64_t nbatch, nout;
+};
+template <typename T>
+hipError_t launch_pad_fft_levels(int m, const FwdLevel<T>* lv, int nlev, hipStream_t s);
 // The same for several levels' spectra in one launch (tiles of m <= 10, outputs in item
 // order, at most kMaxFarSegs levels, each with nbatch > 0).
 template <typename Tin, typename Tout>

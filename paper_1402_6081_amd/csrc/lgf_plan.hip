@@ -699,7 +699,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     hipStream_t s2 = overlap ? pl->far_stream : s;
     hipStream_t s3 = split ? pl->far_stream2 : s2;
     // forward work of level l: PadFFT and the M2L products (Steps 1-2)
-    auto level_up = [&](int l, hipStream_t st, bool sib = true) -> hipError_t {
+    auto level_up = [&](int l, hipStream_t st, bool sib = true, bool fwd = true) -> hipError_t {
         LevelPlan& L = pl->lv[l];
         if (L.pairs() == 0) return hipSuccess;
         const double S1 = Sl(l);
@@ -708,7 +708,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
         const bool reuse0 = l == 1 && pl->lat1;
         const C* fhat = reuse0 ? (const C*)pl->d_fhat0 : (const C*)L.d_fhat;
         const int64_t nsrc_items = reuse0 ? pl->nsrc : L.nint;
-        if (!reuse0) {
+        if (!reuse0 && fwd) {
             // level 1: the sources come first and are the only intervals the lists read
             const int64_t nfwd = l == 1 ? pl->nsrc : L.nint;
             LGF_STEP(st,
@@ -802,8 +802,31 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                                            (T*)pl->lv[l + 1].d_ftil, pl->lv[l + 1].nint, p, s2, pl->d_scratch)),
                          "reg_l" + std::to_string(l) + "_l" + std::to_string(l + 1),
                          (lvN(l) + lvN(l + 1)) * p3 * es, lvN(l) * 2.0 * 3.0 * p3 * p);
+            // every level's forward transform in one launch, then the zero fills and top-level
+            // lists level by level
+            std::vector<FwdLevel<T>> fw;
+            double fbytes = 0.0, fflops = 0.0;
+            int flo = 0, fhi = 0;
+            for (int l = pl->Ltop; l >= 1; --l) {
+                LevelPlan& L = pl->lv[l];
+                if (L.pairs() == 0) continue;
+                const int64_t nfwd = l == 1 ? pl->nsrc : L.nint;  // level 1: the source intervals
+                if (nfwd <= 0) continue;
+                fw.push_back(FwdLevel<T>{(const T*)L.d_ftil, (C*)L.d_fhat, nfwd, L.nint + 1});
+                fbytes += (double)nfwd * (p3 * es + Sl(l) * cs);
+                fflops += (double)nfwd * fft_flops(2 * p);
+                flo = l;
+                if (!fhi) fhi = l;
+            }
+            for (size_t k0 = 0; k0 < fw.size(); k0 += kMaxFarSegs) {
+                const int nk = (int)std::min<size_t>(kMaxFarSegs, fw.size() - k0);
+                const std::string nm = fw.size() == 1 ? lname("fft_fwd_l", flo)
+                                                      : "fft_fwd_l" + std::to_string(flo) + "-" + std::to_string(fhi);
+                LGF_STEP(s2, (launch_pad_fft_levels<T>(p, fw.data() + k0, nk, s2)), nm, k0 == 0 ? fbytes : 0.0,
+                         k0 == 0 ? fflops : 0.0);
+            }
             for (int l = pl->Ltop; l >= 1; --l)
-                if ((e = level_up(l, s2, false)) != hipSuccess) return e;
+                if ((e = level_up(l, s2, false, false)) != hipSuccess) return e;
             std::vector<FarLevel<T>> fl;
             double bytes = 0.0, flops = 0.0;
             int lo = 0, hi = 0, S = 0;
