@@ -15,6 +15,13 @@
 namespace lgfdev {
 
 constexpr int kInterpThreads = 256;
+// Reg up runs one workgroup per parent over eight children: more waves per workgroup
+// hide the latency of its few, long workgroups
+constexpr int kRegUpThreads = 1024;
+// the per-block transfers (Reg 0->1, the final pass)
+constexpr int kBlockThreads = 512;
+// Interp down (one workgroup per parent, or per (parent, child))
+constexpr int kDownThreads = 512;
 
 // ------------------------------------------------------------------ block -> level 1
 // One workgroup per block: the block is staged in LDS with coalesced loads, then the
@@ -22,18 +29,18 @@ constexpr int kInterpThreads = 256;
 // indices at once (the block's x rows, the matrix rows) are padded to N + 1 values, so
 // the reads fall into different LDS banks.
 template <typename T, int N, int P>
-__global__ void __launch_bounds__(kInterpThreads)
+__global__ void __launch_bounds__(kBlockThreads)
     k_reg_block(const T* __restrict__ f, const double* __restrict__ A, T* __restrict__ out) {
     constexpr int N3 = N * N * N, P3 = P * P * P, NR = N + 1;
     __shared__ T X[N * N * NR], t1[N * N * P], t2[N * P * P];
     __shared__ T Am[P * NR];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    for (int i = tid; i < P * N; i += kInterpThreads) Am[(i / N) * NR + i % N] = (T)A[i];
+    for (int i = tid; i < P * N; i += kBlockThreads) Am[(i / N) * NR + i % N] = (T)A[i];
     const T* src = f + b * N3;
-    for (int i = tid; i < N3; i += kInterpThreads) X[(i / N) * NR + i % N] = src[i];
+    for (int i = tid; i < N3; i += kBlockThreads) X[(i / N) * NR + i % N] = src[i];
     __syncthreads();
-    for (int i = tid; i < N * N * P; i += kInterpThreads) {  // x: t1[z][y][d]
+    for (int i = tid; i < N * N * P; i += kBlockThreads) {  // x: t1[z][y][d]
         const int d = i % P, zy = i / P;
         const T* row = X + zy * NR;
         const T* m = Am + d * NR;
@@ -43,7 +50,7 @@ __global__ void __launch_bounds__(kInterpThreads)
         t1[i] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < N * P * P; i += kInterpThreads) {  // y: t2[z][c][d]
+    for (int i = tid; i < N * P * P; i += kBlockThreads) {  // y: t2[z][c][d]
         const int d = i % P, c = (i / P) % P, z = i / (P * P);
         const T* m = Am + c * NR;
         const T* col = t1 + z * N * P + d;
@@ -54,7 +61,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
     __syncthreads();
     T* o = out + b * P3;
-    for (int i = tid; i < P3; i += kInterpThreads) {  // z: out[a][c][d]
+    for (int i = tid; i < P3; i += kBlockThreads) {  // z: out[a][c][d]
         const int cd = i % (P * P), a = i / (P * P);
         const T* m = Am + a * NR;
         T acc = T(0);
@@ -65,8 +72,8 @@ __global__ void __launch_bounds__(kInterpThreads)
 }
 
 // ------------------------------------------------------------------ children -> parent
-template <typename T, int P>
-__global__ void __launch_bounds__(kInterpThreads)
+template <typename T, int P, int NT = kRegUpThreads>
+__global__ void __launch_bounds__(NT)
     k_reg_up(const T* __restrict__ in, const int32_t* __restrict__ child8, const double* __restrict__ C01,
              T* __restrict__ out) {
     constexpr int P3 = P * P * P;
@@ -75,17 +82,17 @@ __global__ void __launch_bounds__(kInterpThreads)
     __shared__ int32_t ch[8];
     const int tid = threadIdx.x;
     const int64_t J = blockIdx.x;
-    for (int i = tid; i < 2 * P * P; i += kInterpThreads) Cm[i] = (T)C01[i];
+    for (int i = tid; i < 2 * P * P; i += NT) Cm[i] = (T)C01[i];
     if (tid < 8) ch[tid] = child8[J * 8 + tid];
     __syncthreads();
-    for (int i = tid; i < 8 * P3; i += kInterpThreads) {
+    for (int i = tid; i < 8 * P3; i += NT) {
         const int c = i / P3, r = i - c * P3;
         const int q = ch[c];
         X[i] = q >= 0 ? in[(int64_t)q * P3 + r] : T(0);
     }
     __syncthreads();
     // x: t1[c][z][y][d] = sum_x C_cx[d][x] X[c][z][y][x]
-    for (int i = tid; i < 8 * P3; i += kInterpThreads) {
+    for (int i = tid; i < 8 * P3; i += NT) {
         const int d = i % P, rest = i / P, c = i / P3;
         const T* m = Cm + (c & 1) * P * P + d * P;
         const T* row = X + rest * P;
@@ -96,7 +103,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
     __syncthreads();
     // y: X[c][z][b][d] = sum_y C_cy[b][y] t1[c][z][y][d]
-    for (int i = tid; i < 8 * P3; i += kInterpThreads) {
+    for (int i = tid; i < 8 * P3; i += NT) {
         const int d = i % P, bb = (i / P) % P, cz = i / (P * P), c = i / P3;
         const T* m = Cm + ((c >> 1) & 1) * P * P + bb * P;
         T s = T(0);
@@ -106,7 +113,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
     __syncthreads();
     // z and the sum over children: out[a][b][d] = sum_c sum_z C_cz[a][z] X[c][z][b][d]
-    for (int i = tid; i < P3; i += kInterpThreads) {
+    for (int i = tid; i < P3; i += NT) {
         const int bd = i % (P * P), a = i / (P * P);
         T s = T(0);
         for (int c = 0; c < 8; ++c) {
@@ -122,7 +129,7 @@ __global__ void __launch_bounds__(kInterpThreads)
 // ------------------------------------------------------------------ parent -> children
 // U is the down-pass value type (double or float-float).
 template <typename U, int P>
-__global__ void __launch_bounds__(kInterpThreads)
+__global__ void __launch_bounds__(kDownThreads)
     k_interp_down(const U* __restrict__ par, const int32_t* __restrict__ child8, const double* __restrict__ C01,
                   U* __restrict__ io) {
     constexpr int P3 = P * P * P;
@@ -131,15 +138,15 @@ __global__ void __launch_bounds__(kInterpThreads)
     __shared__ int32_t ch[8];
     const int tid = threadIdx.x;
     const int64_t J = blockIdx.x;
-    for (int i = tid; i < 2 * P * P; i += kInterpThreads) {
+    for (int i = tid; i < 2 * P * P; i += kDownThreads) {
         const int c = i / (P * P), r = i % (P * P), k = r / P, m = r % P;
         Ct[i] = U(C01[c * P * P + m * P + k]);
     }
     if (tid < 8) ch[tid] = child8[J * 8 + tid];
-    for (int i = tid; i < P3; i += kInterpThreads) X[i] = par[J * P3 + i];
+    for (int i = tid; i < P3; i += kDownThreads) X[i] = par[J * P3 + i];
     __syncthreads();
     // x for both cx: t1[cx][a][b][x'] = sum_d Ct_cx[x'][d] X[a][b][d]
-    for (int i = tid; i < 2 * P3; i += kInterpThreads) {
+    for (int i = tid; i < 2 * P3; i += kDownThreads) {
         const int xo = i % P, ab = (i / P) % (P * P), cx = i / P3;
         const U* m = Ct + cx * P * P + xo * P;
         const U* row = X + ab * P;
@@ -150,7 +157,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
     __syncthreads();
     // y for both cy: t2[cy][cx][a][y'][x'] = sum_b Ct_cy[y'][b] t1[cx][a][b][x']
-    for (int i = tid; i < 4 * P3; i += kInterpThreads) {
+    for (int i = tid; i < 4 * P3; i += kDownThreads) {
         const int xo = i % P, yo = (i / P) % P, a = (i / (P * P)) % P, cx = (i / P3) & 1, cy = i / (2 * P3);
         const U* m = Ct + cy * P * P + yo * P;
         const U* src = t1 + cx * P3 + a * P * P + xo;
@@ -161,7 +168,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     }
     __syncthreads();
     // z per child, accumulate into the child's node values
-    for (int i = tid; i < 8 * P3; i += kInterpThreads) {
+    for (int i = tid; i < 8 * P3; i += kDownThreads) {
         const int r = i % P3, c = i / P3;
         const int q = ch[c];
         if (q < 0) continue;
@@ -245,7 +252,7 @@ __global__ void __launch_bounds__(kInterpThreads)
 }
 
 template <typename U, int P>
-__global__ void __launch_bounds__(kInterpThreads)
+__global__ void __launch_bounds__(kDownThreads)
     k_interp_down_one(const U* __restrict__ par, const int32_t* __restrict__ child8, const double* __restrict__ C01,
                       U* __restrict__ io) {
     constexpr int P3 = P * P * P;
@@ -257,13 +264,13 @@ __global__ void __launch_bounds__(kInterpThreads)
     const int q = child8[J * 8 + c];  // uniform
     if (q < 0) return;
     const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-    for (int i = tid; i < 2 * P * P; i += kInterpThreads) {
+    for (int i = tid; i < 2 * P * P; i += kDownThreads) {
         const int cc = i / (P * P), r = i % (P * P), k = r / P, m = r % P;
         Ct[i] = U(C01[cc * P * P + m * P + k]);
     }
-    for (int i = tid; i < P3; i += kInterpThreads) X[i] = par[J * P3 + i];
+    for (int i = tid; i < P3; i += kDownThreads) X[i] = par[J * P3 + i];
     __syncthreads();
-    for (int i = tid; i < P3; i += kInterpThreads) {  // x: t1[a][b][x']
+    for (int i = tid; i < P3; i += kDownThreads) {  // x: t1[a][b][x']
         const int xo = i % P, ab = i / P;
         const U* m = Ct + cx * P * P + xo * P;
         const U* row = X + ab * P;
@@ -273,7 +280,7 @@ __global__ void __launch_bounds__(kInterpThreads)
         t1[i] = sum;
     }
     __syncthreads();
-    for (int i = tid; i < P3; i += kInterpThreads) {  // y: t2[a][y'][x']
+    for (int i = tid; i < P3; i += kDownThreads) {  // y: t2[a][y'][x']
         const int xo = i % P, yo = (i / P) % P, a = i / (P * P);
         const U* m = Ct + cy * P * P + yo * P;
         const U* src = t1 + a * P * P + xo;
@@ -283,7 +290,7 @@ __global__ void __launch_bounds__(kInterpThreads)
         t2[i] = sum;
     }
     __syncthreads();
-    for (int i = tid; i < P3; i += kInterpThreads) {  // z, accumulated into the child
+    for (int i = tid; i < P3; i += kDownThreads) {  // z, accumulated into the child
         const int yx = i % (P * P), zo = i / (P * P);
         const U* m = Ct + cz * P * P + zo * P;
         U sum = U(0);
@@ -309,7 +316,7 @@ __global__ void k_pad_copy(const T* __restrict__ f, T* __restrict__ out, int64_t
 
 // ------------------------------------------------------------------ level 1 -> block, FP64 add-back
 template <typename T, typename U, int N, int P>
-__global__ void __launch_bounds__(kInterpThreads)
+__global__ void __launch_bounds__(kBlockThreads)
     k_final(const T* vnear, const U* __restrict__ ut, const double* __restrict__ A, T* u,
             const int32_t* __restrict__ l1map, const int32_t* __restrict__ near_flag) {
     constexpr int N3 = N * N * N, P3 = P * P * P, PR = P + 1;
@@ -318,14 +325,14 @@ __global__ void __launch_bounds__(kInterpThreads)
     __shared__ double At[N * PR];  // At[j][k] = A[k][j]
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    for (int i = tid; i < N * P; i += kInterpThreads) {
+    for (int i = tid; i < N * P; i += kBlockThreads) {
         const int jj = i / P, k = i % P;
         At[jj * PR + k] = A[k * N + jj];
     }
     const int64_t q = l1map ? (int64_t)l1map[b] : b;  // level-1 interval of this block
-    for (int i = tid; i < P3; i += kInterpThreads) X[(i / P) * PR + i % P] = to_double(ut[q * P3 + i]);
+    for (int i = tid; i < P3; i += kBlockThreads) X[(i / P) * PR + i % P] = to_double(ut[q * P3 + i]);
     __syncthreads();
-    for (int i = tid; i < P * P * N; i += kInterpThreads) {  // x: t1[a][c][x]
+    for (int i = tid; i < P * P * N; i += kBlockThreads) {  // x: t1[a][c][x]
         const int x = i % N, ac = i / N;
         const double* m = At + x * PR;
         const double* row = X + ac * PR;
@@ -335,7 +342,7 @@ __global__ void __launch_bounds__(kInterpThreads)
         t1[i] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < P * N * N; i += kInterpThreads) {  // y: t2[a][y][x]
+    for (int i = tid; i < P * N * N; i += kBlockThreads) {  // y: t2[a][y][x]
         const int x = i % N, y = (i / N) % N, a = i / (N * N);
         const double* m = At + y * PR;
         const double* col = t1 + a * P * N + x;
@@ -348,7 +355,7 @@ __global__ void __launch_bounds__(kInterpThreads)
     const T* v = vnear + b * N3;
     const bool has_near = !near_flag || near_flag[b];  // no near field: v is not read
     T* o = u + b * N3;
-    for (int i = tid; i < N3; i += kInterpThreads) {  // z: u[z][y][x]
+    for (int i = tid; i < N3; i += kBlockThreads) {  // z: u[z][y][x]
         const int yx = i % (N * N), z = i / (N * N);
         const double* m = At + z * PR;
         double acc = 0.0;
@@ -391,7 +398,7 @@ struct RegBlockRun {
     template <int N, int P>
     struct K {
         static hipError_t run(const T* f, const double* A, T* out, int64_t nb, hipStream_t s) {
-            hipLaunchKernelGGL((k_reg_block<T, N, P>), dim3((unsigned)nb), dim3(kInterpThreads), 0, s, f, A, out);
+            hipLaunchKernelGGL((k_reg_block<T, N, P>), dim3((unsigned)nb), dim3(kBlockThreads), 0, s, f, A, out);
             return hipGetLastError();
         }
     };
@@ -403,7 +410,7 @@ struct FinalRun {
     struct K {
         static hipError_t run(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, const int32_t* l1map,
                               const int32_t* near_flag, hipStream_t s) {
-            hipLaunchKernelGGL((k_final<T, U, N, P>), dim3((unsigned)nb), dim3(kInterpThreads), 0, s, vnear, ut, A,
+            hipLaunchKernelGGL((k_final<T, U, N, P>), dim3((unsigned)nb), dim3(kBlockThreads), 0, s, vnear, ut, A,
                                u, l1map, near_flag);
             return hipGetLastError();
         }
@@ -418,7 +425,7 @@ hipError_t launch_reg_block(const T* f, const double* A, T* out, int64_t nb, int
 
 template <typename T, int P>
 static hipError_t reg_up_p(const T* in, const int32_t* child8, const double* C01, T* out, int64_t np, hipStream_t s) {
-    hipLaunchKernelGGL((k_reg_up<T, P>), dim3((unsigned)np), dim3(kInterpThreads), 0, s, in, child8, C01, out);
+    hipLaunchKernelGGL((k_reg_up<T, P>), dim3((unsigned)np), dim3(kRegUpThreads), 0, s, in, child8, C01, out);
     return hipGetLastError();
 }
 
@@ -457,10 +464,10 @@ static hipError_t interp_down_p(const U* par, const int32_t* child8, const doubl
     // levels with few parents: one workgroup per (parent, child), eight times the
     // workgroups (the same sums in the same order, so the same bits as one per parent)
     if (np <= 256)
-        hipLaunchKernelGGL((k_interp_down_one<U, P>), dim3((unsigned)(np * 8)), dim3(kInterpThreads), 0, s, par,
+        hipLaunchKernelGGL((k_interp_down_one<U, P>), dim3((unsigned)(np * 8)), dim3(kDownThreads), 0, s, par,
                            child8, C01, io);
     else
-        hipLaunchKernelGGL((k_interp_down<U, P>), dim3((unsigned)np), dim3(kInterpThreads), 0, s, par, child8, C01,
+        hipLaunchKernelGGL((k_interp_down<U, P>), dim3((unsigned)np), dim3(kDownThreads), 0, s, par, child8, C01,
                            io);
     return hipGetLastError();
 }
@@ -480,7 +487,7 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
         case 9: return interp_down_p<U, 9>(par, child8, C01, io, nparent, s);
         case 10: return interp_down_p<U, 10>(par, child8, C01, io, nparent, s);
         case 17:
-            hipLaunchKernelGGL((k_interp_down_one<U, 17>), dim3((unsigned)(nparent * 8)), dim3(kInterpThreads), 0, s,
+            hipLaunchKernelGGL((k_interp_down_one<U, 17>), dim3((unsigned)(nparent * 8)), dim3(kDownThreads), 0, s,
                                par, child8, C01, io);
             return hipGetLastError();
         default: return hipErrorInvalidValue;
