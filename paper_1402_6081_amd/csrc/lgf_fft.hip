@@ -377,7 +377,8 @@ static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, 
     return hipGetLastError();
 }
 
-// nt: threads per workgroup (0 = default: 256 for m >= 12, else 128); the autotuner picks
+// nt: threads per workgroup (0 = default: 256, measured faster than 128 for the small
+// tiles of levels >= 1 as well); the autotuner picks
 // among {128, 256, 512} for the level-0 tiles (m = 8, 16).  512 threads are not offered for
 // the FP64 16^3 tile, whose 32-point pencils then no longer fit the register file.
 template <typename T, int m, int NT>
@@ -391,10 +392,9 @@ static hipError_t launch_fwd_segs(const FwdSegs<T>& segs, int64_t nblocks, hipSt
     if constexpr (m == 8 || m == 16) {
         if constexpr (!(m == 16 && sizeof(T) == 8))
             if (nt == 512) return fwd_mnt<T, m, 512>(segs, nblocks, s);
-        if (nt == 128 && m >= 12) return fwd_mnt<T, m, 128>(segs, nblocks, s);
-        if (nt == 256 && m < 12) return fwd_mnt<T, m, 256>(segs, nblocks, s);
+        if (nt == 128) return fwd_mnt<T, m, 128>(segs, nblocks, s);
     }
-    return fwd_mnt<T, m, (m >= 12 ? 256 : 128)>(segs, nblocks, s);
+    return fwd_mnt<T, m, 256>(segs, nblocks, s);
 }
 
 template <typename T, int m>
@@ -423,10 +423,9 @@ static hipError_t launch_inv_segs(const InvSegs<Tin, Tout>& segs, int64_t nblock
     if constexpr ((m == 8 || m == 16) && !std::is_same<A, ff32>::value) {
         if constexpr (!(m == 16 && sizeof(A) == 8))
             if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(segs, nblocks, out_map, opitch, s);
-        if (nt == 128 && m >= 12) return inv_mnt<Tin, A, Tout, m, 128>(segs, nblocks, out_map, opitch, s);
-        if (nt == 256 && m < 12) return inv_mnt<Tin, A, Tout, m, 256>(segs, nblocks, out_map, opitch, s);
+        if (nt == 128) return inv_mnt<Tin, A, Tout, m, 128>(segs, nblocks, out_map, opitch, s);
     }
-    return inv_mnt<Tin, A, Tout, m, (m >= 12 ? 256 : 128)>(segs, nblocks, out_map, opitch, s);
+    return inv_mnt<Tin, A, Tout, m, 256>(segs, nblocks, out_map, opitch, s);
 }
 
 template <typename Tin, typename A, typename Tout, int m>
