@@ -216,24 +216,42 @@ __device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fb, 
     for (int cs = 0; cs < 8; ++cs) f[cs] = load_item(fb, si[ee * 8 + cs], wl);
 }
 
-// Neighbours in order e = 0..26 through a three-buffer pipeline: the sources of e+1 and
-// e+2 are in flight while e is consumed.
+// Neighbours in order e = 0..26 through a pipeline of source buffers: with three, the
+// sources of e+1 and e+2 are in flight while e is consumed.
 // live: wave-uniform mask, bit e set when neighbour e holds a source for some parent of
 // the wave.
 template <typename T, int CPL, int Q>
 __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl, const int32_t* si,
                                          const cplx<T>* tk, uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
-    cplx<T> fa[8], fbuf[8], fc[8];
-    m2l_load<T>(0, fb, wl, si, fa);
-    m2l_load<T>(1, fb, wl, si, fbuf);
+    if constexpr (sizeof(T) == 8 && CPL == 4) {
+        // two buffers: the next neighbour's sources are in flight while one is consumed.
+        // The FP64 four-children lane then needs 90 registers instead of 164, and two
+        // workgroups share a CU (measured 9-12% faster on the larger levels; the other
+        // variants keep three buffers, which measured faster for them)
+        cplx<T> fa[8], fbuf[8];
+        m2l_load<T>(0, fb, wl, si, fa);
 #pragma unroll 1
-    for (int e = 0; e < 27; e += 3) {
-        m2l_load<T>(e + 2, fb, wl, si, fc);
-        if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
-        m2l_load<T>(e + 3, fb, wl, si, fa);
-        if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
-        m2l_load<T>(e + 4, fb, wl, si, fbuf);
-        if (live & (4u << e)) m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
+        for (int e = 0; e < 27; e += 2) {
+            m2l_load<T>(e + 1, fb, wl, si, fbuf);
+            if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
+            if (e + 1 < 27) {
+                m2l_load<T>(e + 2, fb, wl, si, fa);
+                if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
+            }
+        }
+    } else {
+        cplx<T> fa[8], fbuf[8], fc[8];
+        m2l_load<T>(0, fb, wl, si, fa);
+        m2l_load<T>(1, fb, wl, si, fbuf);
+#pragma unroll 1
+        for (int e = 0; e < 27; e += 3) {
+            m2l_load<T>(e + 2, fb, wl, si, fc);
+            if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
+            m2l_load<T>(e + 3, fb, wl, si, fa);
+            if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
+            m2l_load<T>(e + 4, fb, wl, si, fbuf);
+            if (live & (4u << e)) m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
+        }
     }
 }
 
