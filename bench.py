@@ -447,8 +447,8 @@ def main():
     ap.add_argument("--breakdown", default=None, help="write the per-step breakdown JSON here")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported (the multi-GPU "
-              "sharding is a design note only)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU; --gpus %d is not supported (the solve is not sharded "
+              "across GPUs)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
