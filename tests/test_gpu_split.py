@@ -198,3 +198,36 @@ def test_split_rejects_mismatched_fields(L):
     info = plan.info()
     assert info["source_blocks"] == len(src) and info["eval_blocks"] == len(ev)
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_split_schedules_same_bits(L, prec):
+    # the one-stream schedules (overlap 2 and 3) run the levels' transforms and M2L as
+    # multi-level launches; the three-branch schedule launches level by level: same bits,
+    # eager and as graphs
+    rng = np.random.default_rng(71)
+    src, ev = W.split_sets("dilated", rng)
+    n, p = 8, 6
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = L.Plan(src, n, p, 0, prec, eval_blocks=ev)
+    f = torch.from_numpy(rng.standard_normal((len(src), n, n, n))).to("cuda:0", dt)
+    info = plan.info()
+    _say("case: split schedules", prec, "levels", info["levels"], "top", info["top_level"])
+    assert info["top_level"] >= 2  # several far levels: the merged launches have more than one segment
+    plan.set_tuning(overlap=1)
+    ref = plan.solve(f).clone()
+    torch.cuda.synchronize()
+    for ov in (2, 3):
+        plan.set_tuning(overlap=ov)
+        assert torch.equal(plan.solve(f), ref), ov
+        u = torch.empty(plan.out_shape(), dtype=dt, device="cuda:0")
+        g = plan.graph(f, u)
+        for _ in range(2):
+            u.fill_(float("nan"))
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(u, ref), ("graph", ov)
+            _ = plan.solve(f)  # eager work between replays
+            torch.cuda.synchronize()
+        g.close()
+    plan.close()
