@@ -302,3 +302,24 @@ def test_nonfinite_input_check(L, monkeypatch):
     monkeypatch.delenv("LGF_CHECK_FINITE")
     plan.close()
     assert torch.isfinite(good).all()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_schedules_same_bits(L, prec):
+    # a batch whose members have different depths: the union's top levels carry empty
+    # lists for the shallow members (zeroed fields) and the one-stream schedules launch
+    # the transforms and M2L of all levels at once; all three schedules give the same bits
+    _say("case: batch schedules", prec)
+    lays = _layouts(23, [60, 1, "cube2", 7, 200])
+    fs = _fields(lays, 8, 24)
+    bp = L.Plan.batch(lays, 8, 6, 0, prec)
+    f = torch.from_numpy(np.concatenate(fs)).to("cuda:0", bp.dtype)
+    bp.set_tuning(overlap=1)
+    ref = bp.solve(f).clone()
+    torch.cuda.synchronize()
+    for ov in (2, 3):
+        bp.set_tuning(overlap=ov)
+        got = bp.solve(f)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), ov
+    bp.close()
