@@ -118,6 +118,8 @@ lgf_status lgf_plan_estimate(const int32_t* block_ijk, int64_t nblocks, int32_t 
  * issued on another stream and has not finished: its one workspace would be shared),
  * LGF_ERR_DEVICE (launch failure).  With LGF_CHECK_FINITE=1 in the environment the input
  * is scanned first (synchronising hip_stream) and non-finite values give LGF_ERR_ARG.
+ * With LGF_SYNC_CHECK=1 every kernel launch of an eager solve is followed by a
+ * synchronisation, and a failure names its step in lgf_last_error (a debugging aid).
  */
 lgf_status lgf_solve(lgf_plan_t plan, const void* f, void* u, void* hip_stream);
 
