@@ -214,20 +214,20 @@ __device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], con
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fb, int wl, const int32_t* si,
+template <typename T, typename IdxT>
+__device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fb, int wl, const IdxT* si,
                                          cplx<T> (&f)[8]) {
     const int ee = e < 27 ? e : 26;  // past the end: a harmless reload of the last neighbour
 #pragma unroll
-    for (int cs = 0; cs < 8; ++cs) f[cs] = load_item(fb, si[ee * 8 + cs], wl);
+    for (int cs = 0; cs < 8; ++cs) f[cs] = load_item(fb, (int)si[ee * 8 + cs], wl);
 }
 
 // Neighbours in order e = 0..26 through a pipeline of source buffers: with three, the
 // sources of e+1 and e+2 are in flight while e is consumed.
 // live: wave-uniform mask, bit e set when neighbour e holds a source for some parent of
 // the wave.
-template <typename T, int CPL, int Q>
-__device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl, const int32_t* si,
+template <typename T, int CPL, int Q, typename IdxT>
+__device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl, const IdxT* si,
                                          const cplx<T>* tk, uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
     if constexpr (sizeof(T) == 8 && CPL == 4) {
         // two buffers: the next neighbour's sources are in flight while one is consumed.
@@ -235,42 +235,42 @@ __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl,
         // workgroups share a CU (measured 9-12% faster on the larger levels; the other
         // variants keep three buffers, which measured faster for them)
         cplx<T> fa[8], fbuf[8];
-        m2l_load<T>(0, fb, wl, si, fa);
+        m2l_load<T, IdxT>(0, fb, wl, si, fa);
 #pragma unroll 1
         for (int e = 0; e < 27; e += 2) {
-            m2l_load<T>(e + 1, fb, wl, si, fbuf);
+            m2l_load<T, IdxT>(e + 1, fb, wl, si, fbuf);
             if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
             if (e + 1 < 27) {
-                m2l_load<T>(e + 2, fb, wl, si, fa);
+                m2l_load<T, IdxT>(e + 2, fb, wl, si, fa);
                 if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
             }
         }
     } else {
         cplx<T> fa[8], fbuf[8], fc[8];
-        m2l_load<T>(0, fb, wl, si, fa);
-        m2l_load<T>(1, fb, wl, si, fbuf);
+        m2l_load<T, IdxT>(0, fb, wl, si, fa);
+        m2l_load<T, IdxT>(1, fb, wl, si, fbuf);
 #pragma unroll 1
         for (int e = 0; e < 27; e += 3) {
-            m2l_load<T>(e + 2, fb, wl, si, fc);
+            m2l_load<T, IdxT>(e + 2, fb, wl, si, fc);
             if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
-            m2l_load<T>(e + 3, fb, wl, si, fa);
+            m2l_load<T, IdxT>(e + 3, fb, wl, si, fa);
             if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
-            m2l_load<T>(e + 4, fb, wl, si, fbuf);
+            m2l_load<T, IdxT>(e + 4, fb, wl, si, fbuf);
             if (live & (4u << e)) m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
         }
     }
 }
 
-template <typename T, int CPL, int Q = 0>
-__device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fb, int wl, const int32_t* si,
+template <typename T, int CPL, int Q = 0, typename IdxT>
+__device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fb, int wl, const IdxT* si,
                                              const cplx<T>* tk, uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
     if constexpr (Q + 1 < 8 / CPL) {
         if (q != Q) {
-            m2l_dispatch<T, CPL, Q + 1>(q, fb, wl, si, tk, live, ar, ai);
+            m2l_dispatch<T, CPL, Q + 1, IdxT>(q, fb, wl, si, tk, live, ar, ai);
             return;
         }
     }
-    m2l_lane<T, CPL, Q>(fb, wl, si, tk, live, ar, ai);
+    m2l_lane<T, CPL, Q, IdxT>(fb, wl, si, tk, live, ar, ai);
 }
 
 // One launch may cover several levels (segments of the grid, each with its own spectra,
@@ -293,7 +293,7 @@ struct FarSegs {
     int n;
 };
 
-template <typename T, int kFarWaves, int CPL>
+template <typename T, int kFarWaves, int CPL, typename IdxT>
 __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     k_prod_far_sib(const FarSegs<T> segs, int S) {
     constexpr int F = M2LShape<T>::F;
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     constexpr int PPG = PPW * kFarWaves;    // parents per workgroup
     constexpr int NT = 64 * kFarWaves * NQ;
     __shared__ cplx<T> tile[343 * F];
-    __shared__ int32_t sidx[PPG * 216];
+    __shared__ IdxT sidx[PPG * 216];  // 16-bit when every level's items fit (less LDS)
     __shared__ uint32_t live[kFarWaves];  // per group of PPW parents: neighbours holding a source
     // this workgroup's segment (uniform selects over the kernel arguments)
     FarSeg<T> g = segs.s[0];
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     for (int i = threadIdx.x; i < PPG * 216; i += NT) {
         const int Jl = i / 216, k = i - Jl * 216;
         const int J = pb * PPG + Jl;
-        sidx[i] = J < nparents ? src216[(int64_t)J * 216 + k] : nsrc;  // padding parents read zeros
+        sidx[i] = (IdxT)(J < nparents ? src216[(int64_t)J * 216 + k] : nsrc);  // padding parents read zeros
     }
     if (threadIdx.x < kFarWaves) live[threadIdx.x] = 0u;
     __syncthreads();
@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
         bool any = false;
         for (int jl = g * PPW; jl < (g + 1) * PPW; ++jl)
 #pragma unroll
-            for (int cs = 0; cs < 8; ++cs) any |= sidx[jl * 216 + e * 8 + cs] != nsrc;
+            for (int cs = 0; cs < 8; ++cs) any |= (int)sidx[jl * 216 + e * 8 + cs] != nsrc;
         if (any) atomicOr(&live[g], 1u << e);
     }
     __syncthreads();
@@ -353,8 +353,8 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
         ar[i] = T(0);
         ai[i] = T(0);
     }
-    m2l_dispatch<T, CPL>(q, fb, w & 63, sidx + Jl * 216, tile + j, (uint32_t)wave_uniform((int)live[pw]), ar,
-                         ai);
+    m2l_dispatch<T, CPL, 0, IdxT>(q, fb, w & 63, sidx + Jl * 216, tile + j, (uint32_t)wave_uniform((int)live[pw]),
+                                  ar, ai);
     if (J >= nparents || w >= S) return;
     const int32_t* c8 = child8 + (int64_t)J * 8 + q * CPL;
 #pragma unroll
@@ -434,7 +434,18 @@ static hipError_t far_nw(const FarLevel<T>* lv, int nlev, int S, hipStream_t s) 
         grid += xcd_grid(nchunks, ngb);  // a multiple of the XCD count
     }
     segs.n = nlev;
-    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs, S);
+    // FP32: 16-bit list entries in LDS when every level's items (and the sentinel) fit,
+    // which lets three workgroups share a CU
+    if constexpr (sizeof(T) == 4) {
+        bool idx16 = true;
+        for (int k = 0; k < nlev; ++k) idx16 = idx16 && lv[k].nsrc < 65535;
+        if (idx16) {
+            hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL, uint16_t>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s,
+                               segs, S);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL, int32_t>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs, S);
     return hipGetLastError();
 }
 
@@ -453,13 +464,22 @@ static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int S, int waves, hip
     }
 }
 
-// Variant when the plan leaves it open, from measurements on MI355X: levels with at least
-// 64 parents run 4 children per lane in 4 parent groups per workgroup; smaller levels run
-// 2 children per lane (more waves for little work) in 1 (FP64) or 2 (FP32) groups.  A
-// launch over several levels takes the variant of its largest level.  Every variant
+// Variant when the plan leaves it open, from measurements on MI355X:
+//  * FP32 with 16-bit list entries: all 8 children per lane in 4 parent groups per
+//    workgroup at every level size (three workgroups share a CU; 64 -> 53 us for the
+//    128^3 M2L, 340 -> 283 us on the separate-set ring);
+//  * otherwise levels with at least 64 parents run 4 children per lane in 4 parent
+//    groups; smaller levels 2 children per lane (more waves for little work) in 1 (FP64)
+//    or 2 (FP32) groups.
+// A launch over several levels takes the variant of its largest level.  Every variant
 // computes the same bits.
 template <typename T>
-void m2l_default(int64_t nparents, int& waves, int& cpl) {
+void m2l_default(int64_t nparents, bool idx16, int& waves, int& cpl) {
+    if (sizeof(T) == 4 && idx16) {
+        if (waves == 0) waves = 4;
+        if (cpl == 0) cpl = 8;
+        return;
+    }
     const bool big = nparents >= 64;
     if (waves == 0) waves = big ? 4 : (sizeof(T) == 8 ? 1 : 2);
     if (cpl == 0) cpl = big ? 4 : 2;
@@ -469,15 +489,17 @@ template <typename T>
 hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int S, int waves, int cpl, hipStream_t s) {
     int64_t most = 0;
     int k = 0;
+    bool idx16 = true;
     for (int i = 0; i < nlev; ++i) {
         if (lv[i].nparents <= 0) continue;
         if (k != i || !chunk_fits_u32<T>(lv[i].nsrc + 1)) return hipErrorInvalidValue;  // empty levels only at the end
         most = lv[i].nparents > most ? lv[i].nparents : most;
+        idx16 = idx16 && lv[i].nsrc < 65535;
         ++k;
     }
     if (k == 0) return hipSuccess;
     if (k > kMaxFarSegs) return hipErrorInvalidValue;
-    m2l_default<T>(most, waves, cpl);
+    m2l_default<T>(most, idx16, waves, cpl);
     switch (cpl) {
         case 8: return far_cpl<T, 8>(lv, k, S, waves, s);
         case 4: return far_cpl<T, 4>(lv, k, S, waves, s);
