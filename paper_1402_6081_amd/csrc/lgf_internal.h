@@ -86,7 +86,7 @@ template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc,
                                int S, int waves, int cpl, hipStream_t s);
-// The same over several levels with one spectrum size S, in one launch (at most
+// The same over several levels in one launch, each with its own spectrum size S (at most
 // kMaxFarSegs levels, each with nparents > 0, in the order given).
 constexpr int kMaxFarSegs = 8;
 template <typename T>
@@ -97,9 +97,10 @@ struct FarLevel {
     const int32_t* src216;
     cplx<T>* uhat;
     int64_t nparents, nitems, nsrc;
+    int S;
 };
 template <typename T>
-hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int S, int waves, int cpl, hipStream_t s);
+hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves, int cpl, hipStream_t s);
 // Targets tgt[0..ntgt) from CSR lists (the top level of a truncated tree); fhat holds
 // nsrc + 1 items (nsrc < 0: nitems).
 template <typename T>

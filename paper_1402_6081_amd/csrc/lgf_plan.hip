@@ -791,10 +791,11 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nsrc, n, p, s2)), "reg_l0_l1",
                      ns * (n3 + p3) * es, ns * 2.0 * (p * n3 + p * p * n * n + p3 * n));
         const bool coarse = pl->Ltop >= 2;
-        // with one far stream and one tile size on every level, the coarse levels' M2L joins
-        // level 1's in one launch after all the levels' transforms (their small kernels would
-        // otherwise run nearly alone before the near field's large ones start)
-        const bool merge = all && !split && !pl->lat1 && coarse;
+        // with one far stream, the coarse levels' M2L joins level 1's in one launch after all
+        // the levels' transforms (their small kernels would otherwise run nearly alone before
+        // the near field's large ones start).  The transforms go out as one launch too, except
+        // in the lattice scheme, whose level 1 and two-phase levels keep their own launches.
+        const bool merge = all && !split && coarse;
         if (merge) {
             for (int l = 1; l < pl->Ltop; ++l)
                 LGF_STEP(s2,
@@ -805,9 +806,12 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             // every level's forward transform in one launch, then the zero fills and top-level
             // lists level by level
             std::vector<FwdLevel<T>> fw;
+            if (pl->lat1)
+                for (int l = pl->Ltop; l >= 1; --l)
+                    if ((e = level_up(l, s2, false, true)) != hipSuccess) return e;
             double fbytes = 0.0, fflops = 0.0;
             int flo = 0, fhi = 0;
-            for (int l = pl->Ltop; l >= 1; --l) {
+            for (int l = pl->Ltop; l >= 1 && !pl->lat1; --l) {
                 LevelPlan& L = pl->lv[l];
                 if (L.pairs() == 0) continue;
                 const int64_t nfwd = l == 1 ? pl->nsrc : L.nint;  // level 1: the source intervals
@@ -825,19 +829,20 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                 LGF_STEP(s2, (launch_pad_fft_levels<T>(p, fw.data() + k0, nk, s2)), nm, k0 == 0 ? fbytes : 0.0,
                          k0 == 0 ? fflops : 0.0);
             }
-            for (int l = pl->Ltop; l >= 1; --l)
+            for (int l = pl->Ltop; l >= 1 && !pl->lat1; --l)
                 if ((e = level_up(l, s2, false, false)) != hipSuccess) return e;
             std::vector<FarLevel<T>> fl;
             double bytes = 0.0, flops = 0.0;
-            int lo = 0, hi = 0, S = 0;
+            int lo = 0, hi = 0;
             for (int l = 1; l <= pl->Ltop; ++l) {
                 LevelPlan& L = pl->lv[l];
                 if (L.pairs() == 0 || L.sib_pairs == 0) continue;
-                if (S == 0) S = L.spectra->S;
-                if (L.spectra->S != S) return hipErrorInvalidValue;  // one tile size for all levels
                 const LevelPlan& Pp = pl->lv[l + 1];
-                fl.push_back(FarLevel<T>{(const C*)L.d_fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216,
-                                         (C*)L.d_uhat, Pp.nint, L.nint, L.nint});
+                // level 1 of the lattice scheme reads the blocks' own spectra
+                const bool reuse0 = l == 1 && pl->lat1;
+                fl.push_back(FarLevel<T>{reuse0 ? (const C*)pl->d_fhat0 : (const C*)L.d_fhat,
+                                         (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216, (C*)L.d_uhat, Pp.nint,
+                                         L.nint, reuse0 ? pl->nsrc : L.nint, L.spectra->S});
                 bytes += ((double)L.nsrc_int + lvN(l) + 316.0) * Sl(l) * cs;
                 flops += (double)L.sib_pairs * Sl(l) * 8.0;
                 if (!lo) lo = l;
@@ -848,8 +853,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                 const std::string nm = fl.size() == 1 ? lname("prod_l", lo)
                                                       : "prod_l" + std::to_string(lo) + "-" + std::to_string(hi);
                 LGF_STEP(s2,
-                         (launch_prod_far_sib_levels<T>(fl.data() + k0, nk, S, tc.far_waves,
-                                                        tc.far_children, s2)),
+                         (launch_prod_far_sib_levels<T>(fl.data() + k0, nk, tc.far_waves, tc.far_children, s2)),
                          nm, k0 == 0 ? bytes : 0.0, k0 == 0 ? flops : 0.0);
             }
             // every level's inverse in one launch too (levels without list entries are zeroed),
@@ -859,7 +863,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             int ilo = 0, ihi = 0;
             for (int l = pl->Ltop; l >= 1; --l) {
                 LevelPlan& L = pl->lv[l];
-                if (L.pairs() == 0) {
+                if (L.pairs() == 0 || pl->lat1) {
                     if ((e = level_down(l, s2)) != hipSuccess) return e;
                     continue;
                 }

@@ -13,6 +13,8 @@
 // of [-3, 3]^3 at levels >= 1).
 // A plain CSR kernel covers the top level of a truncated tree, whose list is "every
 // non-adjacent interval" and has no such structure.
+#include <algorithm>
+
 #include "lgf_internal.h"
 
 namespace lgfdev {
@@ -274,7 +276,7 @@ __device__ __forceinline__ void m2l_dispatch(int q, const cplx<T>* fb, int wl, c
 }
 
 // One launch may cover several levels (segments of the grid, each with its own spectra,
-// lists and kernel spectra, all with the same spectrum size S): the coarse levels' small
+// lists, kernel spectra and spectrum size S): the coarse levels' small
 // M2L then runs inside the level-1 launch instead of as latency-bound launches of its own.
 // Segment k owns the workgroups [start_k, start_{k+1}); each start is a multiple of the
 // XCD count, so every segment keeps the XCD-aware chunk mapping.
@@ -285,7 +287,7 @@ struct FarSeg {
     const int32_t* child8;
     const int32_t* src216;
     cplx<T>* uhat;
-    int nparents, nitems, nsrc, ngroupblocks, start;
+    int nparents, nitems, nsrc, ngroupblocks, start, S;
 };
 template <typename T>
 struct FarSegs {
@@ -295,7 +297,7 @@ struct FarSegs {
 
 template <typename T, int kFarWaves, int CPL, typename IdxT>
 __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
-    k_prod_far_sib(const FarSegs<T> segs, int S) {
+    k_prod_far_sib(const FarSegs<T> segs) {
     constexpr int F = M2LShape<T>::F;
     constexpr int PPW = M2LShape<T>::PPW;
     constexpr int NQ = 8 / CPL;             // waves per group of parents (one per child subset)
@@ -314,7 +316,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     const int32_t* __restrict__ child8 = g.child8;
     const int32_t* __restrict__ src216 = g.src216;
     cplx<T>* __restrict__ uhat = g.uhat;
-    const int nparents = g.nparents, nitems = g.nitems, nsrc = g.nsrc;
+    const int nparents = g.nparents, nitems = g.nitems, nsrc = g.nsrc, S = g.S;
     const int nchunks = (S + F - 1) / F;
     int chunk, pb;
     if (!xcd_tile_at((int)blockIdx.x - g.start, nchunks, g.ngroupblocks, chunk, pb)) return;
@@ -421,16 +423,16 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
 }
 
 template <typename T, int NW, int CPL>
-static hipError_t far_nw(const FarLevel<T>* lv, int nlev, int S, hipStream_t s) {
+static hipError_t far_nw(const FarLevel<T>* lv, int nlev, hipStream_t s) {
     constexpr int F = M2LShape<T>::F, PPG = M2LShape<T>::PPW * NW;
-    const int nchunks = (S + F - 1) / F;
     FarSegs<T> segs{};
     unsigned grid = 0;
     for (int k = 0; k < nlev; ++k) {
         const int ngb = (int)((lv[k].nparents + PPG - 1) / PPG);
-        segs.s[k] = FarSeg<T>{lv[k].fhat,          lv[k].khat,         lv[k].child8, lv[k].src216,
-                              lv[k].uhat,          (int)lv[k].nparents, (int)lv[k].nitems,
-                              (int)lv[k].nsrc,     ngb,                 (int)grid};
+        const int nchunks = (lv[k].S + F - 1) / F;
+        segs.s[k] = FarSeg<T>{lv[k].fhat,      lv[k].khat,         lv[k].child8,       lv[k].src216,
+                              lv[k].uhat,      (int)lv[k].nparents, (int)lv[k].nitems, (int)lv[k].nsrc,
+                              ngb,             (int)grid,           lv[k].S};
         grid += xcd_grid(nchunks, ngb);  // a multiple of the XCD count
     }
     segs.n = nlev;
@@ -441,26 +443,26 @@ static hipError_t far_nw(const FarLevel<T>* lv, int nlev, int S, hipStream_t s) 
         for (int k = 0; k < nlev; ++k) idx16 = idx16 && lv[k].nsrc < 65535;
         if (idx16) {
             hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL, uint16_t>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s,
-                               segs, S);
+                               segs);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL, int32_t>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs, S);
+    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL, int32_t>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
     return hipGetLastError();
 }
 
 template <typename T, int CPL>
-static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int S, int waves, hipStream_t s) {
+static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int waves, hipStream_t s) {
     // at most 16 waves (1024 threads) per workgroup, and at most 8 in FP64, whose pipeline
     // needs more than the 128 registers a lane gets in a 16-wave workgroup
     constexpr int kMaxWaves = sizeof(T) == 8 ? 8 : 16;
     constexpr int kMaxGroups = kMaxWaves / (8 / CPL) < 4 ? kMaxWaves / (8 / CPL) : 4;
     switch (waves < kMaxGroups ? waves : kMaxGroups) {
-        case 1: return far_nw<T, 1, CPL>(lv, nlev, S, s);
+        case 1: return far_nw<T, 1, CPL>(lv, nlev, s);
         case 4:
-            if constexpr (kMaxGroups >= 4) return far_nw<T, 4, CPL>(lv, nlev, S, s);
+            if constexpr (kMaxGroups >= 4) return far_nw<T, 4, CPL>(lv, nlev, s);
             [[fallthrough]];
-        default: return far_nw<T, 2, CPL>(lv, nlev, S, s);
+        default: return far_nw<T, 2, CPL>(lv, nlev, s);
     }
 }
 
@@ -486,7 +488,7 @@ void m2l_default(int64_t nparents, bool idx16, int& waves, int& cpl) {
 }
 
 template <typename T>
-hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int S, int waves, int cpl, hipStream_t s) {
+hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves, int cpl, hipStream_t s) {
     int64_t most = 0;
     int k = 0;
     bool idx16 = true;
@@ -499,12 +501,38 @@ hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int S, in
     }
     if (k == 0) return hipSuccess;
     if (k > kMaxFarSegs) return hipErrorInvalidValue;
+    const bool open = waves == 0 && cpl == 0;
     m2l_default<T>(most, idx16, waves, cpl);
+    if (open && k > 1) {
+        // with the variant left open, a level whose workgroups in the largest level's variant
+        // would exceed half that level's count (many frequency chunks, few parents: the
+        // 34-point levels of the lattice scheme) gets a launch of its own with its own
+        // default variant; the others stay in one launch
+        constexpr int F = M2LShape<T>::F;
+        const int groups = std::min(waves, (sizeof(T) == 8 ? 8 : 16) / (8 / cpl));
+        const int64_t ppg = (int64_t)M2LShape<T>::PPW * (groups < 4 ? groups : 4);
+        auto wgs = [&](const FarLevel<T>& l) {
+            return (int64_t)xcd_grid((l.S + F - 1) / F, 1) * ((l.nparents + ppg - 1) / ppg);
+        };
+        int64_t wmax = 0;
+        for (int i = 0; i < k; ++i) wmax = std::max(wmax, wgs(lv[i]));
+        FarLevel<T> keep[kMaxFarSegs];
+        int nk = 0;
+        for (int i = 0; i < k; ++i) {
+            if (wgs(lv[i]) == wmax || 2 * wgs(lv[i]) <= wmax) {
+                keep[nk++] = lv[i];
+            } else {
+                const hipError_t e = launch_prod_far_sib_levels<T>(&lv[i], 1, 0, 0, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (nk < k) return launch_prod_far_sib_levels<T>(keep, nk, waves, cpl, s);
+    }
     switch (cpl) {
-        case 8: return far_cpl<T, 8>(lv, k, S, waves, s);
-        case 4: return far_cpl<T, 4>(lv, k, S, waves, s);
-        case 2: return far_cpl<T, 2>(lv, k, S, waves, s);
-        default: return far_cpl<T, 1>(lv, k, S, waves, s);
+        case 8: return far_cpl<T, 8>(lv, k, waves, s);
+        case 4: return far_cpl<T, 4>(lv, k, waves, s);
+        case 2: return far_cpl<T, 2>(lv, k, waves, s);
+        default: return far_cpl<T, 1>(lv, k, waves, s);
     }
 }
 
@@ -513,8 +541,8 @@ hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const i
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc,
                                int S, int waves, int cpl, hipStream_t s) {
     if (nparents <= 0) return hipSuccess;
-    const FarLevel<T> one{fhat, khat, child8, src216, uhat, nparents, nitems, nsrc};
-    return launch_prod_far_sib_levels<T>(&one, 1, S, waves, cpl, s);
+    const FarLevel<T> one{fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S};
+    return launch_prod_far_sib_levels<T>(&one, 1, waves, cpl, s);
 }
 
 template <typename T>
@@ -534,7 +562,7 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
                                             cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t);    \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
                                                cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t); \
-    template hipError_t launch_prod_far_sib_levels<T>(const FarLevel<T>*, int, int, int, int, hipStream_t);      \
+    template hipError_t launch_prod_far_sib_levels<T>(const FarLevel<T>*, int, int, int, hipStream_t);           \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \
                                            const int32_t*, const int32_t*, cplx<T>*, int64_t, int64_t, int, int, \
                                            hipStream_t, int64_t);
