@@ -79,6 +79,7 @@ typedef struct {
     int64_t eval_blocks;      /* blocks of u (B_e); equal to source_blocks and nblocks
                                  unless the plan has separate sets, where nblocks counts
                                  the union the tree of levels >= 1 is built on          */
+    int32_t spectra_mode;     /* lgf_spectra_mode of the plan's kernel spectra          */
 } lgf_plan_info;
 
 /*
@@ -252,6 +253,24 @@ int64_t lgf_memory_in_use(void);
 
 /* Drop cached kernel spectra not referenced by a live plan. */
 lgf_status lgf_spectra_cache_trim(void);
+
+/*
+ * Storage of the kernel spectra k^(P-Q) (Sec. 3.1, pre-computation; Sec. 3.2, unique
+ * kernel vectors per level) for plans created after the call, process-wide (a plan, and
+ * the request server's plans, keep the mode they were created with):
+ *   LGF_SPECTRA_FULL    one spectrum per offset: 27 at level 0, 343 per level >= 1 (default)
+ *   LGF_SPECTRA_REDUCED one spectrum per class of offsets under the 48 signed axis
+ *                       permutations the LGF is invariant under: 4 at level 0, 20 per
+ *                       level >= 1 (the 16 far classes and the 4 near ones), plus 4 bytes
+ *                       per offset.  The Prod kernels read each offset's coefficient at
+ *                       the permuted frequency (conjugated where that frequency lies
+ *                       outside the stored half spectrum).  u differs from the full
+ *                       tables' only by the rounding of the spectrum generation.
+ * Errors: LGF_ERR_ARG (unknown mode).
+ */
+typedef enum { LGF_SPECTRA_FULL = 0, LGF_SPECTRA_REDUCED = 1 } lgf_spectra_mode;
+lgf_status lgf_set_spectra_mode(int32_t mode);
+int32_t lgf_get_spectra_mode(void);
 
 /*
  * Per-step device timing of a plan's solves (measurement support).

@@ -29,6 +29,53 @@ __host__ __device__ __forceinline__ int64_t spec_at(int64_t item, int w, int64_t
     return ((int64_t)(w >> 6) * nitems + item) * kSpecChunk + (w & 63);
 }
 
+// ---------------------------------------------------------------- symmetry-reduced kernel spectra
+// The LGF is invariant under the 48 signed permutations g of the axes (Sec. 2.1), and the
+// kernel tiles are embedded centred (offset r at circulant index r mod M, zero at |r| = M/2),
+// so the spectrum of offset g D is that of D read at the frequency g^-1 omega (Sec. 3.1,
+// pre-computation, on the unique kernel vectors).  A reduced table keeps one spectrum per
+// class D_c = (a, b, c), a >= b >= c >= 0; offset D = (D_0, D_1, D_2) is described by
+//   info = cls | (i_0 | s_0 << 2 | i_1 << 3 | s_1 << 5 | i_2 << 6 | s_2 << 8) << 16,
+// where |D_{i_0}| >= |D_{i_1}| >= |D_{i_2}| and s_j = 1 when D_{i_j} < 0: then
+// nu_j = (s_j ? -1 : 1) * omega_{i_j} (mod M).  Frequencies with nu_x > M/2 lie outside the
+// stored half spectrum [kz][ky][kx <= M/2] and are read as the conjugate at -nu (real
+// kernels), so a reflection costs an index change, not a twiddle multiplication.
+// sym: reduced-table view (info == nullptr: the table holds one spectrum per offset).
+struct SpecSym {
+    const uint32_t* info = nullptr;  // per offset, as above
+    int ncls = 0;                    // spectra in the reduced table
+    int M = 0;                       // padded tile edge
+};
+// Frequency (kx, ky, kz) of spectrum index w = (kz M + ky) H + kx, H = M/2 + 1.
+struct Freq3 {
+    int v[3];
+};
+__device__ __forceinline__ Freq3 freq_of(int w, int M) {
+    const int H = M / 2 + 1;
+    const int t = w / H;
+    return Freq3{{w - t * H, t % M, t / M}};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> sym_coef(const cplx<T>* __restrict__ khat, uint32_t info, const Freq3& om,
+                                            int ncls, int M) {
+    int nu[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t a = (info >> (16 + 3 * j)) & 3u;
+        const int v = a == 0 ? om.v[0] : (a == 1 ? om.v[1] : om.v[2]);
+        nu[j] = ((info >> (18 + 3 * j)) & 1u) && v ? M - v : v;
+    }
+    const bool cj = 2 * nu[0] > M;
+    if (cj) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) nu[j] = nu[j] ? M - nu[j] : 0;
+    }
+    const int idx = (nu[2] * M + nu[1]) * (M / 2 + 1) + nu[0];
+    cplx<T> k = khat[spec_at((int)(info & 0xffffu), idx, ncls)];
+    if (cj) k.y = -k.y;
+    return k;
+}
+
 // ---------------------------------------------------------------- float-float numbers
 // An unevaluated sum hi + lo of two floats (|lo| <= ulp(hi)/2), with error-free
 // transformations (Knuth TwoSum, FMA-based TwoProduct).  Used by the FP32 path to carry

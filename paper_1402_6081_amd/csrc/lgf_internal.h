@@ -75,7 +75,12 @@ template <> struct FarAcc<float> { using type = ff32; };
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
                             cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
-                            int prefetch, hipStream_t s);
+                            int prefetch, hipStream_t s, const SpecSym& sym = SpecSym{});
+// sym: a reduced kernel table (khat then holds sym.ncls spectra) must match the spectrum
+// size S = M^2 (M/2 + 1) and hold at most 65536 spectra
+inline bool sym_fits(const SpecSym& y, int S) {
+    return !y.info || (y.M > 0 && y.ncls > 0 && y.ncls <= 65536 && S == y.M * y.M * (y.M / 2 + 1));
+}
 // Levels >= 1 below the top: over parents (child8 and the 216 candidate sources src216 of
 // each parent), offsets radius 3.
 // waves: parent groups per workgroup (1, 2, 4); cpl: children accumulated per lane (8, 4, 2,
@@ -85,7 +90,7 @@ template <typename T>
 // level reads another level's spectra (level 1 of the lattice scheme reads the blocks').
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc,
-                               int S, int waves, int cpl, hipStream_t s);
+                               int S, int waves, int cpl, hipStream_t s, const SpecSym& sym = SpecSym{});
 // The same over several levels in one launch, each with its own spectrum size S (at most
 // kMaxFarSegs levels, each with nparents > 0, in the order given).
 constexpr int kMaxFarSegs = 8;
@@ -98,6 +103,7 @@ struct FarLevel {
     cplx<T>* uhat;
     int64_t nparents, nitems, nsrc;
     int S;
+    SpecSym sym;  // reduced kernel spectra, or none
 };
 template <typename T>
 hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves, int cpl, hipStream_t s);
@@ -106,7 +112,7 @@ hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
                            const int32_t* off, const int32_t* tgt, cplx<T>* uhat, int64_t ntgt, int64_t nitems,
-                           int noff, int S, hipStream_t s, int64_t nsrc = -1);
+                           int noff, int S, hipStream_t s, int64_t nsrc = -1, const SpecSym& sym = SpecSym{});
 
 // Kernel variants picked per plan (by the autotuner, or defaults).
 struct TuneConfig {
@@ -146,13 +152,17 @@ struct SpectraKey {
     int radius;        // offsets D in [-radius, radius]^3, id = (Dx+R) + (2R+1)((Dy+R) + (2R+1)(Dz+R))
     int prec;          // 0 = f64, 1 = f32
     int m = 0;         // tile edge (0: n at level 0, p above; n at level 1 of the lattice scheme)
+    int sym = 0;       // 1 = symmetry-reduced table (one spectrum per class of offsets)
     bool operator<(const SpectraKey& o) const;
 };
 
 struct SpectraEntry {
     SpectraKey key;
     int M = 0, S = 0, noff = 0;
-    void* dev = nullptr;  // noff x S complex of the plan precision, chunk-major (spec_at), scaled by 1/M^3
+    void* dev = nullptr;  // noff x S complex of the plan precision, chunk-major (spec_at), scaled by 1/M^3;
+                          // reduced tables: ncls x S, with the per-offset descriptions in dev_info
+    uint32_t* dev_info = nullptr;
+    SpecSym sym;          // view of the reduced table (sym.info == nullptr: full table)
     int64_t bytes = 0;
     ~SpectraEntry();
 };
@@ -161,6 +171,13 @@ struct SpectraEntry {
 std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, std::string& err);
 int64_t spectra_bytes_total();
 void spectra_trim();
+// Table kind for plans created afterwards (process-wide): 0 = one spectrum per offset,
+// 1 = symmetry-reduced.
+void spectra_set_mode(int mode);
+int spectra_mode();
+// Classes of the offsets D in [-R, R]^3 under the 48 signed axis permutations, and each
+// offset's description (the layout of SpecSym::info); returns the number of classes.
+int spectra_classes(int R, std::vector<uint32_t>& info, std::vector<int32_t>& rep_offset);
 
 // LGF table [R][R][R] (full octant) on the device, FP64, cached per R.
 const double* green_table_device(int R, hipStream_t s, std::string& err);

@@ -584,6 +584,10 @@ struct lgf_graph_s {
 
 namespace {
 
+// Kernel spectra a Prod step reads per frequency: its offsets' spectra, or the classes of a
+// reduced table.
+double khat_rows(const SpectraEntry& e, int full) { return e.sym.info ? (double)e.sym.ncls : (double)full; }
+
 template <typename P>
 bool dev_alloc(lgf_plan_s* pl, P** out, int64_t bytes) {
     *out = nullptr;
@@ -723,16 +727,17 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             LGF_STEP(st,
                      (launch_prod_far_sib<T>(fhat, (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216, (C*)L.d_uhat,
                                              Pp.nint, L.nint, nsrc_items, L.spectra->S, tc.far_waves,
-                                             tc.far_children, st)),
-                     lname("prod_l", l), ((double)L.nsrc_int + lvN(l) + 316.0) * S1 * cs,
+                                             tc.far_children, st, L.spectra->sym)),
+                     lname("prod_l", l), ((double)L.nsrc_int + lvN(l) + khat_rows(*L.spectra, 316)) * S1 * cs,
                      (double)L.sib_pairs * S1 * 8.0);
         }
         if (L.csr_entries > 0)
             LGF_STEP(st,
                      (launch_prod_far<T>(fhat, (const C*)L.spectra_csr->dev, L.d_csr_ptr, L.d_csr_src, L.d_csr_off,
                                          L.d_csr_tgt, (C*)L.d_uhat, L.ncsr, L.nint, L.spectra_csr->noff,
-                                         L.spectra_csr->S, st, nsrc_items)),
-                     lname("prod_top_l", l), ((double)L.nsrc_int + lvN(l) + L.spectra_csr->noff) * S1 * cs,
+                                         L.spectra_csr->S, st, nsrc_items, L.spectra_csr->sym)),
+                     lname("prod_top_l", l),
+                     ((double)L.nsrc_int + lvN(l) + khat_rows(*L.spectra_csr, L.spectra_csr->noff)) * S1 * cs,
                      (double)L.csr_entries * S1 * 8.0);
         return hipSuccess;
     };
@@ -842,8 +847,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                 const bool reuse0 = l == 1 && pl->lat1;
                 fl.push_back(FarLevel<T>{reuse0 ? (const C*)pl->d_fhat0 : (const C*)L.d_fhat,
                                          (const C*)L.spectra->dev, Pp.d_child8, Pp.d_src216, (C*)L.d_uhat, Pp.nint,
-                                         L.nint, reuse0 ? pl->nsrc : L.nint, L.spectra->S});
-                bytes += ((double)L.nsrc_int + lvN(l) + 316.0) * Sl(l) * cs;
+                                         L.nint, reuse0 ? pl->nsrc : L.nint, L.spectra->S, L.spectra->sym});
+                bytes += ((double)L.nsrc_int + lvN(l) + khat_rows(*L.spectra, 316)) * Sl(l) * cs;
                 flops += (double)L.sib_pairs * Sl(l) * 8.0;
                 if (!lo) lo = l;
                 hi = l;
@@ -920,8 +925,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
         LGF_STEP(s,
                  launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8,
                                      pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nsrc, pl->ntgt0,
-                                     pl->spectra0->S, tc.near_waves, tc.near_prefetch, s),
-                 "prod_l0", (ns + nt0 + 27.0) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
+                                     pl->spectra0->S, tc.near_waves, tc.near_prefetch, s, pl->spectra0->sym),
+                 "prod_l0", (ns + nt0 + khat_rows(*pl->spectra0, 27)) * S0 * cs, (double)pl->near_pairs * S0 * 8.0);
         LGF_STEP(s,
                  (launch_ifft_trunc<T, T, T>(n, (const C*)pl->d_uhat0, u, pl->ntgt0, s, tc.fft0_threads,
                                              pl->d_near_out)),
@@ -988,14 +993,15 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     auto err_status = [&](const std::string& m) {
         return fail(m.find("budget") != std::string::npos ? LGF_ERR_BUDGET : LGF_ERR_DEVICE, m);
     };
-    pl->spectra0 = get_spectra(SpectraKey{n, p, 0, 1, ip}, s, err);
+    const int sm = spectra_mode();  // full or symmetry-reduced tables, fixed for the plan's life
+    pl->spectra0 = get_spectra(SpectraKey{n, p, 0, 1, ip, 0, sm}, s, err);
     if (!pl->spectra0) return err_status(err);
     std::vector<std::vector<int32_t>> csr_off(H.L + 1);
     for (int l = 1; l <= pl->Ltop; ++l) {
         LevelPlan& L = pl->lv[l];
         const int mt = l == 1 && H.lat1 ? n : 0;  // tile edge of the level's spectra (0: p)
         if (L.sib_pairs > 0) {
-            L.spectra = get_spectra(SpectraKey{n, p, l, 3, ip, mt}, s, err);
+            L.spectra = get_spectra(SpectraKey{n, p, l, 3, ip, mt, sm}, s, err);
             if (!L.spectra) return err_status(err);
         }
         if (L.csr_entries > 0) {
@@ -1006,7 +1012,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
             if ((int64_t)W * W * W > 300000)
                 return fail(LGF_ERR_LAYOUT, "top-level offsets too large: use more levels");
             for (const auto& D : H.lv[l].csr_D) csr_off[l].push_back((D[0] + R) + W * ((D[1] + R) + W * (D[2] + R)));
-            L.spectra_csr = get_spectra(SpectraKey{n, p, l, R, ip, mt}, s, err);
+            L.spectra_csr = get_spectra(SpectraKey{n, p, l, R, ip, mt, sm}, s, err);
             if (!L.spectra_csr) return err_status(err);
         }
     }
@@ -1687,6 +1693,7 @@ lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info) {
     info->precision = plan->prec;
     info->source_blocks = plan->nsrc;
     info->eval_blocks = plan->neval;
+    info->spectra_mode = plan->spectra0 ? plan->spectra0->key.sym : 0;
     return LGF_OK;
 }
 
@@ -1707,6 +1714,14 @@ lgf_status lgf_spectra_cache_trim(void) {
     spectra_trim();
     return LGF_OK;
 }
+
+lgf_status lgf_set_spectra_mode(int32_t mode) {
+    if (mode != LGF_SPECTRA_FULL && mode != LGF_SPECTRA_REDUCED) return fail(LGF_ERR_ARG, "unknown spectra mode");
+    spectra_set_mode(mode);
+    return LGF_OK;
+}
+
+int32_t lgf_get_spectra_mode(void) { return spectra_mode(); }
 
 const char* lgf_last_error(void) { return t_err.c_str(); }
 

@@ -80,16 +80,24 @@ template <typename T, int kNearWaves, bool kPrefetch>
 __global__ void __launch_bounds__(64 * kNearWaves)
     k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                         const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
-                        cplx<T>* __restrict__ uhat, int S, int ngroups, int nsrc, int ntgt) {
+                        cplx<T>* __restrict__ uhat, int S, int ngroups, int nsrc, int ntgt, const SpecSym sym) {
     __shared__ cplx<T> tile[45 * 64];  // row (dx+1) + 3 (dy+1) + 9 (dz+2)
     const int lane = threadIdx.x & 63;
     int chunk, gb;
     if (!xcd_tile(S / 64, (ngroups + kNearWaves - 1) / kNearWaves, chunk, gb)) return;
     const int w0 = chunk * 64;
     const int w = w0 + lane;  // frequency (S is a multiple of 64)
+    // reduced spectra: each thread fills the rows of its own frequency w (the loop steps by
+    // whole waves), so the frequency is decoded once
+    const bool red = sym.info != nullptr;
+    Freq3 om{};
+    if (red) om = freq_of(w, sym.M);
     for (int i = threadIdx.x; i < 45 * 64; i += 64 * kNearWaves) {
         const int r = i >> 6, dz = r / 9 - 2;
-        tile[i] = (dz < -1 || dz > 1) ? cplx<T>{T(0), T(0)} : khat[spec_at(r - 9, w0 + (i & 63), 27)];
+        cplx<T> k{T(0), T(0)};
+        if (dz >= -1 && dz <= 1)
+            k = red ? sym_coef(khat, sym.info[r - 9], om, sym.ncls, sym.M) : khat[spec_at(r - 9, w0 + (i & 63), 27)];
+        tile[i] = k;
     }
     __syncthreads();
     const int g = wave_uniform(gb * kNearWaves + (threadIdx.x >> 6));
@@ -288,6 +296,7 @@ struct FarSeg {
     const int32_t* src216;
     cplx<T>* uhat;
     int nparents, nitems, nsrc, ngroupblocks, start, S;
+    SpecSym sym;  // reduced kernel spectra (sym.info == nullptr: one spectrum per offset)
 };
 template <typename T>
 struct FarSegs {
@@ -321,9 +330,17 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     int chunk, pb;
     if (!xcd_tile_at((int)blockIdx.x - g.start, nchunks, g.ngroupblocks, chunk, pb)) return;
     const int w0 = chunk * F;
+    // reduced spectra: NT is a multiple of F, so every row a thread fills has the same
+    // frequency, decoded once
+    const bool red = g.sym.info != nullptr;
+    Freq3 om{};
+    if (red && w0 + (int)threadIdx.x % F < S) om = freq_of(w0 + (int)threadIdx.x % F, g.sym.M);
     for (int i = threadIdx.x; i < 343 * F; i += NT) {
         const int r = i / F, jj = i - r * F;
-        tile[i] = (w0 + jj < S) ? khat[spec_at(r, w0 + jj, 343)] : cplx<T>{T(0), T(0)};
+        cplx<T> k{T(0), T(0)};
+        if (w0 + jj < S)
+            k = red ? sym_coef(khat, g.sym.info[r], om, g.sym.ncls, g.sym.M) : khat[spec_at(r, w0 + jj, 343)];
+        tile[i] = k;
     }
     for (int i = threadIdx.x; i < PPG * 216; i += NT) {
         const int Jl = i / 216, k = i - Jl * 216;
@@ -375,10 +392,13 @@ __global__ void __launch_bounds__(kProdThreads)
     k_prod_far(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
                const int32_t* __restrict__ off, const int32_t* __restrict__ tgt, cplx<T>* __restrict__ uhat, int S,
-               int nitems, int noff, int nsrc) {
+               int nitems, int noff, int nsrc, const SpecSym sym) {
     const int w = blockIdx.y * kProdThreads + threadIdx.x;
     const int64_t i = blockIdx.x;
     if (w >= S) return;
+    const bool red = sym.info != nullptr;
+    Freq3 om{};
+    if (red) om = freq_of(w, sym.M);
     const int64_t P = tgt[i];
     const int e0 = ptr[i], e1 = ptr[i + 1];
     T ar = T(0), ai = T(0);
@@ -386,7 +406,7 @@ __global__ void __launch_bounds__(kProdThreads)
         const int q = src[e];
         const int o = off[e];
         const cplx<T> f = fhat[spec_at(q, w, nsrc + 1)];
-        const cplx<T> k = khat[spec_at(o, w, noff)];
+        const cplx<T> k = red ? sym_coef(khat, sym.info[o], om, sym.ncls, sym.M) : khat[spec_at(o, w, noff)];
         cmac(ar, ai, f, k);
     }
     uhat[spec_at(P, w, nitems)] = cplx<T>{ar, ai};
@@ -394,32 +414,33 @@ __global__ void __launch_bounds__(kProdThreads)
 
 template <typename T, int NW, bool PF>
 static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
-                          cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, hipStream_t s) {
+                          cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, hipStream_t s,
+                          const SpecSym& sym) {
     const unsigned grid = xcd_grid(S / 64, (int)((ngroups + NW - 1) / NW));
     hipLaunchKernelGGL((k_prod_near_grouped<T, NW, PF>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64,
-                       uhat, S, (int)ngroups, (int)nsrc, (int)ntgt);
+                       uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym);
     return hipGetLastError();
 }
 
 template <typename T, bool PF>
 static hipError_t near_pf(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
                           cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
-                          hipStream_t s) {
+                          hipStream_t s, const SpecSym& sym) {
     switch (waves) {
-        case 2: return near_nw<T, 2, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s);
-        case 8: return near_nw<T, 8, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s);
-        default: return near_nw<T, 4, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s);
+        case 2: return near_nw<T, 2, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s, sym);
+        case 8: return near_nw<T, 8, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s, sym);
+        default: return near_nw<T, 4, PF>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, s, sym);
     }
 }
 
 template <typename T>
 hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
                             cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
-                            int prefetch, hipStream_t s) {
+                            int prefetch, hipStream_t s, const SpecSym& sym) {
     if (ngroups <= 0) return hipSuccess;
-    if (S % 64 || !chunk_fits_u32<T>(nsrc + 1)) return hipErrorInvalidValue;
-    return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s)
-                    : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s);
+    if (S % 64 || !chunk_fits_u32<T>(nsrc + 1) || !sym_fits(sym, S)) return hipErrorInvalidValue;
+    return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s, sym)
+                    : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s, sym);
 }
 
 template <typename T, int NW, int CPL>
@@ -432,7 +453,8 @@ static hipError_t far_nw(const FarLevel<T>* lv, int nlev, hipStream_t s) {
         const int nchunks = (lv[k].S + F - 1) / F;
         segs.s[k] = FarSeg<T>{lv[k].fhat,      lv[k].khat,         lv[k].child8,       lv[k].src216,
                               lv[k].uhat,      (int)lv[k].nparents, (int)lv[k].nitems, (int)lv[k].nsrc,
-                              ngb,             (int)grid,           lv[k].S};
+                              ngb,             (int)grid,           lv[k].S,
+                              lv[k].sym};
         grid += xcd_grid(nchunks, ngb);  // a multiple of the XCD count
     }
     segs.n = nlev;
@@ -494,7 +516,8 @@ hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves
     bool idx16 = true;
     for (int i = 0; i < nlev; ++i) {
         if (lv[i].nparents <= 0) continue;
-        if (k != i || !chunk_fits_u32<T>(lv[i].nsrc + 1)) return hipErrorInvalidValue;  // empty levels only at the end
+        if (k != i || !chunk_fits_u32<T>(lv[i].nsrc + 1) || !sym_fits(lv[i].sym, lv[i].S))
+            return hipErrorInvalidValue;  // empty levels only at the end
         most = lv[i].nparents > most ? lv[i].nparents : most;
         idx16 = idx16 && lv[i].nsrc < 65535;
         ++k;
@@ -539,33 +562,36 @@ hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves
 template <typename T>
 hipError_t launch_prod_far_sib(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* child8,
                                const int32_t* src216, cplx<T>* uhat, int64_t nparents, int64_t nitems, int64_t nsrc,
-                               int S, int waves, int cpl, hipStream_t s) {
+                               int S, int waves, int cpl, hipStream_t s, const SpecSym& sym) {
     if (nparents <= 0) return hipSuccess;
-    const FarLevel<T> one{fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S};
+    const FarLevel<T> one{fhat, khat, child8, src216, uhat, nparents, nitems, nsrc, S, sym};
     return launch_prod_far_sib_levels<T>(&one, 1, waves, cpl, s);
 }
 
 template <typename T>
 hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* ptr, const int32_t* src,
                            const int32_t* off, const int32_t* tgt, cplx<T>* uhat, int64_t ntgt, int64_t nitems,
-                           int noff, int S, hipStream_t s, int64_t nsrc) {
+                           int noff, int S, hipStream_t s, int64_t nsrc, const SpecSym& sym) {
     if (ntgt <= 0) return hipSuccess;
     if (nsrc < 0) nsrc = nitems;
+    if (!sym_fits(sym, S)) return hipErrorInvalidValue;
     dim3 grid((unsigned)ntgt, (unsigned)((S + kProdThreads - 1) / kProdThreads));
     hipLaunchKernelGGL(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, tgt, uhat, S,
-                       (int)nitems, noff, (int)nsrc);
+                       (int)nitems, noff, (int)nsrc, sym);
     return hipGetLastError();
 }
 
 #define LGF_INST(T)                                                                                              \
     template hipError_t launch_prod_near<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,      \
-                                            cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t);    \
+                                            cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t,     \
+                                            const SpecSym&);                                                     \
     template hipError_t launch_prod_far_sib<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,   \
-                                               cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t); \
+                                               cplx<T>*, int64_t, int64_t, int64_t, int, int, int, hipStream_t,  \
+                                               const SpecSym&);                                                  \
     template hipError_t launch_prod_far_sib_levels<T>(const FarLevel<T>*, int, int, int, hipStream_t);           \
     template hipError_t launch_prod_far<T>(const cplx<T>*, const cplx<T>*, const int32_t*, const int32_t*,       \
                                            const int32_t*, const int32_t*, cplx<T>*, int64_t, int64_t, int, int, \
-                                           hipStream_t, int64_t);
+                                           hipStream_t, int64_t, const SpecSym&);
 LGF_INST(double)
 LGF_INST(float)
 #undef LGF_INST

@@ -15,6 +15,7 @@
 //    so the inverse transform of a solve needs no normalisation.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -392,14 +393,16 @@ __global__ void k_dft_r2c_x(const double* __restrict__ in, cplx<double>* __restr
     out[id] = cplx<double>{sr, si};
 }
 
-// scale, cast and scatter [noff][S] into the chunk-major layout
+// scale, cast and scatter rows of [*][S] into the chunk-major layout of nout items: item o
+// takes row rows[o] (rows == nullptr: row o)
 template <typename T>
-__global__ void k_scale_cast(const cplx<double>* __restrict__ in, cplx<T>* __restrict__ out, int noff, int S,
-                             double scale) {
+__global__ void k_scale_cast(const cplx<double>* __restrict__ in, cplx<T>* __restrict__ out, int nout, int S,
+                             double scale, const int32_t* __restrict__ rows) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)noff * S) return;
+    if (i >= (int64_t)nout * S) return;
     const int o = (int)(i / S), w = (int)(i % S);
-    out[spec_at(o, w, noff)] = cplx<T>{(T)(in[i].x * scale), (T)(in[i].y * scale)};
+    const cplx<double> v = in[(int64_t)(rows ? rows[o] : o) * S + w];
+    out[spec_at(o, w, nout)] = cplx<T>{(T)(v.x * scale), (T)(v.y * scale)};
 }
 
 // ============================================================== host glue
@@ -457,14 +460,50 @@ int current_device() {
 }  // namespace
 
 bool SpectraKey::operator<(const SpectraKey& o) const {
-    return std::make_tuple(n, p, level, radius, prec, m) < std::make_tuple(o.n, o.p, o.level, o.radius, o.prec, o.m);
+    return std::make_tuple(n, p, level, radius, prec, m, sym) <
+           std::make_tuple(o.n, o.p, o.level, o.radius, o.prec, o.m, o.sym);
 }
 
 SpectraEntry::~SpectraEntry() {
+    if (dev_info) hipFree(dev_info);
     if (dev) {
         hipFree(dev);
         budget_release(bytes);
     }
+}
+
+namespace {
+std::atomic<int> g_spectra_mode{0};
+}
+void spectra_set_mode(int mode) { g_spectra_mode.store(mode ? 1 : 0); }
+int spectra_mode() { return g_spectra_mode.load(); }
+
+int spectra_classes(int R, std::vector<uint32_t>& info, std::vector<int32_t>& rep_offset) {
+    const int W = 2 * R + 1;
+    auto offset = [&](int x, int y, int z) { return (x + R) + W * ((y + R) + W * (z + R)); };
+    // classes a >= b >= c >= 0, numbered in this order
+    std::vector<int32_t> cls_of((size_t)W * W * W, -1);
+    rep_offset.clear();
+    for (int a = 0; a <= R; ++a)
+        for (int b = 0; b <= a; ++b)
+            for (int c = 0; c <= b; ++c) {
+                cls_of[offset(a, b, c)] = (int32_t)rep_offset.size();
+                rep_offset.push_back(offset(a, b, c));
+            }
+    info.assign((size_t)W * W * W, 0u);
+    for (int z = -R; z <= R; ++z)
+        for (int y = -R; y <= R; ++y)
+            for (int x = -R; x <= R; ++x) {
+                const int D[3] = {x, y, z};
+                int ax[3] = {0, 1, 2};  // axes by decreasing |D|, ties in axis order
+                std::stable_sort(ax, ax + 3, [&](int u, int v) { return std::abs(D[u]) > std::abs(D[v]); });
+                const uint32_t cls =
+                    (uint32_t)cls_of[offset(std::abs(D[ax[0]]), std::abs(D[ax[1]]), std::abs(D[ax[2]]))];
+                uint32_t g = 0;
+                for (int j = 0; j < 3; ++j) g |= (uint32_t)(ax[j] | (D[ax[j]] < 0 ? 4 : 0)) << (3 * j);
+                info[offset(x, y, z)] = cls | (g << 16);
+            }
+    return (int)rep_offset.size();
 }
 
 static const double* green_table_locked(int R, hipStream_t s, std::string& err) {
@@ -548,7 +587,12 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
     entry->S = S;
     entry->noff = noff;
     const size_t esz = key.prec == 0 ? sizeof(cplx<double>) : sizeof(cplx<float>);
-    entry->bytes = (int64_t)noff * spec_padded(S) * esz;
+    // reduced table: the class representatives' rows of the full table, and each offset's
+    // description
+    std::vector<uint32_t> info;
+    std::vector<int32_t> rep;
+    const int nrows = key.sym ? spectra_classes(key.radius, info, rep) : noff;
+    entry->bytes = (int64_t)nrows * spec_padded(S) * esz + (int64_t)info.size() * sizeof(uint32_t);
     if (!budget_reserve(entry->bytes)) {
         err = "kernel spectra exceed the device-memory budget";
         return nullptr;
@@ -557,7 +601,12 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
     double* kb = nullptr;
     cplx<double> *t1 = nullptr, *t2 = nullptr;
     double* dtw = nullptr;
-    bool ok = hipMalloc(&entry->dev, entry->bytes) == hipSuccess;
+    int32_t* drep = nullptr;
+    bool ok = hipMalloc(&entry->dev, (size_t)nrows * spec_padded(S) * esz) == hipSuccess;
+    if (key.sym) {
+        ok = ok && hipMalloc(&entry->dev_info, info.size() * sizeof(uint32_t)) == hipSuccess;
+        ok = ok && hipMalloc(&drep, rep.size() * sizeof(int32_t)) == hipSuccess;
+    }
     ok = ok && hipMalloc(&kb, noff * M3 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&t1, (size_t)noff * S * sizeof(cplx<double>)) == hipSuccess;
     ok = ok && hipMalloc(&t2, (size_t)noff * S * sizeof(cplx<double>)) == hipSuccess;
@@ -568,12 +617,22 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
         if (t1) hipFree(t1);
         if (t2) hipFree(t2);
         if (dtw) hipFree(dtw);
+        if (drep) hipFree(drep);
+        if (entry->dev_info) {
+            hipFree(entry->dev_info);
+            entry->dev_info = nullptr;
+        }
         if (entry->dev) {
             hipFree(entry->dev);
             entry->dev = nullptr;
         }
         budget_release(entry->bytes);
         return nullptr;
+    }
+    if (key.sym) {
+        hipMemcpyAsync(entry->dev_info, info.data(), info.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(drep, rep.data(), rep.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        entry->sym = SpecSym{entry->dev_info, nrows, M};
     }
     const std::vector<double> tw = root_table(M);
     hipMemcpyAsync(dtw, tw.data(), 2 * M * sizeof(double), hipMemcpyHostToDevice, s);
@@ -588,17 +647,19 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
     hipLaunchKernelGGL(k_dft_axis, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t2, t1, (int64_t)noff, M,
                        (int64_t)M * H, dtw);
     const double scale = 1.0 / (double)M3;
+    const int64_t tout = (int64_t)nrows * S;
     if (key.prec == 0)
-        hipLaunchKernelGGL(k_scale_cast<double>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t1,
-                           (cplx<double>*)entry->dev, noff, S, scale);
+        hipLaunchKernelGGL(k_scale_cast<double>, dim3((unsigned)((tout + 255) / 256)), dim3(256), 0, s, t1,
+                           (cplx<double>*)entry->dev, nrows, S, scale, (const int32_t*)drep);
     else
-        hipLaunchKernelGGL(k_scale_cast<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t1,
-                           (cplx<float>*)entry->dev, noff, S, scale);
+        hipLaunchKernelGGL(k_scale_cast<float>, dim3((unsigned)((tout + 255) / 256)), dim3(256), 0, s, t1,
+                           (cplx<float>*)entry->dev, nrows, S, scale, (const int32_t*)drep);
     hipError_t e = hipStreamSynchronize(s);
     hipFree(kb);
     hipFree(t1);
     hipFree(t2);
     hipFree(dtw);
+    if (drep) hipFree(drep);
     if (e != hipSuccess) {
         err = std::string("kernel spectra generation failed: ") + hipGetErrorString(e);
         return nullptr;

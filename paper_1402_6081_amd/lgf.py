@@ -34,6 +34,7 @@ class PlanInfo(ctypes.Structure):
         ("intervals", ctypes.c_int64 * 16), ("workspace_bytes", ctypes.c_int64),
         ("spectra_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
         ("source_blocks", ctypes.c_int64), ("eval_blocks", ctypes.c_int64),
+        ("spectra_mode", ctypes.c_int32),
     ]
 
 
@@ -77,7 +78,8 @@ EXPORTS = ["lgf_plan_create", "lgf_plan_estimate", "lgf_plan_create_split", "lgf
            "lgf_plan_set_tuning", "lgf_server_create", "lgf_server_submit", "lgf_server_poll", "lgf_server_wait",
            "lgf_server_stats", "lgf_server_reset_stats", "lgf_server_destroy",
            "lgf_plan_query", "lgf_plan_destroy", "lgf_set_memory_budget", "lgf_memory_in_use",
-           "lgf_spectra_cache_trim", "lgf_last_error", "lgf_green_table", "lgf_far_kernel", "lgf_profile_enable",
+           "lgf_spectra_cache_trim", "lgf_set_spectra_mode", "lgf_get_spectra_mode", "lgf_last_error",
+           "lgf_green_table", "lgf_far_kernel", "lgf_profile_enable",
            "lgf_profile_collect"]
 
 _lib = None
@@ -117,6 +119,7 @@ def library():
         L.lgf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.lgf_plan_destroy.argtypes = [vp]
         L.lgf_set_memory_budget.argtypes = [i64]
+        L.lgf_set_spectra_mode.argtypes = [i32]
         L.lgf_memory_in_use.restype = i64
         L.lgf_last_error.restype = ctypes.c_char_p
         L.lgf_green_table.argtypes = [i32, vp]
@@ -157,8 +160,22 @@ class Plan:
     With `eval_blocks` (lgf_plan_create_split) f lives on `blocks` (B_s) and u on
     `eval_blocks` (B_e)."""
 
-    def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None, _layouts=None, eval_blocks=None):
+    def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None, _layouts=None, eval_blocks=None,
+                 spectra=None):
+        """spectra: "full" or "reduced" kernel spectra for this plan (None: the process-wide
+        mode, set_spectra_mode)."""
         _require_gpu()
+        prev = None
+        if spectra is not None:
+            prev = get_spectra_mode()
+            set_spectra_mode(spectra)
+        try:
+            self._create(blocks, n, p, levels, precision, stream, _layouts, eval_blocks)
+        finally:
+            if prev is not None:
+                set_spectra_mode(prev)
+
+    def _create(self, blocks, n, p, levels, precision, stream, _layouts, eval_blocks):
         self.n, self.p = int(n), int(p)
         self.precision = precision
         prec = {"f64": F64, "f32": F32}[precision]
@@ -191,9 +208,9 @@ class Plan:
         self.offsets = [int(x) for x in offs]
 
     @classmethod
-    def batch(cls, layouts, n, p, levels=0, precision="f64", stream=None):
+    def batch(cls, layouts, n, p, levels=0, precision="f64", stream=None, spectra=None):
         """One plan over independent layouts (lgf_plan_create_batch); fields concatenated in order."""
-        return cls(None, n, p, levels, precision, stream, _layouts=list(layouts))
+        return cls(None, n, p, levels, precision, stream, _layouts=list(layouts), spectra=spectra)
 
     def split(self, x):
         """Views of a batch field [sum N_B, n, n, n] per problem."""
@@ -450,3 +467,17 @@ def memory_in_use():
 
 def trim_spectra_cache():
     _check(library().lgf_spectra_cache_trim())
+
+
+SPECTRA_MODES = {"full": 0, "reduced": 1}
+
+
+def set_spectra_mode(mode):
+    """Kernel spectra of plans created afterwards: "full" (one per offset) or "reduced"
+    (one per symmetry class of offsets), lgf_set_spectra_mode."""
+    _check(library().lgf_set_spectra_mode(SPECTRA_MODES[mode]))
+
+
+def get_spectra_mode():
+    m = int(library().lgf_get_spectra_mode())
+    return {v: k for k, v in SPECTRA_MODES.items()}[m]

@@ -55,3 +55,17 @@ def test_argument_errors_without_gpu_work():
     assert lib.lgf_plan_query(None, None) == 1
     assert lib.lgf_set_memory_budget(-1) == 1
     assert lib.lgf_plan_destroy(None) == 0
+
+
+def test_spectra_mode_switch_without_gpu_work():
+    # the table kind is host state read at plan creation; unknown kinds are rejected
+    import torch  # noqa: F401
+    from paper_1402_6081_amd import lgf as L
+    lib = L.library()
+    assert lib.lgf_get_spectra_mode() == 0  # full tables by default
+    assert lib.lgf_set_spectra_mode(2) == 1 and b"spectra mode" in lib.lgf_last_error()
+    assert lib.lgf_set_spectra_mode(-1) == 1
+    L.set_spectra_mode("reduced")
+    assert L.get_spectra_mode() == "reduced" and lib.lgf_get_spectra_mode() == 1
+    L.set_spectra_mode("full")
+    assert lib.lgf_get_spectra_mode() == 0
