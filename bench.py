@@ -371,6 +371,50 @@ def scheme_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None):
     return out
 
 
+def reduced_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None, scheme=True, compare=True):
+    """Symmetry-reduced kernel spectra (one spectrum per class of offsets under the LGF's 48
+    signed axis permutations) on the 128^3 workload and on the n_I = n + 1 scheme: the rate
+    (tuned, graph-launched as above), the kernel spectra's bytes against the full tables',
+    and the difference from the full-table solve of the same input (compare=False: the
+    reduced solves only, for counter runs)."""
+    import torch
+    out = {}
+    for cfg in (W.config_medium(), W.config_scheme()) if scheme else (W.config_medium(),):
+        npts = int(cfg["f"].size)
+        res = {"unit": "grid points solved/s"}
+        ref64 = None
+        for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            f = torch.from_numpy(cfg["f"]).to("cuda:0", dt)
+            u = torch.empty_like(f)
+            plan = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], prec, spectra="reduced")
+            m = _measure(plan, f, u, steps, warmup, graph=graph, tune=tune)
+            ur = u.double().cpu().numpy()
+            wl = cfg["name"] + "_reduced"
+            r = {"workload": wl, "value": round(npts * steps / m["dt_graph"], 1),
+                 "ms_per_step": round(m["dt_graph"] / steps * 1e3, 5), "latency_ms": _pct(m["lat_graph"]),
+                 "eager_ms_per_step": round(m["dt_eager"] / steps * 1e3, 5), "tuning": m["tuning"],
+                 "spectra_bytes": plan.info()["spectra_bytes"],
+                 "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS, wl, prec)}
+            if breakdown is not None and not scheme:
+                breakdown["reduced_fp64" if prec == "f64" else "reduced_fp32"] = _breakdown(m["prof"])
+            plan.close()
+            if compare:
+                full = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], prec, spectra="full")
+                uf = full.solve(f).double().cpu().numpy()
+                r["full_spectra_bytes"] = full.info()["spectra_bytes"]
+                full.close()
+                r["rel_linf_diff_vs_full_tables"] = float(np.max(np.abs(ur - uf)) / np.max(np.abs(uf)))
+                if prec == "f64":
+                    ref64 = uf
+                else:
+                    r["rel_linf_err_vs_fp64"] = float(np.max(np.abs(ur - ref64)) / np.max(np.abs(ref64)))
+            res[prec] = r
+            del f, u
+            torch.cuda.empty_cache()
+        out[cfg["name"]] = res
+    return out
+
+
 def serve_bench(L, W, nreq=192, seed=5, slots=4, load=0.8):
     """Serving: 32 request layouts (bounding box U{2..16} blocks of 16^3, Eden fill
     U[0.3, 1]), p = 8, FP32, through the request server (resident plans, shared spectra).
@@ -436,6 +480,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-scheme", action="store_true")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the symmetry-reduced spectra runs")
+    ap.add_argument("--reduced-only", action="store_true",
+                    help="only the 128^3 workload with symmetry-reduced spectra (profiling runs)")
     ap.add_argument("--split-only", action="store_true",
                     help="only the separate-set workload (profiling runs); prints its JSON object")
     ap.add_argument("--scheme-only", action="store_true",
@@ -457,10 +504,16 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
-    if args.split_only or args.scheme_only:
+    if args.split_only or args.scheme_only or args.reduced_only:
         breakdown = {}
-        leg, fn = ("split", split_bench) if args.split_only else ("scheme", scheme_bench)
-        out = fn(L, W, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune, breakdown=breakdown)
+        if args.reduced_only:  # the 128^3 workload with reduced spectra, no full-table runs
+            leg = "reduced_spectra"
+            out = reduced_bench(L, W, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune,
+                                breakdown=breakdown, scheme=False, compare=False)
+        else:
+            leg, fn = ("split", split_bench) if args.split_only else ("scheme", scheme_bench)
+            out = fn(L, W, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune,
+                     breakdown=breakdown)
         if args.breakdown:
             with open(args.breakdown, "w") as fh:
                 json.dump(breakdown, fh, indent=1)
@@ -545,6 +598,10 @@ def main():
         result["scheme"] = scheme_bench(L, W, max(5, args.steps // 5), 2, graph=not args.no_graph,
                                         tune=not args.no_tune, breakdown=breakdown)
         print("n_I = n + 1 scheme measured", flush=True, file=sys.stderr)
+    if not args.no_reduced:
+        result["reduced_spectra"] = reduced_bench(L, W, max(5, args.steps // 5), 2, graph=not args.no_graph,
+                                                  tune=not args.no_tune)
+        print("symmetry-reduced spectra measured", flush=True, file=sys.stderr)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg)
