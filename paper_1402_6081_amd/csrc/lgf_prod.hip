@@ -87,17 +87,33 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     if (!xcd_tile(S / 64, (ngroups + kNearWaves - 1) / kNearWaves, chunk, gb)) return;
     const int w0 = chunk * 64;
     const int w = w0 + lane;  // frequency (S is a multiple of 64)
-    // reduced spectra: each thread fills the rows of its own frequency w (the loop steps by
-    // whole waves), so the frequency is decoded once
-    const bool red = sym.info != nullptr;
-    Freq3 om{};
-    if (red) om = freq_of(w, sym.M);
-    for (int i = threadIdx.x; i < 45 * 64; i += 64 * kNearWaves) {
-        const int r = i >> 6, dz = r / 9 - 2;
-        cplx<T> k{T(0), T(0)};
-        if (dz >= -1 && dz <= 1)
-            k = red ? sym_coef(khat, sym.info[r - 9], om, sym.ncls, sym.M) : khat[spec_at(r - 9, w0 + (i & 63), 27)];
-        tile[i] = k;
+    if (sym.info != nullptr) {
+        // reduced spectra: each thread fills rows of its own frequency w (the loop steps by
+        // whole waves), decoded once; the rows' descriptions first, then all the gathers
+        constexpr int NT = 64 * kNearWaves, NR = (45 * 64 + NT - 1) / NT;
+        const Freq3 om = freq_of(w, sym.M);
+        uint32_t inf[NR];
+        bool use[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + k * NT, r = i >> 6, dz = r / 9 - 2;
+            use[k] = i < 45 * 64 && dz >= -1 && dz <= 1;
+            inf[k] = use[k] ? sym.info[r - 9] : 0u;
+        }
+        cplx<T> kv[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+            kv[k] = use[k] ? sym_coef(khat, inf[k], om, sym.ncls, sym.M) : cplx<T>{T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + k * NT;
+            if (i < 45 * 64) tile[i] = kv[k];
+        }
+    } else {
+        for (int i = threadIdx.x; i < 45 * 64; i += 64 * kNearWaves) {
+            const int r = i >> 6, dz = r / 9 - 2;
+            tile[i] = (dz < -1 || dz > 1) ? cplx<T>{T(0), T(0)} : khat[spec_at(r - 9, w0 + (i & 63), 27)];
+        }
     }
     __syncthreads();
     const int g = wave_uniform(gb * kNearWaves + (threadIdx.x >> 6));
@@ -332,15 +348,35 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     const int w0 = chunk * F;
     // reduced spectra: NT is a multiple of F, so every row a thread fills has the same
     // frequency, decoded once
-    const bool red = g.sym.info != nullptr;
-    Freq3 om{};
-    if (red && w0 + (int)threadIdx.x % F < S) om = freq_of(w0 + (int)threadIdx.x % F, g.sym.M);
-    for (int i = threadIdx.x; i < 343 * F; i += NT) {
-        const int r = i / F, jj = i - r * F;
-        cplx<T> k{T(0), T(0)};
-        if (w0 + jj < S)
-            k = red ? sym_coef(khat, g.sym.info[r], om, g.sym.ncls, g.sym.M) : khat[spec_at(r, w0 + jj, 343)];
-        tile[i] = k;
+    if (g.sym.info != nullptr) {
+        // every row's description first, then all the (dependent) gathers, so the loads of
+        // a thread's rows are in flight together
+        constexpr int NR = (343 * F + NT - 1) / NT;
+        const int jj = (int)threadIdx.x % F;
+        const bool wok = w0 + jj < S;
+        const Freq3 om = wok ? freq_of(w0 + jj, g.sym.M) : Freq3{};
+        uint32_t inf[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + k * NT;
+            inf[k] = i < 343 * F ? g.sym.info[i / F] : 0u;
+        }
+        cplx<T> kv[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + k * NT;
+            kv[k] = (i < 343 * F && wok) ? sym_coef(khat, inf[k], om, g.sym.ncls, g.sym.M) : cplx<T>{T(0), T(0)};
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + k * NT;
+            if (i < 343 * F) tile[i] = kv[k];
+        }
+    } else {
+        for (int i = threadIdx.x; i < 343 * F; i += NT) {
+            const int r = i / F, jj = i - r * F;
+            tile[i] = (w0 + jj < S) ? khat[spec_at(r, w0 + jj, 343)] : cplx<T>{T(0), T(0)};
+        }
     }
     for (int i = threadIdx.x; i < PPG * 216; i += NT) {
         const int Jl = i / 216, k = i - Jl * 216;
