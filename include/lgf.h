@@ -257,7 +257,7 @@ lgf_status lgf_spectra_cache_trim(void);
 /*
  * Storage of the kernel spectra k^(P-Q) (Sec. 3.1, pre-computation; Sec. 3.2, unique
  * kernel vectors per level) for plans created after the call, process-wide (a plan, and
- * the request server's plans, keep the mode they were created with):
+ * a request server, for all the plans it creates, keep the mode they were created with):
  *   LGF_SPECTRA_FULL    one spectrum per offset: 27 at level 0, 343 per level >= 1 (default)
  *   LGF_SPECTRA_REDUCED one spectrum per class of offsets under the 48 signed axis
  *                       permutations the LGF is invariant under: 4 at level 0, 20 per

@@ -175,6 +175,9 @@ void spectra_trim();
 // 1 = symmetry-reduced.
 void spectra_set_mode(int mode);
 int spectra_mode();
+// The calling thread's own mode (-1: follow the process-wide one); the request server's
+// dispatcher keeps the mode the server was created with.
+void spectra_set_thread_mode(int mode);
 // Classes of the offsets D in [-R, R]^3 under the 48 signed axis permutations, and each
 // offset's description (the layout of SpecSym::info); returns the number of classes.
 int spectra_classes(int R, std::vector<uint32_t>& info, std::vector<int32_t>& rep_offset);

@@ -72,6 +72,7 @@ std::string layout_key(const int32_t* ijk, int64_t nb) {
 struct lgf_server_s {
     lgf_server_config cfg{};
     int device = 0;
+    int spectra_mode = 0;  // kernel spectra of the server's plans: the process-wide mode at creation
     std::vector<hipStream_t> slots;
     std::vector<bool> slot_busy;
     std::vector<hipEvent_t> ev_pool;
@@ -253,6 +254,7 @@ int try_admit(lgf_server_s* S, const std::shared_ptr<Request>& r) {
 
 void dispatcher(lgf_server_s* S) {
     hipSetDevice(S->device);
+    lgfdev::spectra_set_thread_mode(S->spectra_mode);  // the plans this thread creates
     for (;;) {
         retire(S);
         std::shared_ptr<Request> head;
@@ -303,6 +305,7 @@ lgf_status lgf_server_create(const lgf_server_config* cfg, lgf_server_t* out) {
     }
     auto S = std::make_unique<lgf_server_s>();
     S->cfg = *cfg;
+    S->spectra_mode = lgfdev::spectra_mode();
     if (hipGetDevice(&S->device) != hipSuccess) {
         set_last_error("no HIP device");
         return LGF_ERR_DEVICE;

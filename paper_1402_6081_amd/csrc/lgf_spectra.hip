@@ -474,9 +474,11 @@ SpectraEntry::~SpectraEntry() {
 
 namespace {
 std::atomic<int> g_spectra_mode{0};
+thread_local int t_spectra_mode = -1;  // a thread's own mode, or -1: the process-wide one
 }
 void spectra_set_mode(int mode) { g_spectra_mode.store(mode ? 1 : 0); }
-int spectra_mode() { return g_spectra_mode.load(); }
+void spectra_set_thread_mode(int mode) { t_spectra_mode = mode < 0 ? -1 : (mode ? 1 : 0); }
+int spectra_mode() { return t_spectra_mode >= 0 ? t_spectra_mode : g_spectra_mode.load(); }
 
 int spectra_classes(int R, std::vector<uint32_t>& info, std::vector<int32_t>& rep_offset) {
     const int W = 2 * R + 1;

@@ -177,3 +177,27 @@ def test_reduced_spectra_schedules_same_bits(L):
                 ref = u
             assert np.array_equal(u, ref), (ov, fw, fc)
     plan.close()
+
+
+def test_reduced_spectra_server(L):
+    # a server keeps the mode it was created with: its requests equal reduced-table plans
+    # solved alone, bit for bit, also after the process-wide mode has been switched back
+    n, p, prec = 8, 6, "f32"
+    rng = np.random.default_rng(41)
+    lays = [W.eden_layout(int(k), rng) for k in (30, 55, 30, 80, 42)]
+    fs = [torch.from_numpy(rng.standard_normal((b.shape[0], n, n, n))).to("cuda:0", torch.float32) for b in lays]
+    refs = []
+    for b, f in zip(lays, fs):
+        plan = L.Plan(b, n, p, 0, prec, spectra="reduced")
+        refs.append(plan.solve(f).clone())
+        plan.close()
+    torch.cuda.synchronize()
+    L.set_spectra_mode("reduced")
+    srv = L.Server(n, p, 0, prec, max_slots=3)
+    L.set_spectra_mode("full")
+    us = [torch.full_like(f, float("nan")) for f in fs]
+    res = [srv.wait(t) for t in [srv.submit(b, f, u) for b, f, u in zip(lays, fs, us)]]
+    for i, (r, u, ref) in enumerate(zip(res, us, refs)):
+        assert r["status"] == "LGF_OK", (i, r)
+        assert torch.equal(u, ref), "request %d differs from its reduced-table solve alone" % i
+    srv.close()
