@@ -364,8 +364,21 @@ class Graph:
 class Server:
     """lgf_server_*: a request loop with HBM-budget admission and resident plans."""
 
-    def __init__(self, n, p, levels=0, precision="f32", max_slots=4, budget_bytes=0, max_queue=0):
+    def __init__(self, n, p, levels=0, precision="f32", max_slots=4, budget_bytes=0, max_queue=0, spectra=None):
+        """spectra: "full" or "reduced" kernel spectra for every plan the server creates
+        (None: the process-wide mode at creation, set_spectra_mode)."""
         _require_gpu()
+        prev = None
+        if spectra is not None:
+            prev = get_spectra_mode()
+            set_spectra_mode(spectra)
+        try:
+            self._create(n, p, levels, precision, max_slots, budget_bytes, max_queue)
+        finally:
+            if prev is not None:
+                set_spectra_mode(prev)
+
+    def _create(self, n, p, levels, precision, max_slots, budget_bytes, max_queue):
         self.n = int(n)
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         cfg = ServerConfig(int(budget_bytes), int(max_slots), int(max_queue), self.n, int(p), int(levels),

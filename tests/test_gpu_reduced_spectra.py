@@ -195,9 +195,17 @@ def test_reduced_spectra_server(L):
     L.set_spectra_mode("reduced")
     srv = L.Server(n, p, 0, prec, max_slots=3)
     L.set_spectra_mode("full")
+    srv2 = L.Server(n, p, 0, prec, max_slots=2, spectra="reduced")  # the keyword form
+    assert L.get_spectra_mode() == "full"
     us = [torch.full_like(f, float("nan")) for f in fs]
     res = [srv.wait(t) for t in [srv.submit(b, f, u) for b, f, u in zip(lays, fs, us)]]
     for i, (r, u, ref) in enumerate(zip(res, us, refs)):
         assert r["status"] == "LGF_OK", (i, r)
         assert torch.equal(u, ref), "request %d differs from its reduced-table solve alone" % i
+    us2 = [torch.full_like(f, float("nan")) for f in fs]
+    for t in [srv2.submit(b, f, u) for b, f, u in zip(lays, fs, us2)]:
+        assert srv2.wait(t)["status"] == "LGF_OK"
+    for u, ref in zip(us2, refs):
+        assert torch.equal(u, ref)
     srv.close()
+    srv2.close()
