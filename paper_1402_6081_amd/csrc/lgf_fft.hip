@@ -548,6 +548,8 @@ hipError_t launch_ifft_trunc_levels(int m, const InvLevel<Tin, Tout>* lv, int nl
 template hipError_t launch_ifft_trunc_levels<double, double, double>(int, const InvLevel<double, double>*, int,
                                                                       hipStream_t);
 template hipError_t launch_ifft_trunc_levels<float, ff32, ff32>(int, const InvLevel<float, ff32>*, int, hipStream_t);
+template hipError_t launch_ifft_trunc_levels<float, double, ff32>(int, const InvLevel<float, ff32>*, int,
+                                                                   hipStream_t);
 
 template hipError_t launch_pad_fft<double>(int, const double*, cplx<double>*, int64_t, hipStream_t, int, int64_t,
                                            void*);
@@ -561,5 +563,7 @@ template hipError_t launch_ifft_trunc<float, ff32, ff32>(int, const cplx<float>*
                                                          const int32_t*, void*, int);
 template hipError_t launch_ifft_trunc<float, float, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t, int,
                                                           const int32_t*, void*, int);
+template hipError_t launch_ifft_trunc<float, double, ff32>(int, const cplx<float>*, ff32*, int64_t, hipStream_t, int,
+                                                           const int32_t*, void*, int);
 
 }  // namespace lgfdev

@@ -756,8 +756,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                      lname("fft_inv_l", l), lvN(l) * (Sl(l) * cs + p3 * us), lvN(l) * fft_flops(2 * n));
         } else {
             LGF_STEP(st,
-                     (launch_ifft_trunc<T, U, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, st, 0, nullptr,
-                                                 pl->d_scratch)),
+                     (launch_ifft_trunc<T, double, U>(p, (const C*)L.d_uhat, (U*)L.d_util, L.nint, st, 0, nullptr,
+                                                      pl->d_scratch)),
                      lname("fft_inv_l", l), lvN(l) * (Sl(l) * cs + p3 * us), lvN(l) * fft_flops(2 * p));
         }
         return hipSuccess;
@@ -882,7 +882,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                 const int nk = (int)std::min<size_t>(kMaxFarSegs, il.size() - k0);
                 const std::string nm = il.size() == 1 ? lname("fft_inv_l", ilo)
                                                       : "fft_inv_l" + std::to_string(ilo) + "-" + std::to_string(ihi);
-                LGF_STEP(s2, (launch_ifft_trunc_levels<T, U, U>(p, il.data() + k0, nk, s2)), nm,
+                LGF_STEP(s2, (launch_ifft_trunc_levels<T, double, U>(p, il.data() + k0, nk, s2)), nm,
                          k0 == 0 ? ibytes : 0.0, k0 == 0 ? iflops : 0.0);
             }
             for (int l = pl->Ltop - 1; l >= 1; --l)
