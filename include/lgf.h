@@ -93,8 +93,10 @@ typedef struct {
  *   levels    : tree levels L (leaves at 1); <= 0 selects the full depth
  *               1 + ceil(log2(extent)).  When L is below full depth the top level's
  *               list holds every non-adjacent interval.
- *   prec      : LGF_F64, or LGF_F32 (FP32 transforms and products, FP64 kernel tables
- *               and spectrum generation, FP64 final add of far and near fields)
+ *   prec      : LGF_F64, or LGF_F32 (FP32 forward transforms, products and level-0
+ *               inverse; level >= 1 inverse transforms in FP64 arithmetic with
+ *               float-float node values through Interp; FP64 kernel tables and spectrum
+ *               generation, FP64 final add of far and near fields)
  *   hip_stream: stream for the set-up work (hipStream_t or NULL)
  *   out       : receives the plan on success
  * Errors: LGF_ERR_ARG, LGF_ERR_LAYOUT, LGF_ERR_OOM, LGF_ERR_BUDGET, LGF_ERR_DEVICE.
