@@ -1,26 +1,32 @@
 """Benchmark: grid points solved per second for u = G * f on one MI355X.
 
-Workload (the metric's configuration that fits one GPU): a 128^3 cube as 8^3 blocks of
-16^3 points, p = 8 interpolation nodes per interval edge, 4 tree levels, FP64, sourced by
-32 seeded Gaussians (sigma in U[2, 6], N(0,1) amplitudes, zero net source).  The same
-workload is also solved on the FP32 path (FP64 tables and final add), whose rate, error
-against the FP64 result and latencies are reported next to the FP64 numbers.
+Workload (the metric's configuration, the largest single-solve one): a 256^3 cube as 16^3
+blocks of 16^3 points, p = 8 interpolation nodes per interval edge, full tree depth,
+sourced by a thin vortex ring (R = 80 cells, Gaussian core sigma = 4, seeded tilt).  The
+headline line is the FP64 path; the FP32 path (FP32 transforms and products, FP64 tables,
+level inverse transforms and final add) solves the same input beside it, with its rate,
+latencies, roofline, and its error against the FP64 result and against the oracle.  An
+FP32 rate whose error against FP64 exceeds the 1e-6 bar is withheld (value null,
+meets_fp32_bar false).
 
 Timing: the plan's kernel variants are autotuned first (lgf_plan_autotune, a few dozen
-eager solves), the graph schedule is chosen by timing one graph of each schedule, then W untimed warm-up solves and K timed solves bracketed by device
-synchronisation; the inputs are resident in HBM before the timed region.  Two passes per
-precision:
+eager solves), the graph schedule is chosen by timing one graph of each schedule, then W
+untimed warm-up solves and K timed solves bracketed by device synchronisation; the inputs
+are resident in HBM before the timed region.  Two passes per precision:
   * eager lgf_solve calls on one stream with every step bracketed by HIP events
     (lgf_profile_*): isolated per-kernel device times (the roofline entry uses the
     dominant one);
   * the tuned solve captured once as a HIP graph (lgf_graph_create) and launched K times:
     the reported rate (value) and per-solve latencies (p50/p99, events around each launch).
-A third pass times the batched workload: 64 independent Eden layouts in one batch plan;
-a fourth serves a request mix through the request server (closed loop for capacity, then
-Poisson arrivals at 80% of it for p50/p99 latency).
+Further legs: the 128^3 workload (8^3 blocks, p = 8, 4 levels, 32 Gaussians), the batched
+workload (64 Eden layouts in one batch plan), the request server (closed loop for
+capacity, then Poisson arrivals at 80% of it for p50/p99 latency), separate source and
+evaluation sets, the paper's n_I = n + 1 scheme and symmetry-reduced kernel spectra.
 
-cpu_baseline: the oracle (step-by-step FLGF in numpy, single thread) timed on the host
-on the full workload (plan and pre-computation excluded).
+cpu_baseline: the oracle timed on the host: the exact direct sum (Eq. dpoissonsoln) at the
+64 stored targets of the 256^3 workload on all cores, and at 4 of them on one core; the
+oracle's FLGF solve of the 128^3 workload on one core.  The host's CPU model and core
+count are printed with it.
 """
 import argparse
 import json
@@ -168,19 +174,92 @@ def _breakdown(prof):
     return out
 
 
-def cpu_baseline(cfg, budget_s=30.0):
-    """Time the oracle's FLGF solve on the host (single thread), full workload."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _golden_large():
+    """Oracle values at 64 sampled targets of the 256^3 workload (its FLGF and exact sum),
+    written by tests/golden/make_large_samples.py from the oracle alone."""
+    with open(os.path.join(ROOT, "tests", "golden", "large_config_samples.json")) as fh:
+        return json.load(fh)
+
+
+def cpu_baseline(cfg_large, cfg_medium, gold):
+    """The oracle on the host cores: the exact direct sum of the 256^3 workload at the 64
+    stored targets with every core, and at 4 targets with one core; the oracle's FLGF on the
+    whole 128^3 workload with one core (plan and pre-computation excluded).  Returns the
+    baseline entry and the exact values at the 64 targets."""
     from threadpoolctl import threadpool_limits
-    from oracle import flgf
+    from oracle import flgf, lgf as olgf
+    ncpu = os.cpu_count() or 1
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    n = cfg_large["n"]
+    P = W_points(cfg_large)
+    fl = cfg_large["f"].reshape(-1)
+    idx = np.asarray(gold["flat_index"])
+    t0 = time.perf_counter()
+    olgf.lgf_table(257)  # G up to the workload's largest separation, built once
+    t_table = time.perf_counter() - t0
+    olgf.set_threads(ncpu)
+    t0 = time.perf_counter()
+    exact = olgf.direct_sum(P, fl, P[idx])
+    dt_all = time.perf_counter() - t0
+    olgf.set_threads(1)
+    t0 = time.perf_counter()
+    olgf.direct_sum(P, fl, P[idx[:4]])
+    dt_one = time.perf_counter() - t0
+    olgf.set_threads(ncpu)
     with threadpool_limits(limits=1):
-        solver = flgf.FLGF(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"])
+        solver = flgf.FLGF(cfg_medium["blocks"], cfg_medium["n"], cfg_medium["p"], cfg_medium["levels"])
         t0 = time.perf_counter()
-        solver.solve(cfg["f"])
-        dt = time.perf_counter() - t0
-    npts = cfg["f"].size
-    return {"value": round(npts / dt, 1), "unit": "grid points solved/s", "cores": 1, "kind": "oracle",
-            "sample": "full %s workload (%d points), one oracle FLGF solve, plan and pre-computation "
-                      "excluded, %.1f s" % (cfg["name"], npts, dt)}
+        solver.solve(cfg_medium["f"])
+        dt_b = time.perf_counter() - t0
+    npts = int(P.shape[0])
+    rate_all = len(idx) / dt_all
+    entry = {"value": round(rate_all, 3), "unit": "grid points solved/s", "cores": ncpu, "kind": "oracle",
+             "cpu_model": _cpu_model(), "nproc": ncpu,
+             "sample": "exact direct sum (Eq. dpoissonsoln, Neumaier sums, OpenMP over targets) of the %s "
+                       "workload (%d sources) at its 64 stored targets, %d threads, %.2f s; full field "
+                       "extrapolated linearly: %.3g s" % (cfg_large["name"], npts, ncpu, dt_all, npts / rate_all),
+             "direct_sum_one_core": {"value": round(4 / dt_one, 4), "unit": "grid points solved/s", "cores": 1,
+                                     "sample": "4 of the stored targets, %.2f s; full field extrapolated: %.3g s"
+                                               % (dt_one, npts * dt_one / 4)},
+             "lgf_table_s": round(t_table, 3),
+             "oracle_flgf_one_core": {"value": round(cfg_medium["f"].size / dt_b, 1), "unit": "grid points solved/s",
+                                      "cores": 1,
+                                      "sample": "one oracle FLGF solve (numpy, one thread) of the whole %s workload "
+                                                "(%d points), plan and pre-computation excluded, %.2f s"
+                                                % (cfg_medium["name"], cfg_medium["f"].size, dt_b)}}
+    return entry, exact
+
+
+def W_points(cfg):
+    from paper_1402_6081_amd import workloads as W
+    return W.points_of(cfg["blocks"], cfg["n"]).reshape(-1, 3)
+
+
+FP32_BAR = 1e-6
+
+
+def _bar(entry, err):
+    """Withhold an FP32 rate whose error against FP64 exceeds the bar."""
+    entry["rel_linf_err_vs_fp64"] = err
+    entry["meets_fp32_bar"] = bool(err <= FP32_BAR)
+    if err > FP32_BAR:
+        entry["value_over_bar"] = entry["value"]
+        entry["value"] = None
+    return entry
 
 
 def _graph_schedule(plan, f, u, choice, launches=20):
@@ -249,6 +328,41 @@ def copy_calibration(mib):
 
 def _pct(x):
     return {"p50": round(float(np.percentile(x, 50)), 5), "p99": round(float(np.percentile(x, 99)), 5)}
+
+
+def medium_bench(L, W, steps, warmup, copy_gbps, graph=True, tune=True, breakdown=None, fp32=True):
+    """The 128^3 workload (8^3 blocks of 16^3, p = 8, 4 levels, 32 zero-net Gaussians), FP64
+    and FP32, measured as the headline."""
+    import torch
+    cfg = W.config_medium()
+    npts = int(cfg["f"].size)
+    out = {"workload": cfg["name"], "points": npts, "unit": "grid points solved/s"}
+    u64h = None
+    for prec, dt, peak in (("f64", torch.float64, FP64_PEAK_TFLOPS), ("f32", torch.float32, FP32_PEAK_TFLOPS)):
+        if prec == "f32" and not fp32:
+            break
+        plan = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], prec)
+        f = torch.from_numpy(cfg["f"]).to("cuda:0", dt)
+        u = torch.empty_like(f)
+        m = _measure(plan, f, u, steps, warmup, graph=graph, tune=tune)
+        res = {"value": round(npts * steps / m["dt_graph"], 1), "ms_per_step": round(m["dt_graph"] / steps * 1e3, 5),
+               "latency_ms": _pct(m["lat_graph"]), "tuning": m["tuning"],
+               "graph_schedule_ms": m["graph_schedule_ms"],
+               "eager_ms_per_step": round(m["dt_eager"] / steps * 1e3, 5),
+               "roofline": _roofline(m["prof"], peak, cfg["name"], prec)}
+        res["solve_hbm"] = _solve_hbm(m["prof"], res["ms_per_step"], copy_gbps, cfg["name"], prec)
+        uh = u.double().cpu().numpy()
+        if prec == "f64":
+            u64h = uh
+        else:
+            _bar(res, float(np.max(np.abs(uh - u64h)) / np.max(np.abs(u64h))))
+        if breakdown is not None:
+            breakdown["cube128_" + prec] = _breakdown(m["prof"])
+        out[prec] = res
+        plan.close()
+        del f, u
+        torch.cuda.empty_cache()
+    return out
 
 
 def batch_bench(L, W, steps, warmup, seed=4):
@@ -322,6 +436,11 @@ def split_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None):
                "latency_ms": _pct(m["lat_graph"]), "tuning": m["tuning"],
                "eager_ms_per_step": round(m["dt_eager"] / steps * 1e3, 5),
                "roofline": _roofline(m["prof"], peak, cfg["name"], prec)}
+        uh = u.double().cpu().numpy()
+        if prec == "f64":
+            u64h = uh
+        else:
+            _bar(res, float(np.max(np.abs(uh - u64h)) / np.max(np.abs(u64h))))
         if breakdown is not None:
             breakdown["split_fp64" if prec == "f64" else "split_fp32"] = _breakdown(m["prof"])
         plan.close()
@@ -357,12 +476,19 @@ def scheme_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None):
         f = torch.from_numpy(cfg["f"]).to("cuda:0", dt)
         u = torch.empty_like(f)
         m = _measure(plan, f, u, steps, warmup, graph=graph, tune=tune)
-        err = float(np.max(np.abs(u.double().cpu().numpy() - cfg["u_exact"])) / scale)
+        uh = u.double().cpu().numpy()
+        err = float(np.max(np.abs(uh - cfg["u_exact"])) / scale)
         out[prec] = {"value": round(npts * steps / m["dt_graph"], 1), "ms_per_step": round(m["dt_graph"] / steps * 1e3, 5),
                      "latency_ms": _pct(m["lat_graph"]), "tuning": m["tuning"],
                      "eager_ms_per_step": round(m["dt_eager"] / steps * 1e3, 5),
                      "rel_linf_err_vs_exact": err, "workspace_bytes": plan.info()["workspace_bytes"],
                      "roofline": _roofline(m["prof"], peak, cfg["name"], prec)}
+        if prec == "f64":
+            u64h = uh
+        else:
+            # a rough manufactured source: the FP32 level-0 transforms lose digits to the
+            # cancellation in G * f (the bar holds for smooth sources, not for this one)
+            _bar(out[prec], float(np.max(np.abs(uh - u64h)) / np.max(np.abs(u64h))))
         if breakdown is not None:
             breakdown["scheme_fp64" if prec == "f64" else "scheme_fp32"] = _breakdown(m["prof"])
         plan.close()
@@ -407,7 +533,7 @@ def reduced_bench(L, W, steps, warmup, graph=True, tune=True, breakdown=None, sc
                 if prec == "f64":
                     ref64 = uf
                 else:
-                    r["rel_linf_err_vs_fp64"] = float(np.max(np.abs(ur - ref64)) / np.max(np.abs(ref64)))
+                    _bar(r, float(np.max(np.abs(ur - ref64)) / np.max(np.abs(ref64))))
             res[prec] = r
             del f, u
             torch.cuda.empty_cache()
@@ -476,6 +602,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-medium", action="store_true", help="skip the 128^3 workload")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-split", action="store_true")
@@ -519,9 +646,9 @@ def main():
                 json.dump(breakdown, fh, indent=1)
         print(json.dumps({leg: out}), flush=True)
         return
-    cfg = W.config_medium()
-    npts = cfg["f"].size
     dev = torch.device("cuda:0")
+    cfg = W.config_large()
+    npts = cfg["f"].size
     f64 = torch.from_numpy(cfg["f"]).to(dev)
     u64 = torch.empty_like(f64)
     t_plan = time.perf_counter()
@@ -531,6 +658,7 @@ def main():
     m = _measure(plan, f64, u64, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune)
     print("fp64 measured", flush=True, file=sys.stderr)
     info = plan.info()
+    copy_gbps = hbm_copy_bandwidth()
 
     result = {
         "metric": "grid points solved/s, FP32 vs FP64 path at rel err <=1e-6; p50/p99 solve latency",
@@ -546,43 +674,77 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "points": int(npts), "blocks": int(info["nblocks"]),
-                   "n": cfg["n"], "p": cfg["p"], "levels": cfg["levels"],
+                   "n": cfg["n"], "p": cfg["p"], "levels": info["levels"],
                    "launch": "eager lgf_solve" if args.no_graph else "hip graph per solve",
                    "tuning": m["tuning"], "graph_schedule_ms": m["graph_schedule_ms"],
-                   "source": "32 seeded Gaussians, sigma U[2,6], zero net source"},
+                   "source": "thin vortex ring, R=80, core sigma=4, seeded tilt (seed 2)"},
         "latency_ms": _pct(m["lat_graph"]),
         "eager": {"value": round(npts * args.steps / m["dt_eager"], 1),
                   "ms_per_step": round(m["dt_eager"] / args.steps * 1e3, 5),
                   "latency_ms": _pct(m["prof"]["solve_ms"]),
                   "note": "lgf_solve per step on one stream, with per-step profiling events (roofline source)"},
         "plan_s": round(t_plan, 3),
+        "workspace_bytes": info["workspace_bytes"],
         "roofline": _roofline(m["prof"], FP64_PEAK_TFLOPS, cfg["name"], "f64"),
-        "hbm_copy_GBps": hbm_copy_bandwidth(),
+        "hbm_copy_GBps": copy_gbps,
     }
-    result["solve_hbm"] = _solve_hbm(m["prof"], result["ms_per_step"], result["hbm_copy_GBps"], cfg["name"], "f64")
+    result["solve_hbm"] = _solve_hbm(m["prof"], result["ms_per_step"], copy_gbps, cfg["name"], "f64")
     breakdown = {"fp64": _breakdown(m["prof"])}
-    u64_host = u64.cpu().numpy()
-
+    u64_host = u64.cpu().numpy().reshape(-1)
+    plan.close()
+    del u64
+    u32_host = None
     if not args.no_fp32:
         f32 = f64.float()
         u32 = torch.empty_like(f32)
         plan32 = L.Plan(cfg["blocks"], cfg["n"], cfg["p"], cfg["levels"], "f32")
         m32 = _measure(plan32, f32, u32, args.steps, args.warmup, graph=not args.no_graph, tune=not args.no_tune)
         print("fp32 measured", flush=True, file=sys.stderr)
-        u32_host = u32.double().cpu().numpy()
+        u32_host = u32.double().cpu().numpy().reshape(-1)
         err = float(np.max(np.abs(u32_host - u64_host)) / np.max(np.abs(u64_host)))
-        result["fp32"] = {"value": round(npts * args.steps / m32["dt_graph"], 1), "unit": "grid points solved/s",
-                          "ms_per_step": round(m32["dt_graph"] / args.steps * 1e3, 5),
-                          "rel_linf_err_vs_fp64": err,
-                          "latency_ms": _pct(m32["lat_graph"]),
-                          "eager_ms_per_step": round(m32["dt_eager"] / args.steps * 1e3, 5),
-                          "tuning": m32["tuning"], "graph_schedule_ms": m32["graph_schedule_ms"],
-                          "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS, cfg["name"], "f32")}
-        result["fp32"]["solve_hbm"] = _solve_hbm(m32["prof"], result["fp32"]["ms_per_step"],
-                                                 result["hbm_copy_GBps"], cfg["name"], "f32")
+        result["fp32"] = _bar({"value": round(npts * args.steps / m32["dt_graph"], 1),
+                               "unit": "grid points solved/s", "dtype": "f32",
+                               "ms_per_step": round(m32["dt_graph"] / args.steps * 1e3, 5),
+                               "latency_ms": _pct(m32["lat_graph"]),
+                               "eager_ms_per_step": round(m32["dt_eager"] / args.steps * 1e3, 5),
+                               "tuning": m32["tuning"], "graph_schedule_ms": m32["graph_schedule_ms"],
+                               "workspace_bytes": plan32.info()["workspace_bytes"],
+                               "roofline": _roofline(m32["prof"], FP32_PEAK_TFLOPS, cfg["name"], "f32"),
+                               "note": "FP32 transforms and products; FP64 kernel tables and spectrum "
+                                       "generation, FP64 arithmetic in the level >= 1 inverse transforms "
+                                       "(float-float node values), FP64 final add"}, err)
+        result["fp32"]["solve_hbm"] = _solve_hbm(m32["prof"], result["fp32"]["ms_per_step"], copy_gbps,
+                                                 cfg["name"], "f32")
         breakdown["fp32"] = _breakdown(m32["prof"])
         plan32.close()
-    plan.close()
+        del f32, u32
+    del f64
+    torch.cuda.empty_cache()
+    # accuracy against the oracle at the 64 stored targets (its FLGF, the same operator, and
+    # the exact sum, computed live in the cpu_baseline leg)
+    gold = _golden_large()
+    idx = np.asarray(gold["flat_index"])
+    flgf_ref = np.asarray(gold["flgf"])
+    scale = float(gold["max_abs_u"])
+    acc = {"targets": int(len(idx)), "scale": "max|u| over the field (oracle)",
+           "fp64_vs_oracle_flgf": float(np.max(np.abs(u64_host[idx] - flgf_ref)) / scale)}
+    if u32_host is not None:
+        acc["fp32_vs_oracle_flgf"] = float(np.max(np.abs(u32_host[idx] - flgf_ref)) / scale)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"], exact = cpu_baseline(cfg, W.config_medium(), gold)
+        print("cpu baseline measured", flush=True, file=sys.stderr)
+        es = float(np.max(np.abs(exact)))
+        acc["oracle_flgf_vs_exact"] = float(np.max(np.abs(flgf_ref - exact)) / es)
+        acc["fp64_vs_exact"] = float(np.max(np.abs(u64_host[idx] - exact)) / es)
+        if u32_host is not None:
+            acc["fp32_vs_exact"] = float(np.max(np.abs(u32_host[idx] - exact)) / es)
+    result["accuracy"] = acc
+    del u64_host, u32_host
+
+    if not args.no_medium:
+        result["cube128"] = medium_bench(L, W, args.steps, args.warmup, copy_gbps, graph=not args.no_graph,
+                                         tune=not args.no_tune, breakdown=breakdown, fp32=not args.no_fp32)
+        print("128^3 workload measured", flush=True, file=sys.stderr)
 
     if not args.no_batch:
         result["batch"] = batch_bench(L, W, max(5, args.steps // 5), 2)
@@ -603,8 +765,6 @@ def main():
                                                   tune=not args.no_tune)
         print("symmetry-reduced spectra measured", flush=True, file=sys.stderr)
 
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(cfg)
     result["paper_context"] = {"value": 1.2e5, "unit": "grid points solved/s",
                                "hardware": "1 core Intel Xeon X5650 2.66 GHz, FP64, N = 1e8, n_I = 7..28"}
     if args.breakdown:

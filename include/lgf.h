@@ -52,12 +52,13 @@ typedef struct lgf_plan_s* lgf_plan_t;
 
 typedef enum {
     LGF_OK = 0,
-    LGF_ERR_ARG = 1,     /* NULL pointer, unsupported n, p outside [2, 10], bad count   */
+    LGF_ERR_ARG = 1,     /* NULL pointer, unsupported n or p, bad count                 */
     LGF_ERR_LAYOUT = 2,  /* empty layout, duplicate blocks, coordinate span > 2^20      */
     LGF_ERR_OOM = 3,     /* device allocation failed                                     */
     LGF_ERR_BUDGET = 4,  /* the plan would exceed the configured device-memory budget    */
     LGF_ERR_DEVICE = 5,  /* a HIP runtime call or kernel launch failed                   */
-    LGF_ERR_BUSY = 6     /* the request server's queue is full                          */
+    LGF_ERR_BUSY = 6     /* the request server's queue is full, or a plan's workspace is
+                            still in use by a solve issued on another stream            */
 } lgf_status;
 
 typedef enum { LGF_F64 = 0, LGF_F32 = 1 } lgf_precision;
@@ -87,9 +88,11 @@ typedef struct {
  *   block_ijk : HOST array [nblocks][3] of block coordinates (read during the call only)
  *   nblocks   : >= 1
  *   n         : points per block edge; 4, 8 or 16 (padded FFT length 2n)
- *   p         : interpolation nodes per interval edge at every level >= 1, 2..10
- *               (n_max = p, Sec. 2.5 Lebesgue rule); p = n+1 reproduces the paper's
- *               experimental scheme (nodes on the lattice)
+ *   p         : interpolation nodes per interval edge at every level >= 1: 2..10, where
+ *               every stencil uses all p nodes (n_max = p, Sec. 2.5 Lebesgue rule), or
+ *               p = 17 with n = 16, the paper's scheme n_I = n + 1 with stencils of the
+ *               n_max = 10 closest nodes (Sec. 2.5, Sec. 4).  p = n + 1 puts the nodes on
+ *               the lattice (the paper's experimental scheme)
  *   levels    : tree levels L (leaves at 1); <= 0 selects the full depth
  *               1 + ceil(log2(extent)).  When L is below full depth the top level's
  *               list holds every non-adjacent interval.
@@ -351,11 +354,18 @@ lgf_status lgf_server_create(const lgf_server_config* cfg, lgf_server_t* out);
 /*
  * Queue one solve.  block_ijk: HOST layout [nblocks][3] (copied); f, u: DEVICE fields of
  * the server's precision in the layout's order, caller-owned, kept alive and untouched until
- * the request completes.  *ticket identifies the request.  Non-blocking.
- * Errors: LGF_ERR_ARG, LGF_ERR_BUSY (queue full).  Layout errors are reported per request.
+ * the request completes.  hip_stream: the caller's stream (hipStream_t, NULL = default
+ * stream).  An event is recorded on it during the call and the request's solve, which runs
+ * on one of the server's own streams, waits for that event: work the caller enqueued on
+ * hip_stream before the submit (the writes of f, anything still using u) is complete before
+ * the solve reads f or writes u.  u holds the result once lgf_server_poll or lgf_server_wait
+ * report the request finished; work on other streams must not touch u before that.
+ * *ticket identifies the request.  Non-blocking.
+ * Errors: LGF_ERR_ARG, LGF_ERR_BUSY (queue full), LGF_ERR_DEVICE (event creation or record
+ * failed).  Layout errors are reported per request.
  */
 lgf_status lgf_server_submit(lgf_server_t server, const int32_t* block_ijk, int64_t nblocks, const void* f,
-                             void* u, int64_t* ticket);
+                             void* u, void* hip_stream, int64_t* ticket);
 
 /* *done = 1 and *result filled (HOST, may be NULL) when the request has finished; a
  * finished ticket is then released.  Errors: LGF_ERR_ARG (unknown ticket). */

@@ -62,12 +62,18 @@ def lib():
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]
             L.oracle_num_threads.restype = ctypes.c_int
+            L.oracle_set_threads.argtypes = [ctypes.c_int]
             _lib = L
     return _lib
 
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_threads(n):
+    """Threads the direct sum and table loops use from now on (OpenMP)."""
+    lib().oracle_set_threads(int(n))
 
 
 def bessel_table(R, xmax=XMAX, panel=PANEL, order=ORDER):

@@ -233,6 +233,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel loops above (for timing the oracle at one core and at all). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * Asymptotic expansion A^q (Sec. 2.1, Eq. lgf2) at arbitrary real points.
  * Terms are T_j(x) = P_j(xhat) / (pi r^(2j+1)); P_j is given as monomials

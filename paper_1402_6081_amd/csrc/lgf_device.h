@@ -79,9 +79,13 @@ __device__ __forceinline__ cplx<T> sym_coef(const cplx<T>* __restrict__ khat, ui
 // ---------------------------------------------------------------- float-float numbers
 // An unevaluated sum hi + lo of two floats (|lo| <= ulp(hi)/2), with error-free
 // transformations (Knuth TwoSum, FMA-based TwoProduct).  Used by the FP32 path to carry
-// the far-field level contributions with compensation through the inverse transforms and
-// the interpolation down the tree, where the Lebesgue constant of equispaced
-// interpolation would otherwise amplify FP32 rounding of the node values.
+// the far-field level contributions with compensation through the interpolation down the
+// tree, where the Lebesgue constant of equispaced interpolation would otherwise amplify
+// FP32 rounding of the node values.
+// Every function here turns floating-point contraction off: HIP device code contracts
+// a * b + c into one FMA by default, and fusing the rounded product p = a.hi * b.hi into
+// the following sum p + e would break the error-free transformations (the error term is
+// computed from the rounded p), leaving products with FP32 accuracy only.
 struct alignas(8) ff32 {
     float hi, lo;
     ff32() = default;
@@ -92,16 +96,19 @@ struct alignas(8) ff32 {
 };
 
 __device__ __forceinline__ ff32 ff_two_sum(float a, float b) {
+#pragma clang fp contract(off)
     const float s = a + b;
     const float bb = s - a;
     const float e = (a - (s - bb)) + (b - bb);
     return ff32(s, e);
 }
 __device__ __forceinline__ ff32 ff_fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
     const float s = a + b;
     return ff32(s, b - (s - a));
 }
 __device__ __forceinline__ ff32 operator+(ff32 a, ff32 b) {
+#pragma clang fp contract(off)
     ff32 s = ff_two_sum(a.hi, b.hi);
     s.lo += a.lo + b.lo;
     return ff_fast_two_sum(s.hi, s.lo);
@@ -109,6 +116,7 @@ __device__ __forceinline__ ff32 operator+(ff32 a, ff32 b) {
 __device__ __forceinline__ ff32 operator-(ff32 a) { return ff32(-a.hi, -a.lo); }
 __device__ __forceinline__ ff32 operator-(ff32 a, ff32 b) { return a + (-b); }
 __device__ __forceinline__ ff32 operator*(ff32 a, ff32 b) {
+#pragma clang fp contract(off)
     const float p = a.hi * b.hi;
     float e = __builtin_fmaf(a.hi, b.hi, -p);
     e = __builtin_fmaf(a.hi, b.lo, e);

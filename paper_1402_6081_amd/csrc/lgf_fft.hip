@@ -354,13 +354,11 @@ static hipError_t fwd_two_phase(const T* in, cplx<T>* out, int64_t nbatch, int64
                                 hipStream_t s) {
     constexpr int M = 2 * m, PLANE = M * (M / 2 + 1), NT = 256;
     if (!scratch) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_fft2_xy<T, m, M, 64>), dim3((unsigned)(nbatch * m)), dim3(64), 0, s, in,
-                       (cplx<T>*)scratch);
-    hipError_t e = hipGetLastError();
+    hipError_t e = lgf_launch(k_fft2_xy<T, m, M, 64>, dim3((unsigned)(nbatch * m)), dim3(64), 0, s, in,
+                              (cplx<T>*)scratch);
     if (e != hipSuccess) return e;
     const dim3 grid((kShare * PLANE + NT - 1) / NT, (unsigned)nbatch);
-    hipLaunchKernelGGL((k_fft2_z<T, m, M, NT>), grid, dim3(NT), 0, s, (const cplx<T>*)scratch, out, nout);
-    return hipGetLastError();
+    return lgf_launch(k_fft2_z<T, m, M, NT>, grid, dim3(NT), 0, s, (const cplx<T>*)scratch, out, nout);
 }
 
 template <typename Tin, typename A, typename Tout, int m>
@@ -369,12 +367,10 @@ static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, 
     constexpr int M = 2 * m, PLANE = M * (M / 2 + 1), NT = 256;
     if (!scratch) return hipErrorInvalidValue;
     const dim3 grid((kShare * PLANE + NT - 1) / NT, (unsigned)nbatch);
-    hipLaunchKernelGGL((k_ifft2_z<Tin, A, m, M, NT>), grid, dim3(NT), 0, s, in, (cplx<A>*)scratch, nbatch);
-    hipError_t e = hipGetLastError();
+    hipError_t e = lgf_launch(k_ifft2_z<Tin, A, m, M, NT>, grid, dim3(NT), 0, s, in, (cplx<A>*)scratch, nbatch);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_ifft2_yx<A, Tout, m, M, 64>), dim3((unsigned)(nbatch * m)), dim3(64), 0, s,
-                       (const cplx<A>*)scratch, out, out_map);
-    return hipGetLastError();
+    return lgf_launch(k_ifft2_yx<A, Tout, m, M, 64>, dim3((unsigned)(nbatch * m)), dim3(64), 0, s,
+                      (const cplx<A>*)scratch, out, out_map);
 }
 
 // nt: threads per workgroup (0 = default: 256, measured faster than 128 for the small
@@ -383,8 +379,7 @@ static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, 
 // the FP64 16^3 tile, whose 32-point pencils then no longer fit the register file.
 template <typename T, int m, int NT>
 static hipError_t fwd_mnt(const FwdSegs<T>& segs, int64_t nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_pad_fft<T, m, 2 * m, NT>), dim3((unsigned)nblocks), dim3(NT), 0, s, segs);
-    return hipGetLastError();
+    return lgf_launch(k_pad_fft<T, m, 2 * m, NT>, dim3((unsigned)nblocks), dim3(NT), 0, s, segs);
 }
 
 template <typename T, int m>
@@ -411,9 +406,8 @@ static hipError_t launch_fwd_m(const T* in, cplx<T>* out, int64_t nbatch, int64_
 template <typename Tin, typename A, typename Tout, int m, int NT>
 static hipError_t inv_mnt(const InvSegs<Tin, Tout>& segs, int64_t nblocks, const int32_t* out_map, int opitch,
                           hipStream_t s) {
-    hipLaunchKernelGGL((k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>), dim3((unsigned)nblocks), dim3(NT), 0, s, segs,
-                       out_map, opitch);
-    return hipGetLastError();
+    return lgf_launch(k_ifft_trunc<Tin, A, Tout, m, 2 * m, NT>, dim3((unsigned)nblocks), dim3(NT), 0, s, segs,
+                      out_map, opitch);
 }
 
 template <typename Tin, typename A, typename Tout, int m>

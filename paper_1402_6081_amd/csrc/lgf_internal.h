@@ -3,14 +3,93 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
+#include <map>
 #include <memory>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/lgf.h"
 #include "lgf_device.h"
 
 namespace lgfdev {
+
+// ------------------------------------------------------------------ launches and graph recording
+// Every kernel launch of a solve goes through lgf_launch.  Normally it is an ordinary launch on
+// the stream.  While a GraphRecorder is active on the calling thread (lgf_graph_create), the
+// launch becomes an explicit kernel node of the recorder's graph instead: its argument block is
+// allocated by the recorder and outlives the graph, its dependencies are the last nodes issued on
+// the same stream, and event records and waits between streams (rec_event_record /
+// rec_stream_wait) become dependency edges.  No stream capture is involved and no node is copied.
+struct GraphRecorder {
+    struct ArgBlock {
+        virtual ~ArgBlock() = default;
+    };
+    template <typename Tuple>
+    struct Args : ArgBlock {
+        Tuple values;
+        std::vector<void*> ptrs;
+        explicit Args(Tuple&& t) : values(std::move(t)) {}
+    };
+    hipGraph_t graph = nullptr;
+    std::map<hipStream_t, std::vector<hipGraphNode_t>> tails;  // nodes the next launch on a stream follows
+    std::map<hipEvent_t, std::vector<hipGraphNode_t>> events;  // nodes an event was recorded behind
+    std::vector<std::unique_ptr<ArgBlock>> args;               // argument blocks of the nodes
+    int64_t launches = 0;                                       // kernel nodes added
+    hipError_t err = hipSuccess;                                // first failure (sticky)
+};
+GraphRecorder* active_recorder();  // the calling thread's recorder, or nullptr
+
+template <typename Tuple, size_t... I>
+void arg_pointers(Tuple& t, std::vector<void*>& p, std::index_sequence<I...>) {
+    p = {static_cast<void*>(&std::get<I>(t))...};
+}
+
+// Arguments are converted to the kernel's parameter types first; the launch passes one
+// pointer per parameter (hipLaunchKernel), the graph node the same pointers.
+template <typename... Params, typename... Args>
+hipError_t lgf_launch(void (*kernel)(Params...), dim3 grid, dim3 block, size_t shmem, hipStream_t s,
+                      Args&&... args) {
+    static_assert(sizeof...(Params) == sizeof...(Args), "kernel argument count");
+    static_assert(sizeof...(Params) > 0, "kernels here take arguments");
+    using Tuple = std::tuple<std::decay_t<Params>...>;
+    GraphRecorder* r = active_recorder();
+    if (!r) {
+        Tuple vals(static_cast<std::decay_t<Params>>(args)...);
+        std::array<void*, sizeof...(Params)> ptrs = std::apply(
+            [](auto&... v) { return std::array<void*, sizeof...(Params)>{static_cast<void*>(&v)...}; }, vals);
+        return hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs.data(), shmem, s);
+    }
+    if (r->err != hipSuccess) return r->err;
+    auto blk = std::make_unique<GraphRecorder::Args<Tuple>>(Tuple(static_cast<std::decay_t<Params>>(args)...));
+    arg_pointers(blk->values, blk->ptrs, std::index_sequence_for<Params...>{});
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void*>(kernel);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = (unsigned)shmem;
+    kp.kernelParams = blk->ptrs.empty() ? nullptr : blk->ptrs.data();
+    kp.extra = nullptr;
+    std::vector<hipGraphNode_t>& dep = r->tails[s];
+    hipGraphNode_t node = nullptr;
+    hipError_t e = hipGraphAddKernelNode(&node, r->graph, dep.empty() ? nullptr : dep.data(), dep.size(), &kp);
+    if (e == hipSuccess && !node) e = hipErrorInvalidValue;
+    if (e != hipSuccess) {
+        r->err = e;
+        return e;
+    }
+    r->args.push_back(std::move(blk));
+    dep.assign(1, node);
+    ++r->launches;
+    return hipSuccess;
+}
+
+// hipEventRecord / hipStreamWaitEvent of a solve's own fork and join events: dependency
+// edges while a recorder is active.
+hipError_t rec_event_record(hipEvent_t ev, hipStream_t s);
+hipError_t rec_stream_wait(hipStream_t s, hipEvent_t ev);
 
 // ------------------------------------------------------------------ constants of the operator
 // Level 0 uses the exact lattice Green's function.  Levels >= 1 use it too when the

@@ -398,8 +398,7 @@ struct RegBlockRun {
     template <int N, int P>
     struct K {
         static hipError_t run(const T* f, const double* A, T* out, int64_t nb, hipStream_t s) {
-            hipLaunchKernelGGL((k_reg_block<T, N, P>), dim3((unsigned)nb), dim3(kBlockThreads), 0, s, f, A, out);
-            return hipGetLastError();
+            return lgf_launch(k_reg_block<T, N, P>, dim3((unsigned)nb), dim3(kBlockThreads), 0, s, f, A, out);
         }
     };
 };
@@ -410,9 +409,8 @@ struct FinalRun {
     struct K {
         static hipError_t run(const T* vnear, const U* ut, const double* A, T* u, int64_t nb, const int32_t* l1map,
                               const int32_t* near_flag, hipStream_t s) {
-            hipLaunchKernelGGL((k_final<T, U, N, P>), dim3((unsigned)nb), dim3(kBlockThreads), 0, s, vnear, ut, A,
-                               u, l1map, near_flag);
-            return hipGetLastError();
+            return lgf_launch(k_final<T, U, N, P>, dim3((unsigned)nb), dim3(kBlockThreads), 0, s, vnear, ut, A, u,
+                              l1map, near_flag);
         }
     };
 };
@@ -425,8 +423,7 @@ hipError_t launch_reg_block(const T* f, const double* A, T* out, int64_t nb, int
 
 template <typename T, int P>
 static hipError_t reg_up_p(const T* in, const int32_t* child8, const double* C01, T* out, int64_t np, hipStream_t s) {
-    hipLaunchKernelGGL((k_reg_up<T, P>), dim3((unsigned)np), dim3(kRegUpThreads), 0, s, in, child8, C01, out);
-    return hipGetLastError();
+    return lgf_launch(k_reg_up<T, P>, dim3((unsigned)np), dim3(kRegUpThreads), 0, s, in, child8, C01, out);
 }
 
 template <typename T>
@@ -446,13 +443,11 @@ hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, 
         case 17: {
             constexpr int P3 = 17 * 17 * 17;
             if (!scratch) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_reg_up_part<T, 17>), dim3((unsigned)(np * 8)), dim3(kInterpThreads), 0, s, in,
-                               child8, C01, (T*)scratch);
-            const hipError_t e = hipGetLastError();
+            const hipError_t e = lgf_launch(k_reg_up_part<T, 17>, dim3((unsigned)(np * 8)), dim3(kInterpThreads), 0,
+                                            s, in, child8, C01, (T*)scratch);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_reg_up_sum<T, 17>), dim3((unsigned)((np * P3 + kInterpThreads - 1) / kInterpThreads)),
-                               dim3(kInterpThreads), 0, s, (const T*)scratch, child8, out, np);
-            return hipGetLastError();
+            return lgf_launch(k_reg_up_sum<T, 17>, dim3((unsigned)((np * P3 + kInterpThreads - 1) / kInterpThreads)),
+                              dim3(kInterpThreads), 0, s, (const T*)scratch, child8, out, np);
         }
         default: return hipErrorInvalidValue;
     }
@@ -464,12 +459,9 @@ static hipError_t interp_down_p(const U* par, const int32_t* child8, const doubl
     // levels with few parents: one workgroup per (parent, child), eight times the
     // workgroups (the same sums in the same order, so the same bits as one per parent)
     if (np <= 256)
-        hipLaunchKernelGGL((k_interp_down_one<U, P>), dim3((unsigned)(np * 8)), dim3(kDownThreads), 0, s, par,
-                           child8, C01, io);
-    else
-        hipLaunchKernelGGL((k_interp_down<U, P>), dim3((unsigned)np), dim3(kDownThreads), 0, s, par, child8, C01,
-                           io);
-    return hipGetLastError();
+        return lgf_launch(k_interp_down_one<U, P>, dim3((unsigned)(np * 8)), dim3(kDownThreads), 0, s, par, child8,
+                          C01, io);
+    return lgf_launch(k_interp_down<U, P>, dim3((unsigned)np), dim3(kDownThreads), 0, s, par, child8, C01, io);
 }
 
 template <typename U>
@@ -487,9 +479,8 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
         case 9: return interp_down_p<U, 9>(par, child8, C01, io, nparent, s);
         case 10: return interp_down_p<U, 10>(par, child8, C01, io, nparent, s);
         case 17:
-            hipLaunchKernelGGL((k_interp_down_one<U, 17>), dim3((unsigned)(nparent * 8)), dim3(kDownThreads), 0, s,
-                               par, child8, C01, io);
-            return hipGetLastError();
+            return lgf_launch(k_interp_down_one<U, 17>, dim3((unsigned)(nparent * 8)), dim3(kDownThreads), 0, s, par,
+                              child8, C01, io);
         default: return hipErrorInvalidValue;
     }
 }
@@ -498,8 +489,7 @@ template <typename T>
 hipError_t launch_pad_copy(const T* f, T* out, int64_t nb, int n, int p, hipStream_t s) {
     if (nb <= 0) return hipSuccess;
     const int64_t tot = nb * (int64_t)p * p * p;
-    hipLaunchKernelGGL(k_pad_copy<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f, out, nb, n, p);
-    return hipGetLastError();
+    return lgf_launch(k_pad_copy<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f, out, nb, n, p);
 }
 
 template <typename T, typename U>

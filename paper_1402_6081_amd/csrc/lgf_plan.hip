@@ -71,12 +71,11 @@ __global__ void k_zero(int32_t* p, int64_t words) {
 hipError_t zero_fill(void* p, int64_t bytes, hipStream_t s) {
     const int64_t words = bytes / 4;  // every buffer here is a multiple of 4 bytes
     if (words <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (int32_t*)p, words);
-    return hipGetLastError();
+    return lgf_launch(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (int32_t*)p, words);
 }
 
 // LGF_SYNC_CHECK=1 in the environment: synchronise after every launch and report the
-// first failing step by name (debugging aid; off by default, never inside a capture).
+// first failing step by name (debugging aid; off by default, never while a graph is recorded).
 bool sync_check_enabled() {
     static const bool on = [] {
         const char* v = std::getenv("LGF_SYNC_CHECK");
@@ -85,10 +84,30 @@ bool sync_check_enabled() {
     return on;
 }
 
-thread_local bool t_capturing = false;
+thread_local GraphRecorder* t_rec = nullptr;  // set while lgf_graph_create records a solve
+
+}  // namespace
+
+GraphRecorder* lgfdev::active_recorder() { return t_rec; }
+
+hipError_t lgfdev::rec_event_record(hipEvent_t ev, hipStream_t s) {
+    if (!t_rec) return hipEventRecord(ev, s);
+    t_rec->events[ev] = t_rec->tails[s];
+    return hipSuccess;
+}
+
+hipError_t lgfdev::rec_stream_wait(hipStream_t s, hipEvent_t ev) {
+    if (!t_rec) return hipStreamWaitEvent(s, ev, 0);
+    std::vector<hipGraphNode_t>& t = t_rec->tails[s];
+    for (hipGraphNode_t n : t_rec->events[ev])
+        if (std::find(t.begin(), t.end(), n) == t.end()) t.push_back(n);
+    return hipSuccess;
+}
+
+namespace {
 
 hipError_t checked(hipError_t e, const char* what, hipStream_t s) {
-    if (e == hipSuccess && sync_check_enabled() && !t_capturing) {
+    if (e == hipSuccess && sync_check_enabled() && !t_rec) {
         e = hipStreamSynchronize(s);
         if (e == hipSuccess) e = hipGetLastError();
     }
@@ -571,14 +590,12 @@ struct lgf_plan_s {
 };
 
 struct lgf_graph_s {
-    hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    lgf_plan_s* plan = nullptr;     // the plan whose workspace the graph uses
-    std::vector<hipGraph_t> parts;  // captured pieces whose kernel nodes were copied into graph
+    lgf_plan_s* plan = nullptr;            // the plan whose workspace the graph uses
+    std::unique_ptr<GraphRecorder> rec;    // the graph and the argument blocks of its nodes
     ~lgf_graph_s() {
         if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
-        for (hipGraph_t p : parts) hipGraphDestroy(p);  // outlive every copy of their nodes
+        if (rec && rec->graph) hipGraphDestroy(rec->graph);  // before the argument blocks
     }
 };
 
@@ -613,7 +630,7 @@ struct Marker {
     size_t base = 0;
     int step = 0;
     explicit Marker(lgf_plan_s* p) : pl(p) {
-        on = pl->prof_on && pl->prof_solves < pl->prof_max && !t_capturing;
+        on = pl->prof_on && pl->prof_solves < pl->prof_max && !t_rec;
         if (on) {
             if (pl->prof_solves == 0) pl->steps.clear();
             base = (size_t)pl->prof_cursor;
@@ -645,23 +662,8 @@ inline double fft_flops(int M) {  // Table 1: 2 (8 N_b) log2(8 N_b) for a padded
     return 2.0 * N * std::log2(N);
 }
 
-// Independent pieces of one solve, for graphs assembled from separately captured parts
-// (lgf_graph_create).  Dependencies: FWD0 -> NEAR; REG1 -> {L1, COARSE} -> JOIN;
-// {NEAR, JOIN} -> FINAL; and FWD0 -> L1 when level 1 reads the level-0 spectra (lattice
-// scheme).
-enum : unsigned {
-    kSegNear = 1,     // level 0: Prod, IFFT
-    kSegReg1 = 2,     // Reg block -> level 1
-    kSegL1 = 4,       // level 1: PadFFT, M2L, IFFT
-    kSegCoarse = 8,   // Reg up, levels >= 2 up and down to level 2
-    kSegJoin = 16,    // Interp level 2 -> level 1
-    kSegFinal = 32,   // Interp level 1 -> blocks, add to the near field
-    kSegFwd0 = 64,    // level 0: PadFFT
-    kSegAll = 127
-};
-
 template <typename T>
-hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned segs = kSegAll) {
+hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s) {
     using C = cplx<T>;
     using U = typename FarAcc<T>::type;
     const int n = pl->n, p = pl->p;
@@ -687,19 +689,14 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     } while (0)
     mark.solve_begin(s);
     const bool far = pl->Ltop >= 1;
-    // a subset of segments is issued in order on s alone (no streams or events of its own)
-    const bool all = segs == kSegAll;
     // overlap: 1 (and the default 0) three concurrent branches, 3 two (the coarse levels
     // follow level 1 on one stream), 2 a single stream
     const int ov = tc.overlap == 0 ? (pl->overlap ? 1 : 2) : tc.overlap;
-    const bool overlap = all && ov != 2;
+    const bool overlap = ov != 2;
     // streams: s = near field (level 0), s2 = level 1, s3 = levels >= 2 (the coarse levels'
-    // small kernels run beside the level-1 M2L); one stream when overlap is off.
-    // A whole solve captured on one stream keeps the coarse levels on s2: capturing the
-    // nested fork (s2 -> s3 -> s2) ended in a host crash inside graph creation on this ROCm
-    // stack.  lgf_graph_create builds the concurrent schedule from separately captured
-    // segments instead.
-    const bool split = overlap && ov == 1 && !t_capturing;
+    // small kernels run beside the level-1 M2L); one stream when overlap is off.  The fork and
+    // join events become dependency edges when lgf_graph_create records the solve.
+    const bool split = overlap && ov == 1;
     hipStream_t s2 = overlap ? pl->far_stream : s;
     hipStream_t s3 = split ? pl->far_stream2 : s2;
     // forward work of level l: PadFFT and the M2L products (Steps 1-2)
@@ -778,7 +775,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                  ns * (n3 * es + S0 * cs), ns * fft_flops(2 * n));
         return hipSuccess;
     };
-    if (pl->lat1 && (segs & kSegFwd0) && (e = fwd0()) != hipSuccess) return e;
+    if (pl->lat1 && (e = fwd0()) != hipSuccess) return e;
     // two branches: the level-0 transform goes first and the far field starts behind it.
     // Its 16^3 tiles take most of a CU's LDS, so it cannot share CUs with the M2L; the
     // far field then overlaps the level-0 Prod, whose LDS tile is small.
@@ -786,13 +783,13 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     if (fwd0_first && (e = fwd0()) != hipSuccess) return e;
     if (far) {
         if (overlap) {
-            if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(s2, pl->ev_fork, 0)) != hipSuccess) return e;
+            if ((e = rec_event_record(pl->ev_fork, s)) != hipSuccess) return e;
+            if ((e = rec_stream_wait(s2, pl->ev_fork)) != hipSuccess) return e;
         }
-        if ((segs & kSegReg1) && pl->lat1)  // identity on the grid points: a padded copy
+        if (pl->lat1)  // identity on the grid points: a padded copy
             LGF_STEP(s2, (launch_pad_copy<T>(f, (T*)pl->lv[1].d_ftil, pl->nsrc, n, p, s2)), "reg_l0_l1",
                      ns * (n3 + p3) * es, 0.0);
-        else if (segs & kSegReg1)
+        else
             LGF_STEP(s2, (launch_reg_block<T>(f, pl->d_A, (T*)pl->lv[1].d_ftil, pl->nsrc, n, p, s2)), "reg_l0_l1",
                      ns * (n3 + p3) * es, ns * 2.0 * (p * n3 + p * p * n * n + p3 * n));
         const bool coarse = pl->Ltop >= 2;
@@ -800,7 +797,7 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
         // the levels' transforms (their small kernels would otherwise run nearly alone before
         // the near field's large ones start).  The transforms go out as one launch too, except
         // in the lattice scheme, whose level 1 and two-phase levels keep their own launches.
-        const bool merge = all && !split && coarse;
+        const bool merge = !split && coarse;
         if (merge) {
             for (int l = 1; l < pl->Ltop; ++l)
                 LGF_STEP(s2,
@@ -888,11 +885,11 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
             for (int l = pl->Ltop - 1; l >= 1; --l)
                 if ((e = interp(l, s2)) != hipSuccess) return e;
         }
-        if (!merge && coarse && (segs & kSegCoarse)) {
+        if (!merge && coarse) {
             // levels >= 2 on s3: Reg up, their M2L, and the down pass to level 2
             if (split) {
-                if ((e = hipEventRecord(pl->ev_fork2, s2)) != hipSuccess) return e;
-                if ((e = hipStreamWaitEvent(s3, pl->ev_fork2, 0)) != hipSuccess) return e;
+                if ((e = rec_event_record(pl->ev_fork2, s2)) != hipSuccess) return e;
+                if ((e = rec_stream_wait(s3, pl->ev_fork2)) != hipSuccess) return e;
             }
             for (int l = 1; l < pl->Ltop; ++l)
                 LGF_STEP(s3,
@@ -906,22 +903,22 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                 if ((e = level_down(l, s3)) != hipSuccess) return e;
                 if (l < pl->Ltop && (e = interp(l, s3)) != hipSuccess) return e;
             }
-            if (split && (e = hipEventRecord(pl->ev_join2, s3)) != hipSuccess) return e;
+            if (split && (e = rec_event_record(pl->ev_join2, s3)) != hipSuccess) return e;
         }
         // level 1 on s2
-        if (!merge && (segs & kSegL1)) {
+        if (!merge) {
             if ((e = level_up(1, s2)) != hipSuccess) return e;
             if ((e = level_down(1, s2)) != hipSuccess) return e;
         }
-        if (!merge && coarse && (segs & kSegJoin)) {
-            if (split && (e = hipStreamWaitEvent(s2, pl->ev_join2, 0)) != hipSuccess) return e;
+        if (!merge && coarse) {
+            if (split && (e = rec_stream_wait(s2, pl->ev_join2)) != hipSuccess) return e;
             if ((e = interp(1, s2)) != hipSuccess) return e;
         }
-        if (overlap && (e = hipEventRecord(pl->ev_join, s2)) != hipSuccess) return e;
+        if (overlap && (e = rec_event_record(pl->ev_join, s2)) != hipSuccess) return e;
     }
     // ---- near field (level 0) on the caller's stream
-    if (!pl->lat1 && !fwd0_first && (segs & kSegFwd0) && (e = fwd0()) != hipSuccess) return e;
-    if (segs & kSegNear) {
+    if (!pl->lat1 && !fwd0_first && (e = fwd0()) != hipSuccess) return e;
+    {
         LGF_STEP(s,
                  launch_prod_near<T>((const C*)pl->d_fhat0, (const C*)pl->spectra0->dev, pl->d_g0_tgt8,
                                      pl->d_g0_src64, (C*)pl->d_uhat0, pl->ngroups0, pl->nsrc, pl->ntgt0,
@@ -932,8 +929,8 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
                                              pl->d_near_out)),
                  "fft_inv_l0", nt0 * (S0 * cs + n3 * es), nt0 * fft_flops(2 * n));
     }
-    if (far && (segs & kSegFinal)) {
-        if (overlap && (e = hipStreamWaitEvent(s, pl->ev_join, 0)) != hipSuccess) return e;
+    if (far) {
+        if (overlap && (e = rec_stream_wait(s, pl->ev_join)) != hipSuccess) return e;
         LGF_STEP(s,
                  (launch_final<T, U>(u, (const U*)pl->lv[1].d_util, pl->d_A, u, pl->neval, n, p, s, pl->d_eval_l1,
                                      pl->d_near_flag)),
@@ -944,9 +941,9 @@ hipError_t run_solve(lgf_plan_s* pl, const T* f, T* u, hipStream_t s, unsigned s
     return hipSuccess;
 }
 
-hipError_t solve_dispatch(lgf_plan_s* pl, const void* f, void* u, hipStream_t s, unsigned segs = kSegAll) {
-    return pl->prec == LGF_F64 ? run_solve<double>(pl, (const double*)f, (double*)u, s, segs)
-                               : run_solve<float>(pl, (const float*)f, (float*)u, s, segs);
+hipError_t solve_dispatch(lgf_plan_s* pl, const void* f, void* u, hipStream_t s) {
+    return pl->prec == LGF_F64 ? run_solve<double>(pl, (const double*)f, (double*)u, s)
+                               : run_solve<float>(pl, (const float*)f, (float*)u, s);
 }
 
 lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan_s* pl) {
@@ -1097,109 +1094,45 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
     return LGF_OK;
 }
 
-// Capture the given segments of a solve, issued in order on a private stream, as a graph.
-hipError_t capture_part(lgf_plan_t plan, const void* f, void* u, unsigned segs, hipGraph_t* out) {
-    *out = nullptr;
-    hipStream_t cap = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        t_capturing = true;
-        const hipError_t es = solve_dispatch(plan, f, u, cap, segs);
-        t_capturing = false;
-        e = hipStreamEndCapture(cap, out);
-        if (es != hipSuccess) e = es;
-    }
-    hipStreamDestroy(cap);
-    return e;
-}
-
-// Copy the kernel nodes of a captured single-stream graph (a chain) into `parent`, the first
-// one depending on `deps`; *last receives the copy of the chain's last node (or stays NULL
-// for an empty chain).
-hipError_t append_chain(hipGraph_t parent, hipGraph_t part, const std::vector<hipGraphNode_t>& deps,
-                               hipGraphNode_t* last) {
-    *last = nullptr;
-    size_t nroots = 0;
-    hipError_t e = hipGraphGetRootNodes(part, nullptr, &nroots);
-    if (e != hipSuccess || nroots == 0) return e;
-    if (nroots != 1) return hipErrorInvalidValue;
-    hipGraphNode_t node = nullptr;
-    if ((e = hipGraphGetRootNodes(part, &node, &nroots)) != hipSuccess) return e;
-    std::vector<hipGraphNode_t> d = deps;
-    for (;;) {
-        hipGraphNodeType type;
-        if ((e = hipGraphNodeGetType(node, &type)) != hipSuccess) return e;
-        if (type != hipGraphNodeTypeKernel) return hipErrorInvalidValue;  // only kernels are captured
-        // value-initialised: any field the getter leaves unwritten (extra) must read as NULL
-        // when the copy is added, not as whatever the stack held
-        hipKernelNodeParams kp{};
-        if ((e = hipGraphKernelNodeGetParams(node, &kp)) != hipSuccess) return e;
-        hipGraphNode_t copy = nullptr;
-        if ((e = hipGraphAddKernelNode(&copy, parent, d.empty() ? nullptr : d.data(), d.size(), &kp)) != hipSuccess)
-            return e;
-        *last = copy;
-        d.assign(1, copy);
-        size_t nd = 0;
-        if ((e = hipGraphNodeGetDependentNodes(node, nullptr, &nd)) != hipSuccess) return e;
-        if (nd == 0) return hipSuccess;
-        if (nd != 1) return hipErrorInvalidValue;
-        if ((e = hipGraphNodeGetDependentNodes(node, &node, &nd)) != hipSuccess) return e;
-    }
-}
-
+// One solve as a graph of explicit kernel nodes.  The solve's launch sequence is issued with a
+// recorder active (lgf_launch): each launch adds a kernel node whose argument block the graph
+// owns, depending on the previous node of its stream, and the solve's fork and join events add
+// the edges between streams.  The streams are only names here: nothing is enqueued and no
+// stream is captured.  The result is checked before instantiation: as many kernel nodes as
+// launches were issued, each with a kernel and no `extra` argument form.
 lgf_status make_graph(lgf_plan_t plan, const void* f, void* u, lgf_graph_s** out) {
     *out = nullptr;
-    lgf_graph_s* g = new lgf_graph_s();
+    std::unique_ptr<lgf_graph_s> g(new lgf_graph_s());
     g->plan = plan;
-    hipError_t e = hipSuccess;
-    const int ov = plan->tune.overlap == 0 ? (plan->overlap ? 1 : 2) : plan->tune.overlap;
-    if (ov != 1 || plan->Ltop < 1) {
-        // one stream, or two (fork/join from the capture stream), captured as issued
-        e = capture_part(plan, f, u, kSegAll, &g->graph);
-    } else {
-        // concurrent branches with explicit dependencies:
-        //   fwd0 -> near ----------------------------------\
-        //   reg1 -> level 1 --------------------> join -> final
-        //        \-> coarse levels ----------/
-        // (fwd0 -> level 1 as well in the lattice scheme)
-        // Each branch is captured alone on one stream (a chain of kernel nodes) and its nodes
-        // are copied into one flat graph.
-        e = hipGraphCreate(&g->graph, 0);
-        const bool coarse = plan->Ltop >= 2;
-        hipGraphNode_t last[7] = {};
-        auto add = [&](int slot, unsigned segs, std::initializer_list<int> deps) {
-            if (e != hipSuccess) return;
-            hipGraph_t part = nullptr;
-            e = capture_part(plan, f, u, segs, &part);
-            if (part) g->parts.push_back(part);  // freed with the graph, also after a failure
-            if (e != hipSuccess) return;
-            std::vector<hipGraphNode_t> d;
-            for (int k : deps)
-                if (last[k]) d.push_back(last[k]);
-            e = append_chain(g->graph, part, d, &last[slot]);
-        };
-        add(6, kSegFwd0, {});
-        add(0, kSegNear, {6});
-        add(1, kSegReg1, {});
-        if (plan->lat1)
-            add(2, kSegL1, {1, 6});
-        else
-            add(2, kSegL1, {1});
-        if (coarse) {
-            add(3, kSegCoarse, {1});
-            add(4, kSegJoin, {2, 3});
+    g->rec.reset(new GraphRecorder());
+    hipError_t e = hipGraphCreate(&g->rec->graph, 0);
+    if (e == hipSuccess) {
+        t_rec = g->rec.get();
+        // the caller's branch is named by the null stream (the plan's own streams are not null)
+        e = solve_dispatch(plan, f, u, nullptr);
+        t_rec = nullptr;
+        if (e == hipSuccess) e = g->rec->err;
+    }
+    size_t count = 0;
+    if (e == hipSuccess) e = hipGraphGetNodes(g->rec->graph, nullptr, &count);
+    if (e == hipSuccess && (int64_t)count != g->rec->launches) e = hipErrorInvalidValue;
+    if (e == hipSuccess && count > 0) {
+        std::vector<hipGraphNode_t> nodes(count);
+        e = hipGraphGetNodes(g->rec->graph, nodes.data(), &count);
+        for (size_t i = 0; e == hipSuccess && i < count; ++i) {
+            hipGraphNodeType type;
+            e = hipGraphNodeGetType(nodes[i], &type);
+            if (e == hipSuccess && type != hipGraphNodeTypeKernel) e = hipErrorInvalidValue;
+            hipKernelNodeParams kp{};
+            if (e == hipSuccess) e = hipGraphKernelNodeGetParams(nodes[i], &kp);
+            if (e == hipSuccess && (!kp.func || kp.extra)) e = hipErrorInvalidValue;
         }
-        add(5, kSegFinal, {0, coarse ? 4 : 2});
-        if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     }
-    if (e == hipSuccess && !g->exec) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        delete g;
-        return fail(LGF_ERR_DEVICE, std::string("graph creation failed: ") + hipGetErrorString(e));
-    }
-    *out = g;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->rec->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+        return fail(LGF_ERR_DEVICE, std::string("graph creation failed: ") + hipGetErrorString(e) +
+                                        (t_err.empty() ? "" : " (" + t_err + ")"));
+    *out = g.release();
     return LGF_OK;
 }
 

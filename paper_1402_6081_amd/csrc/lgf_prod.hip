@@ -453,9 +453,8 @@ static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_
                           cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, hipStream_t s,
                           const SpecSym& sym) {
     const unsigned grid = xcd_grid(S / 64, (int)((ngroups + NW - 1) / NW));
-    hipLaunchKernelGGL((k_prod_near_grouped<T, NW, PF>), dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64,
-                       uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym);
-    return hipGetLastError();
+    return lgf_launch(k_prod_near_grouped<T, NW, PF>, dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64,
+                      uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym);
 }
 
 template <typename T, bool PF>
@@ -499,14 +498,10 @@ static hipError_t far_nw(const FarLevel<T>* lv, int nlev, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
         bool idx16 = true;
         for (int k = 0; k < nlev; ++k) idx16 = idx16 && lv[k].nsrc < 65535;
-        if (idx16) {
-            hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL, uint16_t>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s,
-                               segs);
-            return hipGetLastError();
-        }
+        if (idx16)
+            return lgf_launch(k_prod_far_sib<T, NW, CPL, uint16_t>, dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
     }
-    hipLaunchKernelGGL((k_prod_far_sib<T, NW, CPL, int32_t>), dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
-    return hipGetLastError();
+    return lgf_launch(k_prod_far_sib<T, NW, CPL, int32_t>, dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
 }
 
 template <typename T, int CPL>
@@ -612,9 +607,8 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
     if (nsrc < 0) nsrc = nitems;
     if (!sym_fits(sym, S)) return hipErrorInvalidValue;
     dim3 grid((unsigned)ntgt, (unsigned)((S + kProdThreads - 1) / kProdThreads));
-    hipLaunchKernelGGL(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, tgt, uhat, S,
-                       (int)nitems, noff, (int)nsrc, sym);
-    return hipGetLastError();
+    return lgf_launch(k_prod_far<T>, grid, dim3(kProdThreads), 0, s, fhat, khat, ptr, src, off, tgt, uhat, S,
+                      (int)nitems, noff, (int)nsrc, sym);
 }
 
 #define LGF_INST(T)                                                                                              \

@@ -52,6 +52,9 @@ struct Request {
     int64_t nblocks = 0;
     const void* f = nullptr;
     void* u = nullptr;
+    // recorded on the submitter's stream at submit time: the slot stream waits for it, so the
+    // solve reads f (and overwrites u) only after the work the caller queued before submit
+    hipEvent_t ev_ready = nullptr;
     Clock::time_point t_submit, t_start, t_done;
     lgf_status status = LGF_OK;
     std::string error;
@@ -76,6 +79,7 @@ struct lgf_server_s {
     std::vector<hipStream_t> slots;
     std::vector<bool> slot_busy;
     std::vector<hipEvent_t> ev_pool;
+    std::vector<hipEvent_t> ready_pool;  // submit-time events (shared with submitting threads, under mu)
 
     std::mutex mu;
     std::condition_variable cv_work;  // new request or shutdown
@@ -102,6 +106,7 @@ struct lgf_server_s {
     ~lgf_server_s() {
         for (auto& cp : plans) lgf_plan_destroy(cp->plan);
         for (auto e : ev_pool) hipEventDestroy(e);
+        for (auto e : ready_pool) hipEventDestroy(e);
         for (auto s : slots) hipStreamDestroy(s);
     }
 };
@@ -121,6 +126,10 @@ hipEvent_t take_event(lgf_server_s* S) {
 
 void finish(lgf_server_s* S, const std::shared_ptr<Request>& r, lgf_status st, const std::string& err) {
     std::lock_guard<std::mutex> lk(S->mu);
+    if (r->ev_ready) {
+        S->ready_pool.push_back(r->ev_ready);
+        r->ev_ready = nullptr;
+    }
     r->status = st;
     r->error = err;
     r->done = true;
@@ -235,6 +244,13 @@ int try_admit(lgf_server_s* S, const std::shared_ptr<Request>& r) {
     }
     hipStream_t s = S->slots[slot];
     r->t_start = Clock::now();
+    // the solve follows everything the submitter had queued on its stream before the submit
+    if (hipStreamWaitEvent(s, r->ev_ready, 0) != hipSuccess) {
+        S->ev_pool.push_back(r->ev_start);
+        S->ev_pool.push_back(r->ev_end);
+        finish(S, r, LGF_ERR_DEVICE, "stream wait on the submit event failed");
+        return 1;
+    }
     hipEventRecord(r->ev_start, s);
     lgf_status st = lgf_solve(cp->plan, r->f, r->u, s);
     hipEventRecord(r->ev_end, s);
@@ -300,7 +316,7 @@ lgf_status lgf_server_create(const lgf_server_config* cfg, lgf_server_t* out) {
     if (cfg->p < 2 || (cfg->p > 10 && !(cfg->n == 16 && cfg->p == 17)) ||
         (cfg->precision != LGF_F64 && cfg->precision != LGF_F32) ||
         cfg->max_slots < 1 || cfg->max_slots > 16 || cfg->budget_bytes < 0 || cfg->max_queue < 0) {
-        set_last_error("lgf_server_create: p in [2, 10], precision, max_slots in [1, 16], budget >= 0");
+        set_last_error("lgf_server_create: p in [2, 10] (or 17 with n = 16), precision, max_slots in [1, 16], budget >= 0");
         return LGF_ERR_ARG;
     }
     auto S = std::make_unique<lgf_server_s>();
@@ -326,12 +342,34 @@ lgf_status lgf_server_create(const lgf_server_config* cfg, lgf_server_t* out) {
 }
 
 lgf_status lgf_server_submit(lgf_server_t S, const int32_t* block_ijk, int64_t nblocks, const void* f, void* u,
-                             int64_t* ticket) {
+                             void* hip_stream, int64_t* ticket) {
     if (!S || !block_ijk || !f || !u || !ticket || nblocks < 1) {
         set_last_error("bad arguments to lgf_server_submit");
         return LGF_ERR_ARG;
     }
     auto r = std::make_shared<Request>();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!S->ready_pool.empty()) {
+            r->ev_ready = S->ready_pool.back();
+            S->ready_pool.pop_back();
+        }
+    }
+    if (!r->ev_ready && hipEventCreateWithFlags(&r->ev_ready, hipEventDisableTiming) != hipSuccess) {
+        r->ev_ready = nullptr;
+        set_last_error("event creation failed in lgf_server_submit");
+        return LGF_ERR_DEVICE;
+    }
+    auto give_back = [&]() {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->ready_pool.push_back(r->ev_ready);
+        r->ev_ready = nullptr;
+    };
+    if (hipEventRecord(r->ev_ready, (hipStream_t)hip_stream) != hipSuccess) {
+        give_back();
+        set_last_error("lgf_server_submit: recording on the caller's stream failed");
+        return LGF_ERR_DEVICE;
+    }
     r->layout.assign(block_ijk, block_ijk + 3 * nblocks);
     r->key = layout_key(block_ijk, nblocks);
     r->nblocks = nblocks;
@@ -341,10 +379,12 @@ lgf_status lgf_server_submit(lgf_server_t S, const int32_t* block_ijk, int64_t n
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stop) {
+            S->ready_pool.push_back(r->ev_ready);
             set_last_error("server is shutting down");
             return LGF_ERR_ARG;
         }
         if (S->cfg.max_queue > 0 && (int64_t)S->queue.size() >= S->cfg.max_queue) {
+            S->ready_pool.push_back(r->ev_ready);
             set_last_error("request queue is full");
             return LGF_ERR_BUSY;
         }

@@ -109,7 +109,7 @@ def library():
         L.lgf_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.lgf_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.lgf_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
-        L.lgf_server_submit.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(i64)]
+        L.lgf_server_submit.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
         L.lgf_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(RequestResult)]
         L.lgf_server_wait.argtypes = [vp, i64, ctypes.POINTER(RequestResult)]
         L.lgf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -388,8 +388,10 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, blocks, f, u):
-        """Queue u = G * f on `blocks`; returns a ticket.  f, u stay referenced until done."""
+    def submit(self, blocks, f, u, stream=None):
+        """Queue u = G * f on `blocks`; returns a ticket.  f, u stay referenced until done.
+        The solve runs after the work queued on `stream` (default: torch's current stream)
+        before this call, so f may still be in flight there."""
         b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
         shape = (b.shape[0], self.n, self.n, self.n)
         for x in (f, u):
@@ -397,7 +399,7 @@ class Server:
                 raise ValueError("fields must be contiguous %s device tensors of shape %s" % (self.dtype, shape))
         t = ctypes.c_int64()
         _check(library().lgf_server_submit(self._h, b.ctypes.data, b.shape[0], ctypes.c_void_p(f.data_ptr()),
-                                           ctypes.c_void_p(u.data_ptr()), ctypes.byref(t)))
+                                           ctypes.c_void_p(u.data_ptr()), _stream_handle(stream), ctypes.byref(t)))
         self._keep[t.value] = (f, u)
         return t.value
 

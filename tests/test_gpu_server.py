@@ -1,12 +1,15 @@
 """GPU tests of the request server (lgf_server_*): results in a concurrent mix equal the
-results of the same requests solved alone, admission under an HBM budget, queue limits."""
+results of the same requests solved alone and the oracle's, solves ordered after the
+submitter's stream, admission under an HBM budget, queue limits."""
 import sys
 
 import numpy as np
 import pytest
 import torch
 
+from oracle import flgf
 from paper_1402_6081_amd import workloads as W
+from tolerances import FP32_BAR, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -149,4 +152,65 @@ def test_server_poll_and_layout_error(L):
     assert r["status"] == "LGF_ERR_LAYOUT"
     with pytest.raises(L.LGFError):
         srv.poll(t)  # released
+    srv.close()
+
+
+def test_server_serving_config_mix_against_oracle(L):
+    """The serving configuration: n = 16, p = 8, FP32, 4 slots; Eden-box layouts with
+    bounding-box edges U{2..8} blocks and fill U[0.3, 1], zero-net Gaussian sources as in
+    the benchmark's request mix, submitted all at once with repeats (concurrent requests of
+    one layout, plan reuse).  Every result equals the same request solved alone, bit for
+    bit, and the oracle's FLGF within 1e-6 of max|u|."""
+    _say("case: server serving-config mix, n=16 p=8 FP32, 4 slots")
+    n, p = 16, 8
+    rng = np.random.default_rng(55)
+    base = []
+    for _ in range(7):
+        b = W.eden_box_layout(int(rng.integers(2, 9)), float(rng.uniform(0.3, 1.0)), rng)
+        f, _ = W.zero_mean_gaussians(b, n, rng, max(1, b.shape[0] // 8))
+        base.append((b, f))
+    order = [0, 1, 2, 0, 3, 4, 1, 5, 6, 2, 0]
+    dev = torch.device("cuda:0")
+    fs = [torch.from_numpy(f).to(dev, torch.float32) for _, f in base]
+    alone = [_alone(L, b, f, n, p, "f32") for (b, _), f in zip(base, fs)]
+    srv = L.Server(n, p, 0, "f32", max_slots=4)
+    us = [torch.full_like(fs[k], float("nan")) for k in order]
+    tickets = [srv.submit(base[k][0], fs[k], u) for k, u in zip(order, us)]
+    res = [srv.wait(t) for t in tickets]
+    for i, (k, r, u) in enumerate(zip(order, res, us)):
+        assert r["status"] == "LGF_OK", (i, r)
+        assert torch.equal(u, alone[k]), "request %d (layout %d) differs from its solve alone" % (i, k)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(order) and st["failed"] == 0
+    for k, (b, f) in enumerate(base):
+        ref = flgf.solve(b, f, n, p, 0)
+        e = rel(alone[k].double().cpu().numpy(), ref)
+        _say("   layout %d: %d blocks, FP32 vs oracle FLGF rel Linf = %.3e" % (k, b.shape[0], e))
+        assert e <= FP32_BAR
+
+
+def test_server_waits_for_submit_stream(L):
+    """A request's solve starts only after the work its submitter queued on its stream:
+    the source field is written on a side stream behind a bounded spin and submitted at
+    once with that stream; the result equals the solve of the finished field."""
+    _say("case: server ordering after the submitter's stream")
+    n, p = 8, 6
+    rng = np.random.default_rng(66)
+    b = W.eden_layout(90, rng)
+    f_host = torch.from_numpy(rng.standard_normal((b.shape[0], n, n, n))).to(torch.float32)
+    f_ok = f_host.to("cuda:0")
+    ref = _alone(L, b, f_ok, n, p, "f32")
+    srv = L.Server(n, p, 0, "f32", max_slots=2)
+    side = torch.cuda.Stream()
+    f = torch.zeros_like(f_ok)
+    u = torch.full_like(f_ok, float("nan"))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(50_000_000)  # bounded spin (tens of milliseconds)
+        f.copy_(f_ok)
+        t = srv.submit(b, f, u, stream=side)
+    r = srv.wait(t)
+    assert r["status"] == "LGF_OK"
+    assert torch.equal(u, ref)
     srv.close()

@@ -112,7 +112,7 @@ def test_server_config_errors(L):
            L.ServerConfig(0, 4, 0, 16, 8, 0, 7)]    # unknown precision
     for cfg in bad:
         assert lib.lgf_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
-    assert lib.lgf_server_submit(None, None, 1, None, None, None) == 1
+    assert lib.lgf_server_submit(None, None, 1, None, None, None, None) == 1
     assert lib.lgf_server_destroy(None) == 0
     assert lib.lgf_graph_create(None, None, None, None, ctypes.byref(h)) == 1
     t = L.Tuning(0, 4, 0, 0, 0, 0)
