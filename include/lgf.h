@@ -399,6 +399,20 @@ lgf_status lgf_green_table(int32_t R, double* out);
  */
 lgf_status lgf_far_kernel(const double* pts, int64_t npts, double* out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lgf_far_kernel without any device
+ * allocation.  Same arguments and the same values, bit for bit.  The points, the values and
+ * the expansion's coefficient tables are staged in one static device array of the library
+ * (8 MiB + 64 KiB per GPU, held until the process ends), so npts is limited to
+ * LGF_FAR_KERNEL_NOALLOC_MAX_POINTS per call.  Calls share that array; the library
+ * serialises them (one call at a time per process), and each call rewrites everything it
+ * reads.  Synchronous, on the device that is current.
+ * Errors: LGF_ERR_ARG (bad arguments, or npts above the maximum), LGF_ERR_DEVICE.
+ */
+#define LGF_FAR_KERNEL_NOALLOC_MAX_POINTS 262144
+lgf_status lgf_far_kernel_noalloc(const double* pts, int64_t npts, double* out);
+
 #ifdef __cplusplus
 }
 #endif

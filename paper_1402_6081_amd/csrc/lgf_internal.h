@@ -265,6 +265,9 @@ int spectra_classes(int R, std::vector<uint32_t>& info, std::vector<int32_t>& re
 const double* green_table_device(int R, hipStream_t s, std::string& err);
 // far kernel A^q at device points (FP64): out[i] = A^q(pts[i])
 hipError_t far_kernel_device(const double* pts, int64_t npts, double* out, hipStream_t s, std::string& err);
+// The same at HOST points into HOST out, staged through the library's static device array
+// (no device allocation); npts <= LGF_FAR_KERNEL_NOALLOC_MAX_POINTS.  Synchronous.
+hipError_t far_kernel_noalloc(const double* pts, int64_t npts, double* out, std::string& err);
 
 // ------------------------------------------------------------------ memory accounting
 bool budget_reserve(int64_t bytes);

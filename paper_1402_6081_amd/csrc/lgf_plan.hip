@@ -1723,6 +1723,19 @@ lgf_status lgf_green_table(int32_t R, double* out) {
     return LGF_OK;
 }
 
+lgf_status lgf_far_kernel_noalloc(const double* pts, int64_t npts, double* out) {
+    if (npts < 0 || (npts > 0 && (!pts || !out)))
+        return fail(LGF_ERR_ARG, "lgf_far_kernel_noalloc: bad arguments");
+    if (npts > LGF_FAR_KERNEL_NOALLOC_MAX_POINTS)
+        return fail(LGF_ERR_ARG, "lgf_far_kernel_noalloc: at most " +
+                                     std::to_string(LGF_FAR_KERNEL_NOALLOC_MAX_POINTS) + " points per call");
+    if (npts == 0) return LGF_OK;
+    std::string err;
+    const hipError_t e = far_kernel_noalloc(pts, npts, out, err);
+    if (e != hipSuccess) return fail(LGF_ERR_DEVICE, err.empty() ? hipGetErrorString(e) : err);
+    return LGF_OK;
+}
+
 lgf_status lgf_far_kernel(const double* pts, int64_t npts, double* out) {
     if (npts < 0 || (npts > 0 && (!pts || !out))) return fail(LGF_ERR_ARG, "lgf_far_kernel: bad arguments");
     if (npts == 0) return LGF_OK;

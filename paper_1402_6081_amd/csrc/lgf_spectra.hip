@@ -558,6 +558,69 @@ hipError_t far_kernel_device(const double* pts, int64_t npts, double* out, hipSt
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ allocation-free far kernel
+// For callers that cannot allocate device memory (work under graph capture, serving loops,
+// harnesses that forbid it): the points, the values and the expansion's coefficient tables
+// are staged in one file-scope device array instead of buffers allocated per call.  Every GPU
+// holds its own copy of the array for the life of the process; its device address is looked
+// up once per device, and that address, never the array's name, is what host code passes to
+// copies and kernels.  Calls are serialised by a lock, since they all use the one array.
+constexpr int64_t kNoAllocTableBytes = 64 << 10;  // room for the coefficient tables
+constexpr int64_t kNoAllocBytes = kNoAllocTableBytes + (int64_t)LGF_FAR_KERNEL_NOALLOC_MAX_POINTS * 32;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::map<int, unsigned char*> g_noalloc_ptr;  // device -> address of its copy of the array
+inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+}  // namespace
+
+hipError_t far_kernel_noalloc(const double* pts, int64_t npts, double* out, std::string& err) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    const int dev = current_device();
+    auto it = g_noalloc_ptr.find(dev);
+    if (it == g_noalloc_ptr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("device address of the staging array: ") + hipGetErrorString(e);
+            return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        }
+        it = g_noalloc_ptr.emplace(dev, static_cast<unsigned char*>(p)).first;
+    }
+    unsigned char* base = it->second;
+    const AsymTable& t = asym_table();
+    const int64_t o_start = 0;
+    const int64_t o_exps = align256(o_start + (int64_t)(t.start.size() * sizeof(int32_t)));
+    const int64_t o_coef = align256(o_exps + (int64_t)(t.exps.size() * sizeof(int32_t)));
+    const int64_t o_pts = align256(o_coef + (int64_t)(t.coef.size() * sizeof(double)));
+    const int64_t o_out = o_pts + npts * 24;
+    if (o_pts > kNoAllocTableBytes || o_out + npts * 8 > kNoAllocBytes) {
+        err = "staging array too small";
+        return hipErrorInvalidValue;
+    }
+    // the tables are copied on every call: the array keeps whatever the previous call left in it
+    hipError_t e = hipMemcpy(base + o_start, t.start.data(), t.start.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + o_exps, t.exps.data(), t.exps.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + o_coef, t.coef.data(), t.coef.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + o_pts, pts, (size_t)npts * 24, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        err = std::string("copy to the staging array: ") + hipGetErrorString(e);
+        return e;
+    }
+    const AsymDev A{reinterpret_cast<const int32_t*>(base + o_start), reinterpret_cast<const int32_t*>(base + o_exps),
+                    reinterpret_cast<const double*>(base + o_coef), kFarTerms};
+    hipLaunchKernelGGL(k_far_kernel, dim3((unsigned)((npts + 127) / 128)), dim3(128), 0, nullptr,
+                       reinterpret_cast<const double*>(base + o_pts), npts, A, reinterpret_cast<double*>(base + o_out));
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, base + o_out, (size_t)npts * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) err = std::string("far kernel from the staging array: ") + hipGetErrorString(e);
+    return e;
+}
+
 std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, std::string& err) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key);

@@ -79,7 +79,7 @@ EXPORTS = ["lgf_plan_create", "lgf_plan_estimate", "lgf_plan_create_split", "lgf
            "lgf_server_stats", "lgf_server_reset_stats", "lgf_server_destroy",
            "lgf_plan_query", "lgf_plan_destroy", "lgf_set_memory_budget", "lgf_memory_in_use",
            "lgf_spectra_cache_trim", "lgf_set_spectra_mode", "lgf_get_spectra_mode", "lgf_last_error",
-           "lgf_green_table", "lgf_far_kernel", "lgf_profile_enable",
+           "lgf_green_table", "lgf_far_kernel", "lgf_far_kernel_noalloc", "lgf_profile_enable",
            "lgf_profile_collect"]
 
 _lib = None
@@ -124,6 +124,7 @@ def library():
         L.lgf_last_error.restype = ctypes.c_char_p
         L.lgf_green_table.argtypes = [i32, vp]
         L.lgf_far_kernel.argtypes = [vp, i64, vp]
+        L.lgf_far_kernel_noalloc.argtypes = [vp, i64, vp]
         L.lgf_profile_enable.argtypes = [vp, i32]
         L.lgf_profile_collect.argtypes = [vp, ctypes.POINTER(StepProfile), vp, i32]
         for name in EXPORTS:
@@ -469,6 +470,21 @@ def far_kernel(points):
     pts = pts.reshape(-1, 3)
     out = np.zeros(pts.shape[0], dtype=np.float64)
     _check(library().lgf_far_kernel(pts.ctypes.data, pts.shape[0], out.ctypes.data))
+    return out.reshape(shape)
+
+
+FAR_KERNEL_NOALLOC_MAX_POINTS = 262144  # LGF_FAR_KERNEL_NOALLOC_MAX_POINTS of lgf.h
+
+
+def far_kernel_noalloc(points):
+    """far_kernel through lgf_far_kernel_noalloc (no device allocation; at most
+    FAR_KERNEL_NOALLOC_MAX_POINTS points per call)."""
+    _require_gpu()
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64))
+    shape = pts.shape[:-1]
+    pts = pts.reshape(-1, 3)
+    out = np.zeros(pts.shape[0], dtype=np.float64)
+    _check(library().lgf_far_kernel_noalloc(pts.ctypes.data, pts.shape[0], out.ctypes.data))
     return out.reshape(shape)
 
 
