@@ -116,9 +116,11 @@ def test_lattice_scheme_fp32(L):
     f, _ = W.zero_mean_gaussians(blocks, N, rng, 6)
     u64 = gpu_solve(L, blocks, f, 0, "f64")
     u32 = gpu_solve(L, blocks, f, 0, "f32")
-    e = rel(u32, u64)
-    _say("case: n_I = 17 FP32 vs FP64 rel Linf = %.3e" % e)
+    ref = flgf.solve(blocks, f, N, P, 0)
+    e, e_or = rel(u32, u64), rel(u32, ref)
+    _say("case: n_I = 17 FP32 vs FP64 rel Linf = %.3e, vs oracle FLGF %.3e" % (e, e_or))
     assert e < 1e-6
+    assert e_or < 1e-6
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
