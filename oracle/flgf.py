@@ -40,6 +40,11 @@ Readings taken where the paper is silent or ambiguous (all listed in the design 
   * FFT convolution (Sec. 2.2, garbled indices): circular length M = 2m with m = n
     (level 0) or p (level >= 1); kernel value K(r) sits at index r mod M for
     r in [-(m-1), m-1], every other entry is 0; the output is entries [0, m).
+  * A second non-oscillatory kernel (Sec. 5: the method applies to such LGFs): the LGF
+    G_kappa of the screened operator L - kappa (kappa > 0).  It is used at every level
+    from its integrated values (the method needs only kernel evaluations), so every node
+    must lie on the lattice: (p - 1) must divide n, which makes h_l an integer at every
+    level (p = n + 1 is the paper's scheme).
 """
 import numpy as np
 
@@ -215,9 +220,14 @@ def level_geometry(n, p, l):
     return s, h, lattice
 
 
-def kernel_values(x, lattice):
-    """K_l at points x [..., 3] (float64) for a level >= 1 (see module docstring)."""
+def kernel_values(x, lattice, kappa=0.0, h=1):
+    """K_l at points x [..., 3] (float64) for a level >= 1 (see module docstring); with
+    kappa > 0 the screened LGF at the lattice points x, multiples of the spacing h."""
     x = np.asarray(x, dtype=np.float64)
+    if kappa > 0.0:
+        if not lattice:
+            raise ValueError("the screened kernel needs nodes on the lattice")
+        return _lgf.lgf_lattice(np.rint(x).astype(np.int64), kappa, int(h))
     out = _lgf.asymptotic_values(x, Q_FAR)
     if lattice:
         xi = np.rint(x).astype(np.int64)
@@ -240,17 +250,17 @@ def kernel_block(D, m, origin_fn):
     return k
 
 
-def near_kernel_fn(n):
+def near_kernel_fn(n, kappa=0.0):
     def fn(D, r):
-        return _lgf.lgf(D[None, None, None, :] * n + r)
+        return _lgf.lgf(D[None, None, None, :] * n + r, kappa)
     return fn
 
 
-def far_kernel_fn(n, p, l):
+def far_kernel_fn(n, p, l, kappa=0.0):
     s, h, lattice = level_geometry(n, p, l)
 
     def fn(D, r):
-        return kernel_values(D[None, None, None, :] * s + r * h, lattice)
+        return kernel_values(D[None, None, None, :] * s + r * h, lattice, kappa, int(round(h)) if lattice else 1)
     return fn
 
 
@@ -272,8 +282,11 @@ class FLGF:
     """Plan + solve for u = G * f on a block layout, evaluated by the FLGF method.
     f lives on `blocks` (B_s); u is evaluated on `eval_blocks` (B_e), default B_s."""
 
-    def __init__(self, blocks, n, p, levels, eval_blocks=None):
+    def __init__(self, blocks, n, p, levels, eval_blocks=None, kappa=0.0):
         self.n, self.p = int(n), int(p)
+        self.kappa = _lgf._check_kappa(kappa)
+        if self.kappa > 0.0 and self.n % (self.p - 1):
+            raise ValueError("the screened kernel needs nodes on the lattice: (p - 1) must divide n")
         self.tree = Tree(blocks, levels, eval_blocks)
         self.A = block_matrix(self.n, self.p)
         self.C = child_matrices(self.p)
@@ -281,11 +294,11 @@ class FLGF:
         M0 = 2 * self.n
         self.khat0 = {}
         for D in {tuple(d) for d in self.tree.near[2].tolist()}:
-            self.khat0[D] = np.fft.rfftn(kernel_block(D, self.n, near_kernel_fn(self.n)))
+            self.khat0[D] = np.fft.rfftn(kernel_block(D, self.n, near_kernel_fn(self.n, self.kappa)))
         M1 = 2 * self.p
         self.khat = {}
         for l in range(1, self.tree.L + 1):
-            fn = far_kernel_fn(self.n, self.p, l)
+            fn = far_kernel_fn(self.n, self.p, l, self.kappa)
             for D in {tuple(d) for d in self.tree.ilist[l][2].tolist()}:
                 self.khat[(l, D)] = np.fft.rfftn(kernel_block(D, self.p, fn))
         self.M0, self.M1 = M0, M1
@@ -359,5 +372,5 @@ class FLGF:
         return u
 
 
-def solve(blocks, f, n, p, levels, eval_blocks=None):
-    return FLGF(blocks, n, p, levels, eval_blocks).solve(f)
+def solve(blocks, f, n, p, levels, eval_blocks=None, kappa=0.0):
+    return FLGF(blocks, n, p, levels, eval_blocks, kappa).solve(f)

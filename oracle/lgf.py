@@ -10,6 +10,11 @@ the benchmark may import this module; the product path never does.
   oracle's own tests), so the switch is seamless in FP64.
 * direct_sum(): u(t) = sum_m G(t - m) f(m)  (Sec. 2.1, Eq. dpoissonsoln), the exact
   result that the fast method approximates.
+* A second non-oscillatory lattice kernel (the method applies to such LGFs, Sec. 5): the
+  LGF G_kappa of the screened operator L - kappa, kappa >= KAPPA_MIN, by the Bessel
+  integral of Appendix A with the extra factor e^{-kappa t} (no tail term: the factor
+  makes the integrand negligible beyond x = 80 / kappa).  It has no asymptotic expansion
+  here; every value is integrated.  kappa = 0 is the Laplace LGF above.
 """
 import ctypes
 import os
@@ -26,6 +31,7 @@ _LIB = os.path.join(_HERE, "liblgf_oracle.so")
 
 BESSEL_RADIUS = 48   # Bessel-integral region: max|n_i| < 48
 Q_TABLE = 8          # terms of A^q used beyond it
+KAPPA_MIN = 1e-3     # weakest screening: the integral then stops at x = 1e5 (kappa x / 2 >= 50)
 
 # Quadrature parameters of the Bessel integral (converged: halving the panel width,
 # raising the order or moving the split point changes G by <= 1 ulp-ish, see tests).
@@ -54,6 +60,9 @@ def lib():
                                            ctypes.c_int, ctypes.c_void_p]
             L.oracle_lgf_table.restype = ctypes.c_int
             L.oracle_scaled_bessel.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_void_p]
+            L.oracle_lgf_table_screened.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double, ctypes.c_int, ctypes.c_void_p]
+            L.oracle_lgf_table_screened.restype = ctypes.c_int
             L.oracle_direct_sum.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                             ctypes.c_int64, ctypes.c_void_p]
@@ -82,6 +91,27 @@ def bessel_table(R, xmax=XMAX, panel=PANEL, order=ORDER):
     rc = lib().oracle_lgf_table(int(R), float(xmax), float(panel), int(order), out.ctypes.data)
     if rc != 0:
         raise RuntimeError("oracle_lgf_table failed")
+    return out
+
+
+def _check_kappa(kappa):
+    kappa = float(kappa)
+    if not (kappa == 0.0 or kappa >= KAPPA_MIN):
+        raise ValueError("kappa must be 0 (Laplace) or >= %g" % KAPPA_MIN)
+    return kappa
+
+
+def screened_table(R, kappa, h=1, xmax=XMAX, panel=PANEL, order=ORDER):
+    """G_kappa(h a, h b, h c) on the octant 0 <= a, b, c < R by the Bessel integral with
+    the screening factor (kappa >= KAPPA_MIN)."""
+    kappa = _check_kappa(kappa)
+    if kappa == 0.0:
+        raise ValueError("screened_table needs kappa > 0 (the Laplace table is bessel_table)")
+    out = np.zeros((R, R, R), dtype=np.float64)
+    rc = lib().oracle_lgf_table_screened(int(R), int(h), kappa, float(xmax), float(panel), int(order),
+                                         out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("oracle_lgf_table_screened failed (%d)" % rc)
     return out
 
 
@@ -126,9 +156,13 @@ def asymptotic_values(points, q=Q_TABLE):
 _table_cache = {}
 
 
-def lgf_table(R):
-    """Full-octant table G[a, b, c], 0 <= a, b, c < R (Bessel near, A^Q_TABLE far)."""
+def lgf_table(R, kappa=0.0):
+    """Full-octant table G[a, b, c], 0 <= a, b, c < R (Bessel near, A^Q_TABLE far); with
+    kappa > 0 the screened LGF G_kappa, integrated everywhere."""
     R = int(R)
+    kappa = _check_kappa(kappa)
+    if kappa > 0.0:
+        return lattice_table(R, kappa, 1)
     with _lock:
         hit = _table_cache.get(R)
     if hit is not None:
@@ -150,25 +184,54 @@ def lgf_table(R):
     return T
 
 
-def lgf(points):
-    """G at integer points [..., 3]."""
+_lattice_cache = {}
+
+
+def lattice_table(R, kappa, h):
+    """G_kappa(h a, h b, h c), 0 <= a, b, c < R (kappa > 0), cached."""
+    key = (int(R), float(kappa), int(h))
+    with _lock:
+        hit = _lattice_cache.get(key)
+    if hit is not None:
+        return hit
+    T = screened_table(int(R), kappa, int(h))
+    with _lock:
+        _lattice_cache[key] = T
+    return T
+
+
+def lgf(points, kappa=0.0):
+    """G at integer points [..., 3] (G_kappa with kappa > 0)."""
     pts = np.asarray(points, dtype=np.int64)
     ab = np.abs(pts)
     R = int(ab.max()) + 1 if ab.size else 1
-    T = lgf_table(max(R, 2))
+    T = lgf_table(max(R, 2), kappa)
     return T[ab[..., 0], ab[..., 1], ab[..., 2]]
 
 
-def direct_sum(src, f, tgt):
+def lgf_lattice(points, kappa, h):
+    """G_kappa at integer points [..., 3] that are multiples of h (kappa > 0), from a
+    table at spacing h."""
+    pts = np.asarray(points, dtype=np.int64)
+    if np.any(pts % h):
+        raise ValueError("points are not multiples of the spacing")
+    ab = np.abs(pts) // h
+    R = int(ab.max()) + 1 if ab.size else 1
+    T = lattice_table(max(R, 2), kappa, h)
+    return T[ab[..., 0], ab[..., 1], ab[..., 2]]
+
+
+def direct_sum(src, f, tgt, kappa=0.0):
     """u(t) = sum_m G(t - m) f(m) over integer source points src [N,3] (x,y,z),
-    source values f [N], integer targets tgt [T,3].  Brute force, Neumaier sums."""
+    source values f [N], integer targets tgt [T,3].  Brute force, Neumaier sums.  With
+    kappa > 0, G is the screened operator's LGF G_kappa."""
     src = np.ascontiguousarray(np.asarray(src, dtype=np.int32))
     tgt = np.ascontiguousarray(np.asarray(tgt, dtype=np.int32))
     f = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
     lo = np.minimum(src.min(axis=0), tgt.min(axis=0))
     hi = np.maximum(src.max(axis=0), tgt.max(axis=0))
     R = int(np.max(hi - lo)) + 1
-    T = lgf_table(max(R, 2))
+    T = lgf_table(max(R, 2), kappa)
     u = np.zeros(tgt.shape[0], dtype=np.float64)
     bad = lib().oracle_direct_sum(T.ctypes.data, T.shape[0], src.ctypes.data, f.ctypes.data,
                                   src.shape[0], tgt.ctypes.data, tgt.shape[0], u.ctypes.data)
@@ -177,14 +240,14 @@ def direct_sum(src, f, tgt):
     return u
 
 
-def laplacian(U):
-    """[L U](n) = sum_{+-e_i} U(n +- e_i) - 6 U(n) (Sec. 2.1, Eq. dpoisson) on a dense
-    array U[z, y, x] that is zero outside it; returns an array one cell larger on
-    every side (index shift +1)."""
+def laplacian(U, kappa=0.0):
+    """[L U](n) = sum_{+-e_i} U(n +- e_i) - 6 U(n) (Sec. 2.1, Eq. dpoisson), minus kappa U(n)
+    for the screened operator, on a dense array U[z, y, x] that is zero outside it; returns
+    an array one cell larger on every side (index shift +1)."""
     U = np.asarray(U, dtype=np.float64)
     P = np.zeros(tuple(s + 4 for s in U.shape))
     P[2:-2, 2:-2, 2:-2] = U
-    out = -6.0 * P[1:-1, 1:-1, 1:-1]
+    out = -(6.0 + kappa) * P[1:-1, 1:-1, 1:-1]
     out += P[2:, 1:-1, 1:-1] + P[:-2, 1:-1, 1:-1]
     out += P[1:-1, 2:, 1:-1] + P[1:-1, :-2, 1:-1]
     out += P[1:-1, 1:-1, 2:] + P[1:-1, 1:-1, :-2]

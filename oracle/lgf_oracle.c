@@ -18,6 +18,8 @@
  *      a_t(k) = prod_{s=1..t} (4k^2 - (2s-1)^2) / (t! 8^t).
  * 2. Direct sum u(t) = sum_m G(t - m) f(m)  (Sec. 2.1, Eq. dpoissonsoln) with
  *    Neumaier-compensated accumulation, OpenMP over targets.
+ * 3. The LGF of the screened operator L - kappa (a second non-oscillatory lattice kernel,
+ *    Sec. 5), by the same Bessel integral with the extra factor e^{-kappa t}.
  *
  * Build:  gcc -O2 -fopenmp -shared -fPIC lgf_oracle.c -o liblgf_oracle.so -lm
  */
@@ -194,6 +196,74 @@ int oracle_lgf_table(int R, double xmax, double panel_width, int order, double* 
             out[((size_t)p[k][0] * R + p[k][1]) * R + p[k][2]] = g;
     }
     free(tri); free(ak); free(Ib); free(xs); free(ws); free(gx); free(gw);
+    return 0;
+}
+
+/*
+ * LGF of the screened operator L - kappa (kappa > 0; [L u](n) = sum_{+-e_i} u(n +- e_i)
+ * - 6 u(n)).  Its Fourier symbol is 2cos(xi_1) + 2cos(xi_2) + 2cos(xi_3) - 6 - kappa, so the
+ * derivation of Eq. lgf3 from Eq. lgf1 goes through with 6 replaced by 6 + kappa:
+ *     G_kappa(n) = - int_0^inf e^{-(6 + kappa) t} I_{n1}(2t) I_{n2}(2t) I_{n3}(2t) dt
+ *                = -1/2 int_0^inf e^{-kappa x / 2} Ib_{n1}(x) Ib_{n2}(x) Ib_{n3}(x) dx.
+ * The factor e^{-kappa x/2} makes the integrand negligible beyond x = 80 / kappa, so the
+ * integral stops at xmax with no tail term; xmax * kappa / 2 >= 40 is required.
+ * out[(a*R + b)*R + c] = G_kappa(h a, h b, h c) for 0 <= a, b, c < R (lattice spacing h).
+ * Returns 0 on success.
+ */
+int oracle_lgf_table_screened(int R, int h, double kappa, double xmax, double panel_width, int order,
+                              double* out) {
+    if (R < 1 || h < 1 || !(kappa > 0.0) || xmax <= 1.0 || panel_width <= 0.0 || order < 2) return 1;
+    if (0.5 * kappa * xmax < 40.0) return 2;
+    const double smin = log(1e-18), smax = log(xmax);
+    int npan = (int)ceil((smax - smin) / panel_width);
+    double hs = (smax - smin) / npan;
+    int nq = npan * order;
+    int K = h * (R - 1); /* highest Bessel order used */
+    double* gx = (double*)malloc(sizeof(double) * order);
+    double* gw = (double*)malloc(sizeof(double) * order);
+    gauss_legendre(order, gx, gw);
+    double* xs = (double*)malloc(sizeof(double) * nq);
+    double* ws = (double*)malloc(sizeof(double) * nq);
+    for (int p = 0; p < npan; ++p)
+        for (int i = 0; i < order; ++i) {
+            double sv = smin + hs * (p + 0.5 * (gx[i] + 1.0));
+            double x = exp(sv);
+            xs[p * order + i] = x;
+            ws[p * order + i] = 0.5 * hs * gw[i] * x * exp(-0.5 * kappa * x); /* dx = x ds, screening */
+        }
+    double* Ib = (double*)malloc(sizeof(double) * (size_t)nq * (K + 1));
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int q = 0; q < nq; ++q) scaled_bessel_miller(xs[q], K, Ib + (size_t)q * (K + 1));
+    int ntri = 0;
+    for (int a = 0; a < R; ++a)
+        for (int b = 0; b <= a; ++b)
+            for (int c = 0; c <= b; ++c) ++ntri;
+    int* tri = (int*)malloc(sizeof(int) * 3 * ntri);
+    {
+        int t = 0;
+        for (int a = 0; a < R; ++a)
+            for (int b = 0; b <= a; ++b)
+                for (int c = 0; c <= b; ++c) {
+                    tri[3 * t] = a; tri[3 * t + 1] = b; tri[3 * t + 2] = c; ++t;
+                }
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int t = 0; t < ntri; ++t) {
+        int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+        double sm = 0.0, cc = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            const double* I = Ib + (size_t)q * (K + 1);
+            double term = ws[q] * I[h * a] * I[h * b] * I[h * c];
+            double u = sm + term;
+            if (fabs(sm) >= fabs(term)) cc += (sm - u) + term; else cc += (term - u) + sm;
+            sm = u;
+        }
+        double g = -0.5 * (sm + cc);
+        int pm[6][3] = {{a, b, c}, {a, c, b}, {b, a, c}, {b, c, a}, {c, a, b}, {c, b, a}};
+        for (int k = 0; k < 6; ++k)
+            out[((size_t)pm[k][0] * R + pm[k][1]) * R + pm[k][2]] = g;
+    }
+    free(tri); free(Ib); free(xs); free(ws); free(gx); free(gw);
     return 0;
 }
 
