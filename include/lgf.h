@@ -81,6 +81,8 @@ typedef struct {
                                  unless the plan has separate sets, where nblocks counts
                                  the union the tree of levels >= 1 is built on          */
     int32_t spectra_mode;     /* lgf_spectra_mode of the plan's kernel spectra          */
+    double kappa;             /* screening of the operator (lgf_plan_create_screened),
+                                 0 for the Laplace operator                             */
 } lgf_plan_info;
 
 /*
@@ -106,6 +108,24 @@ typedef struct {
  */
 lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p,
                            int32_t levels, lgf_precision prec, void* hip_stream, lgf_plan_t* out);
+
+/*
+ * A plan for the screened operator L - kappa instead of L: u = G_kappa * f with G_kappa the
+ * lattice Green's function of [L_kappa u](n) = sum_{+-e_i} u(n +- e_i) - (6 + kappa) u(n),
+ * the discrete modified-Helmholtz operator (an implicit viscous step on the same grid leads
+ * to it).  The paper's method applies to it unchanged as a second non-oscillatory lattice
+ * kernel (Sec. 5): only the kernel values differ.  They are the Bessel integral of
+ * Appendix A (Eq. lgf3) with 6 + kappa in place of 6, integrated on the device in FP64 at
+ * every point a kernel block uses; there is no asymptotic expansion of G_kappa here, so
+ * every interpolation node must lie on the lattice: (p - 1) must divide n (p = n + 1 is the
+ * paper's scheme; p = 17 with n = 16 uses its local stencils).
+ *   kappa : 0 (the same plan as lgf_plan_create) or in [1e-3, 1e6]
+ * All other arguments, the solve (lgf_solve, graphs, tuning) and the errors as for
+ * lgf_plan_create; LGF_ERR_ARG also for kappa out of range or nodes off the lattice.
+ */
+lgf_status lgf_plan_create_screened(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p,
+                                    int32_t levels, double kappa, lgf_precision prec, void* hip_stream,
+                                    lgf_plan_t* out);
 
 /*
  * Host-only preview of lgf_plan_create: builds the tree and lists of the layout (no device
@@ -391,6 +411,14 @@ const char* lgf_last_error(void);
  *   R^3 doubles.  Synchronous.  Errors: LGF_ERR_ARG (R < 1 or R > 128), LGF_ERR_DEVICE.
  */
 lgf_status lgf_green_table(int32_t R, double* out);
+
+/*
+ * The screened operator's LGF G_kappa (lgf_plan_create_screened) from the library's own
+ * FP64 device integration, for validation: out[(a*R + b)*R + c] = G_kappa(a, b, c) for
+ * 0 <= a, b, c < R, HOST array of R^3 doubles.  Synchronous.
+ * Errors: LGF_ERR_ARG (R < 1, R > 128, kappa outside [1e-3, 1e6]), LGF_ERR_DEVICE.
+ */
+lgf_status lgf_green_table_screened(int32_t R, double kappa, double* out);
 
 /*
  * The library's far-field kernel A^q (Sec. 2.1, Eq. lgf2, q = 8 terms) at npts HOST

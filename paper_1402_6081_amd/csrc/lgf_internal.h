@@ -232,6 +232,7 @@ struct SpectraKey {
     int prec;          // 0 = f64, 1 = f32
     int m = 0;         // tile edge (0: n at level 0, p above; n at level 1 of the lattice scheme)
     int sym = 0;       // 1 = symmetry-reduced table (one spectrum per class of offsets)
+    double kappa = 0;  // screening of the operator L - kappa (0: the Laplace LGF)
     bool operator<(const SpectraKey& o) const;
 };
 
@@ -263,6 +264,10 @@ int spectra_classes(int R, std::vector<uint32_t>& info, std::vector<int32_t>& re
 
 // LGF table [R][R][R] (full octant) on the device, FP64, cached per R.
 const double* green_table_device(int R, hipStream_t s, std::string& err);
+// LGF of the screened operator L - kappa (kappa >= kKappaMin) at lattice spacing h:
+// T[(a*R + b)*R + c] = G_kappa(h a, h b, h c), 0 <= a, b, c < R; device, FP64, cached.
+constexpr double kKappaMin = 1e-3;
+const double* screened_table_device(int R, int h, double kappa, hipStream_t s, std::string& err);
 // far kernel A^q at device points (FP64): out[i] = A^q(pts[i])
 hipError_t far_kernel_device(const double* pts, int64_t npts, double* out, hipStream_t s, std::string& err);
 // The same at HOST points into HOST out, staged through the library's static device array

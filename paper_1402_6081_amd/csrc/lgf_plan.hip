@@ -537,6 +537,7 @@ struct LevelPlan {
 
 struct lgf_plan_s {
     int n = 0, p = 0, L = 0, Ltop = 0;
+    double kappa = 0.0;  // screening of the operator L - kappa (0: the Laplace operator)
     lgf_precision prec = LGF_F64;
     int64_t nb = 0, near_pairs = 0, ngroups0 = 0;
     int64_t nsrc = 0, neval = 0;        // blocks of f / of u (nb for both unless the sets differ)
@@ -946,8 +947,9 @@ hipError_t solve_dispatch(lgf_plan_s* pl, const void* f, void* u, hipStream_t s)
                                : run_solve<float>(pl, (const float*)f, (float*)u, s);
 }
 
-lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan_s* pl) {
+lgf_status setup_device(HostPlan& H, lgf_precision prec, double kappa, hipStream_t s, lgf_plan_s* pl) {
     const int n = H.n, p = H.p;
+    pl->kappa = kappa;
     pl->n = n;
     pl->p = p;
     pl->prec = prec;
@@ -991,14 +993,14 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
         return fail(m.find("budget") != std::string::npos ? LGF_ERR_BUDGET : LGF_ERR_DEVICE, m);
     };
     const int sm = spectra_mode();  // full or symmetry-reduced tables, fixed for the plan's life
-    pl->spectra0 = get_spectra(SpectraKey{n, p, 0, 1, ip, 0, sm}, s, err);
+    pl->spectra0 = get_spectra(SpectraKey{n, p, 0, 1, ip, 0, sm, kappa}, s, err);
     if (!pl->spectra0) return err_status(err);
     std::vector<std::vector<int32_t>> csr_off(H.L + 1);
     for (int l = 1; l <= pl->Ltop; ++l) {
         LevelPlan& L = pl->lv[l];
         const int mt = l == 1 && H.lat1 ? n : 0;  // tile edge of the level's spectra (0: p)
         if (L.sib_pairs > 0) {
-            L.spectra = get_spectra(SpectraKey{n, p, l, 3, ip, mt, sm}, s, err);
+            L.spectra = get_spectra(SpectraKey{n, p, l, 3, ip, mt, sm, kappa}, s, err);
             if (!L.spectra) return err_status(err);
         }
         if (L.csr_entries > 0) {
@@ -1009,7 +1011,7 @@ lgf_status setup_device(HostPlan& H, lgf_precision prec, hipStream_t s, lgf_plan
             if ((int64_t)W * W * W > 300000)
                 return fail(LGF_ERR_LAYOUT, "top-level offsets too large: use more levels");
             for (const auto& D : H.lv[l].csr_D) csr_off[l].push_back((D[0] + R) + W * ((D[1] + R) + W * (D[2] + R)));
-            L.spectra_csr = get_spectra(SpectraKey{n, p, l, R, ip, mt, sm}, s, err);
+            L.spectra_csr = get_spectra(SpectraKey{n, p, l, R, ip, mt, sm, kappa}, s, err);
             if (!L.spectra_csr) return err_status(err);
         }
     }
@@ -1318,11 +1320,12 @@ static lgf_status check_args(int32_t n, int32_t p, lgf_precision prec) {
     return LGF_OK;
 }
 
-static lgf_status make_plan(HostPlan& H, lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
+static lgf_status make_plan(HostPlan& H, lgf_precision prec, void* hip_stream, lgf_plan_t* out,
+                            double kappa = 0.0) {
     lgf_status st = check_host(H);
     if (st != LGF_OK) return st;
     lgf_plan_s* pl = new lgf_plan_s();
-    st = setup_device(H, prec, (hipStream_t)hip_stream, pl);
+    st = setup_device(H, prec, kappa, (hipStream_t)hip_stream, pl);
     if (st != LGF_OK) {
         delete pl;
         return st;
@@ -1339,9 +1342,20 @@ static lgf_status check_layout(const int32_t* ijk, int64_t nblocks, const char* 
     return LGF_OK;
 }
 
+// The screened operator L - kappa: kappa = 0 (the Laplace operator) or kappa >= kKappaMin;
+// its kernel is integrated at every point used, so every node must lie on the lattice.
+static lgf_status check_kappa(double kappa, int32_t n, int32_t p) {
+    if (kappa == 0.0) return LGF_OK;
+    if (!(kappa >= kKappaMin) || !(kappa <= 1e6))
+        return fail(LGF_ERR_ARG, "kappa must be 0 or lie in [1e-3, 1e6]");
+    if (p < 2 || n % (p - 1) != 0)
+        return fail(LGF_ERR_ARG, "the screened operator needs nodes on the lattice: (p - 1) must divide n");
+    return LGF_OK;
+}
+
 static lgf_status create_plan(const int32_t* src_ijk, int64_t nsrc, const int32_t* eval_ijk, int64_t neval,
                               int32_t n, int32_t p, int32_t levels, lgf_precision prec, void* hip_stream,
-                              lgf_plan_t* out) {
+                              lgf_plan_t* out, double kappa = 0.0) {
     t_err.clear();
     if (!out) return fail(LGF_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -1349,12 +1363,13 @@ static lgf_status create_plan(const int32_t* src_ijk, int64_t nsrc, const int32_
     if (st == LGF_OK && eval_ijk) st = check_layout(eval_ijk, neval, "eval_ijk");
     if (st == LGF_OK && nsrc + (eval_ijk ? neval : 0) > (int64_t)1 << 30) st = fail(LGF_ERR_ARG, "too many blocks");
     if (st == LGF_OK) st = check_args(n, p, prec);
+    if (st == LGF_OK) st = check_kappa(kappa, n, p);
     if (st != LGF_OK) return st;
     try {
         HostPlan H;
         st = build_host(src_ijk, nsrc, n, p, levels, H, eval_ijk, neval);
         if (st != LGF_OK) return st;
-        return make_plan(H, prec, hip_stream, out);
+        return make_plan(H, prec, hip_stream, out, kappa);
     } catch (const std::bad_alloc&) {
         return fail(LGF_ERR_OOM, "host allocation failed");
     } catch (...) {
@@ -1365,6 +1380,11 @@ static lgf_status create_plan(const int32_t* src_ijk, int64_t nsrc, const int32_
 lgf_status lgf_plan_create(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
                            lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
     return create_plan(block_ijk, nblocks, nullptr, 0, n, p, levels, prec, hip_stream, out);
+}
+
+lgf_status lgf_plan_create_screened(const int32_t* block_ijk, int64_t nblocks, int32_t n, int32_t p, int32_t levels,
+                                    double kappa, lgf_precision prec, void* hip_stream, lgf_plan_t* out) {
+    return create_plan(block_ijk, nblocks, nullptr, 0, n, p, levels, prec, hip_stream, out, kappa);
 }
 
 lgf_status lgf_plan_create_split(const int32_t* source_ijk, int64_t nsource, const int32_t* eval_ijk,
@@ -1627,6 +1647,7 @@ lgf_status lgf_plan_query(lgf_plan_t plan, lgf_plan_info* info) {
     info->source_blocks = plan->nsrc;
     info->eval_blocks = plan->neval;
     info->spectra_mode = plan->spectra0 ? plan->spectra0->key.sym : 0;
+    info->kappa = plan->kappa;
     return LGF_OK;
 }
 
@@ -1720,6 +1741,18 @@ lgf_status lgf_green_table(int32_t R, double* out) {
     for (int a = 0; a < R; ++a)
         for (int b = 0; b < R; ++b)
             for (int c = 0; c < R; ++c) out[((size_t)a * R + b) * R + c] = full[((size_t)a * Rt + b) * Rt + c];
+    return LGF_OK;
+}
+
+lgf_status lgf_green_table_screened(int32_t R, double kappa, double* out) {
+    if (R < 1 || R > 128 || !out) return fail(LGF_ERR_ARG, "lgf_green_table_screened: R must be in [1, 128]");
+    if (!(kappa >= kKappaMin) || !(kappa <= 1e6))
+        return fail(LGF_ERR_ARG, "lgf_green_table_screened: kappa must lie in [1e-3, 1e6]");
+    std::string err;
+    const double* G = screened_table_device(R, 1, kappa, nullptr, err);
+    if (!G) return fail(LGF_ERR_DEVICE, err);
+    if (hipMemcpy(out, G, (size_t)R * R * R * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(LGF_ERR_DEVICE, "copy of the screened Green's function table failed");
     return LGF_OK;
 }
 

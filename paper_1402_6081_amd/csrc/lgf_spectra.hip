@@ -120,6 +120,28 @@ __global__ void k_bessel_nodes(const double* __restrict__ xs, int nq, int R, dou
     for (int k = 0; k < R; ++k) out[k] *= inv;
 }
 
+// LGF of the screened operator L - kappa at lattice spacing h, one thread per (a, b, c):
+// the derivation of Eq. lgf3 from Eq. lgf1 holds with 6 + kappa in place of 6, i.e. the
+// integrand gains the factor e^{-kappa t} = e^{-kappa x / 2}.  That factor is below e^{-40}
+// beyond the last abscissa for kappa >= kKappaMin, so there is no tail term.
+__global__ void k_green_table_screened(const double* __restrict__ I, const double* __restrict__ xs,
+                                       const double* __restrict__ w, int nq, int K1, int R, int h, double kappa,
+                                       double* __restrict__ G) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)R * R * R) return;
+    const int c = (int)(id % R), b = (int)((id / R) % R), a = (int)(id / ((int64_t)R * R));
+    const int ka = h * a, kb = h * b, kc = h * c;
+    double sum = 0.0, comp = 0.0;
+    for (int q = 0; q < nq; ++q) {
+        const double* Iq = I + (int64_t)q * K1;
+        const double y = w[q] * exp(-0.5 * kappa * xs[q]) * Iq[ka] * Iq[kb] * Iq[kc] - comp;
+        const double t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    }
+    G[id] = -0.5 * (sum - comp);
+}
+
 // One thread per (a, b, c): G[a][b][c].
 __global__ void k_green_table(const double* __restrict__ I, const double* __restrict__ w, int nq, int R,
                               double xsplit, double* __restrict__ G) {
@@ -319,8 +341,9 @@ __global__ void k_far_kernel(const double* __restrict__ pts, int64_t npts, AsymD
 //   mode 0: exact G (table) at integer points
 //   mode 1: lattice nodes: G where max|x_i| < kLatticeRadius, A^q elsewhere
 //   mode 2: A^q everywhere
+//   mode 3: the screened LGF from a table at lattice spacing hg (every point is a multiple)
 __global__ void k_kernel_block(double* __restrict__ out, int M, int m, int radius, double s, double h, int mode,
-                               const double* __restrict__ G, int Rg, AsymDev A) {
+                               const double* __restrict__ G, int Rg, AsymDev A, int hg) {
     const int M3 = M * M * M;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= M3) return;
@@ -337,7 +360,11 @@ __global__ void k_kernel_block(double* __restrict__ out, int M, int m, int radiu
     }
     double v = 0.0;
     if (valid) {
-        if (mode == 0) {
+        if (mode == 3) {
+            const double x = D[0] * s + r[0] * h, y = D[1] * s + r[1] * h, z = D[2] * s + r[2] * h;
+            const int a0 = (int)rint(fabs(x)) / hg, a1 = (int)rint(fabs(y)) / hg, a2 = (int)rint(fabs(z)) / hg;
+            v = G[((int64_t)a0 * Rg + a1) * Rg + a2];
+        } else if (mode == 0) {
             const int a0 = abs(D[0] * (int)s + r[0]), a1 = abs(D[1] * (int)s + r[1]), a2 = abs(D[2] * (int)s + r[2]);
             v = G[((int64_t)a0 * Rg + a1) * Rg + a2];
         } else {
@@ -460,8 +487,8 @@ int current_device() {
 }  // namespace
 
 bool SpectraKey::operator<(const SpectraKey& o) const {
-    return std::make_tuple(n, p, level, radius, prec, m, sym) <
-           std::make_tuple(o.n, o.p, o.level, o.radius, o.prec, o.m, o.sym);
+    return std::make_tuple(n, p, level, radius, prec, m, sym, kappa) <
+           std::make_tuple(o.n, o.p, o.level, o.radius, o.prec, o.m, o.sym, o.kappa);
 }
 
 SpectraEntry::~SpectraEntry() {
@@ -546,6 +573,57 @@ static const double* green_table_locked(int R, hipStream_t s, std::string& err) 
 const double* green_table_device(int R, hipStream_t s, std::string& err) {
     std::lock_guard<std::mutex> lk(g_mu);
     return green_table_locked(R, s, err);
+}
+
+namespace {
+std::map<std::tuple<int, int, int, double>, double*> g_screened;  // (device, R, h, kappa) -> table
+}
+
+static const double* screened_table_locked(int R, int h, double kappa, hipStream_t s, std::string& err) {
+    const int dev = current_device();
+    const auto key = std::make_tuple(dev, R, h, kappa);
+    auto it = g_screened.find(key);
+    if (it != g_screened.end()) return it->second;
+    if (!(kappa >= kKappaMin) || R < 1 || h < 1) {
+        err = "screened LGF table: bad arguments";
+        return nullptr;
+    }
+    const Quadrature& Q = quadrature();
+    const int nq = (int)Q.x.size();
+    const int K1 = h * (R - 1) + 1;  // Bessel orders 0 .. h (R - 1)
+    double *dx = nullptr, *dw = nullptr, *dI = nullptr, *dG = nullptr;
+    const size_t gbytes = (size_t)R * R * R * sizeof(double);
+    if (hipMalloc(&dx, nq * sizeof(double)) != hipSuccess || hipMalloc(&dw, nq * sizeof(double)) != hipSuccess ||
+        hipMalloc(&dI, (size_t)nq * K1 * sizeof(double)) != hipSuccess || hipMalloc(&dG, gbytes) != hipSuccess) {
+        err = "hipMalloc failed for the screened Green's function table";
+        if (dx) hipFree(dx);
+        if (dw) hipFree(dw);
+        if (dI) hipFree(dI);
+        if (dG) hipFree(dG);
+        return nullptr;
+    }
+    hipMemcpyAsync(dx, Q.x.data(), nq * sizeof(double), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dw, Q.w.data(), nq * sizeof(double), hipMemcpyHostToDevice, s);
+    hipLaunchKernelGGL(k_bessel_nodes, dim3((nq + 63) / 64), dim3(64), 0, s, dx, nq, K1, dI);
+    const int64_t tot = (int64_t)R * R * R;
+    hipLaunchKernelGGL(k_green_table_screened, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, dI, dx, dw, nq,
+                       K1, R, h, kappa, dG);
+    hipError_t e = hipStreamSynchronize(s);
+    hipFree(dx);
+    hipFree(dw);
+    hipFree(dI);
+    if (e != hipSuccess) {
+        err = std::string("screened Green's function table kernels failed: ") + hipGetErrorString(e);
+        hipFree(dG);
+        return nullptr;
+    }
+    g_screened[key] = dG;
+    return dG;
+}
+
+const double* screened_table_device(int R, int h, double kappa, hipStream_t s, std::string& err) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return screened_table_locked(R, h, kappa, s, err);
 }
 
 hipError_t far_kernel_device(const double* pts, int64_t npts, double* out, hipStream_t s, std::string& err) {
@@ -642,8 +720,24 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
         hl = sl / (key.p - 1);
         mode = (sint % (key.p - 1) == 0) ? 1 : 2;
     }
-    const int Rg = std::max(2 * key.n, kLatticeRadius);
-    const double* G = green_table_locked(Rg, s, err);
+    int Rg = std::max(2 * key.n, kLatticeRadius);
+    int hg = 1;  // lattice spacing of the table
+    const double* G = nullptr;
+    if (key.kappa > 0.0) {
+        // the screened kernel is integrated at every point it is used: a table at the
+        // level's node spacing out to the farthest offset (every node is on the lattice)
+        if (mode == 2) {
+            err = "the screened operator needs nodes on the lattice";
+            return nullptr;
+        }
+        hg = key.level == 0 ? 1 : (int)std::llround(hl);
+        const int64_t reach = (int64_t)std::llround(key.radius * sl + (m - 1) * hl);
+        Rg = (int)(reach / hg) + 1;
+        mode = 3;
+        G = screened_table_locked(Rg, hg, key.kappa, s, err);
+    } else {
+        G = green_table_locked(Rg, s, err);
+    }
     if (!G) return nullptr;
 
     auto entry = std::make_shared<SpectraEntry>();
@@ -702,7 +796,7 @@ std::shared_ptr<SpectraEntry> get_spectra(const SpectraKey& key, hipStream_t s, 
     const std::vector<double> tw = root_table(M);
     hipMemcpyAsync(dtw, tw.data(), 2 * M * sizeof(double), hipMemcpyHostToDevice, s);
     hipLaunchKernelGGL(k_kernel_block, dim3((unsigned)((M3 + 255) / 256), noff), dim3(256), 0, s, kb, M, m,
-                       key.radius, sl, hl, mode, G, Rg, asym_view(dev));
+                       key.radius, sl, hl, mode, G, Rg, asym_view(dev), hg);
     // x: real rows -> half spectrum; then y and z complex passes
     const int64_t rows = (int64_t)noff * M * M;
     hipLaunchKernelGGL(k_dft_r2c_x, dim3((unsigned)((rows * H + 255) / 256)), dim3(256), 0, s, kb, t1, rows, M, dtw);

@@ -34,7 +34,7 @@ class PlanInfo(ctypes.Structure):
         ("intervals", ctypes.c_int64 * 16), ("workspace_bytes", ctypes.c_int64),
         ("spectra_bytes", ctypes.c_int64), ("precision", ctypes.c_int32),
         ("source_blocks", ctypes.c_int64), ("eval_blocks", ctypes.c_int64),
-        ("spectra_mode", ctypes.c_int32),
+        ("spectra_mode", ctypes.c_int32), ("kappa", ctypes.c_double),
     ]
 
 
@@ -72,14 +72,15 @@ class StepProfile(ctypes.Structure):
     ]
 
 
-EXPORTS = ["lgf_plan_create", "lgf_plan_estimate", "lgf_plan_create_split", "lgf_plan_estimate_split",
+EXPORTS = ["lgf_plan_create", "lgf_plan_create_screened", "lgf_plan_estimate", "lgf_plan_create_split", "lgf_plan_estimate_split",
            "lgf_plan_create_batch", "lgf_plan_solve_offsets", "lgf_solve", "lgf_solve_many",
            "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy", "lgf_plan_autotune", "lgf_plan_get_tuning",
            "lgf_plan_set_tuning", "lgf_server_create", "lgf_server_submit", "lgf_server_poll", "lgf_server_wait",
            "lgf_server_stats", "lgf_server_reset_stats", "lgf_server_destroy",
            "lgf_plan_query", "lgf_plan_destroy", "lgf_set_memory_budget", "lgf_memory_in_use",
            "lgf_spectra_cache_trim", "lgf_set_spectra_mode", "lgf_get_spectra_mode", "lgf_last_error",
-           "lgf_green_table", "lgf_far_kernel", "lgf_far_kernel_noalloc", "lgf_profile_enable",
+           "lgf_green_table", "lgf_green_table_screened", "lgf_far_kernel", "lgf_far_kernel_noalloc",
+           "lgf_profile_enable",
            "lgf_profile_collect"]
 
 _lib = None
@@ -94,6 +95,8 @@ def library():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.lgf_plan_create.argtypes = [vp, i64, i32, i32, i32, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.lgf_plan_create_screened.argtypes = [vp, i64, i32, i32, i32, ctypes.c_double, ctypes.c_int, vp,
+                                               ctypes.POINTER(vp)]
         L.lgf_plan_create_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32, i32, i32,
                                             ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.lgf_plan_solve_offsets.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)]
@@ -123,6 +126,7 @@ def library():
         L.lgf_memory_in_use.restype = i64
         L.lgf_last_error.restype = ctypes.c_char_p
         L.lgf_green_table.argtypes = [i32, vp]
+        L.lgf_green_table_screened.argtypes = [i32, ctypes.c_double, vp]
         L.lgf_far_kernel.argtypes = [vp, i64, vp]
         L.lgf_far_kernel_noalloc.argtypes = [vp, i64, vp]
         L.lgf_profile_enable.argtypes = [vp, i32]
@@ -159,12 +163,16 @@ class Plan:
     """lgf_plan_create / lgf_solve / lgf_plan_query / lgf_plan_destroy.
 
     With `eval_blocks` (lgf_plan_create_split) f lives on `blocks` (B_s) and u on
-    `eval_blocks` (B_e)."""
+    `eval_blocks` (B_e).  With `kappa` > 0 (lgf_plan_create_screened) the operator is the
+    screened L - kappa."""
 
     def __init__(self, blocks, n, p, levels=0, precision="f64", stream=None, _layouts=None, eval_blocks=None,
-                 spectra=None):
+                 spectra=None, kappa=0.0):
         """spectra: "full" or "reduced" kernel spectra for this plan (None: the process-wide
         mode, set_spectra_mode)."""
+        self.kappa = float(kappa)
+        if self.kappa != 0.0 and (_layouts is not None or eval_blocks is not None):
+            raise ValueError("the screened operator is for single-set plans")
         _require_gpu()
         prev = None
         if spectra is not None:
@@ -189,6 +197,10 @@ class Plan:
                                                    self.p, int(levels), prec, _stream_handle(stream),
                                                    ctypes.byref(h)))
             self.eval_blocks = e
+        elif _layouts is None and self.kappa != 0.0:
+            b = _layout(blocks)
+            _check(library().lgf_plan_create_screened(b.ctypes.data, b.shape[0], self.n, self.p, int(levels),
+                                                      self.kappa, prec, _stream_handle(stream), ctypes.byref(h)))
         elif _layouts is None:
             b = _layout(blocks)
             _check(library().lgf_plan_create(b.ctypes.data, b.shape[0], self.n, self.p, int(levels), prec,
@@ -459,6 +471,14 @@ def green_table(R):
     _require_gpu()
     out = np.zeros((R, R, R), dtype=np.float64)
     _check(library().lgf_green_table(int(R), out.ctypes.data))
+    return out
+
+
+def green_table_screened(R, kappa):
+    """G_kappa[a, b, c] for 0 <= a, b, c < R from the library's FP64 device integration."""
+    _require_gpu()
+    out = np.zeros((R, R, R), dtype=np.float64)
+    _check(library().lgf_green_table_screened(int(R), float(kappa), out.ctypes.data))
     return out
 
 
