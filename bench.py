@@ -365,6 +365,66 @@ def medium_bench(L, W, steps, warmup, copy_gbps, graph=True, tune=True, breakdow
     return out
 
 
+def context_bench(L, W, steps=3, warmup=1, seed=7):
+    """The paper's own test geometries at its scale (Sec. 4.1-4.2, Table 2): a cube, a sphere
+    and a spherical shell of thickness 0.1 D, each about 1e8 points as ~24k blocks of 16^3,
+    with a random manufactured solution (u_rand ~ U[-1, 1], zero on the boundary points, f =
+    L u_rand, so G * f = u_rand exactly and the error is known in O(N)).  Schemes p = 8 and
+    the paper's n_I = n + 1 = 17 (n_max = 10), FP64 and FP32, full depth, default kernel
+    variants, eager solves.  Reported per case: points/s, the error against u_rand (relative
+    L-infinity, computed on the device), plan time against solve time."""
+    import torch
+    shapes = (("cube29", W.cube_layout(29)), ("sphere36", W.sphere_layout(36)), ("shell44", W.shell_layout(44)))
+    out = {"note": "context only: the paper's Table 2 rates are 1.2e5 points/s per Xeon X5650 core, FP64, "
+                   "n_I = 7..28, N = 1e8; here one MI355X, default kernel variants, eager solves",
+           "unit": "grid points solved/s"}
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    for name, blocks in shapes:
+        t0 = time.perf_counter()
+        u_ex, f = W.manufactured_pair(blocks, 16, rng)
+        t_gen = time.perf_counter() - t0
+        npts = int(f.size)
+        res = {"blocks": int(len(blocks)), "points": npts, "host_generation_s": round(t_gen, 1)}
+        ue = torch.from_numpy(u_ex).to(dev)
+        scale = float(torch.max(torch.abs(ue)))
+        del u_ex
+        for p in (8, 17):
+            for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+                fd = torch.from_numpy(f).to(dev, dt)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan = L.Plan(blocks, 16, p, 0, prec)
+                torch.cuda.synchronize()
+                t_plan = time.perf_counter() - t0
+                u = torch.empty_like(fd)
+                for _ in range(warmup):
+                    plan.solve(fd, u)
+                torch.cuda.synchronize()
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+                for a, b in ev:
+                    a.record()
+                    plan.solve(fd, u)
+                    b.record()
+                torch.cuda.synchronize()
+                ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+                err = float(torch.max(torch.abs(u.double() - ue))) / scale
+                info = plan.info()
+                res["p%d_%s" % (p, prec)] = {"value": round(npts / (ms * 1e-3), 1), "ms_per_solve": round(ms, 3),
+                                              "rel_linf_err_vs_exact": err, "plan_s": round(t_plan, 3),
+                                              "plan_over_solve": round(t_plan / (ms * 1e-3), 1),
+                                              "levels": info["levels"], "workspace_GB": round(info["workspace_bytes"] / 1e9, 2)}
+                print("context %s p=%d %s: %.3f ms, err %.3g, plan %.2f s" % (name, p, prec, ms, err, t_plan),
+                      file=sys.stderr, flush=True)
+                plan.close()
+                del fd, u
+                torch.cuda.empty_cache()
+        del ue
+        torch.cuda.empty_cache()
+        out[name] = res
+    return out
+
+
 def batch_bench(L, W, steps, warmup, seed=4):
     """64 independent Eden layouts of 8..512 blocks of 16^3, p = 8, FP32: one batch plan,
     one graph launch per batch, against the same 64 solves issued as separate plans."""
@@ -612,6 +672,8 @@ def main():
                     help="only the 128^3 workload with symmetry-reduced spectra (profiling runs)")
     ap.add_argument("--split-only", action="store_true",
                     help="only the separate-set workload (profiling runs); prints its JSON object")
+    ap.add_argument("--context", action="store_true",
+                    help="only the paper-scale context run (cube, sphere, shell of ~1e8 points); prints its JSON object")
     ap.add_argument("--scheme-only", action="store_true",
                     help="only the n_I = n + 1 scheme workload (profiling runs); prints its JSON object")
     ap.add_argument("--no-graph", action="store_true", help="eager solves only (counter runs)")
@@ -631,6 +693,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+    if args.context:
+        print(json.dumps({"context": context_bench(L, W)}), flush=True)
+        return
     if args.split_only or args.scheme_only or args.reduced_only:
         breakdown = {}
         if args.reduced_only:  # the 128^3 workload with reduced spectra, no full-table runs

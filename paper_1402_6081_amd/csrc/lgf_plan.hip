@@ -1162,7 +1162,7 @@ bool valid_tune(const TuneConfig& c) {
     const bool f = c.fft0_threads == 0 || c.fft0_threads == 128 || c.fft0_threads == 256 || c.fft0_threads == 512;
     const bool nw = (c.near_waves == 2 || c.near_waves == 4 || c.near_waves == 8) &&
                     (c.near_prefetch == 0 || c.near_prefetch == 1);
-    const bool fw = c.far_waves == 1 || c.far_waves == 2 || c.far_waves == 4;
+    const bool fw = c.far_waves == 1 || c.far_waves == 2 || c.far_waves == 4 || c.far_waves == 8 || c.far_waves == 16;
     const bool fc = c.far_children == 0 || c.far_children == 1 || c.far_children == 2 || c.far_children == 4 ||
                     c.far_children == 8;
     const bool fw0 = c.far_waves == 0;
@@ -1552,7 +1552,7 @@ lgf_status lgf_plan_autotune(lgf_plan_t plan, const void* f, void* u, void* hip_
     TuneConfig best = start;
     best.overlap = 2;
     float best_ms = timed(best);
-    const std::vector<std::vector<int>> opts = {{128, 256, 512}, {2, 4, 8}, {0, 1}, {0, 1, 2, 4}, {0, 8, 4, 2, 1}};
+    const std::vector<std::vector<int>> opts = {{128, 256, 512}, {2, 4, 8}, {0, 1}, {0, 1, 2, 4, 8, 16}, {0, 8, 4, 2, 1}};
     for (int sweep = 0; sweep < 2; ++sweep) {
         for (int knob = 0; knob < 5; ++knob) {
             for (int v : opts[knob]) {

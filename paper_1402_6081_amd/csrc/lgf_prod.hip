@@ -126,19 +126,30 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     }
     const int32_t* sg = src64 + (int64_t)g * 64;
     const cplx<T>* fbase = fhat + (int64_t)chunk * (nsrc + 1) * 64;  // this chunk's items (uniform)
-    // source z slab sz contributes to target slab cz through kernel rows dz = cz - (sz - 1)
+    // source z slab sz contributes to target slab cz through kernel rows dz = cz - (sz - 1).
+    // Each of the slab's 18 kernel values (9 (dx, dy) x 2 target slabs) is read from LDS once
+    // and applied to the 4 targets (cx, cy) whose source cx - dx, cy - dy lies in the slab.
+    // (dy, dx) run from +1 down to -1, so every target still adds its sources in increasing
+    // (sy, sx) order: the same terms in the same order as a loop over the sources.
     auto slab = [&](int sz, const cplx<T>(&f)[16]) {
         const cplx<T>* t0 = tile + (9 * (3 - sz)) * 64 + lane;  // row base for cz = 0
         const cplx<T>* t1 = tile + (9 * (4 - sz)) * 64 + lane;  // and cz = 1
 #pragma unroll
-        for (int sxy = 0; sxy < 16; ++sxy) {
-            const int sx = (sxy & 3) - 1, sy = (sxy >> 2) - 1;
+        for (int dy = 1; dy >= -1; --dy) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int dx = (c & 1) - sx, dy = ((c >> 1) & 1) - sy;
-                if (dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;  // compile-time
-                const cplx<T> k = ((c >> 2) ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
-                cmac(ar[c], ai[c], f[sxy], k);
+            for (int dx = 1; dx >= -1; --dx) {
+#pragma unroll
+                for (int cz = 0; cz < 2; ++cz) {
+                    const cplx<T> k = (cz ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
+#pragma unroll
+                    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+                        for (int cx = 0; cx < 2; ++cx) {
+                            const int c = cx | (cy << 1) | (cz << 2);
+                            const int sxy = (cx - dx + 1) + 4 * (cy - dy + 1);
+                            cmac(ar[c], ai[c], f[sxy], k);
+                        }
+                }
             }
         }
     };
@@ -493,30 +504,32 @@ static hipError_t far_nw(const FarLevel<T>* lv, int nlev, hipStream_t s) {
         grid += xcd_grid(nchunks, ngb);  // a multiple of the XCD count
     }
     segs.n = nlev;
-    // FP32: 16-bit list entries in LDS when every level's items (and the sentinel) fit,
-    // which lets three workgroups share a CU
-    if constexpr (sizeof(T) == 4) {
-        bool idx16 = true;
-        for (int k = 0; k < nlev; ++k) idx16 = idx16 && lv[k].nsrc < 65535;
-        if (idx16)
-            return lgf_launch(k_prod_far_sib<T, NW, CPL, uint16_t>, dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
-    }
+    // 16-bit list entries in LDS when every level's items (and the sentinel) fit: less LDS
+    // per workgroup, so more workgroups share a CU
+    bool idx16 = true;
+    for (int k = 0; k < nlev; ++k) idx16 = idx16 && lv[k].nsrc < 65535;
+    if (idx16)
+        return lgf_launch(k_prod_far_sib<T, NW, CPL, uint16_t>, dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
     return lgf_launch(k_prod_far_sib<T, NW, CPL, int32_t>, dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
 }
 
 template <typename T, int CPL>
 static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int waves, hipStream_t s) {
     // at most 16 waves (1024 threads) per workgroup, and at most 8 in FP64, whose pipeline
-    // needs more than the 128 registers a lane gets in a 16-wave workgroup
+    // needs more than the 128 registers a lane gets in a 16-wave workgroup.  Larger groups
+    // share one kernel tile among more parents (more waves per CU for the same LDS).
     constexpr int kMaxWaves = sizeof(T) == 8 ? 8 : 16;
-    constexpr int kMaxGroups = kMaxWaves / (8 / CPL) < 4 ? kMaxWaves / (8 / CPL) : 4;
-    switch (waves < kMaxGroups ? waves : kMaxGroups) {
-        case 1: return far_nw<T, 1, CPL>(lv, nlev, s);
-        case 4:
-            if constexpr (kMaxGroups >= 4) return far_nw<T, 4, CPL>(lv, nlev, s);
-            [[fallthrough]];
-        default: return far_nw<T, 2, CPL>(lv, nlev, s);
-    }
+    constexpr int kMaxGroups = kMaxWaves / (8 / CPL);
+    const int g = waves < kMaxGroups ? waves : kMaxGroups;
+    if constexpr (kMaxGroups >= 16)
+        if (g >= 16) return far_nw<T, 16, CPL>(lv, nlev, s);
+    if constexpr (kMaxGroups >= 8)
+        if (g >= 8) return far_nw<T, 8, CPL>(lv, nlev, s);
+    if constexpr (kMaxGroups >= 4)
+        if (g >= 4) return far_nw<T, 4, CPL>(lv, nlev, s);
+    if constexpr (kMaxGroups >= 2)
+        if (g >= 2) return far_nw<T, 2, CPL>(lv, nlev, s);
+    return far_nw<T, 1, CPL>(lv, nlev, s);
 }
 
 // Variant when the plan leaves it open, from measurements on MI355X:
@@ -564,7 +577,7 @@ hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves
         // default variant; the others stay in one launch
         constexpr int F = M2LShape<T>::F;
         const int groups = std::min(waves, (sizeof(T) == 8 ? 8 : 16) / (8 / cpl));
-        const int64_t ppg = (int64_t)M2LShape<T>::PPW * (groups < 4 ? groups : 4);
+        const int64_t ppg = (int64_t)M2LShape<T>::PPW * groups;
         auto wgs = [&](const FarLevel<T>& l) {
             return (int64_t)xcd_grid((l.S + F - 1) / F, 1) * ((l.nparents + ppg - 1) / ppg);
         };

@@ -179,7 +179,7 @@ def test_autotune_keeps_results(L):
     choice = plan.autotune(f, reps=2)
     assert choice["fft0_threads"] in (0, 128, 256, 512)
     assert choice["near_waves"] in (2, 4, 8)
-    assert choice["far_waves"] in (0, 1, 2, 4)
+    assert choice["far_waves"] in (0, 1, 2, 4, 8, 16)
     assert choice["far_children"] in (0, 1, 2, 4, 8)
     assert choice["overlap"] in (0, 1, 2, 3)
     assert choice["near_prefetch"] in (0, 1)
@@ -207,7 +207,7 @@ def test_every_variant_same_bits(L, prec):
         torch.cuda.synchronize()
         variants = [dict(fft0_threads=ft) for ft in (0, 128, 256, 512)]
         variants += [dict(near_waves=nw, near_prefetch=pf) for nw in (2, 4, 8) for pf in (0, 1)]
-        variants += [dict(far_waves=fw, far_children=fc) for fw in (0, 1, 2, 4) for fc in (0, 1, 2, 4, 8)]
+        variants += [dict(far_waves=fw, far_children=fc) for fw in (0, 1, 2, 4, 8, 16) for fc in (0, 1, 2, 4, 8)]
         variants += [dict(overlap=ov) for ov in (1, 2, 3)]
         for v in variants:
             plan.set_tuning(**v)
