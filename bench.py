@@ -41,7 +41,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
-FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (packed FP32 instructions)
+# The kernels are compiled without packed FP32 instructions, so one FP32 FMA per lane per
+# cycle: 256 CUs x 64 lanes x 2 flops x 2.4 GHz, the same as the FP64 vector rate
+FP32_ISSUE_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
 def _time_solves(plan, f, u, steps, warmup):
@@ -138,6 +141,11 @@ def _roofline(prof, dtype_peak_tflops, workload=None, prec=None):
         roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": dtype_peak_tflops, "unit": "TFLOP/s",
                 "frac": round(tfl / dtype_peak_tflops, 4)}
     traffic, src = measured_traffic(workload, prec, dom["name"]) if workload else (None, None)
+    if dtype_peak_tflops == FP32_PEAK_TFLOPS:
+        # the same kernel against the FP32 rate the build can issue (no packed instructions)
+        roof["fp32_issue_peak_tflops"] = round(FP32_ISSUE_TFLOPS, 1)
+        roof["frac_of_fp32_issue_peak"] = round(tfl / FP32_ISSUE_TFLOPS, 4)
+        roof["achieved_tflops"] = round(tfl, 3)
     roof.update({"kernel_step": dom["name"], "avg_ms": round(avg_s * 1e3, 5),
                  "algorithmic_bytes": dom["bytes"], "algorithmic_flops": dom["flops"],
                  "traffic": traffic})
@@ -676,6 +684,8 @@ def main():
                     help="only the paper-scale context run (cube, sphere, shell of ~1e8 points); prints its JSON object")
     ap.add_argument("--scheme-only", action="store_true",
                     help="only the n_I = n + 1 scheme workload (profiling runs); prints its JSON object")
+    ap.add_argument("--medium-only", action="store_true",
+                    help="only the 128^3 workload (profiling runs); prints its JSON object")
     ap.add_argument("--no-graph", action="store_true", help="eager solves only (counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="default kernel variants, no autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -695,6 +705,15 @@ def main():
         copy_calibration(args.copy_calibration)
     if args.context:
         print(json.dumps({"context": context_bench(L, W)}), flush=True)
+        return
+    if args.medium_only:
+        breakdown = {}
+        out = medium_bench(L, W, args.steps, args.warmup, hbm_copy_bandwidth(), graph=not args.no_graph,
+                           tune=not args.no_tune, breakdown=breakdown, fp32=not args.no_fp32)
+        if args.breakdown:
+            with open(args.breakdown, "w") as fh:
+                json.dump(breakdown, fh, indent=1)
+        print(json.dumps({"cube128": out}), flush=True)
         return
     if args.split_only or args.scheme_only or args.reduced_only:
         breakdown = {}

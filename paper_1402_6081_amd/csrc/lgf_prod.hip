@@ -53,6 +53,11 @@ __device__ __forceinline__ void cmac(T& ar, T& ai, const cplx<T>& f, const cplx<
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Keeps the compiler from moving instructions across this point.  Placed after a batch of
+// independent gathers, it keeps them issued together (all in flight at once) instead of
+// each load being sunk to its first use, which left one or two loads in flight per wave.
+__device__ __forceinline__ void issue_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 // Coefficient lane_off of item `item` in a frequency chunk whose items start at the
 // wave-uniform `base` (64 coefficients per item).  A 32-bit byte offset from a uniform base
 // lets the gather use a scalar base register plus one vector offset instead of 64-bit
@@ -162,10 +167,12 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         for (int sz = 0; sz < 4; sz += 2) {
 #pragma unroll
             for (int sxy = 0; sxy < 16; ++sxy) fb[sxy] = load_item(fbase, sg[(sz + 1) * 16 + sxy], lane);
+            issue_fence();
             slab(sz, fa);
             const int sn = sz + 2 < 4 ? sz + 2 : sz;  // past the end: a harmless reload
 #pragma unroll
             for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load_item(fbase, sg[sn * 16 + sxy], lane);
+            issue_fence();
             slab(sz + 1, fb);
         }
     } else {
@@ -174,6 +181,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             cplx<T> f[16];
 #pragma unroll
             for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load_item(fbase, sg[sz * 16 + sxy], lane);
+            issue_fence();
             slab(sz, f);
         }
     }
@@ -276,9 +284,11 @@ __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl,
 #pragma unroll 1
         for (int e = 0; e < 27; e += 2) {
             m2l_load<T, IdxT>(e + 1, fb, wl, si, fbuf);
+            issue_fence();
             if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
             if (e + 1 < 27) {
                 m2l_load<T, IdxT>(e + 2, fb, wl, si, fa);
+                issue_fence();
                 if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
             }
         }
@@ -289,10 +299,13 @@ __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl,
 #pragma unroll 1
         for (int e = 0; e < 27; e += 3) {
             m2l_load<T, IdxT>(e + 2, fb, wl, si, fc);
+            issue_fence();
             if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
             m2l_load<T, IdxT>(e + 3, fb, wl, si, fa);
+            issue_fence();
             if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
             m2l_load<T, IdxT>(e + 4, fb, wl, si, fbuf);
+            issue_fence();
             if (live & (4u << e)) m2l_neighbour<T, CPL, Q>(e + 2, fc, tk, ar, ai);
         }
     }
@@ -533,9 +546,11 @@ static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int waves, hipStream_
 }
 
 // Variant when the plan leaves it open, from measurements on MI355X:
-//  * FP32 with 16-bit list entries: all 8 children per lane in 4 parent groups per
-//    workgroup at every level size (three workgroups share a CU; 64 -> 53 us for the
-//    128^3 M2L, 340 -> 283 us on the separate-set ring);
+//  * FP32 with 16-bit list entries: all 8 children per lane, in 4 parent groups per
+//    workgroup, or 8 for levels of at least 256 parents (the 256^3 M2L 329 -> 269 us; the
+//    128^3 one, 64 parents, stays fastest with 4: 53 us);
+//  * FP64 with 16-bit entries and at least 256 parents: all children per lane in 4 groups
+//    (the 256^3 M2L 610 -> 527 us);
 //  * otherwise levels with at least 64 parents run 4 children per lane in 4 parent
 //    groups; smaller levels 2 children per lane (more waves for little work) in 1 (FP64)
 //    or 2 (FP32) groups.
@@ -544,6 +559,11 @@ static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int waves, hipStream_
 template <typename T>
 void m2l_default(int64_t nparents, bool idx16, int& waves, int& cpl) {
     if (sizeof(T) == 4 && idx16) {
+        if (waves == 0) waves = nparents >= 256 ? 8 : 4;
+        if (cpl == 0) cpl = 8;
+        return;
+    }
+    if (sizeof(T) == 8 && idx16 && nparents >= 256) {
         if (waves == 0) waves = 4;
         if (cpl == 0) cpl = 8;
         return;
