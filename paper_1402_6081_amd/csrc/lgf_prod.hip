@@ -79,14 +79,14 @@ __host__ __forceinline__ bool chunk_fits_u32(int64_t items) {
 // (the last is 0), uhat ntgt items (targets and sources are numbered separately, so the
 // evaluation blocks may differ from the source blocks).
 // One wave = 64 consecutive frequencies of one group; the 4 waves of a workgroup share the
-// frequency chunk and its kernel tile in LDS.  The tile has rows for dz in [-2, 2] (the
-// rows with |dz| = 2 are zero) so the source-slab loop needs no branches.
+// frequency chunk and its kernel tile in LDS: the 27 near offsets, row (dx+1) + 3 (dy+1) +
+// 9 (dz+1).
 template <typename T, int kNearWaves, bool kPrefetch>
 __global__ void __launch_bounds__(64 * kNearWaves)
     k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                         const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
                         cplx<T>* __restrict__ uhat, int S, int ngroups, int nsrc, int ntgt, const SpecSym sym) {
-    __shared__ cplx<T> tile[45 * 64];  // row (dx+1) + 3 (dy+1) + 9 (dz+2)
+    __shared__ cplx<T> tile[27 * 64];
     const int lane = threadIdx.x & 63;
     int chunk, gb;
     if (!xcd_tile(S / 64, (ngroups + kNearWaves - 1) / kNearWaves, chunk, gb)) return;
@@ -95,15 +95,15 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     if (sym.info != nullptr) {
         // reduced spectra: each thread fills rows of its own frequency w (the loop steps by
         // whole waves), decoded once; the rows' descriptions first, then all the gathers
-        constexpr int NT = 64 * kNearWaves, NR = (45 * 64 + NT - 1) / NT;
+        constexpr int NT = 64 * kNearWaves, NR = (27 * 64 + NT - 1) / NT;
         const Freq3 om = freq_of(w, sym.M);
         uint32_t inf[NR];
         bool use[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-            const int i = (int)threadIdx.x + k * NT, r = i >> 6, dz = r / 9 - 2;
-            use[k] = i < 45 * 64 && dz >= -1 && dz <= 1;
-            inf[k] = use[k] ? sym.info[r - 9] : 0u;
+            const int i = (int)threadIdx.x + k * NT;
+            use[k] = i < 27 * 64;
+            inf[k] = use[k] ? sym.info[i >> 6] : 0u;
         }
         cplx<T> kv[NR];
 #pragma unroll
@@ -112,13 +112,10 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int i = (int)threadIdx.x + k * NT;
-            if (i < 45 * 64) tile[i] = kv[k];
+            if (i < 27 * 64) tile[i] = kv[k];
         }
     } else {
-        for (int i = threadIdx.x; i < 45 * 64; i += 64 * kNearWaves) {
-            const int r = i >> 6, dz = r / 9 - 2;
-            tile[i] = (dz < -1 || dz > 1) ? cplx<T>{T(0), T(0)} : khat[spec_at(r - 9, w0 + (i & 63), 27)];
-        }
+        for (int i = threadIdx.x; i < 27 * 64; i += 64 * kNearWaves) tile[i] = khat[spec_at(i >> 6, w0 + (i & 63), 27)];
     }
     __syncthreads();
     const int g = wave_uniform(gb * kNearWaves + (threadIdx.x >> 6));
@@ -135,16 +132,21 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     // Each of the slab's 18 kernel values (9 (dx, dy) x 2 target slabs) is read from LDS once
     // and applied to the 4 targets (cx, cy) whose source cx - dx, cy - dy lies in the slab.
     // (dy, dx) run from +1 down to -1, so every target still adds its sources in increasing
-    // (sy, sx) order: the same terms in the same order as a loop over the sources.
+    // (sy, sx) order: the same terms in the same order as a loop over the sources.  The end
+    // slabs reach one target slab only (sz = 0: cz = 0; sz = 3: cz = 1): the other row would
+    // be |dz| = 2, outside the near field, and is skipped by a wave-uniform branch.
     auto slab = [&](int sz, const cplx<T>(&f)[16]) {
-        const cplx<T>* t0 = tile + (9 * (3 - sz)) * 64 + lane;  // row base for cz = 0
-        const cplx<T>* t1 = tile + (9 * (4 - sz)) * 64 + lane;  // and cz = 1
+        // kernel row bases for cz = 0 (dz = 1 - sz) and cz = 1 (dz = 2 - sz); an end slab's
+        // unused one is pointed at row 0
+        const cplx<T>* t0 = tile + 9 * (sz < 3 ? 2 - sz : 0) * 64 + lane;
+        const cplx<T>* t1 = tile + 9 * (sz > 0 ? 3 - sz : 0) * 64 + lane;
 #pragma unroll
         for (int dy = 1; dy >= -1; --dy) {
 #pragma unroll
             for (int dx = 1; dx >= -1; --dx) {
 #pragma unroll
                 for (int cz = 0; cz < 2; ++cz) {
+                    if (cz ? sz == 0 : sz == 3) continue;  // |dz| = 2 (wave-uniform)
                     const cplx<T> k = (cz ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
 #pragma unroll
                     for (int cy = 0; cy < 2; ++cy)
