@@ -225,7 +225,10 @@ lgf_status lgf_graph_destroy(lgf_graph_t graph);
 
 /*
  * Kernel variants of a plan.  Variants differ in scheduling only: every variant gives the
- * same u bit for bit.  0 selects the library's default where listed.
+ * same u bit for bit.  0 selects the library's default where listed.  LGF_M2L_WIDE_LISTS=1
+ * in the environment makes the level >= 1 Prod keep 32-bit source-list entries at every
+ * level size (it switches to them by itself for levels of 65535 or more intervals); the
+ * bits are the same.
  */
 typedef struct {
     int32_t fft0_threads;   /* threads per workgroup of the level-0 transforms: 0, 128, 256, 512    */

@@ -14,6 +14,7 @@
 // A plain CSR kernel covers the top level of a truncated tree, whose list is "every
 // non-adjacent interval" and has no such structure.
 #include <algorithm>
+#include <cstdlib>
 
 #include "lgf_internal.h"
 
@@ -504,6 +505,14 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
                     : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s, sym);
 }
 
+// LGF_M2L_WIDE_LISTS=1 in the environment keeps the 32-bit list entries at every level
+// size, the form levels of 65535 or more items take (read at each launch; the same bits
+// either way).
+static bool m2l_wide_lists() {
+    const char* v = std::getenv("LGF_M2L_WIDE_LISTS");
+    return v && v[0] == '1';
+}
+
 template <typename T, int NW, int CPL>
 static hipError_t far_nw(const FarLevel<T>* lv, int nlev, hipStream_t s) {
     constexpr int F = M2LShape<T>::F, PPG = M2LShape<T>::PPW * NW;
@@ -521,7 +530,7 @@ static hipError_t far_nw(const FarLevel<T>* lv, int nlev, hipStream_t s) {
     segs.n = nlev;
     // 16-bit list entries in LDS when every level's items (and the sentinel) fit: less LDS
     // per workgroup, so more workgroups share a CU
-    bool idx16 = true;
+    bool idx16 = !m2l_wide_lists();
     for (int k = 0; k < nlev; ++k) idx16 = idx16 && lv[k].nsrc < 65535;
     if (idx16)
         return lgf_launch(k_prod_far_sib<T, NW, CPL, uint16_t>, dim3(grid), dim3(64 * NW * (8 / CPL)), 0, s, segs);
@@ -579,7 +588,7 @@ template <typename T>
 hipError_t launch_prod_far_sib_levels(const FarLevel<T>* lv, int nlev, int waves, int cpl, hipStream_t s) {
     int64_t most = 0;
     int k = 0;
-    bool idx16 = true;
+    bool idx16 = !m2l_wide_lists();
     for (int i = 0; i < nlev; ++i) {
         if (lv[i].nparents <= 0) continue;
         if (k != i || !chunk_fits_u32<T>(lv[i].nsrc + 1) || !sym_fits(lv[i].sym, lv[i].S))

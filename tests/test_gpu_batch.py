@@ -219,6 +219,32 @@ def test_every_variant_same_bits(L, prec):
         plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_wide_m2l_lists_same_bits(L, prec, monkeypatch):
+    """The M2L's 32-bit source-list entries, which levels of 65535 or more items take
+    (forced here at a small size by LGF_M2L_WIDE_LISTS=1), give the bits of the 16-bit
+    entries in every M2L variant and schedule."""
+    rng = np.random.default_rng(19)
+    blocks = W.eden_layout(150, rng)
+    _say("case: wide M2L lists", prec)
+    plan = L.Plan(blocks, 8, 6, 0, prec)
+    f = torch.from_numpy(rng.standard_normal(plan.shape())).to("cuda:0", plan.dtype)
+    variants = [dict(far_waves=fw, far_children=fc, overlap=2) for fw in (0, 1, 4, 16) for fc in (0, 1, 8)]
+    variants += [dict(far_waves=0, far_children=0, overlap=ov) for ov in (1, 3)]
+    refs = []
+    for v in variants:
+        plan.set_tuning(**v)
+        refs.append(plan.solve(f).clone())
+    monkeypatch.setenv("LGF_M2L_WIDE_LISTS", "1")
+    for v, ref in zip(variants, refs):
+        plan.set_tuning(**v)
+        got = plan.solve(f)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, got), v
+    monkeypatch.delenv("LGF_M2L_WIDE_LISTS")
+    plan.close()
+
+
 def test_batch_workload_fp32_against_fp64_and_exact(L):
     """The batched workload: 64 Eden layouts of U{8..512} blocks of 16^3, p = 8, one batch
     plan.  Every solve of the FP32 batch against the FP64 batch (<= 1e-6); 4 sampled solves

@@ -3,7 +3,7 @@ element, on seeded inputs.
 
 Tolerances (relative L-infinity, max|u - u_ref| / max|u_ref|):
   * FP64 solve vs oracle B (same FLGF operator, different rounding order):
-    max(1e-12, 2 Lambda_p^3 eps_64).  Both sides evaluate the same linear operator in
+    max(1e-12, Lambda_p^3 eps_64).  Both sides evaluate the same linear operator in
     FP64; rounding differences of node values are amplified by up to the Lebesgue
     constant Lambda_p^3 of p equispaced nodes in 3D (Sec. 2.5, Eq. leb: the paper's
     own bound Lambda^3 eps = 1.25e-12 at n_max = 10).

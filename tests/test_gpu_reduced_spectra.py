@@ -5,7 +5,7 @@ A reduced table holds one spectrum per class of offsets under the 48 signed axis
 permutations the LGF is invariant under (4 at level 0, 20 at radius 3); the Prod kernels
 read every other offset's coefficient at the permuted frequency.  Bars:
   * FP64 against the oracle within the single-set plans' tolerance
-    max(1e-12, 2 Lambda_p^3 eps_64);
+    max(1e-12, Lambda_p^3 eps_64);
   * against the full-table plan of the same layout: FP64 within 1e-13 of max|u| (only the
     rounding of the spectrum generation differs), FP32 within 1e-6;
   * the spectra bytes shrink to the classes' share."""

@@ -3,7 +3,7 @@ edge at every level, interpolation stencils of the n_max = 10 closest nodes (Sec
 Sec. 4).  Level 1 works on the blocks' own spectra (its nodes are the blocks' grid points);
 levels >= 2 use 34-point transforms in two phases.
 
-Tolerances: FP64 against the oracle's FLGF within max(1e-12, 2 Lambda^3 eps_64), Lambda the
+Tolerances: FP64 against the oracle's FLGF within max(1e-12, Lambda^3 eps_64), Lambda the
 Lebesgue constant of the 10-node local stencils; FP64 against the exact sum within the
 oracle's own truncation error + 1e-12 (manufactured solution, Sec. 4.1); graphs, batches and
 kernel variants bit for bit."""

@@ -1,7 +1,7 @@
 """GPU parity of the screened operator L - kappa (lgf_plan_create_screened), a second
 non-oscillatory lattice kernel (Sec. 5), against the oracle: the device's integrated
 G_kappa table, FP64 solves against the oracle's FLGF with the same kernel (element by
-element, max(1e-12, 2 Lambda^3 eps_64)) and against the exact direct sum (truncation
+element, max(1e-12, Lambda^3 eps_64)) and against the exact direct sum (truncation
 + 1e-12), a manufactured solution, the FP32 path (1e-6), graphs and symmetry-reduced
 spectra with the screened kernel, and the argument checks."""
 import sys

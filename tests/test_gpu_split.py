@@ -2,7 +2,7 @@
 Eq. bconv with B_s != B_e) through the C ABI.
 
 Tolerances as for the single-set plans: FP64 against the oracle's FLGF (separate source
-and evaluation trees) within max(1e-12, 2 Lambda_p^3 eps_64); FP32 against FP64 and the
+and evaluation trees) within max(1e-12, Lambda_p^3 eps_64); FP32 against FP64 and the
 oracle within 1e-6 of max|u| over the evaluation blocks, on smooth sources.  Properties that hold at any size are checked bit for bit: a split
 plan equals the single-set plan of the union with zero sources outside B_s, restricted to
 B_e, and equal sets through the split entry equal the single-set plan."""
