@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpaper_lgf.so")
-SOURCES = ["lgf_fft.hip", "lgf_prod.hip", "lgf_interp.hip", "lgf_spectra.hip", "lgf_plan.hip", "lgf_server.hip"]
+SOURCES = ["lgf_host.cpp", "lgf_fft.hip", "lgf_prod.hip", "lgf_interp.hip", "lgf_spectra.hip", "lgf_plan.hip",
+           "lgf_server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

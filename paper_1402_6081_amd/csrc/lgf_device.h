@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lgf_host.h"
+
 namespace lgfdev {
 
 template <typename T>
@@ -23,8 +25,6 @@ struct alignas(2 * sizeof(T)) cplx {
 // work one frequency chunk at a time across all items, so the data they touch together is
 // contiguous (no aliasing of many items onto the same memory channels), and a wave's 64
 // lanes of one item read or write one 64-coefficient run.  S is padded to a multiple of 64.
-constexpr int kSpecChunk = 64;
-__host__ __device__ constexpr int spec_padded(int S) { return (S + kSpecChunk - 1) / kSpecChunk * kSpecChunk; }
 __host__ __device__ __forceinline__ int64_t spec_at(int64_t item, int w, int64_t nitems) {
     return ((int64_t)(w >> 6) * nitems + item) * kSpecChunk + (w & 63);
 }

@@ -13,6 +13,7 @@
 
 #include "../../include/lgf.h"
 #include "lgf_device.h"
+#include "lgf_host.h"
 
 namespace lgfdev {
 
@@ -97,8 +98,6 @@ hipError_t rec_stream_wait(hipStream_t s, hipEvent_t ev);
 // everywhere else the far kernel is the asymptotic expansion with kFarTerms terms.
 constexpr int kLatticeRadius = 32;
 constexpr int kFarTerms = 8;
-constexpr int kMaxLevels = 16;
-constexpr int kNmax = 10;  // most nodes one interpolation stencil uses (the paper's n_max)
 
 // ------------------------------------------------------------------ launchers (device code)
 // out: chunk-major spectra of nout items, of which the first nbatch are written (nout = 0:
@@ -134,10 +133,6 @@ struct InvLevel {
 };
 template <typename Tin, typename A, typename Tout>
 hipError_t launch_ifft_trunc_levels(int m, const InvLevel<Tin, Tout>* lv, int nlev, hipStream_t s);
-inline bool two_phase_tile(int m) { return m == 17; }
-inline int64_t two_phase_scratch_bytes(int m, int64_t nbatch) {
-    return two_phase_tile(m) ? nbatch * (int64_t)m * (2 * m) * (m + 1) * 16 : 0;
-}
 
 // Far-field node values of the down pass: double on the FP64 path, float-float on the
 // FP32 path (8 bytes either way).
@@ -283,7 +278,5 @@ void budget_set(int64_t bytes);
 // Workspace bytes a plan of this layout would own (host-only work: builds the lists).
 lgf_status plan_estimate(const int32_t* ijk, int64_t nblocks, int n, int p, int levels, lgf_precision prec,
                          int64_t* bytes);
-// Sets the calling thread's lgf_last_error message.
-void set_last_error(const std::string& msg);
 
 }  // namespace lgfdev

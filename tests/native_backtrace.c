@@ -17,7 +17,8 @@ static void on_signal(int sig, siginfo_t* info, void* ctx) {
     (void)ctx;
     static const char head[] = "\n---- native backtrace ----\n";
     void* frames[64];
-    write(2, head, sizeof head - 1);
+    ssize_t w = write(2, head, sizeof head - 1);
+    (void)w;
     int n = backtrace(frames, 64);
     backtrace_symbols_fd(frames, n, 2);
     for (int i = 0; i < 3; ++i)
