@@ -79,25 +79,48 @@ __host__ __forceinline__ bool chunk_fits_u32(int64_t items) {
 // sentinel item (index nsrc) when that block is not a source.  fhat holds nsrc + 1 items
 // (the last is 0), uhat ntgt items (targets and sources are numbered separately, so the
 // evaluation blocks may differ from the source blocks).
-// One wave = 64 consecutive frequencies of one group; the 4 waves of a workgroup share the
-// frequency chunk and its kernel tile in LDS: the 27 near offsets, row (dx+1) + 3 (dy+1) +
-// 9 (dz+1).
-template <typename T, int kNearWaves, bool kPrefetch>
+// A lane owns FPL consecutive frequencies: FPL = 1, a wave covers one 64-frequency chunk;
+// FPL = 2 (FP32), a wave covers two consecutive chunks, lanes 0-31 the first and 32-63 the
+// second, each lane loading 16 bytes per item as the FP64 lanes do.  The waves of a
+// workgroup are different groups of the same chunk(s) and share the kernel tile in LDS: the
+// 27 near offsets, row (dx+1) + 3 (dy+1) + 9 (dz+1).  Every frequency is computed with the
+// same arithmetic in the same order whatever FPL and the number of waves.
+template <typename T, int FPL>
+struct alignas(FPL * sizeof(cplx<T>)) LaneCoef {
+    cplx<T> v[FPL];
+};
+
+template <typename T, int kNearWaves, bool kPrefetch, int FPL>
 __global__ void __launch_bounds__(64 * kNearWaves)
     k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                         const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
                         cplx<T>* __restrict__ uhat, int S, int ngroups, int nsrc, int ntgt, const SpecSym sym) {
-    __shared__ cplx<T> tile[27 * 64];
+    using V = LaneCoef<T, FPL>;
+    __shared__ V tile[27 * 64];
     const int lane = threadIdx.x & 63;
-    int chunk, gb;
-    if (!xcd_tile(S / 64, (ngroups + kNearWaves - 1) / kNearWaves, chunk, gb)) return;
-    const int w0 = chunk * 64;
-    const int w = w0 + lane;  // frequency (S is a multiple of 64)
+    const int nchunks = S / 64;
+    int unit, gb;
+    if (!xcd_tile((nchunks + FPL - 1) / FPL, (ngroups + kNearWaves - 1) / kNearWaves, unit, gb)) return;
+    // this thread's chunk and first frequency in it; with FPL = 2 the second half of the
+    // wave may fall past the last chunk, and then reads the first half's chunk and stores
+    // nothing
+    auto lane_pos = [&](int ln, int& ch, int& wl) {
+        const int half = FPL == 2 ? (ln >> 5) : 0;
+        ch = unit * FPL + half;
+        wl = FPL == 2 ? 2 * (ln & 31) : ln;
+    };
+    int my_chunk, wl;
+    lane_pos(lane, my_chunk, wl);
+    const bool live = my_chunk < nchunks;
+    if (!live) my_chunk = unit * FPL;
+    const int w = my_chunk * 64 + wl;  // first frequency of this lane (S is a multiple of 64)
     if (sym.info != nullptr) {
-        // reduced spectra: each thread fills rows of its own frequency w (the loop steps by
+        // reduced spectra: each thread fills rows of its own frequencies (the loop steps by
         // whole waves), decoded once; the rows' descriptions first, then all the gathers
         constexpr int NT = 64 * kNearWaves, NR = (27 * 64 + NT - 1) / NT;
-        const Freq3 om = freq_of(w, sym.M);
+        Freq3 om[FPL];
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) om[q] = freq_of(w + q, sym.M);
         uint32_t inf[NR];
         bool use[NR];
 #pragma unroll
@@ -106,29 +129,46 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             use[k] = i < 27 * 64;
             inf[k] = use[k] ? sym.info[i >> 6] : 0u;
         }
-        cplx<T> kv[NR];
+        V kv[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k)
-            kv[k] = use[k] ? sym_coef(khat, inf[k], om, sym.ncls, sym.M) : cplx<T>{T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < FPL; ++q)
+                kv[k].v[q] = use[k] ? sym_coef(khat, inf[k], om[q], sym.ncls, sym.M) : cplx<T>{T(0), T(0)};
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int i = (int)threadIdx.x + k * NT;
             if (i < 27 * 64) tile[i] = kv[k];
         }
     } else {
-        for (int i = threadIdx.x; i < 27 * 64; i += 64 * kNearWaves) tile[i] = khat[spec_at(i >> 6, w0 + (i & 63), 27)];
+        for (int i = threadIdx.x; i < 27 * 64; i += 64 * kNearWaves) {
+            int ch, wi;
+            lane_pos(i & 63, ch, wi);
+            if (ch >= nchunks) ch = unit * FPL;
+            tile[i] = *reinterpret_cast<const V*>(khat + spec_at(i >> 6, ch * 64 + wi, 27));
+        }
     }
     __syncthreads();
     const int g = wave_uniform(gb * kNearWaves + (threadIdx.x >> 6));
     if (g >= ngroups) return;
-    T ar[8], ai[8];
+    T ar[FPL][8], ai[FPL][8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        ar[c] = T(0);
-        ai[c] = T(0);
-    }
+    for (int q = 0; q < FPL; ++q)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            ar[q][c] = T(0);
+            ai[q][c] = T(0);
+        }
     const int32_t* sg = src64 + (int64_t)g * 64;
-    const cplx<T>* fbase = fhat + (int64_t)chunk * (nsrc + 1) * 64;  // this chunk's items (uniform)
+    // the first chunk's items (wave-uniform base) and this lane's offset from it, in
+    // coefficients: its chunk, then its frequencies within the item
+    const cplx<T>* fbase = fhat + (int64_t)(unit * FPL) * (nsrc + 1) * 64;
+    const uint32_t loff = ((uint32_t)(my_chunk - unit * FPL) * (uint32_t)(nsrc + 1) * 64u + (uint32_t)wl) *
+                          (uint32_t)sizeof(cplx<T>);
+    auto load = [&](int item) -> V {
+        const uint32_t off = (uint32_t)item * 64u * (uint32_t)sizeof(cplx<T>) + loff;
+        return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(fbase) + off);
+    };
     // source z slab sz contributes to target slab cz through kernel rows dz = cz - (sz - 1).
     // Each of the slab's 18 kernel values (9 (dx, dy) x 2 target slabs) is read from LDS once
     // and applied to the 4 targets (cx, cy) whose source cx - dx, cy - dy lies in the slab.
@@ -136,11 +176,11 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     // (sy, sx) order: the same terms in the same order as a loop over the sources.  The end
     // slabs reach one target slab only (sz = 0: cz = 0; sz = 3: cz = 1): the other row would
     // be |dz| = 2, outside the near field, and is skipped by a wave-uniform branch.
-    auto slab = [&](int sz, const cplx<T>(&f)[16]) {
+    auto slab = [&](int sz, const V(&f)[16]) {
         // kernel row bases for cz = 0 (dz = 1 - sz) and cz = 1 (dz = 2 - sz); an end slab's
         // unused one is pointed at row 0
-        const cplx<T>* t0 = tile + 9 * (sz < 3 ? 2 - sz : 0) * 64 + lane;
-        const cplx<T>* t1 = tile + 9 * (sz > 0 ? 3 - sz : 0) * 64 + lane;
+        const V* t0 = tile + 9 * (sz < 3 ? 2 - sz : 0) * 64 + lane;
+        const V* t1 = tile + 9 * (sz > 0 ? 3 - sz : 0) * 64 + lane;
 #pragma unroll
         for (int dy = 1; dy >= -1; --dy) {
 #pragma unroll
@@ -148,14 +188,15 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 #pragma unroll
                 for (int cz = 0; cz < 2; ++cz) {
                     if (cz ? sz == 0 : sz == 3) continue;  // |dz| = 2 (wave-uniform)
-                    const cplx<T> k = (cz ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
+                    const V k = (cz ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
 #pragma unroll
                     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
                         for (int cx = 0; cx < 2; ++cx) {
                             const int c = cx | (cy << 1) | (cz << 2);
                             const int sxy = (cx - dx + 1) + 4 * (cy - dy + 1);
-                            cmac(ar[c], ai[c], f[sxy], k);
+#pragma unroll
+                            for (int q = 0; q < FPL; ++q) cmac(ar[q][c], ai[q][c], f[sxy].v[q], k.v[q]);
                         }
                 }
             }
@@ -163,31 +204,32 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     };
     if constexpr (kPrefetch) {
         // the next slab's 16 source values are in flight while this slab is consumed
-        cplx<T> fa[16], fb[16];
+        V fa[16], fb[16];
 #pragma unroll
-        for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load_item(fbase, sg[sxy], lane);
+        for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load(sg[sxy]);
 #pragma unroll 1
         for (int sz = 0; sz < 4; sz += 2) {
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) fb[sxy] = load_item(fbase, sg[(sz + 1) * 16 + sxy], lane);
+            for (int sxy = 0; sxy < 16; ++sxy) fb[sxy] = load(sg[(sz + 1) * 16 + sxy]);
             issue_fence();
             slab(sz, fa);
             const int sn = sz + 2 < 4 ? sz + 2 : sz;  // past the end: a harmless reload
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load_item(fbase, sg[sn * 16 + sxy], lane);
+            for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load(sg[sn * 16 + sxy]);
             issue_fence();
             slab(sz + 1, fb);
         }
     } else {
 #pragma unroll 1
         for (int sz = 0; sz < 4; ++sz) {  // source z slab; x and y unrolled
-            cplx<T> f[16];
+            V f[16];
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load_item(fbase, sg[sz * 16 + sxy], lane);
+            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load(sg[sz * 16 + sxy]);
             issue_fence();
             slab(sz, f);
         }
     }
+    if (!live) return;
     const int32_t* tg = tgt8 + (int64_t)g * 8;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -196,8 +238,14 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             // streamed past the caches: the output is read once, by the inverse transform, and
             // must not evict the source spectra this kernel re-reads (measured: this Prod 15%
             // faster, the inverse 10% slower, the pair 7% faster at 128^3 FP64)
-            typedef T pair_t __attribute__((ext_vector_type(2)));  // one store per coefficient
-            __builtin_nontemporal_store(pair_t{ar[c], ai[c]}, reinterpret_cast<pair_t*>(uhat + spec_at(t, w, ntgt)));
+            typedef T vec_t __attribute__((ext_vector_type(2 * FPL)));  // one store per lane
+            vec_t o;
+#pragma unroll
+            for (int q = 0; q < FPL; ++q) {
+                o[2 * q] = ar[q][c];
+                o[2 * q + 1] = ai[q][c];
+            }
+            __builtin_nontemporal_store(o, reinterpret_cast<vec_t*>(uhat + spec_at(t, w, ntgt)));
         }
     }
 }
@@ -475,13 +523,19 @@ __global__ void __launch_bounds__(kProdThreads)
     uhat[spec_at(P, w, nitems)] = cplx<T>{ar, ai};
 }
 
+// Frequencies per lane of the level-0 Prod: 2 in FP32, so that every lane moves 16 bytes
+// per item as in FP64 (half the load and store instructions per byte).
+template <typename T>
+constexpr int kNearFpl = sizeof(T) == 4 ? 2 : 1;
+
 template <typename T, int NW, bool PF>
 static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
                           cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, hipStream_t s,
                           const SpecSym& sym) {
-    const unsigned grid = xcd_grid(S / 64, (int)((ngroups + NW - 1) / NW));
-    return lgf_launch(k_prod_near_grouped<T, NW, PF>, dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8, src64,
-                      uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym);
+    constexpr int FPL = kNearFpl<T>;
+    const unsigned grid = xcd_grid((S / 64 + FPL - 1) / FPL, (int)((ngroups + NW - 1) / NW));
+    return lgf_launch(k_prod_near_grouped<T, NW, PF, FPL>, dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8,
+                      src64, uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym);
 }
 
 template <typename T, bool PF>
@@ -500,7 +554,8 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
                             cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, int waves,
                             int prefetch, hipStream_t s, const SpecSym& sym) {
     if (ngroups <= 0) return hipSuccess;
-    if (S % 64 || !chunk_fits_u32<T>(nsrc + 1) || !sym_fits(sym, S)) return hipErrorInvalidValue;
+    // a lane's 32-bit offsets span kNearFpl consecutive chunks of the source spectra
+    if (S % 64 || !chunk_fits_u32<T>((nsrc + 1) * kNearFpl<T>) || !sym_fits(sym, S)) return hipErrorInvalidValue;
     return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s, sym)
                     : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s, sym);
 }
