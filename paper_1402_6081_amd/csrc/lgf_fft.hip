@@ -414,9 +414,10 @@ static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, 
 }
 
 // nt: threads per workgroup (0 = default: 256, measured faster than 128 for the small
-// tiles of levels >= 1 as well); the autotuner picks
-// among {128, 256, 512} for the level-0 tiles (m = 8, 16).  512 threads are not offered for
-// the FP64 16^3 tile, whose 32-point pencils then no longer fit the register file.
+// tiles of levels >= 1 as well); the autotuner picks among {128, 256, 512} for the level-0
+// tiles (m = 8, 16).  The forward FP64 16^3 tile is not offered 512 threads: its 32-point
+// pencils would then spill (the inverse's fit, 219 registers, and are its default).
+
 // Grid of the forward transform of ntiles tiles.  Tiles whose LDS allows at most two
 // workgroups per CU (the level-0 tiles) get a persistent grid, as many workgroups as are
 // resident at once, each prefetching its next tile's input; smaller tiles one workgroup
@@ -487,9 +488,11 @@ template <typename Tin, typename A, typename Tout, int m>
 static hipError_t launch_inv_segs(const InvSegs<Tin, Tout>& segs, int64_t nblocks, const int32_t* out_map,
                                   int opitch, hipStream_t s, int nt = 0) {
     if (opitch <= 0) opitch = m;
+    // FP64 16^3 tiles default to 512 threads: one workgroup fills a CU's LDS, and 8 waves
+    // keep twice the column loads in flight (256^3: 331 -> 299 us; 128^3: 51 -> 47 us)
+    if (nt == 0 && m == 16 && sizeof(A) == 8) nt = 512;
     if constexpr ((m == 8 || m == 16) && !std::is_same<A, ff32>::value) {
-        if constexpr (!(m == 16 && sizeof(A) == 8))
-            if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(segs, nblocks, out_map, opitch, s);
+        if (nt == 512) return inv_mnt<Tin, A, Tout, m, 512>(segs, nblocks, out_map, opitch, s);
         if (nt == 128) return inv_mnt<Tin, A, Tout, m, 128>(segs, nblocks, out_map, opitch, s);
     }
     return inv_mnt<Tin, A, Tout, m, 256>(segs, nblocks, out_map, opitch, s);
