@@ -418,42 +418,15 @@ static hipError_t inv_two_phase(const cplx<Tin>* in, Tout* out, int64_t nbatch, 
 // tiles (m = 8, 16).  The forward FP64 16^3 tile is not offered 512 threads: its 32-point
 // pencils would then spill (the inverse's fit, 219 registers, and are its default).
 
-// Grid of the forward transform of ntiles tiles.  Tiles whose LDS allows at most two
-// workgroups per CU (the level-0 tiles) get a persistent grid, as many workgroups as are
-// resident at once, each prefetching its next tile's input; smaller tiles one workgroup
-// each (measured: the 256^3 level-0 FP64 transform 375 -> 248 us, FP32 143 -> 108 us; the
-// small level >= 1 tiles were 5% slower persistent).
-template <typename K>
-static int64_t fwd_grid(K kernel, int nt, int64_t ntiles) {
-    static std::mutex mu;
-    static std::map<std::pair<int, const void*>, int64_t> cache;  // (device, kernel) -> resident workgroups
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
-    const auto key = std::make_pair(dev, reinterpret_cast<const void*>(kernel));
-    int64_t resident = 0;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) {
-            resident = it->second;
-        } else {
-            int per_cu = 0, cus = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu < 1)
-                per_cu = 1;
-            if (dev < 0 ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-                cus = 256;
-            resident = per_cu <= 2 ? (int64_t)per_cu * cus : 0;  // 0: not persistent
-            cache[key] = resident;
-        }
-    }
-    return resident > 0 ? std::min(ntiles, resident) : ntiles;
-}
-
+// Tiles whose LDS allows at most two workgroups per CU (the level-0 tiles) get a
+// persistent grid (measured: the 256^3 level-0 FP64 transform 375 -> 248 us, FP32 143 ->
+// 108 us; the small level >= 1 tiles were 5% slower persistent, so they keep one
+// workgroup per tile).
 template <typename T, int m, int NT>
 static hipError_t fwd_mnt(const FwdSegs<T>& segs, int64_t nblocks, hipStream_t s) {
     auto kernel = k_pad_fft<T, m, 2 * m, NT>;
-    return lgf_launch(kernel, dim3((unsigned)fwd_grid(kernel, NT, nblocks)), dim3(NT), 0, s, segs, nblocks);
+    return lgf_launch(kernel, dim3((unsigned)persistent_grid(kernel, NT, nblocks, 2)), dim3(NT), 0, s, segs,
+                      nblocks);
 }
 
 template <typename T, int m>

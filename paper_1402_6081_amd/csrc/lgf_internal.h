@@ -4,6 +4,8 @@
 #include <stdint.h>
 
 #include <array>
+#include <algorithm>
+#include <mutex>
 #include <map>
 #include <memory>
 #include <string>
@@ -98,6 +100,37 @@ hipError_t rec_stream_wait(hipStream_t s, hipEvent_t ev);
 // everywhere else the far kernel is the asymptotic expansion with kFarTerms terms.
 constexpr int kLatticeRadius = 32;
 constexpr int kFarTerms = 8;
+
+// Grid of a persistent kernel over ntiles tiles (a workgroup takes tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...): as many workgroups as are resident at once when the
+// kernel's occupancy is at most max_per_cu workgroups per CU, where a workgroup's own
+// latency would otherwise idle its CU; else one workgroup per tile.
+template <typename K>
+int64_t persistent_grid(K kernel, int nt, int64_t ntiles, int max_per_cu) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int64_t> cache;  // (device, kernel) -> resident workgroups
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const auto key = std::make_pair(dev, reinterpret_cast<const void*>(kernel));
+    int64_t resident = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            resident = it->second;
+        } else {
+            int per_cu = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            if (dev < 0 ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            resident = per_cu <= max_per_cu ? (int64_t)per_cu * cus : 0;  // 0: one workgroup per tile
+            cache[key] = resident;
+        }
+    }
+    return resident > 0 ? std::min(ntiles, resident) : ntiles;
+}
 
 // ------------------------------------------------------------------ launchers (device code)
 // out: chunk-major spectra of nout items, of which the first nbatch are written (nout = 0:
