@@ -6,7 +6,8 @@
 // One workgroup per tile; the tile lives in a [z < m][ky < M][kx <= M/2] LDS array (the
 // largest intermediate of either direction), the real input/output is staged in the
 // not-yet-used upper ky half of each z plane so that HBM reads and writes are fully
-// coalesced.  Passes: x (real rows), y (complex
+// coalesced.  The staged rows are padded to m + 1 values: the x pass reads (and the
+// inverse writes) one row per lane, and rows m apart would share LDS banks.  Passes: x (real rows), y (complex
 // columns of the z < m planes), z (complex columns, straight to/from HBM).
 #include <algorithm>
 #include <map>
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const FwdSegs<T> segs, int64_t t
             const int i = tid + k * NT;
             if (i < m * m * m) {
                 const int z = i / (m * m), r = i - z * (m * m);
-                reinterpret_cast<T*>(buf + z * PLANE + m * H)[r] = pre[k];
+                reinterpret_cast<T*>(buf + z * PLANE + m * H)[(r / m) * (m + 1) + r % m] = pre[k];
             }
         }
         __syncthreads();
@@ -95,7 +96,7 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const FwdSegs<T> segs, int64_t t
         // x pass: real rows (z, y) -> kx in [0, M/2]
         for (int row = tid; row < m * m; row += NT) {
             const int z = row / m, y = row - z * m;
-            const T* s = reinterpret_cast<const T*>(buf + z * PLANE + m * H) + y * m;
+            const T* s = reinterpret_cast<const T*>(buf + z * PLANE + m * H) + y * (m + 1);
             T xr[m], xi[m];
 #pragma unroll
             for (int j = 0; j < m; ++j) {
@@ -225,7 +226,7 @@ __global__ void __launch_bounds__(NT) k_ifft_trunc(const InvSegs<Tin, Tout> segs
         }
         A x[m];
         pencil_c2r<A, m, M>(Yr, Yi, x);
-        A* d = reinterpret_cast<A*>(buf + z * PLANE + m * H) + y * m;
+        A* d = reinterpret_cast<A*>(buf + z * PLANE + m * H) + y * (m + 1);
 #pragma unroll
         for (int j = 0; j < m; ++j) d[j] = x[j];
     }
@@ -235,12 +236,12 @@ __global__ void __launch_bounds__(NT) k_ifft_trunc(const InvSegs<Tin, Tout> segs
     if (opitch == m) {
         for (int i = tid; i < m * m * m; i += NT) {
             const int z = i / (m * m), r = i - z * (m * m);
-            dst[i] = (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[r];
+            dst[i] = (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[(r / m) * (m + 1) + r % m];
         }
     } else {
         for (int i = tid; i < opitch * opitch * opitch; i += NT) {
             const int x = i % opitch, y = (i / opitch) % opitch, z = i / (opitch * opitch);
-            dst[i] = (z < m && y < m && x < m) ? (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[y * m + x]
+            dst[i] = (z < m && y < m && x < m) ? (Tout)reinterpret_cast<const A*>(buf + z * PLANE + m * H)[y * (m + 1) + x]
                                                : Tout(0);
         }
     }
