@@ -89,12 +89,13 @@ typedef struct {
  * Build a plan (Sec. 3.1 tree and lists; Step 0 pre-computation, Eq. precomp).
  *   block_ijk : HOST array [nblocks][3] of block coordinates (read during the call only)
  *   nblocks   : >= 1
- *   n         : points per block edge; 4, 8 or 16 (padded FFT length 2n)
+ *   n         : points per block edge; 4, 6, 8, 12 or 16 (padded FFT length 2n)
  *   p         : interpolation nodes per interval edge at every level >= 1: 2..10, where
  *               every stencil uses all p nodes (n_max = p, Sec. 2.5 Lebesgue rule), or
- *               p = 17 with n = 16, the paper's scheme n_I = n + 1 with stencils of the
- *               n_max = 10 closest nodes (Sec. 2.5, Sec. 4).  p = n + 1 puts the nodes on
- *               the lattice (the paper's experimental scheme)
+ *               p = n + 1 with n = 12 or 16 (13 or 17 nodes), the paper's scheme
+ *               n_I = n + 1 with stencils of the n_max = 10 closest nodes (Sec. 2.5,
+ *               Sec. 4).  p = n + 1 puts the nodes on the lattice (the paper's
+ *               experimental scheme; n = 6, p = 7 and n = 12, p = 13 are its n_I = 7 and 13)
  *   levels    : tree levels L (leaves at 1); <= 0 selects the full depth
  *               1 + ceil(log2(extent)).  When L is below full depth the top level's
  *               list holds every non-adjacent interval.

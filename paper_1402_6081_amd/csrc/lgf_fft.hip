@@ -499,6 +499,8 @@ hipError_t launch_pad_fft(int m, const T* in, cplx<T>* out, int64_t nbatch, hipS
         case 8: return launch_fwd_m<T, 8>(in, out, nbatch, nout, s, nt);
         case 9: return launch_fwd_m<T, 9>(in, out, nbatch, nout, s);
         case 10: return launch_fwd_m<T, 10>(in, out, nbatch, nout, s);
+        case 12: return launch_fwd_m<T, 12>(in, out, nbatch, nout, s);
+        case 13: return launch_fwd_m<T, 13>(in, out, nbatch, nout, s);
         case 16: return launch_fwd_m<T, 16>(in, out, nbatch, nout, s, nt);
         default: return hipErrorInvalidValue;
     }
@@ -508,7 +510,7 @@ template <typename Tin, typename A, typename Tout>
 hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbatch, hipStream_t s, int nt,
                              const int32_t* out_map, void* scratch, int opitch) {
     if (nbatch <= 0) return hipSuccess;
-    if (opitch > 0 && opitch != m && m != 16) return hipErrorInvalidValue;  // pitched output: 16^3 tiles only
+    if (opitch > 0 && opitch < m) return hipErrorInvalidValue;  // output tiles hold the m^3 results
     switch (m) {
         case 17: return inv_two_phase<Tin, A, Tout, 17>(in, out, nbatch, out_map, scratch, s);
         case 2: return launch_inv_m<Tin, A, Tout, 2>(in, out, nbatch, out_map, opitch, s);
@@ -520,6 +522,16 @@ hipError_t launch_ifft_trunc(int m, const cplx<Tin>* in, Tout* out, int64_t nbat
         case 8: return launch_inv_m<Tin, A, Tout, 8>(in, out, nbatch, out_map, opitch, s, nt);
         case 9: return launch_inv_m<Tin, A, Tout, 9>(in, out, nbatch, out_map, opitch, s);
         case 10: return launch_inv_m<Tin, A, Tout, 10>(in, out, nbatch, out_map, opitch, s);
+        // the large tiles (level 0 of n = 12 and 16, levels >= 1 of the 13-node scheme) are
+        // not inverted in float-float arithmetic
+        case 12:
+            if constexpr (!std::is_same<A, ff32>::value)
+                return launch_inv_m<Tin, A, Tout, 12>(in, out, nbatch, out_map, opitch, s);
+            return hipErrorInvalidValue;
+        case 13:
+            if constexpr (!std::is_same<A, ff32>::value)
+                return launch_inv_m<Tin, A, Tout, 13>(in, out, nbatch, out_map, opitch, s);
+            return hipErrorInvalidValue;
         case 16:
             if constexpr (!std::is_same<A, ff32>::value)
                 return launch_inv_m<Tin, A, Tout, 16>(in, out, nbatch, out_map, opitch, s, nt);

@@ -375,7 +375,7 @@ int64_t scratch_need(const HostPlan& H) {
         if (H.lv[l].pairs() > 0 && !(l == 1 && H.lat1)) nmax = std::max(nmax, H.lv[l].nint);
     for (int l = 2; l <= H.Ltop; ++l) pmax = std::max(pmax, H.lv[l].nint);  // Reg up: children's partials
     const int64_t p3 = (int64_t)H.p * H.p * H.p;
-    const int64_t reg = H.p == 17 ? pmax * 8 * p3 * 8 : 0;
+    const int64_t reg = H.p > kNmax ? pmax * 8 * p3 * 8 : 0;  // Reg up of the local-stencil scheme
     return std::max(two_phase_scratch_bytes(H.p, nmax), reg);
 }
 

@@ -37,6 +37,12 @@ inline int64_t two_phase_scratch_bytes(int m, int64_t nbatch) {
     return two_phase_tile(m) ? nbatch * (int64_t)m * (2 * m) * (m + 1) * 16 : 0;
 }
 
+// Block edges n the transforms take (padded length 2n), and the node counts p allowed with
+// them: 2..10 (every stencil uses all p nodes), or p = n + 1 > n_max for n = 12 and 16 (the
+// paper's scheme n_I = n + 1 with stencils of the n_max closest nodes).
+inline bool block_edge_ok(int n) { return n == 4 || n == 6 || n == 8 || n == 12 || n == 16; }
+inline bool nodes_ok(int n, int p) { return p >= 2 && (p <= kNmax || ((n == 12 || n == 16) && p == n + 1)); }
+
 // The calling thread's lgf_last_error message.
 std::string& err_text();
 inline void set_last_error(const std::string& msg) { err_text() = msg; }

@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(kBlockThreads)
 }
 
 // ------------------------------------------------------------------ launchers
-// (n, p) -> compile-time kernel: n in {4, 8, 16}, p in [2, 10], and (16, 17)
+// (n, p) -> compile-time kernel: n in {4, 6, 8, 12, 16}, p in [2, 10], and (12, 13), (16, 17)
 template <template <int, int> class K, typename... Args>
 static hipError_t dispatch_np(int n, int p, Args... args) {
 #define LGF_NP(NN)                                          \
@@ -384,9 +384,13 @@ static hipError_t dispatch_np(int n, int p, Args... args) {
     }
     switch (n) {
         case 4: LGF_NP(4)
+        case 6: LGF_NP(6)
         case 8: LGF_NP(8)
+        case 12:
+            if (p == 13) return K<12, 13>::run(args...);  // the lattice scheme n_I = n + 1
+            LGF_NP(12)
         case 16:
-            if (p == 17) return K<16, 17>::run(args...);  // the lattice scheme n_I = n + 1
+            if (p == 17) return K<16, 17>::run(args...);
             LGF_NP(16)
         default: return hipErrorInvalidValue;
     }
@@ -426,6 +430,21 @@ static hipError_t reg_up_p(const T* in, const int32_t* child8, const double* C01
     return lgf_launch(k_reg_up<T, P>, dim3((unsigned)np), dim3(kRegUpThreads), 0, s, in, child8, C01, out);
 }
 
+// Tiles of more than n_max nodes: one workgroup per (parent, child) writes each child's
+// contribution to scratch, a second kernel adds them in child order (eight children of so
+// many nodes do not fit one workgroup's LDS).
+template <typename T, int P>
+static hipError_t reg_up_parts(const T* in, const int32_t* child8, const double* C01, T* out, int64_t np,
+                               hipStream_t s, void* scratch) {
+    constexpr int P3 = P * P * P;
+    if (!scratch) return hipErrorInvalidValue;
+    const hipError_t e = lgf_launch(k_reg_up_part<T, P>, dim3((unsigned)(np * 8)), dim3(kInterpThreads), 0, s, in,
+                                    child8, C01, (T*)scratch);
+    if (e != hipSuccess) return e;
+    return lgf_launch(k_reg_up_sum<T, P>, dim3((unsigned)((np * P3 + kInterpThreads - 1) / kInterpThreads)),
+                      dim3(kInterpThreads), 0, s, (const T*)scratch, child8, out, np);
+}
+
 template <typename T>
 hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, T* out, int64_t np, int p,
                          hipStream_t s, void* scratch) {
@@ -440,15 +459,8 @@ hipError_t launch_reg_up(const T* in, const int32_t* child8, const double* C01, 
         case 8: return reg_up_p<T, 8>(in, child8, C01, out, np, s);
         case 9: return reg_up_p<T, 9>(in, child8, C01, out, np, s);
         case 10: return reg_up_p<T, 10>(in, child8, C01, out, np, s);
-        case 17: {
-            constexpr int P3 = 17 * 17 * 17;
-            if (!scratch) return hipErrorInvalidValue;
-            const hipError_t e = lgf_launch(k_reg_up_part<T, 17>, dim3((unsigned)(np * 8)), dim3(kInterpThreads), 0,
-                                            s, in, child8, C01, (T*)scratch);
-            if (e != hipSuccess) return e;
-            return lgf_launch(k_reg_up_sum<T, 17>, dim3((unsigned)((np * P3 + kInterpThreads - 1) / kInterpThreads)),
-                              dim3(kInterpThreads), 0, s, (const T*)scratch, child8, out, np);
-        }
+        case 13: return reg_up_parts<T, 13>(in, child8, C01, out, np, s, scratch);
+        case 17: return reg_up_parts<T, 17>(in, child8, C01, out, np, s, scratch);
         default: return hipErrorInvalidValue;
     }
 }
@@ -478,6 +490,9 @@ hipError_t launch_interp_down(const U* par, const int32_t* child8, const double*
         case 8: return interp_down_p<U, 8>(par, child8, C01, io, nparent, s);
         case 9: return interp_down_p<U, 9>(par, child8, C01, io, nparent, s);
         case 10: return interp_down_p<U, 10>(par, child8, C01, io, nparent, s);
+        case 13:
+            return lgf_launch(k_interp_down_one<U, 13>, dim3((unsigned)(nparent * 8)), dim3(kDownThreads), 0, s, par,
+                              child8, C01, io);
         case 17:
             return lgf_launch(k_interp_down_one<U, 17>, dim3((unsigned)(nparent * 8)), dim3(kDownThreads), 0, s, par,
                               child8, C01, io);

@@ -874,9 +874,9 @@ lgf_status check_finite(lgf_plan_s* pl, const void* f, hipStream_t s) {
 extern "C" {
 
 static lgf_status check_args(int32_t n, int32_t p, lgf_precision prec) {
-    if (n != 4 && n != 8 && n != 16) return fail(LGF_ERR_ARG, "n must be 4, 8 or 16");
-    if (p < 2 || (p > kNmax && !(n == 16 && p == n + 1)))
-        return fail(LGF_ERR_ARG, "p must lie in [2, 10], or be n + 1 = 17 for n = 16 (stencils of 10 nodes)");
+    if (!block_edge_ok(n)) return fail(LGF_ERR_ARG, "n must be 4, 6, 8, 12 or 16");
+    if (!nodes_ok(n, p))
+        return fail(LGF_ERR_ARG, "p must lie in [2, 10], or be n + 1 for n = 12 or 16 (stencils of 10 nodes)");
     if (prec != LGF_F64 && prec != LGF_F32) return fail(LGF_ERR_ARG, "unknown precision");
     return LGF_OK;
 }

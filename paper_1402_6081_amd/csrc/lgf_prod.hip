@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     using V = LaneCoef<T, FPL>;
     __shared__ V tile[27 * 64];
     const int lane = threadIdx.x & 63;
-    const int nchunks = S / 64;
+    const int nchunks = (S + 63) / 64;  // the last chunk may be partial (frequencies w >= S unused)
     int unit, gb;
     if (!xcd_tile((nchunks + FPL - 1) / FPL, (ngroups + kNearWaves - 1) / kNearWaves, unit, gb)) return;
     // this thread's chunk and first frequency in it; with FPL = 2 the second half of the
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         for (int k = 0; k < NR; ++k)
 #pragma unroll
             for (int q = 0; q < FPL; ++q)
-                kv[k].v[q] = use[k] ? sym_coef(khat, inf[k], om[q], sym.ncls, sym.M) : cplx<T>{T(0), T(0)};
+                kv[k].v[q] = use[k] && w + q < S ? sym_coef(khat, inf[k], om[q], sym.ncls, sym.M) : cplx<T>{T(0), T(0)};
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int i = (int)threadIdx.x + k * NT;
@@ -145,7 +145,8 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             int ch, wi;
             lane_pos(i & 63, ch, wi);
             if (ch >= nchunks) ch = unit * FPL;
-            tile[i] = *reinterpret_cast<const V*>(khat + spec_at(i >> 6, ch * 64 + wi, 27));
+            const int wt = ch * 64 + wi;
+            tile[i] = wt < S ? *reinterpret_cast<const V*>(khat + spec_at(i >> 6, wt, 27)) : V{};
         }
     }
     __syncthreads();
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             slab(sz, f);
         }
     }
-    if (!live) return;
+    if (!live || w >= S) return;  // (S is even, so a lane's two frequencies are both below it or not)
     const int32_t* tg = tgt8 + (int64_t)g * 8;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -533,7 +534,7 @@ static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_
                           cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, hipStream_t s,
                           const SpecSym& sym) {
     constexpr int FPL = kNearFpl<T>;
-    const unsigned grid = xcd_grid((S / 64 + FPL - 1) / FPL, (int)((ngroups + NW - 1) / NW));
+    const unsigned grid = xcd_grid(((S + 63) / 64 + FPL - 1) / FPL, (int)((ngroups + NW - 1) / NW));
     return lgf_launch(k_prod_near_grouped<T, NW, PF, FPL>, dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8,
                       src64, uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym);
 }
@@ -555,7 +556,8 @@ hipError_t launch_prod_near(const cplx<T>* fhat, const cplx<T>* khat, const int3
                             int prefetch, hipStream_t s, const SpecSym& sym) {
     if (ngroups <= 0) return hipSuccess;
     // a lane's 32-bit offsets span kNearFpl consecutive chunks of the source spectra
-    if (S % 64 || !chunk_fits_u32<T>((nsrc + 1) * kNearFpl<T>) || !sym_fits(sym, S)) return hipErrorInvalidValue;
+    if (S <= 0 || S % 2 || !chunk_fits_u32<T>((nsrc + 1) * kNearFpl<T>) || !sym_fits(sym, S))
+        return hipErrorInvalidValue;
     return prefetch ? near_pf<T, true>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s, sym)
                     : near_pf<T, false>(fhat, khat, tgt8, src64, uhat, ngroups, nsrc, ntgt, S, waves, s, sym);
 }

@@ -155,14 +155,14 @@ lgf_status lgf_server_create(const lgf_server_config* cfg, lgf_server_t* out) {
         return LGF_ERR_ARG;
     }
     *out = nullptr;
-    if (cfg->n != 4 && cfg->n != 8 && cfg->n != 16) {
-        set_last_error("n must be 4, 8 or 16");
+    if (!block_edge_ok(cfg->n)) {
+        set_last_error("n must be 4, 6, 8, 12 or 16");
         return LGF_ERR_ARG;
     }
-    if (cfg->p < 2 || (cfg->p > 10 && !(cfg->n == 16 && cfg->p == 17)) ||
+    if (!nodes_ok(cfg->n, cfg->p) ||
         (cfg->precision != LGF_F64 && cfg->precision != LGF_F32) ||
         cfg->max_slots < 1 || cfg->max_slots > 16 || cfg->budget_bytes < 0 || cfg->max_queue < 0) {
-        set_last_error("lgf_server_create: p in [2, 10] (or 17 with n = 16), precision, max_slots in [1, 16], budget >= 0");
+        set_last_error("lgf_server_create: p in [2, 10] (or n + 1 with n = 12, 16), precision, max_slots in [1, 16], budget >= 0");
         return LGF_ERR_ARG;
     }
     auto S = std::make_unique<lgf_server_s>();

@@ -1,12 +1,15 @@
-"""GPU parity of the paper's own scheme family at n = 16: n_I = n + 1 = 17 nodes per interval
-edge at every level, interpolation stencils of the n_max = 10 closest nodes (Sec. 2.5 and
-Sec. 4).  Level 1 works on the blocks' own spectra (its nodes are the blocks' grid points);
-levels >= 2 use 34-point transforms in two phases.
+"""GPU parity of the paper's own scheme family n_I = n + 1 (Sec. 2.5, Sec. 4): at n = 16,
+n_I = 17 nodes per interval edge with interpolation stencils of the n_max = 10 closest
+nodes; level 1 works on the blocks' own spectra (its nodes are the blocks' grid points) and
+levels >= 2 use 34-point transforms in two phases.  Also the other members the paper runs
+in Table 2 that fit the block transforms: n_I = 7 (n = 6, global stencils) and n_I = 13
+(n = 12, local stencils, 26-point transforms in one phase), and the family's convergence on
+one domain against a manufactured solution.
 
 Tolerances: FP64 against the oracle's FLGF within max(1e-12, Lambda^3 eps_64), Lambda the
-Lebesgue constant of the 10-node local stencils; FP64 against the exact sum within the
-oracle's own truncation error + 1e-12 (manufactured solution, Sec. 4.1); graphs, batches and
-kernel variants bit for bit."""
+Lebesgue constant of the stencils; FP64 against the exact sum within the oracle's own
+truncation error + 1e-12 (manufactured solution, Sec. 4.1); FP32 within 1e-6 on smooth
+sources; graphs, batches and kernel variants bit for bit."""
 import sys
 import zlib
 
@@ -16,6 +19,7 @@ import torch
 
 from oracle import flgf, lgf as olgf
 from paper_1402_6081_amd import workloads as W
+import tolerances
 
 pytestmark = pytest.mark.gpu
 N, P = 16, 17
@@ -40,9 +44,7 @@ def rel(a, b):
 
 
 def fp64_tol():
-    t = np.linspace(0, P - 1, 20001)
-    leb = float(np.max(np.sum(np.abs(flgf.lagrange(P, t)), axis=0)))
-    return max(1e-12, 2.0 * leb ** 3 * 2.22e-16)
+    return tolerances.fp64_tol(P)
 
 
 def _dev(x, prec):
@@ -167,3 +169,86 @@ def test_lattice_scheme_separate_sets(L):
     e = rel(got, ref)
     _say("case: n_I = 17 separate sets, rel Linf vs oracle = %.3e" % e)
     assert e < fp64_tol()
+
+
+# ---------------------------------------------------------------- n_I = 7 and 13 (Table 2)
+FAMILY = [
+    (6, 7, "eden40_L0", lambda r: W.eden_layout(40, r), 0),
+    (6, 7, "cube5_L2_truncated", lambda r: W.cube_layout(5), 2),
+    (12, 13, "cube4_L0", lambda r: W.cube_layout(4), 0),
+    (12, 13, "eden24_L0", lambda r: W.eden_layout(24, r), 0),
+    (12, 13, "eden30_L1_truncated", lambda r: W.eden_layout(30, r), 1),
+]
+
+
+def _plan_solve(L, blocks, f, n, p, levels, prec):
+    plan = L.Plan(blocks, n, p, levels, prec)
+    u = plan.solve(_dev(f, prec))
+    torch.cuda.synchronize()
+    out = u.double().cpu().numpy()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("case", FAMILY, ids=["nI%d_%s" % (c[1], c[2]) for c in FAMILY])
+def test_scheme_family_fp64_matches_oracle(L, case):
+    n, p, label, mk, levels = case
+    rng = np.random.default_rng(zlib.crc32(("%d_%s" % (p, label)).encode()))
+    blocks = mk(rng)
+    f = rng.standard_normal((len(blocks), n, n, n))
+    _say("case: n_I = %d," % p, label, "blocks", len(blocks))
+    ref = flgf.solve(blocks, f, n, p, levels)
+    got = _plan_solve(L, blocks, f, n, p, levels, "f64")
+    e = rel(got, ref)
+    _say("   rel Linf vs oracle = %.3e (tol %.1e)" % (e, tolerances.fp64_tol(p)))
+    assert e < tolerances.fp64_tol(p)
+
+
+@pytest.mark.parametrize("n,p", [(6, 7), (12, 13)])
+def test_scheme_family_fp32(L, n, p):
+    rng = np.random.default_rng(63 + p)
+    blocks = W.eden_layout(40, rng)
+    f, _ = W.zero_mean_gaussians(blocks, n, rng, 6)
+    u64 = _plan_solve(L, blocks, f, n, p, 0, "f64")
+    u32 = _plan_solve(L, blocks, f, n, p, 0, "f32")
+    ref = flgf.solve(blocks, f, n, p, 0)
+    e, e_or = rel(u32, u64), rel(u32, ref)
+    _say("case: n_I = %d FP32 vs FP64 rel Linf = %.3e, vs oracle FLGF %.3e" % (p, e, e_or))
+    assert e < tolerances.FP32_BAR and e_or < tolerances.FP32_BAR
+
+
+def test_table2_family_converges_on_gpu(L):
+    """One 96^3 cube as blocks of n = 6, 8, 12 and 16 with n_I = n + 1 (7, 9, 13, 17), one
+    manufactured solution (Sec. 4.1): the device's error against u_rand for every scheme,
+    equal to the oracle's FLGF error (within 1%) for n_I = 13 and 17, and falling like
+    n_I^-10.7 as the paper reports (exponents between neighbouring schemes in [9, 13])."""
+    rng = np.random.default_rng(11)
+    b8 = W.cube_layout(12)
+    u8 = W.random_manufactured(b8, 8, rng)
+    D = np.zeros((96, 96, 96))
+    for i, (bx, by, bz) in enumerate(b8.tolist()):
+        D[bz * 8:(bz + 1) * 8, by * 8:(by + 1) * 8, bx * 8:(bx + 1) * 8] = u8[i]
+    LD = olgf.laplacian(D)[1:-1, 1:-1, 1:-1]
+    err = {}
+    for n in (6, 8, 12, 16):
+        b = W.cube_layout(96 // n)
+        cut = lambda A: np.stack([A[bz * n:(bz + 1) * n, by * n:(by + 1) * n, bx * n:(bx + 1) * n]
+                                  for bx, by, bz in b.tolist()])
+        u, f = cut(D), cut(LD)
+        got = _plan_solve(L, b, f, n, n + 1, 0, "f64")
+        err[n + 1] = rel(got, u)
+        msg = "   n_I = %2d (%d blocks of %d^3): device error vs u_rand %.3e" % (n + 1, len(b), n, err[n + 1])
+        if n >= 12:
+            ref = flgf.solve(b, f, n, n + 1, 0)
+            eo, par = rel(ref, u), rel(got, ref)
+            msg += ", oracle FLGF error %.3e, device vs oracle %.1e" % (eo, par)
+            # f = L u_rand is rough: G * f cancels partial fields far larger than u, so two
+            # FP64 evaluations of it differ by rounding on the scale of those fields (1e-11 of
+            # max|u| here, where parity on smooth sources is 1e-15); the device's error is the
+            # method's error, to far better than 1%
+            assert abs(err[n + 1] - eo) <= 0.01 * eo
+        _say(msg)
+    slope = lambda a, c: np.log(err[a] / err[c]) / np.log(c / a)
+    _say("   exponents: 9 -> 13: %.1f, 13 -> 17: %.1f" % (slope(9, 13), slope(13, 17)))
+    assert err[7] > err[9] > err[13] > err[17] and err[17] < 2e-9
+    assert 9.0 < slope(9, 13) < 13.0 and 9.0 < slope(13, 17) < 13.0

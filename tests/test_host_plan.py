@@ -98,16 +98,19 @@ def test_layout_errors(L):
     with pytest.raises(L.LGFError) as e:
         L.plan_estimate(np.array([[0, 0, 0], [1 << 21, 0, 0]]), 8, 6)
     assert e.value.name == "LGF_ERR_LAYOUT"
-    with pytest.raises(L.LGFError) as e:
-        L.plan_estimate(np.array([[0, 0, 0]]), 6, 6)
-    assert e.value.name == "LGF_ERR_ARG"
+    for n, p in ((10, 6), (12, 11), (16, 13), (8, 12)):  # n unsupported; p > 10 only as n + 1 for n = 12, 16
+        with pytest.raises(L.LGFError) as e:
+            L.plan_estimate(np.array([[0, 0, 0]]), n, p)
+        assert e.value.name == "LGF_ERR_ARG"
+    for n, p in ((6, 7), (12, 13), (12, 8), (16, 17)):  # the scheme family n_I = n + 1 and others
+        assert L.plan_estimate(np.array([[0, 0, 0], [3, 0, 0]]), n, p)["n"] == n
 
 
 def test_server_config_errors(L):
     lib = L.library()
     h = ctypes.c_void_p()
     bad = [L.ServerConfig(0, 0, 0, 16, 8, 0, 1),    # no slots
-           L.ServerConfig(0, 4, 0, 12, 8, 0, 1),    # n unsupported
+           L.ServerConfig(0, 4, 0, 10, 8, 0, 1),    # n unsupported
            L.ServerConfig(-1, 4, 0, 16, 8, 0, 1),   # negative budget
            L.ServerConfig(0, 4, 0, 16, 8, 0, 7)]    # unknown precision
     for cfg in bad:

@@ -111,6 +111,28 @@ def test_paper_scheme_converges_like_n_I_to_minus_10():
     assert err[16] < 2e-9 and err[8] > 300 * err[16], err
 
 
+def test_table2_scheme_family_converges_like_n_I_to_minus_10():
+    # the paper's scheme family n_I = n + 1 (Sec. 4; Table 2 runs n_I = 7, 13, 28) on one
+    # domain: a 96^3 cube as blocks of n = 8, 12 and 16 (p = 9 global stencils, p = 13 and
+    # 17 local stencils of 10 nodes), one manufactured solution (Sec. 4.1).  The paper
+    # reports the error falling like n_I^-10.7 for n_I in [11, 28]: the measured exponents
+    # between neighbouring schemes lie within [9, 13]
+    D = None
+    err = {}
+    for n in (8, 12, 16):
+        b = W.cube_layout(96 // n)
+        if D is None:
+            u8 = W.random_manufactured(b, n, np.random.default_rng(11))
+            D = _dense(b, n, u8)
+            LD = lgf.laplacian(D)[1:-1, 1:-1, 1:-1]
+        u, f = _blocks(b, n, D), _blocks(b, n, LD)
+        got = flgf.solve(b, f, n, n + 1, 0)
+        err[n + 1] = np.max(np.abs(got - u)) / np.max(np.abs(u))
+    slope = lambda a, c: np.log(err[a] / err[c]) / np.log(c / a)
+    assert err[17] < 2e-9 and err[13] < err[9] and err[17] < err[13], err
+    assert 9.0 < slope(9, 13) < 13.0 and 9.0 < slope(13, 17) < 13.0, (err, slope(9, 13), slope(13, 17))
+
+
 def test_manufactured_pair_is_the_laplacian_of_u():
     # the shared input generator's f = L u_rand agrees with the oracle's own Laplacian
     rng = np.random.default_rng(9)
