@@ -379,30 +379,34 @@ def context_bench(L, W, steps=3, warmup=1, seed=7):
     with a random manufactured solution (u_rand ~ U[-1, 1], zero on the boundary points, f =
     L u_rand, so G * f = u_rand exactly and the error is known in O(N)).  Schemes p = 8 and
     the paper's n_I = n + 1 = 17 (n_max = 10), FP64 and FP32, full depth, default kernel
-    variants, eager solves.  Reported per case: points/s, the error against u_rand (relative
-    L-infinity, computed on the device), plan time against solve time."""
+    variants, eager solves.  The cube is also run as the paper's Table 2 schemes n_I = 7
+    (77^3 blocks of 6^3) and n_I = 13 (38^3 blocks of 12^3), about 1e8 points each.
+    Reported per case: points/s, the error against u_rand (relative L-infinity, computed on
+    the device), plan time against solve time."""
     import torch
-    shapes = (("cube29", W.cube_layout(29)), ("sphere36", W.sphere_layout(36)), ("shell44", W.shell_layout(44)))
+    shapes = (("cube29", W.cube_layout(29), 16, (8, 17)), ("sphere36", W.sphere_layout(36), 16, (8, 17)),
+              ("shell44", W.shell_layout(44), 16, (8, 17)), ("cube77_n6", W.cube_layout(77), 6, (7,)),
+              ("cube38_n12", W.cube_layout(38), 12, (13,)))
     out = {"note": "context only: the paper's Table 2 rates are 1.2e5 points/s per Xeon X5650 core, FP64, "
                    "n_I = 7..28, N = 1e8; here one MI355X, default kernel variants, eager solves",
            "unit": "grid points solved/s"}
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(seed)
-    for name, blocks in shapes:
+    for name, blocks, n, schemes in shapes:
         t0 = time.perf_counter()
-        u_ex, f = W.manufactured_pair(blocks, 16, rng)
+        u_ex, f = W.manufactured_pair(blocks, n, rng)
         t_gen = time.perf_counter() - t0
         npts = int(f.size)
-        res = {"blocks": int(len(blocks)), "points": npts, "host_generation_s": round(t_gen, 1)}
+        res = {"blocks": int(len(blocks)), "n": n, "points": npts, "host_generation_s": round(t_gen, 1)}
         ue = torch.from_numpy(u_ex).to(dev)
         scale = float(torch.max(torch.abs(ue)))
         del u_ex
-        for p in (8, 17):
+        for p in schemes:
             for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
                 fd = torch.from_numpy(f).to(dev, dt)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                plan = L.Plan(blocks, 16, p, 0, prec)
+                plan = L.Plan(blocks, n, p, 0, prec)
                 torch.cuda.synchronize()
                 t_plan = time.perf_counter() - t0
                 u = torch.empty_like(fd)
