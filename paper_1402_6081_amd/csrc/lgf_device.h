@@ -263,13 +263,129 @@ __device__ __forceinline__ void fft_reg(T (&re)[N], T (&im)[N]) {
     }
 }
 
+constexpr int smallest_factor(int v) {
+    for (int r = 2; r * r <= v; ++r)
+        if (v % r == 0) return r;
+    return v;
+}
+
+// acc + a * c for a compile-time constant c, fused where T is a machine float
+template <typename T>
+__device__ __forceinline__ T madd_const(T a, double c, T acc) {
+    if constexpr (std::is_floating_point<T>::value)
+        return fma(a, (T)c, acc);
+    else
+        return acc + a * T(c);
+}
+
+// In-place DFT of odd prime length N in registers, by conjugate input pairs: with
+// a_j = x_j + x_{N-j} and b_j = x_j - x_{N-j} (0 < j <= h = (N - 1) / 2),
+//   X_0 = x_0 + sum_j a_j,
+//   X_k, X_{N-k} = x_0 + sum_j a_j cos(2 pi jk/N)  +/-  SIGN i sum_j b_j sin(2 pi jk/N),
+// a quarter of the real multiplications of the direct sum.
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void dft_prime(T (&re)[N], T (&im)[N]) {
+    constexpr int h = (N - 1) / 2;
+    constexpr RootTable<N> R{};
+    T ar[h + 1], ai[h + 1], br[h + 1], bi[h + 1];
+    T s0r = re[0], s0i = im[0];
+#pragma unroll
+    for (int j = 1; j <= h; ++j) {
+        ar[j] = re[j] + re[N - j];
+        ai[j] = im[j] + im[N - j];
+        br[j] = re[j] - re[N - j];
+        bi[j] = im[j] - im[N - j];
+        s0r = s0r + ar[j];
+        s0i = s0i + ai[j];
+    }
+    T outr[N], outi[N];
+    outr[0] = s0r;
+    outi[0] = s0i;
+#pragma unroll
+    for (int k = 1; k <= h; ++k) {
+        T cr = re[0], ci = im[0];
+        T sr = br[1] * T(R.s[k % N]), si = bi[1] * T(R.s[k % N]);
+        cr = madd_const<T>(ar[1], R.c[k % N], cr);
+        ci = madd_const<T>(ai[1], R.c[k % N], ci);
+#pragma unroll
+        for (int j = 2; j <= h; ++j) {
+            const int idx = (j * k) % N;
+            cr = madd_const<T>(ar[j], R.c[idx], cr);
+            ci = madd_const<T>(ai[j], R.c[idx], ci);
+            sr = madd_const<T>(br[j], R.s[idx], sr);
+            si = madd_const<T>(bi[j], R.s[idx], si);
+        }
+        // i * SIGN * (sr + i si) = SIGN * (-si + i sr)
+        if constexpr (SIGN > 0) {
+            outr[k] = cr - si;
+            outi[k] = ci + sr;
+            outr[N - k] = cr + si;
+            outi[N - k] = ci - sr;
+        } else {
+            outr[k] = cr + si;
+            outi[k] = ci - sr;
+            outr[N - k] = cr - si;
+            outi[N - k] = ci + sr;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        re[k] = outr[k];
+        im[k] = outi[k];
+    }
+}
+
+// In-place DFT of any length N in registers, X_k = sum_j x_j e^{SIGN 2 pi i jk/N}:
+// radix-2 for powers of two, the conjugate-pair sum for odd primes, and otherwise one
+// Cooley-Tukey step N = r N2 (r the smallest prime factor; decimation in time):
+//   X_{k1 + N2 k2} = sum_{j1 < r} e^{SIGN 2 pi i j1 k2 / r} [e^{SIGN 2 pi i j1 k1 / N} Y_{j1}(k1)],
+// with Y_{j1} the N2-point DFT of x_{j1}, x_{j1 + r}, x_{j1 + 2r}, ...
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void dft_reg(T (&re)[N], T (&im)[N]) {
+    if constexpr (N == 1) {
+        return;
+    } else if constexpr (is_pow2(N)) {
+        fft_reg<T, N, SIGN>(re, im);
+    } else if constexpr (smallest_factor(N) == N) {
+        dft_prime<T, N, SIGN>(re, im);
+    } else {
+        constexpr int r = smallest_factor(N), N2 = N / r;
+        constexpr RootTable<N> R{};
+        T sr[r][N2], si[r][N2];
+#pragma unroll
+        for (int j1 = 0; j1 < r; ++j1) {
+#pragma unroll
+            for (int j2 = 0; j2 < N2; ++j2) {
+                sr[j1][j2] = re[j2 * r + j1];
+                si[j1][j2] = im[j2 * r + j1];
+            }
+            dft_reg<T, N2, SIGN>(sr[j1], si[j1]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < N2; ++k1) {
+            T tr[r], ti[r];
+#pragma unroll
+            for (int j1 = 0; j1 < r; ++j1) {
+                const int idx = (j1 * k1) % N;
+                cmul_const<T>(sr[j1][k1], si[j1][k1], R.c[idx], SIGN * R.s[idx], tr[j1], ti[j1]);
+            }
+            dft_reg<T, r, SIGN>(tr, ti);
+#pragma unroll
+            for (int k2 = 0; k2 < r; ++k2) {
+                re[k1 + N2 * k2] = tr[k2];
+                im[k1 + N2 * k2] = ti[k2];
+            }
+        }
+    }
+}
+
 // Forward transform of m inputs zero-padded to M outputs:
 //   X[k] = sum_{j<m} x[j] e^{-2 pi i jk/M},  k < M.
-// Power-of-two M with m = M/2: X[2k] = FFT_m(x)[k], X[2k+1] = FFT_m(x_j w^j)[k].
+// With M = 2m: X[2k] = DFT_m(x)[k], X[2k+1] = DFT_m(x_j w^j)[k] (w = e^{-2 pi i/M}).
 // Otherwise a direct DFT with compile-time roots.
 template <typename T, int m, int M>
 __device__ __forceinline__ void pencil_fwd(const T (&xr)[m], const T (&xi)[m], T (&Xr)[M], T (&Xi)[M]) {
-    if constexpr (is_pow2(M) && 2 * m == M && m >= 2) {
+    if constexpr (2 * m == M && m >= 2) {
         constexpr RootTable<M> R{};
         T er[m], ei[m], orr[m], oi[m];
 #pragma unroll
@@ -278,8 +394,8 @@ __device__ __forceinline__ void pencil_fwd(const T (&xr)[m], const T (&xi)[m], T
             ei[j] = xi[j];
             cmul_const<T>(xr[j], xi[j], R.c[j], -R.s[j], orr[j], oi[j]);
         }
-        fft_reg<T, m, -1>(er, ei);
-        fft_reg<T, m, -1>(orr, oi);
+        dft_reg<T, m, -1>(er, ei);
+        dft_reg<T, m, -1>(orr, oi);
 #pragma unroll
         for (int k = 0; k < m; ++k) {
             Xr[2 * k] = er[k];
@@ -307,9 +423,10 @@ __device__ __forceinline__ void pencil_fwd(const T (&xr)[m], const T (&xi)[m], T
 }
 
 // Truncated inverse: x[j] = sum_{k<M} X[k] e^{+2 pi i jk/M}, j < m (unnormalised).
+// With M = 2m: x[j] = IDFT_m(X[2k])[j] + w^j IDFT_m(X[2k+1])[j] (w = e^{+2 pi i/M}).
 template <typename T, int m, int M>
 __device__ __forceinline__ void pencil_inv(const T (&Xr)[M], const T (&Xi)[M], T (&xr)[m], T (&xi)[m]) {
-    if constexpr (is_pow2(M) && 2 * m == M && m >= 2) {
+    if constexpr (2 * m == M && m >= 2) {
         constexpr RootTable<M> R{};
         T er[m], ei[m], orr[m], oi[m];
 #pragma unroll
@@ -319,8 +436,8 @@ __device__ __forceinline__ void pencil_inv(const T (&Xr)[M], const T (&Xi)[M], T
             orr[k] = Xr[2 * k + 1];
             oi[k] = Xi[2 * k + 1];
         }
-        fft_reg<T, m, +1>(er, ei);
-        fft_reg<T, m, +1>(orr, oi);
+        dft_reg<T, m, +1>(er, ei);
+        dft_reg<T, m, +1>(orr, oi);
 #pragma unroll
         for (int j = 0; j < m; ++j) {
             T tr, ti;
@@ -421,10 +538,64 @@ __device__ __forceinline__ void c2r_each(const T (&Yr)[M / 2 + 1], const T (&Yi)
     }
 }
 
+// Forward transform of m real inputs zero-padded to M = 2m, its first H = m + 1 outputs
+// X[k] = sum_{j<m} x[j] e^{-2 pi i jk/M}, from one complex m-point DFT of the inputs packed
+// two to a value, y_j = x_{2j} + i x_{2j+1}:  with Y = DFT_m(y),
+//   X_k = E_k + e^{-2 pi i k/M} O_k,  E_k = (Y_k + conj Y_{m-k}) / 2,  O_k = (Y_k - conj Y_{m-k}) / 2i
+// (indices of Y mod m; E and O are the m-point DFTs of the even and odd inputs).
+template <typename T, int m, int M>
+__device__ __forceinline__ void pencil_r2c(const T (&x)[m], T (&Xr)[M / 2 + 1], T (&Xi)[M / 2 + 1]) {
+    static_assert(M == 2 * m, "padded length is twice the input length");
+    constexpr RootTable<M> R{};
+    T yr[m], yi[m];
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+        yr[j] = 2 * j < m ? x[2 * j] : T(0);
+        yi[j] = 2 * j + 1 < m ? x[2 * j + 1] : T(0);
+    }
+    dft_reg<T, m, -1>(yr, yi);
+#pragma unroll
+    for (int k = 0; k <= m; ++k) {
+        const int a = k % m, b = (m - k) % m;
+        const T er = T(0.5) * (yr[a] + yr[b]), ei = T(0.5) * (yi[a] - yi[b]);
+        // O = (Y_a - conj Y_b) / 2i
+        const T orr = T(0.5) * (yi[a] + yi[b]), oi = T(-0.5) * (yr[a] - yr[b]);
+        T tr, ti;
+        cmul_const<T>(orr, oi, R.c[k % M], -R.s[k % M], tr, ti);
+        Xr[k] = er + tr;
+        Xi[k] = ei + ti;
+    }
+}
+
 // Real part only of the truncated inverse of a Hermitian spectrum given by its first
 // H = M/2 + 1 coefficients (C2R): x[j] = sum_{k<M} Z[k] e^{+2 pi i jk/M}, Z[M-k] = conj Z[k].
+// For M = 2m other than a power of two the outputs are formed two to a complex value,
+// y_j = x_{2j} + i x_{2j+1} = IDFT_m(E + i O)[j], one m-point DFT, with (w = e^{+2 pi i/M})
+//   E_k = Y_k + conj Y_{m-k},  O_k = (Y_k - conj Y_{m-k}) w^k   (0 < k < m),
+//   E_0 = Re Y_0 + Re Y_m,     O_0 = Re Y_0 - Re Y_m,
+// the even- and odd-sample spectra, Hermitian in k by construction (so both inverses are
+// real).  Powers of two take the full complex pencil.
 template <typename T, int m, int M>
 __device__ __forceinline__ void pencil_c2r(const T (&Yr)[M / 2 + 1], const T (&Yi)[M / 2 + 1], T (&x)[m]) {
+    if constexpr (!is_pow2(M) && 2 * m == M && m >= 2) {
+        constexpr RootTable<M> R{};
+        T cr[m], ci[m];
+        cr[0] = Yr[0] + Yr[m];
+        ci[0] = Yr[0] - Yr[m];
+#pragma unroll
+        for (int k = 1; k < m; ++k) {
+            const T er = Yr[k] + Yr[m - k], ei = Yi[k] - Yi[m - k];
+            const T dr = Yr[k] - Yr[m - k], di = Yi[k] + Yi[m - k];
+            T orr, oi;
+            cmul_const<T>(dr, di, R.c[k], R.s[k], orr, oi);
+            cr[k] = er - oi;
+            ci[k] = ei + orr;
+        }
+        dft_reg<T, m, +1>(cr, ci);
+#pragma unroll
+        for (int j = 0; j < m; ++j) x[j] = (j & 1) ? ci[j / 2] : cr[j / 2];
+        return;
+    }
     T Zr[M], Zi[M];
 #pragma unroll
     for (int k = 0; k <= M / 2; ++k) {

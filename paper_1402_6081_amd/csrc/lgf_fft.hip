@@ -97,17 +97,23 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const FwdSegs<T> segs, int64_t t
         for (int row = tid; row < m * m; row += NT) {
             const int z = row / m, y = row - z * m;
             const T* s = reinterpret_cast<const T*>(buf + z * PLANE + m * H) + y * (m + 1);
-            T xr[m], xi[m];
-#pragma unroll
-            for (int j = 0; j < m; ++j) {
-                xr[j] = s[j];
-                xi[j] = T(0);
-            }
-            T Xr[M], Xi[M];
-            pencil_fwd<T, m, M>(xr, xi, Xr, Xi);
             cplx<T>* d = buf + z * PLANE + y * H;
+            T xr[m];
 #pragma unroll
-            for (int k = 0; k < H; ++k) d[k] = cplx<T>{Xr[k], Xi[k]};
+            for (int j = 0; j < m; ++j) xr[j] = s[j];
+            if constexpr (is_pow2(M)) {
+                T xi[m], Xr[M], Xi[M];
+#pragma unroll
+                for (int j = 0; j < m; ++j) xi[j] = T(0);
+                pencil_fwd<T, m, M>(xr, xi, Xr, Xi);
+#pragma unroll
+                for (int k = 0; k < H; ++k) d[k] = cplx<T>{Xr[k], Xi[k]};
+            } else {
+                T Xr[H], Xi[H];
+                pencil_r2c<T, m, M>(xr, Xr, Xi);
+#pragma unroll
+                for (int k = 0; k < H; ++k) d[k] = cplx<T>{Xr[k], Xi[k]};
+            }
         }
         __syncthreads();
         // y pass: columns (z, kx), y < m -> ky < M

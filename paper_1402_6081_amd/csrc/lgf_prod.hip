@@ -617,8 +617,11 @@ static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int waves, hipStream_
 //  * FP32 with 16-bit list entries: all 8 children per lane, in 4 parent groups per
 //    workgroup, or 8 for levels of at least 256 parents (the 256^3 M2L 329 -> 269 us; the
 //    128^3 one, 64 parents, stays fastest with 4: 53 us);
-//  * FP64 with 16-bit entries and at least 256 parents: all children per lane in 4 groups
-//    (the 256^3 M2L 610 -> 527 us);
+//  * FP64 with at least 256 parents: all children per lane in 4 groups (the 256^3 M2L
+//    610 -> 527 us);
+//  * levels of at least 256 parents with 32-bit entries (65535 or more intervals) as
+//    with 16-bit ones (a 77^3-block cube of n = 6, p = 7: FP64 66 -> 62 ms per solve,
+//    FP32 42 -> 36 ms);
 //  * otherwise levels with at least 64 parents run 4 children per lane in 4 parent
 //    groups; smaller levels 2 children per lane (more waves for little work) in 1 (FP64)
 //    or 2 (FP32) groups.
@@ -626,12 +629,12 @@ static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int waves, hipStream_
 // computes the same bits.
 template <typename T>
 void m2l_default(int64_t nparents, bool idx16, int& waves, int& cpl) {
-    if (sizeof(T) == 4 && idx16) {
+    if (sizeof(T) == 4 && (idx16 || nparents >= 256)) {
         if (waves == 0) waves = nparents >= 256 ? 8 : 4;
         if (cpl == 0) cpl = 8;
         return;
     }
-    if (sizeof(T) == 8 && idx16 && nparents >= 256) {
+    if (sizeof(T) == 8 && nparents >= 256) {
         if (waves == 0) waves = 4;
         if (cpl == 0) cpl = 8;
         return;
