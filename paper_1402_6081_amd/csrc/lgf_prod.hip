@@ -261,8 +261,9 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 // children (the subset Q of the children is fixed per wave, so all its index arithmetic is
 // compile-time).  Per neighbour e the lane loads the 8 source coefficients once; its
 // (child, source child) pairs need only the kernel values at delta = c - cs, each read once
-// from LDS and applied to every pair with that delta.  The delta loop is unrolled; the
-// interaction-list condition |D|_inf >= 2 is a wave-uniform branch.
+// from LDS and applied to every pair with that delta.  The delta loop is unrolled and has
+// no branch: the interaction-list condition |D|_inf >= 2 is met by zero kernel rows at the
+// near offsets (the centre neighbour, all of whose pairs are near, is skipped whole).
 // Every child sums its terms in the same order (neighbour e, then delta) whatever CPL and
 // the number of waves, so all variants give identical results.  A neighbour whose children
 // are all the zero sentinel for every parent of a wave (absent intervals, or intervals
@@ -279,7 +280,11 @@ struct M2LShape {
 template <int CPL, int Q>
 __device__ constexpr int m2l_child(int i) { return Q * CPL + i; }
 
-// The contribution of neighbour e to this lane's children, with source values fa.
+// The contribution of neighbour e to this lane's children, with source values fa.  The
+// kernel tile holds zeros in the near-offset rows (|D| <= 1), which only near pairs would
+// read, so every delta is applied without a branch (an exact zero term leaves the sum's
+// bits unchanged); the deltas of one dz slab form one scheduling region, so the
+// multiply-adds of several deltas interleave.
 template <typename T, int CPL, int Q>
 __device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], const cplx<T>* tk, T (&ar)[CPL],
                                               T (&ai)[CPL]) {
@@ -287,27 +292,28 @@ __device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], con
     const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;  // wave-uniform
     const cplx<T>* kb = tk + ((3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 - 2 * ez)) * F;
 #pragma unroll
-    for (int d = 0; d < 27; ++d) {
-        const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
-        bool used = false;  // compile-time: does a child of this subset pair with delta d?
+    for (int dz = -1; dz <= 1; ++dz) {
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) {
-            const int c = m2l_child<CPL, Q>(i);
-            const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
-            used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
-        }
-        if (!used) continue;
-        const int Dx = dx - 2 * ex, Dy = dy - 2 * ey, Dz = dz - 2 * ez;
-        // near offsets are not in the interaction list (uniform branch)
-        if (Dx >= -1 && Dx <= 1 && Dy >= -1 && Dy <= 1 && Dz >= -1 && Dz <= 1) continue;
-        const cplx<T> k = kb[(dx + 7 * dy + 49 * dz) * F];
+        for (int dd = 0; dd < 9; ++dd) {
+            const int dx = dd % 3 - 1, dy = dd / 3 - 1;
+            bool used = false;  // compile-time: does a child of this subset pair with delta d?
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) {
-            const int c = m2l_child<CPL, Q>(i);
-            const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
-            if (csx < 0 || csx > 1 || csy < 0 || csy > 1 || csz < 0 || csz > 1) continue;  // compile-time
-            cmac(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
+            for (int i = 0; i < CPL; ++i) {
+                const int c = m2l_child<CPL, Q>(i);
+                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+                used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
+            }
+            if (!used) continue;
+            const cplx<T> k = kb[(dx + 7 * dy + 49 * dz) * F];
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) {
+                const int c = m2l_child<CPL, Q>(i);
+                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+                if (csx < 0 || csx > 1 || csy < 0 || csy > 1 || csz < 0 || csz > 1) continue;  // compile-time
+                cmac(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
+            }
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -396,6 +402,12 @@ struct FarSegs {
     int n;
 };
 
+// tile row r = (Dx+3) + 7 (Dy+3) + 49 (Dz+3) of a near offset (|D| <= 1 on every axis)
+__device__ __forceinline__ bool m2l_near_row(int r) {
+    const int dx = r % 7 - 3, dy = (r / 7) % 7 - 3, dz = r / 49 - 3;
+    return dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+}
+
 template <typename T, int kFarWaves, int CPL, typename IdxT>
 __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     k_prod_far_sib(const FarSegs<T> segs) {
@@ -441,7 +453,8 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int i = (int)threadIdx.x + k * NT;
-            kv[k] = (i < 343 * F && wok) ? sym_coef(khat, inf[k], om, g.sym.ncls, g.sym.M) : cplx<T>{T(0), T(0)};
+            kv[k] = (i < 343 * F && wok && !m2l_near_row(i / F)) ? sym_coef(khat, inf[k], om, g.sym.ncls, g.sym.M)
+                                                                  : cplx<T>{T(0), T(0)};
         }
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
@@ -451,7 +464,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     } else {
         for (int i = threadIdx.x; i < 343 * F; i += NT) {
             const int r = i / F, jj = i - r * F;
-            tile[i] = (w0 + jj < S) ? khat[spec_at(r, w0 + jj, 343)] : cplx<T>{T(0), T(0)};
+            tile[i] = (w0 + jj < S && !m2l_near_row(r)) ? khat[spec_at(r, w0 + jj, 343)] : cplx<T>{T(0), T(0)};
         }
     }
     for (int i = threadIdx.x; i < PPG * 216; i += NT) {
@@ -484,8 +497,9 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
         ar[i] = T(0);
         ai[i] = T(0);
     }
-    m2l_dispatch<T, CPL, 0, IdxT>(q, fb, w & 63, sidx + Jl * 216, tile + j, (uint32_t)wave_uniform((int)live[pw]),
-                                  ar, ai);
+    // the centre neighbour (the parent itself) holds only near pairs
+    m2l_dispatch<T, CPL, 0, IdxT>(q, fb, w & 63, sidx + Jl * 216, tile + j,
+                                  (uint32_t)wave_uniform((int)live[pw]) & ~(1u << 13), ar, ai);
     if (J >= nparents || w >= S) return;
     const int32_t* c8 = child8 + (int64_t)J * 8 + q * CPL;
 #pragma unroll
