@@ -152,8 +152,10 @@ __global__ void __launch_bounds__(NT) k_pad_fft(const FwdSegs<T> segs, int64_t t
 }
 
 // Inverse: spectrum elements of type Tin, arithmetic in A, real output of type Tout.
-// (FP64 path: all double.  FP32 path: float at level 0; at levels >= 1 float spectra are
-// inverted in float-float arithmetic and written as float-float node values.)
+// (FP64 path: all double.  FP32 path: float at level 0 and at level 1 of the lattice
+// scheme; at the other levels >= 1 the float spectra are inverted in double arithmetic and
+// written as float-float node values (each double rounded to a hi + lo float pair).  The
+// float-float arithmetic instantiation A = ff32 is kept for tiles up to 10 nodes.)
 // One launch may invert several levels' spectra (segments of the grid with their own
 // input, output and item count; one workgroup per item).
 template <typename Tin, typename Tout>
