@@ -293,12 +293,37 @@ __global__ void __launch_bounds__(64 * kNearWaves)
 // are all the zero sentinel for every parent of a wave (absent intervals, or intervals
 // without sources) is skipped by that wave: the terms it would add are exact zeros.
 // Lanes: F consecutive frequencies (one 128-byte segment of a spectrum) x 64/F parents.
-// The workgroup's waves share the [343][F] kernel tile and the parents' source indices in LDS.
+// The workgroup's waves share the [343][F] kernel tile (in FP64 its upper half, below) and
+// the parents' source indices in LDS.
 template <typename T>
 struct M2LShape {
     static constexpr int F = 128 / (int)sizeof(cplx<T>);  // frequencies per chunk: 8 FP64, 16 FP32
     static constexpr int PPW = 64 / F;                     // parents per wave
 };
+// FP64 keeps half the kernel tile, the rows from the middle one (D = 0) up: 22 instead of
+// 44 KB of LDS, so four 4-wave workgroups share a CU.  The kernel spectra of opposite
+// offsets are complex conjugates (the kernel is real and even, Sec. 2.1, and its padded
+// tile is placed symmetrically about the origin: offset r at circulant index r mod M, zero
+// at M/2; so the -D tile is the D tile reflected, and its DFT the conjugate).  With row id
+// r = (Dx+3) + 7 (Dy+3) + 49 (Dz+3), row r < 171 is read as the conjugate of row 342 - r.
+template <typename T>
+struct M2LTile {
+    static constexpr bool kHalf = sizeof(T) == 8;
+    static constexpr int kRow0 = kHalf ? 171 : 0;  // first row id kept
+    static constexpr int kRows = 343 - kRow0;
+};
+
+// v with its sign flipped when flip (wave-uniform): one integer XOR on the sign bit
+template <typename T>
+__device__ __forceinline__ T neg_if(T v, bool flip) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long m = (unsigned long long)flip << 63;
+        return __longlong_as_double(__double_as_longlong(v) ^ (long long)m);
+    } else {
+        const unsigned m = (unsigned)flip << 31;
+        return __uint_as_float(__float_as_uint(v) ^ m);
+    }
+}
 
 // child i of subset Q when a lane accumulates CPL children (subsets split z, then y, then x)
 template <int CPL, int Q>
@@ -314,7 +339,9 @@ __device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], con
                                               T (&ai)[CPL]) {
     constexpr int F = M2LShape<T>::F;
     const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;  // wave-uniform
-    const cplx<T>* kb = tk + ((3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 - 2 * ez)) * F;
+    // row id of delta d = 0 for this neighbour, relative to the tile's first row
+    const int rb = (3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 - 2 * ez) - M2LTile<T>::kRow0;
+    const cplx<T>* kb = tk + rb * F;
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
 #pragma unroll
@@ -328,7 +355,14 @@ __device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], con
                 used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
             }
             if (!used) continue;
-            const cplx<T> k = kb[(dx + 7 * dy + 49 * dz) * F];
+            cplx<T> k;
+            if constexpr (M2LTile<T>::kHalf) {
+                const int rr = rb + dx + 7 * dy + 49 * dz;  // wave-uniform
+                k = tk[(rr >= 0 ? rr : -rr) * F];
+                k.y = neg_if<T>(k.y, rr < 0);
+            } else {
+                k = kb[(dx + 7 * dy + 49 * dz) * F];
+            }
 #pragma unroll
             for (int i = 0; i < CPL; ++i) {
                 const int c = m2l_child<CPL, Q>(i);
@@ -356,11 +390,12 @@ __device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fb, 
 template <typename T, int CPL, int Q, typename IdxT>
 __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl, const IdxT* si,
                                          const cplx<T>* tk, uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
-    if constexpr (sizeof(T) == 8 && CPL == 4) {
-        // two buffers: the next neighbour's sources are in flight while one is consumed.
-        // The FP64 four-children lane then needs 90 registers instead of 164, and two
-        // workgroups share a CU (measured 9-12% faster on the larger levels; the other
-        // variants keep three buffers, which measured faster for them)
+    if constexpr (sizeof(T) == 8 && CPL >= 4) {
+        // FP64 with 4 or 8 children per lane: two buffers, the next neighbour's sources in
+        // flight while one is consumed.  The four-children lane then needs 90 registers
+        // instead of 164 (9-12% faster on the larger levels); the all-children lane 112
+        // instead of 152, and with the halved kernel tile four 4-wave workgroups share a CU.
+        // The other variants keep three buffers, which measured faster for them.
         cplx<T> fa[8], fbuf[8];
         m2l_load<T, IdxT>(0, fb, wl, si, fa);
 #pragma unroll 1
@@ -440,7 +475,8 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     constexpr int NQ = 8 / CPL;             // waves per group of parents (one per child subset)
     constexpr int PPG = PPW * kFarWaves;    // parents per workgroup
     constexpr int NT = 64 * kFarWaves * NQ;
-    __shared__ cplx<T> tile[343 * F];
+    constexpr int kRows = M2LTile<T>::kRows, kRow0 = M2LTile<T>::kRow0;
+    __shared__ cplx<T> tile[kRows * F];
     __shared__ IdxT sidx[PPG * 216];  // 16-bit when every level's items fit (less LDS)
     __shared__ uint32_t live[kFarWaves];  // per group of PPW parents: neighbours holding a source
     // this workgroup's segment (uniform selects over the kernel arguments)
@@ -463,7 +499,7 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
     if (g.sym.info != nullptr) {
         // every row's description first, then all the (dependent) gathers, so the loads of
         // a thread's rows are in flight together
-        constexpr int NR = (343 * F + NT - 1) / NT;
+        constexpr int NR = (kRows * F + NT - 1) / NT;
         const int jj = (int)threadIdx.x % F;
         const bool wok = w0 + jj < S;
         const Freq3 om = wok ? freq_of(w0 + jj, g.sym.M) : Freq3{};
@@ -471,23 +507,24 @@ __global__ void __launch_bounds__(64 * kFarWaves * (8 / CPL))
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int i = (int)threadIdx.x + k * NT;
-            inf[k] = i < 343 * F ? g.sym.info[i / F] : 0u;
+            inf[k] = i < kRows * F ? g.sym.info[kRow0 + i / F] : 0u;
         }
         cplx<T> kv[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int i = (int)threadIdx.x + k * NT;
-            kv[k] = (i < 343 * F && wok && !m2l_near_row(i / F)) ? sym_coef(khat, inf[k], om, g.sym.ncls, g.sym.M)
-                                                                  : cplx<T>{T(0), T(0)};
+            kv[k] = (i < kRows * F && wok && !m2l_near_row(kRow0 + i / F))
+                        ? sym_coef(khat, inf[k], om, g.sym.ncls, g.sym.M)
+                        : cplx<T>{T(0), T(0)};
         }
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int i = (int)threadIdx.x + k * NT;
-            if (i < 343 * F) tile[i] = kv[k];
+            if (i < kRows * F) tile[i] = kv[k];
         }
     } else {
-        for (int i = threadIdx.x; i < 343 * F; i += NT) {
-            const int r = i / F, jj = i - r * F;
+        for (int i = threadIdx.x; i < kRows * F; i += NT) {
+            const int r = kRow0 + i / F, jj = i % F;
             tile[i] = (w0 + jj < S && !m2l_near_row(r)) ? khat[spec_at(r, w0 + jj, 343)] : cplx<T>{T(0), T(0)};
         }
     }
@@ -655,8 +692,9 @@ static hipError_t far_cpl(const FarLevel<T>* lv, int nlev, int waves, hipStream_
 //  * FP32 with 16-bit list entries: all 8 children per lane, in 4 parent groups per
 //    workgroup, or 8 for levels of at least 256 parents (the 256^3 M2L 329 -> 269 us; the
 //    128^3 one, 64 parents, stays fastest with 4: 53 us);
-//  * FP64 with at least 256 parents: all children per lane in 4 groups (the 256^3 M2L
-//    610 -> 527 us);
+//  * FP64 with at least 64 parents: all children per lane in 4 groups (the 256^3 M2L
+//    610 -> 527 us; with the halved kernel tile also the 128^3 one, 64 parents: 103 -> 99
+//    us against 4 children per lane);
 //  * levels of at least 256 parents with 32-bit entries (65535 or more intervals) as
 //    with 16-bit ones (a 77^3-block cube of n = 6, p = 7: FP64 66 -> 62 ms per solve,
 //    FP32 42 -> 36 ms);
@@ -672,7 +710,7 @@ void m2l_default(int64_t nparents, bool idx16, int& waves, int& cpl) {
         if (cpl == 0) cpl = 8;
         return;
     }
-    if (sizeof(T) == 8 && nparents >= 256) {
+    if (sizeof(T) == 8 && nparents >= 64) {
         if (waves == 0) waves = 4;
         if (cpl == 0) cpl = 8;
         return;
