@@ -300,16 +300,17 @@ struct M2LShape {
     static constexpr int F = 128 / (int)sizeof(cplx<T>);  // frequencies per chunk: 8 FP64, 16 FP32
     static constexpr int PPW = 64 / F;                     // parents per wave
 };
-// FP64 keeps half the kernel tile, the rows from the middle one (D = 0) up: 22 instead of
-// 44 KB of LDS, so four 4-wave workgroups share a CU.  The kernel spectra of opposite
+// FP64 keeps the half of the kernel tile with Dz >= 0 (196 of its 343 rows): 25 instead
+// of 44 KB of LDS, so four 4-wave workgroups share a CU.  The kernel spectra of opposite
 // offsets are complex conjugates (the kernel is real and even, Sec. 2.1, and its padded
 // tile is placed symmetrically about the origin: offset r at circulant index r mod M, zero
-// at M/2; so the -D tile is the D tile reflected, and its DFT the conjugate).  With row id
-// r = (Dx+3) + 7 (Dy+3) + 49 (Dz+3), row r < 171 is read as the conjugate of row 342 - r.
+// at M/2; so the -D tile is the D tile reflected, and its DFT the conjugate).  An offset
+// with Dz < 0 is read as the conjugate of the row of -D.  In a neighbour step the deltas of
+// one dz slab share Dz = dz - 2 ez, so a slab either reads D or conjugates throughout.
 template <typename T>
 struct M2LTile {
     static constexpr bool kHalf = sizeof(T) == 8;
-    static constexpr int kRow0 = kHalf ? 171 : 0;  // first row id kept
+    static constexpr int kRow0 = kHalf ? 147 : 0;  // first row id kept: D = (-3, -3, 0)
     static constexpr int kRows = 343 - kRow0;
 };
 
@@ -325,51 +326,92 @@ __device__ __forceinline__ T neg_if(T v, bool flip) {
     }
 }
 
+// ar + i ai += f * conj(k): the conjugate's sign goes into the FMAs' operands (the same
+// roundings as cmac with the sign-flipped k)
+template <typename T>
+__device__ __forceinline__ void cmac_conj(T& ar, T& ai, const cplx<T>& f, const cplx<T>& k) {
+    ar = fma(f.x, k.x, ar);
+    ar = fma(f.y, k.y, ar);
+    ai = fma(-f.x, k.y, ai);
+    ai = fma(f.y, k.x, ai);
+}
+
 // child i of subset Q when a lane accumulates CPL children (subsets split z, then y, then x)
 template <int CPL, int Q>
 __device__ constexpr int m2l_child(int i) { return Q * CPL + i; }
+
+// The deltas of one dz slab applied to this lane's children.  kb points at the row of
+// delta d = 0; delta d reads kb[s (dx + 7 dy) F] with s = 1, or s = -1 when the slab reads
+// the rows of -D.  CONJ: 0 reads D, 1 conjugates (compile-time), 2 decides by flip
+// (wave-uniform, one sign-bit XOR per kernel value).
+template <typename T, int CPL, int Q, int CONJ>
+__device__ __forceinline__ void m2l_slab(int dz, const cplx<T>* kb, bool flip, const cplx<T> (&fa)[8],
+                                         T (&ar)[CPL], T (&ai)[CPL]) {
+    constexpr int F = M2LShape<T>::F;
+#pragma unroll
+    for (int dd = 0; dd < 9; ++dd) {
+        const int dx = dd % 3 - 1, dy = dd / 3 - 1;
+        bool used = false;  // compile-time: does a child of this subset pair with delta d?
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            const int c = m2l_child<CPL, Q>(i);
+            const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+            used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
+        }
+        if (!used) continue;
+        cplx<T> k;
+        if constexpr (CONJ == 2) {
+            k = kb[(flip ? -(dx + 7 * dy) : dx + 7 * dy) * F];
+            k.y = neg_if<T>(k.y, flip);
+        } else {
+            k = kb[(CONJ ? -(dx + 7 * dy) : dx + 7 * dy) * F];
+        }
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            const int c = m2l_child<CPL, Q>(i);
+            const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
+            if (csx < 0 || csx > 1 || csy < 0 || csy > 1 || csz < 0 || csz > 1) continue;  // compile-time
+            if constexpr (CONJ == 1)
+                cmac_conj(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
+            else
+                cmac(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
+        }
+    }
+}
 
 // The contribution of neighbour e to this lane's children, with source values fa.  The
 // kernel tile holds zeros in the near-offset rows (|D| <= 1), which only near pairs would
 // read, so every delta is applied without a branch (an exact zero term leaves the sum's
 // bits unchanged); the deltas of one dz slab form one scheduling region, so the
-// multiply-adds of several deltas interleave.
-template <typename T, int CPL, int Q>
+// multiply-adds of several deltas interleave.  LAYER = ez of the neighbours this code
+// serves when known at compile time (FP64: each slab then reads D or conjugates in code of
+// its own), else 2.
+template <typename T, int CPL, int Q, int LAYER = 2>
 __device__ __forceinline__ void m2l_neighbour(int e, const cplx<T> (&fa)[8], const cplx<T>* tk, T (&ar)[CPL],
                                               T (&ai)[CPL]) {
     constexpr int F = M2LShape<T>::F;
-    const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = e / 9 - 1;  // wave-uniform
-    // row id of delta d = 0 for this neighbour, relative to the tile's first row
-    const int rb = (3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 - 2 * ez) - M2LTile<T>::kRow0;
-    const cplx<T>* kb = tk + rb * F;
+    const int ex = e % 3 - 1, ey = (e / 3) % 3 - 1, ez = LAYER == 2 ? e / 9 - 1 : LAYER;  // wave-uniform
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
-#pragma unroll
-        for (int dd = 0; dd < 9; ++dd) {
-            const int dx = dd % 3 - 1, dy = dd / 3 - 1;
-            bool used = false;  // compile-time: does a child of this subset pair with delta d?
-#pragma unroll
-            for (int i = 0; i < CPL; ++i) {
-                const int c = m2l_child<CPL, Q>(i);
-                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
-                used |= csx >= 0 && csx <= 1 && csy >= 0 && csy <= 1 && csz >= 0 && csz <= 1;
-            }
-            if (!used) continue;
-            cplx<T> k;
-            if constexpr (M2LTile<T>::kHalf) {
-                const int rr = rb + dx + 7 * dy + 49 * dz;  // wave-uniform
-                k = tk[(rr >= 0 ? rr : -rr) * F];
-                k.y = neg_if<T>(k.y, rr < 0);
+        if constexpr (M2LTile<T>::kHalf) {
+            // the halved tile's row (Dx+3) + 7 (Dy+3) + 49 Dz holds D, Dz = dz - 2 ez
+            const cplx<T>* plain = tk + ((3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (dz - 2 * ez)) * F;
+            const cplx<T>* mirror = tk + ((3 + 2 * ex) + 7 * (3 + 2 * ey) + 49 * (2 * ez - dz)) * F;
+            if constexpr (LAYER == 2) {
+                const bool flip = dz - 2 * ez < 0;
+                m2l_slab<T, CPL, Q, 2>(dz, flip ? mirror : plain, flip, fa, ar, ai);
+            } else if constexpr (LAYER < 0) {
+                m2l_slab<T, CPL, Q, 0>(dz, plain, false, fa, ar, ai);
             } else {
-                k = kb[(dx + 7 * dy + 49 * dz) * F];
+                // LAYER = 1: every slab conjugates; LAYER = 0: the dz = -1 slab only
+                if (LAYER == 1 || dz < 0)
+                    m2l_slab<T, CPL, Q, 1>(dz, mirror, true, fa, ar, ai);
+                else
+                    m2l_slab<T, CPL, Q, 0>(dz, plain, false, fa, ar, ai);
             }
-#pragma unroll
-            for (int i = 0; i < CPL; ++i) {
-                const int c = m2l_child<CPL, Q>(i);
-                const int csx = (c & 1) - dx, csy = ((c >> 1) & 1) - dy, csz = (c >> 2) - dz;
-                if (csx < 0 || csx > 1 || csy < 0 || csy > 1 || csz < 0 || csz > 1) continue;  // compile-time
-                cmac(ar[i], ai[i], fa[csx | (csy << 1) | (csz << 2)], k);
-            }
+        } else {
+            m2l_slab<T, CPL, Q, 0>(dz, tk + ((3 - 2 * ex) + 7 * (3 - 2 * ey) + 49 * (3 + dz - 2 * ez)) * F, false,
+                                   fa, ar, ai);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -393,22 +435,33 @@ __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl,
     if constexpr (sizeof(T) == 8 && CPL >= 4) {
         // FP64 with 4 or 8 children per lane: two buffers, the next neighbour's sources in
         // flight while one is consumed.  The four-children lane then needs 90 registers
-        // instead of 164 (9-12% faster on the larger levels); the all-children lane 112
-        // instead of 152, and with the halved kernel tile four 4-wave workgroups share a CU.
-        // The other variants keep three buffers, which measured faster for them.
+        // instead of 164 (9-12% faster on the larger levels); the all-children lane 116
+        // instead of 152, and with the halved kernel tile four 4-wave workgroups share a CU
+        // (with the conjugation compiled per layer, below: the 256^3 M2L 550 -> 432 us, the
+        // 128^3 one 97 -> 81 us, the Table 2 scheme cubes 11-12% faster than with the full
+        // tile).  The other variants keep three buffers, which measured faster for them.
+        // one loop per layer ez of neighbours (9 each), so that every slab's conjugation is
+        // known at compile time; the buffer holding the next neighbour alternates between
+        // layers (9 is odd)
         cplx<T> fa[8], fbuf[8];
-        m2l_load<T, IdxT>(0, fb, wl, si, fa);
+        auto layer = [&](auto lc, int e0, cplx<T>(&x)[8], cplx<T>(&y)[8]) {
+            constexpr int LY = decltype(lc)::value;
 #pragma unroll 1
-        for (int e = 0; e < 27; e += 2) {
-            m2l_load<T, IdxT>(e + 1, fb, wl, si, fbuf);
-            issue_fence();
-            if (live & (1u << e)) m2l_neighbour<T, CPL, Q>(e, fa, tk, ar, ai);
-            if (e + 1 < 27) {
-                m2l_load<T, IdxT>(e + 2, fb, wl, si, fa);
+            for (int e = e0; e < e0 + 9; e += 2) {
+                m2l_load<T, IdxT>(e + 1, fb, wl, si, y);
                 issue_fence();
-                if (live & (2u << e)) m2l_neighbour<T, CPL, Q>(e + 1, fbuf, tk, ar, ai);
+                if (live & (1u << e)) m2l_neighbour<T, CPL, Q, LY>(e, x, tk, ar, ai);
+                if (e + 1 < e0 + 9) {
+                    m2l_load<T, IdxT>(e + 2, fb, wl, si, x);
+                    issue_fence();
+                    if (live & (2u << e)) m2l_neighbour<T, CPL, Q, LY>(e + 1, y, tk, ar, ai);
+                }
             }
-        }
+        };
+        m2l_load<T, IdxT>(0, fb, wl, si, fa);
+        layer(std::integral_constant<int, -1>{}, 0, fa, fbuf);  // leaves neighbour 9 in fbuf
+        layer(std::integral_constant<int, 0>{}, 9, fbuf, fa);   // leaves neighbour 18 in fa
+        layer(std::integral_constant<int, 1>{}, 18, fa, fbuf);
     } else {
         cplx<T> fa[8], fbuf[8], fc[8];
         m2l_load<T, IdxT>(0, fb, wl, si, fa);
