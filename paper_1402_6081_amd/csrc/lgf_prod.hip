@@ -85,7 +85,8 @@ __host__ __forceinline__ bool chunk_fits_u32(int64_t items) {
 // FPL = 2 (FP32), a wave covers two consecutive chunks, lanes 0-31 the first and 32-63 the
 // second, each lane loading 16 bytes per item as the FP64 lanes do.  The waves of a
 // workgroup are different groups of the same chunk(s) and share the kernel tile in LDS: the
-// 27 near offsets, row (dx+1) + 3 (dy+1) + 9 (dz+1).  Every frequency is computed with the
+// 27 near offsets, row (dx+1) + 3 (dy+1) + 9 (dz+1).  A workgroup serves `rounds` blocks of
+// groups in turn with that tile.  Every frequency is computed with the
 // same arithmetic in the same order whatever FPL and the number of waves.
 template <typename T, int FPL>
 struct alignas(FPL * sizeof(cplx<T>)) LaneCoef {
@@ -96,13 +97,17 @@ template <typename T, int kNearWaves, bool kPrefetch, int FPL>
 __global__ void __launch_bounds__(64 * kNearWaves)
     k_prod_near_grouped(const cplx<T>* __restrict__ fhat, const cplx<T>* __restrict__ khat,
                         const int32_t* __restrict__ tgt8, const int32_t* __restrict__ src64,
-                        cplx<T>* __restrict__ uhat, int S, int ngroups, int nsrc, int ntgt, const SpecSym sym) {
+                        cplx<T>* __restrict__ uhat, int S, int ngroups, int nsrc, int ntgt, const SpecSym sym,
+                        int rounds) {
     using V = LaneCoef<T, FPL>;
     __shared__ V tile[27 * 64];
     const int lane = threadIdx.x & 63;
     const int nchunks = (S + 63) / 64;  // the last chunk may be partial (frequencies w >= S unused)
+    // a workgroup serves `rounds` blocks of kNearWaves groups of one chunk (block gb, then
+    // gb + gstride, ...) with one kernel tile
+    const int gstride = ((ngroups + kNearWaves - 1) / kNearWaves + rounds - 1) / rounds;
     int unit, gb;
-    if (!xcd_tile((nchunks + FPL - 1) / FPL, (ngroups + kNearWaves - 1) / kNearWaves, unit, gb)) return;
+    if (!xcd_tile((nchunks + FPL - 1) / FPL, gstride, unit, gb)) return;
     // this thread's chunk and first frequency in it; with FPL = 2 the second half of the
     // wave may fall past the last chunk, and then reads the first half's chunk and stores
     // nothing
@@ -152,17 +157,8 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         }
     }
     __syncthreads();
-    const int g = wave_uniform(gb * kNearWaves + (threadIdx.x >> 6));
-    if (g >= ngroups) return;
     T ar[FPL][8], ai[FPL][8];
-#pragma unroll
-    for (int q = 0; q < FPL; ++q)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            ar[q][c] = T(0);
-            ai[q][c] = T(0);
-        }
-    const int32_t* sg = src64 + (int64_t)g * 64;
+    const int32_t* sg = src64;  // this round's group: its 64 source items
     // the first chunk's items (wave-uniform base) and this lane's offset from it, in
     // coefficients: its chunk, then its frequencies within the item
     const cplx<T>* fbase = fhat + (int64_t)(unit * FPL) * (nsrc + 1) * 64;
@@ -182,8 +178,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
     // with that row dropped at compile time (measured: the 256^3 FP64 Prod 698 -> 677 us,
     // FP32 371 -> 364 us, against one wave-uniform branch per row).
     // END: 0 for the first slab, 3 for the last, -1 for a middle one, so the end slabs'
-    // skipped row is a compile-time choice and no slab body has a branch; -2 leaves the
-    // choice to a wave-uniform branch on sz (the prefetching variant's rolled loop)
+    // skipped row is a compile-time choice and no slab body has a branch
     auto slab = [&](auto endc, int sz, const V(&f)[16]) {
         constexpr int END = decltype(endc)::value;
         // kernel row bases for cz = 0 (dz = 1 - sz) and cz = 1 (dz = 2 - sz); an end slab's
@@ -196,11 +191,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             for (int dx = 1; dx >= -1; --dx) {
 #pragma unroll
                 for (int cz = 0; cz < 2; ++cz) {
-                    if constexpr (END == -2) {
-                        if (cz ? sz == 0 : sz == 3) continue;  // |dz| = 2 (wave-uniform)
-                    } else {
-                        if (cz ? END == 0 : END == 3) continue;  // |dz| = 2 (compile-time)
-                    }
+                    if (cz ? END == 0 : END == 3) continue;  // |dz| = 2 (compile-time)
                     const V k = (cz ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
 #pragma unroll
                     for (int cy = 0; cy < 2; ++cy)
@@ -215,62 +206,122 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             }
         }
     };
+    // the half h of slab sz: source rows sy = 2h + j (j = 0, 1) in f[4 j + sx]; a target
+    // row cy meets them through dy = cy - sy + 1, so half 0 uses dy = 1, 0 and half 1
+    // dy = 0, -1
+    auto half = [&](auto endc, int sz, auto hc, const V(&f)[8]) {
+        constexpr int END = decltype(endc)::value, h = decltype(hc)::value;
+        const V* t0 = tile + 9 * (sz < 3 ? 2 - sz : 0) * 64 + lane;
+        const V* t1 = tile + 9 * (sz > 0 ? 3 - sz : 0) * 64 + lane;
+#pragma unroll
+        for (int dy = 1; dy >= -1; --dy) {
+#pragma unroll
+            for (int dx = 1; dx >= -1; --dx) {
+#pragma unroll
+                for (int cz = 0; cz < 2; ++cz) {
+                    if (cz ? END == 0 : END == 3) continue;  // |dz| = 2 (compile-time)
+                    if (h == 0 ? dy < 0 : dy > 0) continue;  // no target row meets this half
+                    const V k = (cz ? t1 : t0)[((dx + 1) + 3 * (dy + 1)) * 64];
+#pragma unroll
+                    for (int cy = 0; cy < 2; ++cy) {
+                        const int sy = cy - dy + 1;
+                        if (sy < 2 * h || sy > 2 * h + 1) continue;
+#pragma unroll
+                        for (int cx = 0; cx < 2; ++cx) {
+                            const int c = cx | (cy << 1) | (cz << 2);
+                            const int sxy = (cx - dx + 1) + 4 * (sy - 2 * h);
+#pragma unroll
+                            for (int q = 0; q < FPL; ++q) cmac(ar[q][c], ai[q][c], f[sxy].v[q], k.v[q]);
+                        }
+                    }
+                }
+            }
+        }
+    };
     using First = std::integral_constant<int, 0>;
     using Mid = std::integral_constant<int, -1>;
     using Last = std::integral_constant<int, 3>;
-    using Any = std::integral_constant<int, -2>;
-    if constexpr (kPrefetch) {
-        // the next slab's 16 source values are in flight while this slab is consumed
-        V fa[16], fb[16];
-#pragma unroll
-        for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load(sg[sxy]);
+    using H0 = std::integral_constant<int, 0>;
+    using H1 = std::integral_constant<int, 1>;
 #pragma unroll 1
-        for (int sz = 0; sz < 4; sz += 2) {
+    for (int r = 0; r < rounds; ++r) {
+        const int g = wave_uniform((gb + r * gstride) * kNearWaves + (threadIdx.x >> 6));
+        if (g >= ngroups) break;
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) fb[sxy] = load(sg[(sz + 1) * 16 + sxy]);
-            issue_fence();
-            slab(Any{}, sz, fa);
-            const int sn = sz + 2 < 4 ? sz + 2 : sz;  // past the end: a harmless reload
+        for (int q = 0; q < FPL; ++q)
 #pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) fa[sxy] = load(sg[sn * 16 + sxy]);
-            issue_fence();
-            slab(Any{}, sz + 1, fb);
-        }
-    } else {
-        V f[16];
-#pragma unroll
-        for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load(sg[sxy]);
-        issue_fence();
-        slab(First{}, 0, f);
-#pragma unroll 1
-        for (int sz = 1; sz < 3; ++sz) {  // the middle source z slabs; x and y unrolled
-#pragma unroll
-            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load(sg[sz * 16 + sxy]);
-            issue_fence();
-            slab(Mid{}, sz, f);
-        }
-#pragma unroll
-        for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load(sg[48 + sxy]);
-        issue_fence();
-        slab(Last{}, 3, f);
-    }
-    if (!live || w >= S) return;  // (S is even, so a lane's two frequencies are both below it or not)
-    const int32_t* tg = tgt8 + (int64_t)g * 8;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int t = tg[c];
-        if (t >= 0) {
-            // streamed past the caches: the output is read once, by the inverse transform, and
-            // must not evict the source spectra this kernel re-reads (measured: this Prod 15%
-            // faster, the inverse 10% slower, the pair 7% faster at 128^3 FP64)
-            typedef T vec_t __attribute__((ext_vector_type(2 * FPL)));  // one store per lane
-            vec_t o;
-#pragma unroll
-            for (int q = 0; q < FPL; ++q) {
-                o[2 * q] = ar[q][c];
-                o[2 * q + 1] = ai[q][c];
+            for (int c = 0; c < 8; ++c) {
+                ar[q][c] = T(0);
+                ai[q][c] = T(0);
             }
-            __builtin_nontemporal_store(o, reinterpret_cast<vec_t*>(uhat + spec_at(t, w, ntgt)));
+        sg = src64 + (int64_t)g * 64;
+        if constexpr (kPrefetch) {
+            // half slabs (source rows sy = 2h, 2h + 1) through two buffers of 8 values: the next
+            // half's loads are in flight while this half is consumed, in the registers the
+            // one-slab form uses for its 16 values.  A target meets the rows of the first half
+            // before those of the second, so it adds the same terms in the same order.
+            V fa[8], fb[8];
+            auto ld = [&](int sz, int h, V(&x)[8]) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[i] = load(sg[sz * 16 + 8 * h + i]);
+            };
+            ld(0, 0, fa);
+            ld(0, 1, fb);
+            issue_fence();
+            half(First{}, 0, H0{}, fa);
+            ld(1, 0, fa);
+            issue_fence();
+            half(First{}, 0, H1{}, fb);
+#pragma unroll 1
+            for (int sz = 1; sz < 3; ++sz) {
+                ld(sz, 1, fb);
+                issue_fence();
+                half(Mid{}, sz, H0{}, fa);
+                ld(sz + 1, 0, fa);
+                issue_fence();
+                half(Mid{}, sz, H1{}, fb);
+            }
+            ld(3, 1, fb);
+            issue_fence();
+            half(Last{}, 3, H0{}, fa);
+            issue_fence();
+            half(Last{}, 3, H1{}, fb);
+        } else {
+            V f[16];
+#pragma unroll
+            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load(sg[sxy]);
+            issue_fence();
+            slab(First{}, 0, f);
+#pragma unroll 1
+            for (int sz = 1; sz < 3; ++sz) {  // the middle source z slabs; x and y unrolled
+#pragma unroll
+                for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load(sg[sz * 16 + sxy]);
+                issue_fence();
+                slab(Mid{}, sz, f);
+            }
+#pragma unroll
+            for (int sxy = 0; sxy < 16; ++sxy) f[sxy] = load(sg[48 + sxy]);
+            issue_fence();
+            slab(Last{}, 3, f);
+        }
+        if (!live || w >= S) continue;  // (S is even, so a lane's two frequencies are both below it or not)
+        const int32_t* tg = tgt8 + (int64_t)g * 8;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int t = tg[c];
+            if (t >= 0) {
+                // streamed past the caches: the output is read once, by the inverse transform, and
+                // must not evict the source spectra this kernel re-reads (measured: this Prod 15%
+                // faster, the inverse 10% slower, the pair 7% faster at 128^3 FP64)
+                typedef T vec_t __attribute__((ext_vector_type(2 * FPL)));  // one store per lane
+                vec_t o;
+#pragma unroll
+                for (int q = 0; q < FPL; ++q) {
+                    o[2 * q] = ar[q][c];
+                    o[2 * q + 1] = ai[q][c];
+                }
+                __builtin_nontemporal_store(o, reinterpret_cast<vec_t*>(uhat + spec_at(t, w, ntgt)));
+            }
         }
     }
 }
@@ -666,14 +717,25 @@ __global__ void __launch_bounds__(kProdThreads)
 template <typename T>
 constexpr int kNearFpl = sizeof(T) == 4 ? 2 : 1;
 
+// Group blocks per workgroup of the level-0 Prod: every round reuses the workgroup's kernel
+// tile, and the smaller grid leaves CUs to the far-field kernels running beside it (graph
+// solves, 4-wave workgroups: 256^3 FP32 0.947 -> 0.929 ms with 2 rounds, 128^3 FP64
+// 0.277 -> 0.259 ms and FP32 0.154 -> 0.149 ms with 4; the same bits)
+static int near_rounds(int nunits, int nblocks) {
+    const int64_t wgs = (int64_t)nunits * nblocks;
+    return wgs >= 16384 ? 2 : (wgs >= 1024 ? 4 : 1);
+}
+
 template <typename T, int NW, bool PF>
 static hipError_t near_nw(const cplx<T>* fhat, const cplx<T>* khat, const int32_t* tgt8, const int32_t* src64,
                           cplx<T>* uhat, int64_t ngroups, int64_t nsrc, int64_t ntgt, int S, hipStream_t s,
                           const SpecSym& sym) {
     constexpr int FPL = kNearFpl<T>;
-    const unsigned grid = xcd_grid(((S + 63) / 64 + FPL - 1) / FPL, (int)((ngroups + NW - 1) / NW));
+    const int nunits = ((S + 63) / 64 + FPL - 1) / FPL, nblocks = (int)((ngroups + NW - 1) / NW);
+    const int rounds = near_rounds(nunits, nblocks);
+    const unsigned grid = xcd_grid(nunits, (nblocks + rounds - 1) / rounds);
     return lgf_launch(k_prod_near_grouped<T, NW, PF, FPL>, dim3(grid), dim3(64 * NW), 0, s, fhat, khat, tgt8,
-                      src64, uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym);
+                      src64, uhat, S, (int)ngroups, (int)nsrc, (int)ntgt, sym, rounds);
 }
 
 template <typename T, bool PF>

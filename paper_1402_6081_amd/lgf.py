@@ -282,7 +282,7 @@ class Plan:
         _check(library().lgf_plan_get_tuning(self._h, ctypes.byref(t)))
         return {k: getattr(t, k) for k in TUNING_FIELDS}
 
-    def set_tuning(self, fft0_threads=0, near_waves=8, near_prefetch=0, far_waves=0, far_children=0, overlap=0):
+    def set_tuning(self, fft0_threads=0, near_waves=4, near_prefetch=0, far_waves=0, far_children=0, overlap=0):
         t = Tuning(int(fft0_threads), int(near_waves), int(near_prefetch), int(far_waves), int(far_children),
                    int(overlap))
         _check(library().lgf_plan_set_tuning(self._h, ctypes.byref(t)))
