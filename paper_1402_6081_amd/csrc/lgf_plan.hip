@@ -891,9 +891,6 @@ static lgf_status make_plan(HostPlan& H, lgf_precision prec, void* hip_stream, l
         delete pl;
         return st;
     }
-    // the level-0 Prod's pipelined half slabs measured faster in FP32 graph solves (256^3
-    // 0.938 -> 0.928 ms, 128^3 0.151 -> 0.149 ms) and not in FP64
-    if (prec == LGF_F32) pl->tune.near_prefetch = 1;
     apply_cached_tune(pl);
     *out = pl;
     return LGF_OK;
