@@ -234,7 +234,8 @@ lgf_status lgf_graph_destroy(lgf_graph_t graph);
 typedef struct {
     int32_t fft0_threads;   /* threads per workgroup of the level-0 transforms: 0, 128, 256, 512    */
     int32_t near_waves;     /* waves per workgroup of the level-0 Prod: 2, 4, 8                      */
-    int32_t near_prefetch;  /* level-0 Prod issues the next half source slab's loads early: 0, 1    */
+    int32_t near_prefetch;  /* level-0 Prod issues the next half source slab's loads early: 0, 1
+                               (a new plan starts with 1 from 256 level-0 groups of 2^3 blocks)     */
     int32_t far_waves;      /* parent groups per workgroup of the level >= 1 Prod: 0, 1, 2, 4, 8, 16
                                (clamped to at most 16 waves per workgroup, 8 in FP64)       */
     int32_t far_children;   /* children accumulated per lane of that kernel: 0, 1, 2, 4, 8           */

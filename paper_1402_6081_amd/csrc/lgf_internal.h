@@ -225,7 +225,7 @@ hipError_t launch_prod_far(const cplx<T>* fhat, const cplx<T>* khat, const int32
 struct TuneConfig {
     int fft0_threads = 0;  // 0 = default per tile size, else 128 / 256 / 512
     int near_waves = 4;    // waves per workgroup of the level-0 Prod kernel: 2, 4, 8
-    int near_prefetch = 0; // that kernel's source loads half a z slab ahead: 0, 1
+    int near_prefetch = 0; // that kernel's source loads half a z slab ahead: 0, 1 (by plan size)
     int far_waves = 0;     // parent groups per workgroup of the level >= 1 Prod kernel: 1, 2, 4, 0 = by level size
     int far_children = 0;  // children per lane of that kernel: 8, 4, 2, 1, or 0 = by level size
     int overlap = 0;       // far-field chain on a second stream: 1 = yes, 2 = no, 0 = default (yes)

@@ -248,10 +248,10 @@ __global__ void __launch_bounds__(64 * kNearWaves)
         const int g = wave_uniform((gb + r * gstride) * kNearWaves + (threadIdx.x >> 6));
         if (g >= ngroups) break;
         // 4-wave workgroups whose groups all exist step through the source slabs together
-        // (a barrier before each slab's loads): the waves' groups are neighbours and share
-        // half their sources, which the lockstep serves from L1 (the 256^3 Prod 689 -> 662 us
-        // FP64, 363 -> 353 us FP32; with 8 waves it was slower).  The condition is uniform
-        // over the workgroup, so every wave meets the same barriers.
+        // (a barrier before each slab's, or half slab's, loads): the waves' groups are
+        // neighbours and share half their sources, which the lockstep serves from L1 (the
+        // 256^3 Prod 689 -> 662 us FP64, 363 -> 353 us FP32; with 8 waves it was slower).
+        // The condition is uniform over the workgroup, so every wave meets the same barriers.
         const bool lockstep = kNearWaves == 4 && (gb + r * gstride) * kNearWaves + kNearWaves <= ngroups;
 #pragma unroll
         for (int q = 0; q < FPL; ++q)
@@ -268,6 +268,7 @@ __global__ void __launch_bounds__(64 * kNearWaves)
             // before those of the second, so it adds the same terms in the same order.
             V fa[8], fb[8];
             auto ld = [&](int sz, int h, V(&x)[8]) {
+                if (lockstep) __syncthreads();
 #pragma unroll
                 for (int i = 0; i < 8; ++i) x[i] = load(sg[sz * 16 + 8 * h + i]);
             };
