@@ -497,14 +497,16 @@ __device__ __forceinline__ void m2l_load(int e, const cplx<T>* __restrict__ fb, 
 template <typename T, int CPL, int Q, typename IdxT>
 __device__ __forceinline__ void m2l_lane(const cplx<T>* __restrict__ fb, int wl, const IdxT* si,
                                          const cplx<T>* tk, uint32_t live, T (&ar)[CPL], T (&ai)[CPL]) {
-    if constexpr (sizeof(T) == 8 && CPL >= 4) {
-        // FP64 with 4 or 8 children per lane: two buffers, the next neighbour's sources in
-        // flight while one is consumed.  The four-children lane then needs 90 registers
+    if constexpr (CPL >= 4) {
+        // 4 or 8 children per lane: two buffers, the next neighbour's sources in flight
+        // while one is consumed.  The FP64 four-children lane then needs 90 registers
         // instead of 164 (9-12% faster on the larger levels); the all-children lane 116
         // instead of 152, and with the halved kernel tile four 4-wave workgroups share a CU
         // (with the conjugation compiled per layer, below: the 256^3 M2L 550 -> 432 us, the
         // 128^3 one 97 -> 81 us, the Table 2 scheme cubes 11-12% faster than with the full
-        // tile).  The other variants keep three buffers, which measured faster for them.
+        // tile).  FP32 with the unrolled layers: 74 instead of 92 registers, six waves per
+        // SIMD instead of five, the 256^3 M2L 252 -> 234 us.  The one- and two-children
+        // lanes keep three buffers, which measured faster for them.
         // one loop per layer ez of neighbours (9 each), so that every slab's conjugation is
         // known at compile time; the buffer holding the next neighbour alternates between
         // layers (9 is odd).  The loops are unrolled: each neighbour's offset is then a
